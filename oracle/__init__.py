@@ -1,0 +1,200 @@
+"""FP64 CPU oracle for the finite-strain Hill-48 hex8 path (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` import this module.  The product
+library never calls it, and it imports nothing from the product package.
+
+The C source (``oracle.c``) follows the paper step by step; see its header for
+the passages.  This module only marshals numpy arrays.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+NPARAM = 11
+NGRAD = 7
+
+
+def build(force=True):
+    """Compile liboracle.so with gcc (OpenMP, -O2)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    src = os.path.join(_HERE, "oracle.c")
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", src, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    lib.oracle_eig_sym3.argtypes = [P, P, P]
+    lib.oracle_log_strain.argtypes = [P, P]
+    lib.oracle_material_point.argtypes = [P] * 3 + [P] * 9
+    lib.oracle_material_point.restype = ctypes.c_int
+    lib.oracle_element.argtypes = [P] * 8
+    lib.oracle_csr_pattern.argtypes = [i32, i32, P, P, P, P, P]
+    lib.oracle_csr_pattern.restype = ctypes.c_int
+    lib.oracle_residual_tangent.argtypes = [i32, i32] + [P] * 13 + [ctypes.c_int]
+    lib.oracle_residual_tangent.restype = ctypes.c_int
+    lib.oracle_trial_yield.argtypes = [i32, i32] + [P] * 6 + [ctypes.c_int]
+    lib.oracle_residual_vjp.argtypes = [i32, i32] + [P] * 9 + [ctypes.c_int]
+    lib.oracle_residual_vjp.restype = ctypes.c_int
+    _lib = lib
+    del i64
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def eig_sym3(A):
+    A = _f64(A).reshape(3, 3)
+    w = np.zeros(3)
+    Q = np.zeros((3, 3))
+    _load().oracle_eig_sym3(_p(A), _p(w), _p(Q))
+    return w, Q
+
+
+def log_strain(F):
+    F = _f64(F).reshape(3, 3)
+    eps = np.zeros((3, 3))
+    _load().oracle_log_strain(_p(F), _p(eps))
+    return eps
+
+
+def material_point(F, hist_n, prm):
+    """Return a dict with S, P, T (3x3), hist (7), A (3,3,3,3), Cep, Cep_implicit,
+    Cmat (6x6 Mandel), plastic, iters, converged, dgamma, ftr, sy_n."""
+    F = _f64(F).reshape(3, 3)
+    h = _f64(hist_n).reshape(7)
+    p = _f64(prm).reshape(NPARAM)
+    S, P, T = np.zeros((3, 3)), np.zeros((3, 3)), np.zeros((3, 3))
+    hn = np.zeros(7)
+    A = np.zeros(81)
+    Cep, CepI, Cm = np.zeros((6, 6)), np.zeros((6, 6)), np.zeros((6, 6))
+    info = np.zeros(6)
+    rc = _load().oracle_material_point(_p(F), _p(h), _p(p), _p(S), _p(P), _p(T), _p(hn), _p(A),
+                                       _p(Cep), _p(CepI), _p(Cm), _p(info))
+    return dict(S=S, P=P, T=T, hist=hn, A=A.reshape(3, 3, 3, 3), Cep=Cep, Cep_implicit=CepI,
+                Cmat=Cm, plastic=bool(info[0]), iters=int(info[1]), converged=bool(info[2]),
+                dgamma=info[3], ftr=info[4], sy_n=info[5], rc=rc)
+
+
+def element(Xe, de, he, prm, want_K=True):
+    """Element residual (24), tangent (24x24), updated history (8x7), diag (4)."""
+    Xe = _f64(Xe).reshape(8, 3)
+    de = _f64(de).reshape(8, 3)
+    he = _f64(he).reshape(8, 7)
+    p = _f64(prm).reshape(NPARAM)
+    R = np.zeros(24)
+    K = np.zeros((24, 24)) if want_K else None
+    hn = np.zeros((8, 7))
+    diag = np.zeros(4, dtype=np.int32)
+    _load().oracle_element(_p(Xe), _p(de), _p(he), _p(p), _p(R), _p(K), _p(hn), _p(diag))
+    return R, K, hn, diag
+
+
+def csr_pattern(conn, n_nodes, with_rank=True):
+    """Return (row_ptr, col_idx, elem_rank [n_elems, 64]) or raise on a bad mesh."""
+    conn = _i32(conn).reshape(-1, 8)
+    ne = conn.shape[0]
+    row_ptr = np.zeros(3 * n_nodes + 1, dtype=np.int32)
+    nnz = np.zeros(1, dtype=np.int64)
+    lib = _load()
+    rc = lib.oracle_csr_pattern(n_nodes, ne, _p(conn), _p(nnz), _p(row_ptr), None, None)
+    if rc != 0:
+        raise ValueError(f"oracle_csr_pattern: invalid mesh (status {rc})")
+    col_idx = np.zeros(int(nnz[0]), dtype=np.int32)
+    rank = np.zeros((ne, 64), dtype=np.uint8) if with_rank else None
+    rc = lib.oracle_csr_pattern(n_nodes, ne, _p(conn), _p(nnz), _p(row_ptr), _p(col_idx), _p(rank))
+    if rc != 0:
+        raise ValueError(f"oracle_csr_pattern: invalid mesh (status {rc})")
+    return row_ptr, col_idx, rank
+
+
+def expand_params(prm, n_elems):
+    """Uniform [11] or per-element [n_elems, 11] parameters -> [n_elems, 11]."""
+    prm = _f64(prm)
+    if prm.ndim == 1:
+        return np.ascontiguousarray(np.broadcast_to(prm, (n_elems, NPARAM)))
+    return _f64(prm.reshape(n_elems, NPARAM))
+
+
+def residual_tangent(X, conn, row_ptr, col_idx, prm, d, hist_n, bc_mask=None, want_K=True,
+                     n_threads=0):
+    """Assembled residual R [3n], CSR values K [nnz] (or None), hist_np1 [7, 8ne],
+    rnorm2 (double, long double), diag [4]."""
+    X = _f64(X).reshape(-1, 3)
+    conn = _i32(conn).reshape(-1, 8)
+    nn, ne = X.shape[0], conn.shape[0]
+    prm = expand_params(prm, ne)
+    d = _f64(d).reshape(nn, 3)
+    hist_n = _f64(hist_n).reshape(7, 8 * ne)
+    bc = None if bc_mask is None else np.ascontiguousarray(bc_mask, dtype=np.uint8)
+    R = np.zeros(3 * nn)
+    K = np.zeros(len(col_idx)) if want_K else None
+    hn = np.zeros((7, 8 * ne))
+    rn = np.zeros(2)
+    diag = np.zeros(4, dtype=np.int32)
+    rp = _i32(row_ptr)
+    ci = _i32(col_idx)
+    rc = _load().oracle_residual_tangent(nn, ne, _p(X), _p(conn), _p(rp), _p(ci), _p(prm), _p(d),
+                                         _p(hist_n), _p(bc), _p(R), _p(K), _p(hn), _p(rn), _p(diag),
+                                         int(n_threads))
+    if rc != 0:
+        raise RuntimeError("oracle_residual_tangent: element entry missing from the CSR pattern")
+    return R, K, hn, rn, diag
+
+
+def trial_yield(X, conn, prm, d, hist_n, n_threads=0):
+    X = _f64(X).reshape(-1, 3)
+    conn = _i32(conn).reshape(-1, 8)
+    nn, ne = X.shape[0], conn.shape[0]
+    prm = expand_params(prm, ne)
+    d = _f64(d).reshape(nn, 3)
+    hist_n = _f64(hist_n).reshape(7, 8 * ne)
+    flag = np.zeros(8 * ne, dtype=np.uint8)
+    _load().oracle_trial_yield(nn, ne, _p(X), _p(conn), _p(prm), _p(d), _p(hist_n), _p(flag),
+                               int(n_threads))
+    return flag
+
+
+def residual_vjp(X, conn, prm, d, hist_n, lam, n_threads=0):
+    """Return (g_uniform [7], g_elem [7, n_elems], diag [4])."""
+    X = _f64(X).reshape(-1, 3)
+    conn = _i32(conn).reshape(-1, 8)
+    nn, ne = X.shape[0], conn.shape[0]
+    prm = expand_params(prm, ne)
+    d = _f64(d).reshape(nn, 3)
+    hist_n = _f64(hist_n).reshape(7, 8 * ne)
+    lam = _f64(lam).reshape(nn, 3)
+    gu = np.zeros(7)
+    ge = np.zeros((7, ne))
+    diag = np.zeros(4, dtype=np.int32)
+    _load().oracle_residual_vjp(nn, ne, _p(X), _p(conn), _p(prm), _p(d), _p(hist_n), _p(lam),
+                                _p(gu), _p(ge), _p(diag), int(n_threads))
+    return gu, ge, diag

@@ -1,0 +1,93 @@
+/*
+ * oracle.h -- FP64 CPU reference for the hex8 finite-strain Hill-48 residual,
+ * consistent tangent, CSR assembly and parameter VJP.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source with the HIP path.
+ *
+ * Conventions (all arrays row-major, host memory, double precision):
+ *   node coordinates / displacements : [n_nodes][3]
+ *   connectivity                     : [n_elems][8], VTK hex order, 0-based
+ *   parameters                       : [n_elems][11]
+ *        (E, nu, F, G, H, L, M, N, K, eps0, n)  in MPa / mm
+ *   history (per Gauss point q=8e+g) : [7][8*n_elems]
+ *        eps_p 11,22,33,23,13,12 (tensor components), alpha
+ *   3x3 tensors                      : [9], entry (i,j) at 3*i+j
+ *   Mandel 6-vectors                 : (11,22,33,sqrt2*23,sqrt2*13,sqrt2*12)
+ */
+#ifndef FEM_ORACLE_H
+#define FEM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORACLE_NPARAM 11
+#define ORACLE_NGRAD 7
+
+/* Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations. */
+void oracle_eig_sym3(const double A[9], double w[3], double Q[9]);
+
+/* Logarithmic strain eps = 1/2 ln(F^T F). */
+void oracle_log_strain(const double F[9], double eps[9]);
+
+/* Material point: geometric preprocessor, Hill-48/Swift return map and
+ * geometric postprocessor.  Outputs (any may be NULL):
+ *   S, P, T       second/first Piola-Kirchhoff and logarithmic stress [9]
+ *   hist_np1      updated (eps_p, alpha) [7]
+ *   A             dP_aA/dF_bB at index ((a*3+A)*3+b)*3+B  [81]
+ *   Cep           closed-form algorithmic tangent dT/deps (Mandel) [36]
+ *   Cep_implicit  the same tangent by implicit differentiation [36]
+ *   Cmat          Lagrangian tangent 2 dS/dC (Mandel) [36]
+ *   info          [0]=plastic flag, [1]=local iterations, [2]=converged,
+ *                 [3]=delta gamma, [4]=trial yield value f_tr, [5]=sigma_y(alpha_n)
+ * Returns 0 on success, 1 if the local Newton did not converge. */
+int oracle_material_point(const double F[9], const double hist_n[7], const double prm[11],
+                          double *S, double *P, double *T, double *hist_np1, double *A,
+                          double *Cep, double *Cep_implicit, double *Cmat, double *info);
+
+/* Element residual R[24] (index 3*I+a) and tangent K[576] (row 3*I+a, col 3*J+b)
+ * from node coordinates X[8][3], displacements d[8][3] and per-GP history
+ * hist[8][7] (GP-major).  hist_np1[8][7] may be NULL.  diag[4] accumulates
+ * (local Newton failures, detJ0<=0, detF<=0, non-finite). */
+void oracle_element(const double X[24], const double d[24], const double hist[56],
+                    const double prm[11], double R[24], double K[576], double hist_np1[56],
+                    int32_t diag[4]);
+
+/* CSR pattern.  Phase 1 (col_idx == NULL): fills row_ptr[3*n_nodes+1] and *nnz.
+ * Phase 2: fills col_idx[nnz] and, if elem_rank != NULL, elem_rank[n_elems][64]
+ * with rank(I,J) = position of node conn[e][J] in the sorted adjacency of conn[e][I].
+ * Returns 0, or -5 if a node belongs to no element / an index is out of range. */
+int oracle_csr_pattern(int32_t n_nodes, int32_t n_elems, const int32_t *conn,
+                       int64_t *nnz, int32_t *row_ptr, int32_t *col_idx, uint8_t *elem_rank);
+
+/* Global residual / tangent.  R[3n] (required), K[nnz] (may be NULL),
+ * hist_np1 (may be NULL), bc_mask[3n] (may be NULL), rnorm2[2] (may be NULL:
+ * [0] = double sum of R^2, [1] = long-double sum rounded to double),
+ * diag[4] (may be NULL).  n_threads <= 0 uses the OpenMP default. */
+int oracle_residual_tangent(int32_t n_nodes, int32_t n_elems, const double *X,
+                            const int32_t *conn, const int32_t *row_ptr, const int32_t *col_idx,
+                            const double *prm, const double *d, const double *hist_n,
+                            const uint8_t *bc_mask, double *R, double *K, double *hist_np1,
+                            double *rnorm2, int32_t *diag, int n_threads);
+
+/* Trial-state yield test only: flag[q] = 1 if f_tr > 0 at Gauss point q. */
+void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *conn,
+                        const double *prm, const double *d, const double *hist_n,
+                        uint8_t *flag, int n_threads);
+
+/* Parameter VJP  g_elem[7][n_elems] = lam^T dR/dtheta_e for the 7 parameters
+ * (F, G, H, N, K, eps0, n), by forward-mode implicit differentiation of the
+ * local update; g_uniform[7] = sum over elements (either may be NULL). */
+int oracle_residual_vjp(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *conn,
+                        const double *prm, const double *d, const double *hist_n,
+                        const double *lam, double *g_uniform, double *g_elem, int32_t *diag,
+                        int n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,301 @@
+"""Pins of the CPU oracle at the material point (CPU only).
+
+Each check compares the oracle with something other than itself: a library
+routine (scipy matrix logarithm / exponential), a separately written textbook
+algorithm (J2 radial return and its algorithmic tangent), closed forms for
+uniaxial stress and simple shear with linear hardening, invariants
+(objectivity), and central finite differences.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sl
+from scipy.optimize import brentq
+
+import oracle
+from paper_2606_17390_amd import synth
+
+E, NU = 200000.0, 0.3
+MU = E / (2 * (1 + NU))
+KAPPA = E / (3 * (1 - 2 * NU))
+LAME = E * NU / ((1 + NU) * (1 - 2 * NU))
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def vm_params(K=500.0, eps0=0.01, n=0.2):
+    return synth.params(K=K, eps0=eps0, n=n)
+
+
+def mandel(M):
+    s = np.sqrt(2.0)
+    return np.array([M[0, 0], M[1, 1], M[2, 2], s * M[1, 2], s * M[0, 2], s * M[0, 1]])
+
+
+def hist_vec(epsp, alpha):
+    return np.array([epsp[0, 0], epsp[1, 1], epsp[2, 2], epsp[1, 2], epsp[0, 2], epsp[0, 1], alpha])
+
+
+def _small_history(rng, mag=3e-4):
+    """random deviatoric eps^p_n of size ~mag and alpha_n in [0, 0.1]"""
+    D = rng.standard_normal((3, 3))
+    D = 0.5 * (D + D.T)
+    D -= np.trace(D) / 3 * np.eye(3)
+    D *= mag / np.linalg.norm(D)
+    return hist_vec(D, rng.uniform(0.0, 0.1))
+
+
+# ---------------------------------------------------------------- eigen / log
+
+def test_eig_reconstructs_and_is_orthonormal():
+    rng = np.random.default_rng(10)
+    for A in [np.zeros((3, 3)), np.eye(3), np.diag([1.0, 1.0, 2.0]), np.diag([3.0, 1e-9, 1e-9])] + \
+             [(lambda B: B + B.T)(rng.standard_normal((3, 3))) for _ in range(20)]:
+        w, Q = oracle.eig_sym3(A)
+        assert np.abs(Q @ np.diag(w) @ Q.T - A).max() <= 1e-14 * max(1.0, np.abs(A).max())
+        assert np.abs(Q.T @ Q - np.eye(3)).max() <= 1e-14
+        assert np.allclose(np.sort(w), np.linalg.eigvalsh(A), atol=1e-14 * max(1.0, np.abs(A).max()))
+
+
+@pytest.mark.parametrize("scale", [0.0, 1e-9, 1e-4, 0.05, 0.3])
+def test_log_strain_matches_matrix_log(scale):
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        F = np.eye(3) + scale * rng.standard_normal((3, 3))
+        eps = oracle.log_strain(F)
+        ref = 0.5 * np.real(sl.logm(F.T @ F))
+        assert np.abs(eps - ref).max() <= 1e-14 + 1e-12 * np.abs(ref).max()
+
+
+def test_log_strain_of_rotation_is_zero_and_of_stretch_is_log():
+    rng = np.random.default_rng(12)
+    Q = sl.expm((lambda W: W - W.T)(rng.standard_normal((3, 3))))
+    assert np.abs(oracle.log_strain(Q)).max() < 1e-14
+    R = sl.expm((lambda W: W - W.T)(rng.standard_normal((3, 3))))
+    lam = np.array([1.3, 0.8, 1.05])
+    # F = R U with U = Q diag(lam) Q^T: eps = Q diag(ln lam) Q^T
+    F = R @ Q @ np.diag(lam) @ Q.T
+    assert np.allclose(oracle.log_strain(F), Q @ np.diag(np.log(lam)) @ Q.T, atol=1e-14)
+
+
+# ---------------------------------------------------------------- von Mises reduction
+
+def j2_radial_return(eps, epsp_n, alpha_n, K, eps0, n):
+    """Textbook small-strain J2 radial return (applied to log strains)."""
+    ee = eps - epsp_n
+    tr = np.trace(ee)
+    Ttr = LAME * tr * np.eye(3) + 2 * MU * ee
+    s = Ttr - np.trace(Ttr) / 3 * np.eye(3)
+    q = np.sqrt(1.5 * np.sum(s * s))
+    sy = lambda a: K * (eps0 + a) ** n
+    dsy = lambda a: n * K * (eps0 + a) ** (n - 1)
+    if q - sy(alpha_n) <= 0:
+        Cel = LAME * np.outer([1, 1, 1, 0, 0, 0], [1, 1, 1, 0, 0, 0]) + 2 * MU * np.eye(6)
+        return Ttr, epsp_n, alpha_n, Cel, False
+    dg = brentq(lambda x: q - 3 * MU * x - sy(alpha_n + x), 0.0, q / (3 * MU), xtol=1e-300, rtol=1e-15)
+    nflow = 1.5 * s / q
+    T = Ttr - 2 * MU * dg * nflow
+    epsp = epsp_n + dg * nflow
+    # Simo-Hughes algorithmic tangent: kappa 1x1 + 2 mu theta Idev - 2 mu thetabar nhat x nhat
+    theta = 1 - 3 * MU * dg / q
+    thetab = 1 / (1 + dsy(alpha_n + dg) / (3 * MU)) - (1 - theta)
+    nhat = mandel(s / np.sqrt(np.sum(s * s)))
+    one = np.array([1, 1, 1, 0, 0, 0.0])
+    Idev = np.eye(6) - np.outer(one, one) / 3
+    C = KAPPA * np.outer(one, one) + 2 * MU * theta * Idev - 2 * MU * thetab * np.outer(nhat, nhat)
+    return T, epsp, alpha_n + dg, C, True
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_hill_reduces_to_von_mises(seed):
+    rng = np.random.default_rng(100 + seed)
+    prm = vm_params(K=rng.uniform(450, 550), eps0=rng.uniform(0.005, 0.015), n=rng.uniform(0.1, 0.3))
+    F = sl.expm(0.01 * rng.standard_normal((3, 3)) + 0.02 * np.diag(rng.uniform(-1, 1, 3)))
+    h = _small_history(rng)
+    epsp = np.array([[h[0], h[5], h[4]], [h[5], h[1], h[3]], [h[4], h[3], h[2]]])
+    r = oracle.material_point(F, h, prm)
+    eps = 0.5 * np.real(sl.logm(F.T @ F))
+    T, epsp1, a1, C, plastic = j2_radial_return(eps, epsp, h[6], prm[8], prm[9], prm[10])
+    assert r["plastic"] == plastic
+    assert rel(r["T"], T) <= 1e-12
+    assert rel(r["hist"][:6], hist_vec(epsp1, a1)[:6]) <= 1e-11
+    assert abs(r["hist"][6] - a1) <= 1e-13
+    assert rel(r["Cep"], C) <= 1e-12
+    assert rel(r["Cep_implicit"], C) <= 1e-12
+
+
+# ---------------------------------------------------------------- closed forms, generic Hill
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_uniaxial_linear_hardening_closed_form(axis):
+    """Uniaxial stress along `axis`, Swift with n = 1 (linear hardening
+    sigma_y = K eps0 + K alpha), virgin state: closed-form strains."""
+    Fh, Gh, Hh = 0.31, 0.62, 0.47
+    K, eps0 = 800.0, 0.3
+    prm = synth.params(F=Fh, G=Gh, H=Hh, K=K, eps0=eps0, n=1.0)
+    # phi = s*sigma with s^2 = (G+H, F+H, F+G)[axis]; lateral flow coefficients
+    s2 = [Gh + Hh, Fh + Hh, Fh + Gh][axis]
+    s = np.sqrt(s2)
+    lat = {0: {1: Hh, 2: Gh}, 1: {0: Hh, 2: Fh}, 2: {0: Gh, 1: Fh}}[axis]
+    sig0, Hp = K * eps0, K
+    e11 = 0.02
+    abar = (s * E * e11 - sig0) / (s2 * E + Hp)
+    sig = (sig0 + Hp * abar) / s
+    eps = np.zeros(3)
+    eps[axis] = e11
+    for j, c in lat.items():
+        eps[j] = -NU * sig / E - abar * c / s
+    F = np.diag(np.exp(eps))
+    r = oracle.material_point(F, np.zeros(7), prm)
+    T = np.zeros((3, 3))
+    T[axis, axis] = sig
+    assert r["plastic"] and r["converged"]
+    assert np.abs(r["T"] - T).max() <= 1e-12 * sig
+    assert abs(r["hist"][6] - abar) <= 1e-13
+    # plastic strain: dgamma * N with N = H T / phi
+    epp = np.zeros(3)
+    epp[axis] = abar * s
+    for j, c in lat.items():
+        epp[j] = -abar * c / s
+    assert np.abs(r["hist"][:3] - epp).max() <= 1e-13
+
+
+@pytest.mark.parametrize("pair", [(1, 2), (0, 2), (0, 1)])
+def test_simple_shear_linear_hardening_closed_form(pair):
+    """Pure shear stress T_ij = tau: phi = sqrt(2 c) tau with c = L, M or N."""
+    Lh, Mh, Nh = 1.2, 1.7, 1.45
+    K, eps0 = 900.0, 0.25
+    prm = synth.params(F=0.4, G=0.6, H=0.5, L=Lh, M=Mh, N=Nh, K=K, eps0=eps0, n=1.0)
+    c = {(1, 2): Lh, (0, 2): Mh, (0, 1): Nh}[pair]
+    sig0, Hp = K * eps0, K
+    g = 0.01  # tensor shear strain eps_ij
+    r2c = np.sqrt(2 * c)
+    dg = (g - sig0 / (2 * MU * r2c)) / (Hp / (2 * MU * r2c) + np.sqrt(c / 2))
+    tau = (sig0 + Hp * dg) / r2c
+    epsT = np.zeros((3, 3))
+    epsT[pair] = epsT[pair[::-1]] = g
+    F = sl.expm(epsT)
+    r = oracle.material_point(F, np.zeros(7), prm)
+    T = np.zeros((3, 3))
+    T[pair] = T[pair[::-1]] = tau
+    assert r["plastic"]
+    assert np.abs(r["T"] - T).max() <= 1e-12 * tau
+    assert abs(r["dgamma"] - dg) <= 1e-14
+
+
+# ---------------------------------------------------------------- tangents vs FD
+
+def _random_state(rng, plastic=True, scale=0.02):
+    prm = synth.params(F=rng.uniform(0.2, 0.8), G=rng.uniform(0.2, 0.8), H=rng.uniform(0.2, 0.8),
+                       L=rng.uniform(1.2, 1.8), M=rng.uniform(1.2, 1.8), N=rng.uniform(1.2, 1.8))
+    h = _small_history(rng)
+    for _ in range(100):
+        F = np.eye(3) + scale * rng.uniform(0.01, 1.0) * rng.standard_normal((3, 3))
+        r = oracle.material_point(F, h, prm)
+        if r["plastic"] == plastic:
+            return F, h, prm
+    raise RuntimeError("no state of the requested kind")
+
+
+@pytest.mark.parametrize("plastic", [False, True])
+@pytest.mark.parametrize("seed", range(4))
+def test_cep_closed_form_implicit_and_fd_agree(plastic, seed):
+    rng = np.random.default_rng(200 + seed)
+    F, h, prm = _random_state(rng, plastic)
+    r = oracle.material_point(F, h, prm)
+    eps = 0.5 * np.real(sl.logm(F.T @ F))
+    assert rel(r["Cep"], r["Cep_implicit"]) <= 1e-12
+    # T as a function of eps: F = expm(eps) gives exactly 1/2 ln C = eps
+    Cfd = np.zeros((6, 6))
+    hh = 1e-7
+    for j in range(6):
+        e = np.zeros(6)
+        e[j] = 1.0
+        D = np.array([[e[0], e[5], e[4]], [e[5], e[1], e[3]], [e[4], e[3], e[2]]])
+        D[np.triu_indices(3, 1)] /= np.sqrt(2.0)
+        D[np.tril_indices(3, -1)] /= np.sqrt(2.0)
+        Tp = oracle.material_point(sl.expm(eps + hh * D), h, prm)["T"]
+        Tm = oracle.material_point(sl.expm(eps - hh * D), h, prm)["T"]
+        Cfd[:, j] = mandel((Tp - Tm) / (2 * hh))
+    assert rel(r["Cep"], Cfd) <= 1e-6
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_second_pk_is_projection_of_log_stress(seed):
+    """S = P_L : T = 2 d(T : 1/2 ln C)/dC with T held fixed (FD of scipy logm)."""
+    rng = np.random.default_rng(300 + seed)
+    F, h, prm = _random_state(rng, plastic=bool(seed % 2), scale=0.1 if seed % 2 else 0.01)
+    r = oracle.material_point(F, h, prm)
+    C = F.T @ F
+    T = r["T"]
+    g = lambda Cm: np.sum(T * 0.5 * np.real(sl.logm(Cm)))
+    Sfd = np.zeros((3, 3))
+    hh = 1e-6
+    for i in range(3):
+        for j in range(i, 3):
+            D = np.zeros((3, 3))
+            D[i, j] = D[j, i] = 1.0 if i == j else 0.5
+            Sfd[i, j] = Sfd[j, i] = 2 * (g(C + hh * D) - g(C - hh * D)) / (2 * hh)
+    assert rel(r["S"], Sfd) <= 1e-7
+
+
+@pytest.mark.parametrize("case", ["elastic", "plastic", "identity", "near_repeated", "large"])
+def test_nominal_tangent_matches_fd_of_first_pk(case):
+    rng = np.random.default_rng({"elastic": 1, "plastic": 2, "identity": 3, "near_repeated": 4,
+                                 "large": 5}[case])
+    if case == "identity":
+        F = np.eye(3)
+        h = _small_history(rng)
+        prm = synth.params(F=0.3, G=0.7, H=0.45)
+    elif case == "near_repeated":
+        Q = sl.expm((lambda W: W - W.T)(rng.standard_normal((3, 3))))
+        F = Q @ np.diag([1.01, 1.01 + 1e-9, 0.99]) @ Q.T
+        h = _small_history(rng)
+        prm = synth.params(F=0.3, G=0.7, H=0.45)
+    elif case == "large":
+        F, h, prm = _random_state(rng, plastic=True, scale=0.25)
+    else:
+        F, h, prm = _random_state(rng, plastic=(case == "plastic"))
+    r = oracle.material_point(F, h, prm)
+    A = r["A"]
+    hh = 1e-7
+    Afd = np.zeros((3, 3, 3, 3))
+    for b in range(3):
+        for B in range(3):
+            Fp, Fm = F.copy(), F.copy()
+            Fp[b, B] += hh
+            Fm[b, B] -= hh
+            pp, pm = oracle.material_point(Fp, h, prm), oracle.material_point(Fm, h, prm)
+            if pp["plastic"] != r["plastic"] or pm["plastic"] != r["plastic"]:
+                pytest.skip("FD stencil crosses the yield surface")
+            Afd[:, :, b, B] = (pp["P"] - pm["P"]) / (2 * hh)
+    assert rel(A, Afd) <= 2e-6
+    # major symmetry A_aAbB = A_bBaA
+    assert rel(A, np.transpose(A, (2, 3, 0, 1))) <= 1e-12
+
+
+def test_objectivity_of_material_point():
+    rng = np.random.default_rng(7)
+    F, h, prm = _random_state(rng, plastic=True)
+    Q = sl.expm((lambda W: W - W.T)(rng.standard_normal((3, 3))))
+    r0 = oracle.material_point(F, h, prm)
+    r1 = oracle.material_point(Q @ F, h, prm)
+    assert rel(r1["S"], r0["S"]) <= 1e-12
+    assert rel(r1["P"], Q @ r0["P"]) <= 1e-12
+    assert rel(r1["hist"], r0["hist"]) <= 1e-12
+
+
+def test_elastic_state_keeps_history_and_undeformed_state_has_initial_stress():
+    prm = synth.params(F=0.3, G=0.7, H=0.45)
+    h = np.array([0.001, -0.0004, -0.0006, 0.0002, 0.0, -0.0001, 0.03])
+    r = oracle.material_point(np.eye(3), h, prm)
+    assert not r["plastic"]
+    assert np.array_equal(r["hist"], h)
+    ep = np.array([[h[0], h[5], h[4]], [h[5], h[1], h[3]], [h[4], h[3], h[2]]])
+    T = LAME * np.trace(-ep) * np.eye(3) + 2 * MU * (-ep)
+    assert rel(r["T"], T) <= 1e-14
+    # at C = I, P_L is the identity: S = T
+    assert rel(r["S"], T) <= 1e-14

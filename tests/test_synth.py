@@ -1,0 +1,47 @@
+"""Seeded input generators: shapes, determinism and the stated workload
+properties (CPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_17390_amd import synth
+
+
+def test_generators_are_deterministic():
+    a, b = synth.sheet_slab(), synth.sheet_slab()
+    for f in ("X", "conn", "d", "hist_n", "prm", "bc_mask", "lam"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))
+
+
+def test_workload_sizes():
+    p0 = synth.tiny_cube()
+    assert (p0.n_elems, p0.n_nodes) == (64, 125)
+    p1 = synth.sheet_slab()
+    assert (p1.n_elems, p1.n_nodes) == (6400, 8405)
+    assert 3 * p1.n_nodes - int(p1.bc_mask.sum()) == 20172
+    p3 = synth.void_specimen()
+    assert p3.n_elems == 60000 and p3.meta["n_grid_elems"] == 80000
+    conn_nodes = np.unique(p3.conn)
+    assert conn_nodes.size == p3.n_nodes  # no orphan nodes after renumbering
+    assert abs(np.linalg.norm(p3.lam) - 1.0) < 1e-12
+
+
+def test_sheet_slab_strain_increment_is_five_percent():
+    p = synth.sheet_slab()
+    assert p.prm.shape == (11,) and 0.2 <= p.prm[2] <= 0.8
+
+
+@pytest.mark.slow
+def test_large_cube_yields_at_thirty_percent_of_gauss_points():
+    p = synth.large_cube()
+    assert p.n_elems == 1_000_000 and p.n_nodes == 1_030_301
+    flag = oracle.trial_yield(p.X, p.conn, p.prm, p.d, p.hist_n)
+    assert abs(flag.mean() - 0.30) <= 0.005
+
+
+def test_batch_sizes_are_log_uniform_and_uneven():
+    rng = np.random.default_rng(4000)
+    sizes = np.exp(rng.uniform(np.log(2000), np.log(60000), size=64))
+    assert sizes.min() >= 2000 and sizes.max() <= 60000
+    spec = synth.uneven_slab(4001, 3000)
+    assert abs(spec.n_elems - 3000) / 3000 < 0.5
