@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark of the hex8 finite-strain Hill-48 residual + tangent + CSR pass.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (synthetic, seeded): the 100x100x100 hex8 cube (1,000,000 elements,
+1,030,301 nodes, 3,090,903 dofs, 8,000,000 Gauss points, nnz 245,438,109),
+per-element Hill-48 F,G,H from smooth random fields, 30% of the Gauss points
+yielding at the trial state, x = 0 face constrained.  A step is one
+fem_residual_tangent call in FP32-mixed precision (fill of R and K, element
+kernel with return map / residual / tangent / CSR scatter, Dirichlet rows,
+FP64 residual norm), inputs resident in HBM.  Prints ONE JSON line.
+
+Also reported (same JSON line): the plain FP64 pass on the same cube, the
+parameter VJP on the 200x200x2 voided specimen, the batched 64-specimen
+forward + VJP graph, the roofline of the dominant kernel (live HIP-event
+timing of the element kernel), and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(p, nnz, prec_mixed, per_elem_cols):
+    """Bytes an ideal pass moves through HBM, each array once."""
+    ne, nn = p.n_elems, p.n_nodes
+    ngp = 8 * ne
+    kb = 4 if prec_mixed else 8
+    b = 0
+    b += nn * 24          # X
+    b += nn * 24          # d
+    b += ne * 32          # conn
+    b += ngp * 56         # hist_n
+    b += ne * 8 * per_elem_cols  # per-element parameters
+    b += ne * 64          # elem_rank
+    b += (3 * nn + 1) * 4  # row_ptr
+    b += 3 * nn * 8       # R
+    b += nnz * kb         # K values
+    b += ngp * 56         # hist_np1
+    return b
+
+
+def time_passes(fn, steps, warmup, torch, kernel, fem):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    fem.timing_read(kernel)  # drop launches of the warm-up
+    fem.timing_enable(True)
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fem.timing_enable(False)
+    kms, nl = fem.timing_read(kernel)
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3, (kms / nl if nl else None)
+
+
+def cpu_baseline(p, n_sample):
+    """CPU oracle (OpenMP, all host threads) on the first n_sample elements."""
+    import numpy as np
+
+    import oracle
+    conn = p.conn[:n_sample]
+    used = np.unique(conn)
+    remap = -np.ones(p.n_nodes, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    sc = remap[conn].astype(np.int32)
+    X, d = p.X[used], p.d[used]
+    prm = p.prm[:n_sample]
+    hist = np.ascontiguousarray(p.hist_n[:, :8 * n_sample])
+    rp, ci, _ = oracle.csr_pattern(sc, used.size, with_rank=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    oracle.residual_tangent(X, sc, rp, ci, prm, d, hist, n_threads=cores)
+    dt = time.perf_counter() - t0
+    return dict(value=8 * n_sample / dt, unit="GP/s", cores=cores, kind="oracle",
+                sample=f"first {n_sample} elements ({8 * n_sample} Gauss points) of the 100^3 cube, "
+                       f"FP64 residual+tangent+CSR, {dt:.2f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline pass only")
+    ap.add_argument("--cpu-sample", type=int, default=200000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the path is a design "
+              "note (z-slab row ownership, one-plane halo), not an implementation", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_17390_amd import fem, synth
+
+    torch.cuda.set_device(0)
+    log("generating the 100^3 cube")
+    p = synth.large_cube()
+    mesh = fem.Mesh(p.X, p.conn)
+    params = fem.Params(p.prm, p.n_elems)
+    d = torch.as_tensor(p.d).cuda()
+    h = torch.as_tensor(p.hist_n).cuda()
+    bc = torch.as_tensor(p.bc_mask).cuda()
+    csr = fem.csr_pattern(mesh)
+    per_elem_cols = bin(params.per_elem_mask).count("1")
+    n_gp = 8 * p.n_elems
+    log(f"nnz {csr.nnz}, per-element parameter columns {per_elem_cols}")
+
+    # ---- headline: FP32-mixed residual + tangent + CSR pass
+    out_m = fem.Forward(mesh, csr, fem.FP32_MIXED)
+    ms_m, wall_m, kms_m = time_passes(
+        lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP32_MIXED, out=out_m),
+        args.steps, args.warmup, torch, fem.KERNEL_FORWARD, fem)
+    plastic = float((out_m.hist[6] != h[6]).double().mean().cpu())
+    diag_m = out_m.diag.cpu().tolist()
+    log(f"mixed: {ms_m:.3f} ms/pass, kernel {kms_m:.3f} ms, plastic {plastic:.4f}, diag {diag_m}")
+    result = {}
+    extras = {}
+    if not args.no_extras:
+        out_d = fem.Forward(mesh, csr, fem.FP64)
+        ms_d, _, kms_d = time_passes(
+            lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP64, out=out_d),
+            max(args.steps // 2, 3), 2, torch, fem.KERNEL_FORWARD, fem)
+        # mixed vs FP64 on this very workload
+        torch.cuda.synchronize()
+        kd = out_d.K
+        km = out_m.K.double()
+        err_k = float(((km - kd).abs().max() / kd.abs().max()).cpu())
+        err_r = float(((out_m.R - out_d.R).abs().max() / out_d.R.abs().max()).cpu())
+        del km
+        log(f"fp64: {ms_d:.3f} ms/pass, kernel {kms_d:.3f} ms; mixed vs fp64 K {err_k:.2e} R {err_r:.2e}")
+        extras["fp64"] = dict(gp_updates_per_s=n_gp / (ms_d * 1e-3), ms_per_pass=ms_d, kernel_ms=kms_d,
+                              hbm_algorithmic_GBps=algorithmic_bytes(p, csr.nnz, False, per_elem_cols) / (kms_d * 1e6))
+        extras["mixed_vs_fp64_rel_err"] = dict(K=err_k, R=err_r)
+        del out_d, kd
+        torch.cuda.empty_cache()
+
+        # ---- VJP on the voided specimen
+        pv = synth.void_specimen()
+        mv = fem.Mesh(pv.X, pv.conn)
+        pv_params = fem.Params(pv.prm, pv.n_elems)
+        dv = torch.as_tensor(pv.d).cuda()
+        hv = torch.as_tensor(pv.hist_n).cuda()
+        lv = torch.as_tensor(pv.lam).cuda()
+        vj = {}
+        for name, prec in (("fp64", fem.FP64), ("mixed", fem.FP32_MIXED)):
+            vo = fem.Vjp(mv)
+            ms_v, _, kms_v = time_passes(
+                lambda: fem.residual_vjp(mv, pv_params, dv, hv, lv, prec=prec, out=vo),
+                args.steps, args.warmup, torch, fem.KERNEL_VJP, fem)
+            vj[name] = dict(vjp_per_s=1e3 / ms_v, gp_vjp_per_s=8 * pv.n_elems / (ms_v * 1e-3), ms_per_vjp=ms_v,
+                            kernel_ms=kms_v)
+            log(f"vjp {name}: {ms_v:.3f} ms")
+        extras["vjp_void_specimen"] = dict(n_elems=pv.n_elems, **vj)
+
+        # ---- batched: 64 uneven specimens, forward (mixed) + VJP (mixed) in one graph
+        specs = synth.batch64()
+        mb = synth.concat(specs)
+        bmesh = fem.Mesh(mb.X, mb.conn)
+        bcsr = fem.csr_pattern(bmesh)
+        bparams = fem.Params(mb.meta["spec_prm"], mb.n_elems, per_spec=True)
+        batch = fem.Batch(mb.meta["elem_off"])
+        bd = torch.as_tensor(mb.d).cuda()
+        bh = torch.as_tensor(mb.hist_n).cuda()
+        bl = torch.as_tensor(mb.lam).cuda()
+        bbc = torch.as_tensor(mb.bc_mask).cuda()
+        st = torch.cuda.Stream()
+        bo = fem.Forward(bmesh, bcsr, fem.FP32_MIXED)
+        bvo = fem.Vjp(bmesh, batch.n_spec)
+        g = fem.Graph()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            with g.capture(st):
+                fem.residual_tangent(bmesh, bcsr, bparams, bd, bh, bc_mask=bbc, prec=fem.FP32_MIXED, out=bo,
+                                     batch=batch, stream=st)
+                fem.residual_vjp(bmesh, bparams, bd, bh, bl, prec=fem.FP32_MIXED, out=bvo, batch=batch, stream=st)
+            for _ in range(3):
+                g.replay(st)
+            st.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(args.steps):
+                g.replay(st)
+            e1.record(st)
+            st.synchronize()
+        ms_b = e0.elapsed_time(e1) / args.steps
+        # the same work as 64 separate plain FP64 calls
+        sep = []
+        for s in specs:
+            ms_ = fem.Mesh(s.X, s.conn)
+            sep.append((ms_, fem.csr_pattern(ms_), fem.Params(s.prm, s.n_elems), torch.as_tensor(s.d).cuda(),
+                        torch.as_tensor(s.hist_n).cuda(), torch.as_tensor(s.lam).cuda(),
+                        torch.as_tensor(s.bc_mask).cuda()))
+        sep_out = [(fem.Forward(a[0], a[1], fem.FP64), fem.Vjp(a[0])) for a in sep]
+
+        def run_sep():
+            for (ms_, cs, pr, dd, hh, ll, bb), (fo, vo) in zip(sep, sep_out):
+                fem.residual_tangent(ms_, cs, pr, dd, hh, bc_mask=bb, prec=fem.FP64, out=fo)
+                fem.residual_vjp(ms_, pr, dd, hh, ll, prec=fem.FP64, out=vo)
+        ms_sep, _, _ = time_passes(run_sep, max(args.steps // 4, 3), 2, torch, fem.KERNEL_FORWARD, fem)
+        extras["batched_64"] = dict(n_elems=mb.n_elems, ms_graph_fwd_vjp_mixed=ms_b,
+                                    specimen_fwd_vjp_per_s=64 / (ms_b * 1e-3),
+                                    gp_updates_per_s=8 * mb.n_elems / (ms_b * 1e-3),
+                                    ms_64_separate_fp64_calls=ms_sep)
+        log(f"batched graph {ms_b:.3f} ms vs separate fp64 {ms_sep:.3f} ms")
+        del sep, sep_out
+
+    value = n_gp / (ms_m * 1e-3)
+    abytes = algorithmic_bytes(p, csr.nnz, True, per_elem_cols)
+    achieved = abytes / (kms_m * 1e6)  # GB/s
+    roof = dict(bound="hbm", kernel="fwd_kernel<float> (FP32-mixed element kernel)", achieved=achieved,
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                algorithmic_bytes_per_launch=abytes, kernel_ms=kms_m)
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        result_cpu = cpu_baseline(p, args.cpu_sample)
+    else:
+        result_cpu = None
+    result.update({
+        "metric": "Gauss-point updates/s (residual + tangent + CSR assembly), FP32-mixed",
+        "value": value,
+        "unit": "GP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_m,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "large_cube 100x100x100 hex8, 1e6 elements, 3,090,903 dofs, 8e6 Gauss points, "
+                               "per-element Hill-48 fields, 30% plastic at trial, x=0 face constrained",
+                   "n_elems": p.n_elems, "nnz": csr.nnz, "plastic_fraction": plastic, "diag": diag_m},
+        "roofline": roof,
+        "cpu_baseline": result_cpu,
+        "extras": extras,
+    })
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * fem.h -- C ABI of libfem.so, the MI355X (gfx950) library for the hot path of
+ * a finite-strain anisotropic-plasticity finite-element step:
+ *
+ *   per hex8 element and each of its 2x2x2 Gauss points: logarithmic strain
+ *   from C = F^T F, Hill-48 return mapping with Swift isotropic hardening,
+ *   second and first Piola-Kirchhoff stress, element residual R^e and
+ *   consistent tangent K^e = dR^e/dd^e, assembled into a fixed CSR pattern;
+ *   and the vector-Jacobian product lambda^T dR/dtheta for material parameters.
+ *
+ * It follows the discrete equilibrium problem of JAX-FEM-ANISO (arXiv
+ * 2606.17390): R(d) = A_e R^e(d^e; h_n, theta) with
+ * R^e_I = int P(F, h_n) . grad N_I dV (Sec. 2.2.4, element residual), K = dR/dd
+ * (Sec. 2.2.4, global tangent), history h_n = (eps^p_n, alpha_n) from the last
+ * converged increment (Sec. 2.2.4), the constitutive update of Sec. 2.2.2-2.2.3
+ * and App. C (Alg. C1, C2), Dirichlet rows by row elimination (App. E,
+ * Alg. E1) and the VJP term (dR/dtheta)^T lambda of Alg. 1 / Eq. (main_grad).
+ *
+ * Memory: every pointer marked "device" is HIP device memory owned by the
+ * caller; the library never frees or retains it.  Host pointers are marked
+ * "host".  All work is enqueued on `stream` (a hipStream_t; NULL = the null
+ * stream) and is asynchronous unless stated otherwise; output arrays are
+ * overwritten, never accumulated into.  Scratch space comes from the caller
+ * through a workspace pointer whose size the *_workspace_bytes functions
+ * return.  Functions return FEM_OK or a negative fem_status; the message of
+ * the last error on the calling thread is returned by fem_last_error().
+ * Numerical trouble (non-converged local Newton, inverted elements,
+ * non-finite values) never aborts: it is counted in the optional diag[4]
+ * array.  Calls on different streams that write the same buffers race.
+ *
+ * Units: mm and MPa.  Layouts:
+ *   X, d, R, lam : node-major [n_nodes][3] doubles; dof index = 3*node + comp
+ *   conn         : element-major [n_elems][8] int32, VTK hex corner order:
+ *                  (-,-,-) (+,-,-) (+,+,-) (-,+,-) (-,-,+) (+,-,+) (+,+,+) (-,+,+)
+ *   Gauss points : g = i + 2j + 4k at (xi, eta, zeta) = ((2i-1), (2j-1), (2k-1))/sqrt3,
+ *                  weight 1; Gauss point q = 8*e + g
+ *   hist         : [7][8*n_elems] doubles: eps^p 11, 22, 33, 23, 13, 12 (tensor
+ *                  components of the logarithmic plastic strain), alpha
+ *   params       : FEM_P_* below; Hill-48 in the F,G,H,L,M,N form
+ *                  phi^2 = F(T22-T33)^2 + G(T33-T11)^2 + H(T11-T22)^2
+ *                          + 2L T23^2 + 2M T13^2 + 2N T12^2,
+ *                  Swift sigma_y = K (eps0 + alpha)^n, alpha_{n+1} = alpha_n + dgamma
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FEM_OK = 0,
+    FEM_EINVAL = -1,    /* invalid argument (NULL where required, bad size, bad enum) */
+    FEM_EHIP = -2,      /* a HIP runtime call failed */
+    FEM_ENOMEM = -3,    /* workspace smaller than required */
+    FEM_EOVERFLOW = -4, /* nnz does not fit in int32 */
+    FEM_EMESH = -5      /* node index out of range, orphan node, more than 64 neighbours */
+} fem_status;
+
+typedef enum {
+    FEM_FP64 = 0,      /* everything in FP64 */
+    FEM_FP32_MIXED = 1 /* kinematics, log strain, stress pull-back, B^T C B and
+                          assembly in FP32; trial stress, yield function, local
+                          return-mapping Newton and residual norm in FP64;
+                          K_vals is float */
+} fem_precision;
+
+enum {
+    FEM_P_E, FEM_P_NU, FEM_P_F, FEM_P_G, FEM_P_H, FEM_P_L, FEM_P_M, FEM_P_N,
+    FEM_P_K, FEM_P_EPS0, FEM_P_NEXP, FEM_NPARAM
+};
+/* differentiated parameters, in this order */
+enum { FEM_G_F, FEM_G_G, FEM_G_H, FEM_G_N, FEM_G_K, FEM_G_EPS0, FEM_G_NEXP, FEM_NGRAD };
+
+typedef struct {
+    int32_t n_nodes, n_elems;
+    const double *X;     /* device [n_nodes][3] reference coordinates */
+    const int32_t *conn; /* device [n_elems][8] */
+} fem_mesh;
+
+/* Parameter k is read from p[k] (device): one value, or n_elems values if
+ * bit k of per_elem_mask is set, or n_spec values indexed by specimen if bit k
+ * of per_spec_mask is set (batched calls).  per_elem wins if both are set. */
+typedef struct {
+    const double *p[FEM_NPARAM];
+    uint32_t per_elem_mask;
+    uint32_t per_spec_mask;
+} fem_params;
+
+/* CSR matrix of the tangent, 3x3 node blocks: row 3I+a holds columns 3J+b
+ * for every node J sharing an element with I (I included), ascending.
+ * elem_rank[64*e + 8*i + j] = position of node conn[e][j] in the sorted
+ * neighbour list of node conn[e][i], so that K(3I+a, 3J+b) sits at
+ * row_ptr[3I+a] + 3*rank + b. */
+typedef struct {
+    int32_t n_rows;     /* 3 * n_nodes */
+    int64_t nnz;        /* set by fem_csr_pattern */
+    int32_t *row_ptr;   /* device [n_rows + 1] */
+    int32_t *col_idx;   /* device [nnz] */
+    uint8_t *elem_rank; /* device [n_elems][64] */
+} fem_csr;
+
+/* Batched mode: n_spec specimens concatenated (node ids in conn already
+ * offset); elements of specimen s are [elem_off[s], elem_off[s+1]).  A NULL
+ * fem_batch* means a single specimen. */
+typedef struct {
+    int32_t n_spec;
+    const int64_t *elem_off; /* device [n_spec + 1], elem_off[0] = 0, elem_off[n_spec] = n_elems */
+} fem_batch;
+
+/* Launch configuration of the element kernels (set by the autotuner). */
+typedef struct {
+    int32_t block;         /* threads per workgroup: 64, 128 or 256 (8 per element) */
+    int32_t waves_per_cu;  /* persistent grid = waves_per_cu * CUs * 64 / block workgroups */
+    int32_t xcd_remap;     /* 1: consecutive tiles stay on one XCD's L2 */
+} fem_launch;
+
+enum { FEM_KERNEL_FORWARD = 0, FEM_KERNEL_VJP = 1 };
+
+/* Library version (major*10000 + minor*100 + patch). */
+int fem_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fem_last_error(void);
+
+/* Set (cfg != NULL) or reset (cfg == NULL) the launch configuration of a
+ * kernel for a precision; process-wide.  Returns FEM_EINVAL for bad values. */
+int fem_set_launch(int kernel, fem_precision prec, const fem_launch *cfg);
+int fem_get_launch(int kernel, fem_precision prec, fem_launch *cfg);
+
+/* Workspace bytes for each operation (host-only query, no GPU work). */
+size_t fem_csr_workspace_bytes(int32_t n_nodes, int32_t n_elems);
+size_t fem_forward_workspace_bytes(int32_t n_nodes, int32_t n_elems);
+size_t fem_vjp_workspace_bytes(int32_t n_elems, int32_t n_spec);
+
+/*
+ * fem_csr_pattern -- build the CSR pattern of K from the connectivity
+ * (App. E, Alg. E1; the pattern is built once per mesh and reused).
+ * Two calls:
+ *   csr->col_idx == NULL : fills csr->row_ptr (device, [3*n_nodes+1]) and
+ *                          csr->nnz; synchronises `stream` to read nnz back.
+ *   csr->col_idx != NULL : fills col_idx [nnz] and, if non-NULL, elem_rank.
+ * ws: device workspace of at least fem_csr_workspace_bytes(n_nodes, n_elems)
+ * bytes.  Errors: FEM_EINVAL (NULL pointers, negative sizes), FEM_ENOMEM,
+ * FEM_EMESH (node id out of range, orphan node, more than 64 neighbours),
+ * FEM_EOVERFLOW (nnz >= 2^31), FEM_EHIP.
+ */
+int fem_csr_pattern(const fem_mesh *mesh, fem_csr *csr, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * fem_residual_tangent -- one residual + tangent + assembly pass
+ * (Sec. 2.2.4 element residual and stiffness, App. C Alg. C1/C2 at every
+ * Gauss point, App. E row elimination).
+ *   d        device [n_nodes][3] current displacement
+ *   hist_n   device [7][8*n_elems] history of the last converged increment
+ *   bc_mask  device [3*n_nodes] uint8 (1 = constrained dof) or NULL: rows of
+ *            constrained dofs become identity rows of K and R is zeroed there
+ *   prec     FEM_FP64 or FEM_FP32_MIXED
+ *   R        device [3*n_nodes] residual, or NULL (then rnorm2 must be NULL)
+ *   K_vals   device [nnz] double (FEM_FP64) or float (FEM_FP32_MIXED), or NULL
+ *            for a residual-only pass; requires csr->row_ptr/col_idx/elem_rank
+ *   hist_np1 device [7][8*n_elems] updated history for this d (never committed
+ *            by the library), or NULL
+ *   rnorm2   device [1] FP64 sum of R_i^2 after row elimination, or NULL
+ *   diag     device [4] int32 counters (local Newton not converged, detJ0 <= 0,
+ *            det F <= 0, non-finite values), or NULL
+ *   ws       device workspace of fem_forward_workspace_bytes() bytes
+ * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP.
+ */
+int fem_residual_tangent(const fem_mesh *mesh, const fem_batch *batch, const fem_csr *csr,
+                         const fem_params *params, const double *d, const double *hist_n,
+                         const uint8_t *bc_mask, fem_precision prec, double *R, void *K_vals,
+                         double *hist_np1, double *rnorm2, int32_t *diag, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/*
+ * fem_residual_vjp -- g = lam^T dR/dtheta for theta = (F, G, H, N, K, eps0, n)
+ * (Alg. 1 "Evaluate VJP", Eq. (main_grad); the derivative of the converged
+ * local update follows App. D, applied in reverse mode; the local state is
+ * recomputed from d and hist_n, nothing is stored between calls).
+ *   lam       device [n_nodes][3] cotangent
+ *   g_uniform device [n_spec][7] (n_spec = 1 without batch): sum of g_elem over
+ *             the specimen's elements, i.e. the gradient for parameters that are
+ *             uniform over the specimen; or NULL
+ *   g_elem    device [7][n_elems] per-element gradient, or NULL
+ *   ws        device workspace of fem_vjp_workspace_bytes(n_elems, n_spec) bytes
+ * The reduction to g_uniform is deterministic.  Elastic Gauss points
+ * contribute exactly zero.  Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP.
+ */
+int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_params *params,
+                     const double *d, const double *hist_n, const double *lam, fem_precision prec,
+                     double *g_uniform, double *g_elem, int32_t *diag, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * Kernel timing for benchmarks: while enabled, every launch of the element
+ * kernel of `kernel` (FEM_KERNEL_FORWARD / FEM_KERNEL_VJP) is bracketed by a
+ * pair of HIP events recorded on the launch stream.  fem_timing_read waits
+ * for the recorded events, returns the summed elapsed milliseconds and the
+ * number of launches since the previous read, and releases the events.
+ * Do not enable while capturing a graph.
+ */
+int fem_timing_enable(int on);
+int fem_timing_read(int kernel, double *total_ms, int32_t *launches);
+
+/*
+ * HIP graph helpers for launch-bound callers (e.g. many small specimens):
+ * capture the library calls issued on `stream` between begin and end into an
+ * executable graph.  The library issues no memset nodes (buffers are cleared
+ * by kernels), so a graph may be replayed any number of times.
+ */
+int fem_graph_begin(void *stream);
+int fem_graph_end(void *stream, void **graph_exec);
+int fem_graph_launch(void *graph_exec, void *stream);
+int fem_graph_destroy(void *graph_exec);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEM_H */

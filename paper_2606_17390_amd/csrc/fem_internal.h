@@ -1,0 +1,73 @@
+// fem_internal.h -- host-side helpers shared by the library's translation
+// units: error reporting, launch configuration, device properties,
+// workspace carving and the small utility kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+
+#include "../../include/fem.h"
+
+namespace fem {
+
+// Thread-local last-error message; returns `code` for convenience.
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+
+#define FEM_HIP_CHECK(expr)                                                                        \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return ::fem::set_error(FEM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                    __FILE__, __LINE__);                                           \
+    } while (0)
+
+// Compute units of the current device (cached per device id).
+int device_cu_count();
+
+// Launch configuration in effect for a kernel / precision.
+fem_launch launch_config(int kernel, int prec);
+
+// Number of workgroups of a persistent launch over n_tiles tiles.
+int persistent_grid(const fem_launch& cfg, int64_t n_tiles);
+
+// Bump allocator over a caller-provided workspace (256-byte aligned pieces).
+struct WsCarver {
+    char* base;
+    size_t cap, used;
+    explicit WsCarver(void* p, size_t c) : base(static_cast<char*>(p)), cap(c), used(0) {}
+    template <typename T>
+    T* take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + count * sizeof(T);
+        return (used <= cap && base) ? reinterpret_cast<T*>(base + off) : nullptr;
+    }
+    bool ok() const { return used <= cap; }
+};
+
+// Size a carver would need for the same sequence of takes (base == nullptr).
+struct WsCounter {
+    size_t used = 0;
+    template <typename T>
+    void take(size_t count) {
+        used = ((used + 255) & ~size_t(255)) + count * sizeof(T);
+    }
+};
+
+// Zero `bytes` bytes at p on stream s with a kernel (no memset node, so a
+// captured graph may replay it).
+hipError_t zero_bytes(void* p, size_t bytes, hipStream_t s);
+
+// Kernel timing (fem_timing_enable): returns true if enabled; then
+// timing_begin / timing_end bracket one launch on stream s.
+bool timing_on();
+void* timing_begin(hipStream_t s);
+void timing_end(void* token, int kernel, hipStream_t s);
+
+// Fixed grid of the deterministic two-stage norm reduction.
+constexpr int kNormBlocks = 512;
+constexpr int kNormThreads = 256;
+
+}  // namespace fem

@@ -1,0 +1,636 @@
+// forward.hip -- residual + consistent tangent + CSR assembly pass.
+//
+// One lane per Gauss point, 8 lanes per element, BLOCK/8 elements per
+// workgroup; a persistent grid walks element tiles (XCD-aware order so that
+// neighbouring elements, which share CSR entries, stay on one L2).
+//
+// Per Gauss point (Sec. 2.2.2-2.2.4, App. C Alg. C1):
+//   gather node coordinates / displacements of the element through LDS,
+//   F = I + sum d_I (x) grad N_I, C - I, Jacobi eigen-decomposition,
+//   eps = sum 1/2 ln(c_a) N_a (x) N_a, elastic predictor and Hill-48 return
+//   map (always FP64), S = P_L : T, P = F S, and the Lagrangian tangent
+//   C = P_L : Cep : P_L + T : L_L assembled in the eigenframe of C.
+// The element residual and the 24x24 tangent
+//   R^e_Ia  = sum_g w detJ0 P_aA dN_I/dX_A,
+//   K^e_IaJb = sum_g w detJ0 dN_I/dX_A (delta_ab S_AB + F_aC C_CADB F_bD) dN_J/dX_B
+// are formed per Gauss point in the eigenframe (g^ = Q^T grad N, f^ = F Q),
+// summed over the 8 lanes of an element through LDS and scattered into the
+// fixed CSR pattern with hardware float atomics.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fem_device.h"
+#include "fem_internal.h"
+
+namespace fem {
+namespace {
+
+struct FwdArgs {
+    int32_t n_nodes, n_elems;
+    const double* X;
+    const int32_t* conn;
+    const double* prm[FEM_NPARAM];
+    uint32_t pe_mask, ps_mask;
+    int32_t n_spec;
+    const int64_t* elem_off;
+    const int32_t* row_ptr;
+    const uint8_t* elem_rank;
+    const double* d;
+    const double* hist_n;
+    double* R;
+    void* K;
+    double* hist_np1;
+    int32_t* diag;
+    int64_t n_gp;
+    int64_t n_tiles;
+    int32_t xcd_remap;
+};
+
+// specimen of element e (elem_off has n_spec + 1 prefix entries)
+__device__ inline int spec_of(const int64_t* __restrict__ off, int n_spec, int64_t e) {
+    int lo = 0, hi = n_spec - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename A>
+__device__ inline Mat load_material(const A& a, int64_t e) {
+    int sp = 0;
+    if (a.ps_mask) sp = spec_of(a.elem_off, a.n_spec, e);
+    double v[FEM_NPARAM];
+#pragma unroll
+    for (int k = 0; k < FEM_NPARAM; ++k) {
+        const int64_t idx = ((a.pe_mask >> k) & 1u) ? e : (((a.ps_mask >> k) & 1u) ? (int64_t)sp : 0);
+        v[k] = a.prm[k][idx];
+    }
+    Mat m;
+    m.E = v[0];
+    m.nu = v[1];
+    m.F = v[2];
+    m.G = v[3];
+    m.H = v[4];
+    m.L = v[5];
+    m.M = v[6];
+    m.N = v[7];
+    m.K = v[8];
+    m.eps0 = v[9];
+    m.nexp = v[10];
+    return m;
+}
+
+// Tile range of this workgroup in a persistent launch.  Workgroups are
+// dispatched round-robin over the 8 XCDs; with xcd_remap the tiles are cut in
+// 8 contiguous chunks and chunk x is walked by the workgroups of XCD x.
+__device__ inline void tile_range(int64_t n_tiles, int remap, int64_t& first, int64_t& end, int64_t& step) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    if (remap && (nb % 8) == 0 && nb >= 8) {
+        const int x = b & 7, k = b >> 3, per = nb >> 3;
+        const int64_t chunk = (n_tiles + 7) / 8;
+        first = (int64_t)x * chunk + k;
+        end = min((int64_t)(x + 1) * chunk, n_tiles);
+        step = per;
+    } else {
+        first = b;
+        end = n_tiles;
+        step = nb;
+    }
+}
+
+// Everything one lane needs after the constitutive update, in working type R.
+template <typename R>
+struct GP {
+    R g[8][3];   // grad N_I (physical)
+    R detJ;
+    R H[3][3];   // displacement gradient, F = I + H
+    R Q[3][3];   // eigenvectors of C (columns)
+    R mu[3];     // eigenvalues of C - I
+    R eh[3];     // 1/2 ln c_a
+};
+
+template <typename R>
+__device__ inline void kin_and_log(const R xs[8][3], const R ds[8][3], int gp, GP<R>& s, double eps[6]) {
+    kinematics<R>(xs, ds, gp, s.g, s.detJ, s.H);
+    R M[3][3];
+    cauchy_green_minus_identity<R>(s.H, M);
+    eig_sym3<R>(M, s.mu, s.Q);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s.eh[a] = R(0.5) * m_log1p(s.mu[a]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int i = mi(k), j = mj(k);
+        R v = s.Q[i][0] * s.eh[0] * s.Q[j][0] + s.Q[i][1] * s.eh[1] * s.Q[j][1] + s.Q[i][2] * s.eh[2] * s.Q[j][2];
+        eps[k] = (double)(mw<R>(k) * v);
+    }
+}
+
+template <typename R>
+__device__ inline void atomic_add(R* p, R v) {
+    unsafeAtomicAdd(p, v);
+}
+
+template <typename R, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
+    constexpr int EPB = BLOCK / 8;
+    __shared__ double sXD[EPB][8][6];
+    __shared__ int32_t sRow[EPB][8];
+    __shared__ int32_t sLen[EPB][8];
+    __shared__ uint8_t sRank[EPB][64];
+    __shared__ R red[32][BLOCK + 1];
+
+    const int tid = threadIdx.x;
+    const int slot = tid >> 3, gp = tid & 7;
+    const bool want_K = a.K != nullptr;
+    int32_t cnt_fail = 0, cnt_j0 = 0, cnt_jf = 0, cnt_nan = 0;
+
+    int64_t t0, t1, ts;
+    tile_range(a.n_tiles, a.xcd_remap, t0, t1, ts);
+    for (int64_t tile = t0; tile < t1; tile += ts) {
+        const int64_t e_raw = tile * EPB + slot;
+        const bool valid = e_raw < a.n_elems;
+        const int64_t e = valid ? e_raw : (int64_t)a.n_elems - 1;
+        const int64_t q = e * 8 + gp;
+
+        // ---- gather (own node through LDS); an out-of-range node id is
+        // replaced by node 0 and counted, so no access leaves its buffer
+        int32_t node = a.conn[q];
+        if ((uint32_t)node >= (uint32_t)a.n_nodes) {
+            if (valid) ++cnt_nan;
+            node = 0;
+        }
+        sXD[slot][gp][0] = a.X[3 * (int64_t)node + 0];
+        sXD[slot][gp][1] = a.X[3 * (int64_t)node + 1];
+        sXD[slot][gp][2] = a.X[3 * (int64_t)node + 2];
+        sXD[slot][gp][3] = a.d[3 * (int64_t)node + 0];
+        sXD[slot][gp][4] = a.d[3 * (int64_t)node + 1];
+        sXD[slot][gp][5] = a.d[3 * (int64_t)node + 2];
+        if (want_K) {
+            const int32_t r0 = a.row_ptr[3 * (int64_t)node];
+            sRow[slot][gp] = r0;
+            sLen[slot][gp] = a.row_ptr[3 * (int64_t)node + 1] - r0;
+            const uint64_t rk = reinterpret_cast<const uint64_t*>(a.elem_rank)[q];
+            *reinterpret_cast<uint64_t*>(&sRank[slot][gp * 8]) = rk;
+        }
+        double hn[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) hn[k] = a.hist_n[k * a.n_gp + q];
+        const Mat mat = load_material(a, e);
+        __syncthreads();
+
+        // ---- kinematics, log strain (R), local update (double)
+        GP<R> s;
+        double eps[6];
+        {
+            R xs[8][3], ds[8][3];
+#pragma unroll
+            for (int I = 0; I < 8; ++I)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xs[I][c] = (R)(sXD[slot][I][c] - sXD[slot][0][c]);
+                    ds[I][c] = (R)(sXD[slot][I][3 + c] - sXD[slot][0][3 + c]);
+                }
+            kin_and_log<R>(xs, ds, gp, s, eps);
+        }
+        Modes md;
+        hill_modes(mat, md);
+        Local loc;
+        local_update(eps, hn, mat, md, loc);
+        if constexpr (std::is_same<R, float>::value) {
+            // guard band: a trial state this close to the yield surface is
+            // re-evaluated with FP64 kinematics so that the elastic/plastic
+            // decision and the stress are those of the FP64 path
+            if (fabs(loc.ftr) < 2e-4 * loc.sy_n) {
+                GP<double> sd;
+                double xs[8][3], ds[8][3];
+#pragma unroll
+                for (int I = 0; I < 8; ++I)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        xs[I][c] = sXD[slot][I][c] - sXD[slot][0][c];
+                        ds[I][c] = sXD[slot][I][3 + c] - sXD[slot][0][3 + c];
+                    }
+                kin_and_log<double>(xs, ds, gp, sd, eps);
+                local_update(eps, hn, mat, md, loc);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    s.mu[i] = (R)sd.mu[i];
+                    s.eh[i] = (R)sd.eh[i];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        s.Q[i][j] = (R)sd.Q[i][j];
+                        s.H[i][j] = (R)sd.H[i][j];
+                    }
+                }
+            }
+        }
+        if (valid) {
+            cnt_fail += loc.converged ? 0 : 1;
+            cnt_j0 += (s.detJ <= R(0)) ? 1 : 0;
+            R F[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) F[i][j] = s.H[i][j] + ((i == j) ? R(1) : R(0));
+            const R detF = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
+                           F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+                           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+            cnt_jf += (detF <= R(0)) ? 1 : 0;
+            if (a.hist_np1) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) a.hist_np1[k * a.n_gp + q] = loc.hist[k];
+            }
+        }
+
+        // ---- pull-back in the eigenframe of C
+        R Th[3][3];
+        {
+            R Tm[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Tm[k] = (R)loc.T[k];
+            mandel_to_frame<R>(s.Q, Tm, Th);
+        }
+        R f1[3][3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int r = p; r < 3; ++r) {
+                const R v = (p == r) ? R(0.5) / (R(1) + s.mu[p]) : dd1<R>(s.mu[p], s.mu[r], s.eh[p], s.eh[r]);
+                f1[p][r] = v;
+                f1[r][p] = v;
+            }
+        R Sh[3][3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Sh[p][r] = R(2) * f1[p][r] * Th[p][r];
+        R fh[3][3];  // f^_ap = F_aC Q_Cp
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) fh[i][p] = s.Q[i][p] + (s.H[i][0] * s.Q[0][p] + s.H[i][1] * s.Q[1][p] + s.H[i][2] * s.Q[2][p]);
+        R gh[8][3];  // g^_Iq = grad N_IA Q_Aq
+#pragma unroll
+        for (int I = 0; I < 8; ++I)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) gh[I][p] = s.g[I][0] * s.Q[0][p] + s.g[I][1] * s.Q[1][p] + s.g[I][2] * s.Q[2][p];
+        const R wdet = s.detJ;
+
+        // ---- residual: R_Ia = w detJ0 sum_q (f^ S^)_aq g^_Iq
+        {
+            R Ph[3][3];
+            bool fin = true;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    Ph[i][p] = wdet * (fh[i][0] * Sh[0][p] + fh[i][1] * Sh[1][p] + fh[i][2] * Sh[2][p]);
+                    fin = fin && isfinite((double)Ph[i][p]);
+                }
+            if (valid && !fin) ++cnt_nan;
+#pragma unroll
+            for (int I = 0; I < 8; ++I)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    red[3 * I + i][tid] = Ph[i][0] * gh[I][0] + Ph[i][1] * gh[I][1] + Ph[i][2] * gh[I][2];
+            __syncthreads();
+            if (valid && a.R) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    R sum = R(0);
+#pragma unroll
+                    for (int g2 = 0; g2 < 8; ++g2) sum += red[3 * gp + i][slot * 8 + g2];
+                    atomic_add<double>(a.R + 3 * (int64_t)node + i, (double)sum);
+                }
+            }
+            __syncthreads();
+        }
+
+        if (want_K) {
+            // ---- Cep rotated to the eigenframe: E + sum coef_i b^_i b^_i^T - beta m^ m^^T
+            R Ch[6][6];
+            {
+                const R lamL = (R)md.lam, mu2 = (R)md.mu2;
+#pragma unroll
+                for (int I = 0; I < 6; ++I)
+#pragma unroll
+                    for (int J = 0; J < 6; ++J) Ch[I][J] = ((I < 3 && J < 3) ? lamL : R(0)) + ((I == J) ? mu2 : R(0));
+                if (loc.plastic) {
+                    R B[5][6];
+                    R v1[3] = {(R)md.v1[0], (R)md.v1[1], (R)md.v1[2]};
+                    R v2[3] = {(R)md.v2[0], (R)md.v2[1], (R)md.v2[2]};
+                    rot_diag<R>(s.Q, v1, B[0]);
+                    rot_diag<R>(s.Q, v2, B[1]);
+                    rot_shear<R, 1, 2>(s.Q, B[2]);
+                    rot_shear<R, 0, 2>(s.Q, B[3]);
+                    rot_shear<R, 0, 1>(s.Q, B[4]);
+                    R mh[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        R v = R(0);
+#pragma unroll
+                        for (int i = 0; i < 5; ++i) v += (R)loc.mvec[i] * B[i][k];
+                        mh[k] = v;
+                    }
+                    const R beta = (R)loc.beta;
+#pragma unroll
+                    for (int I = 0; I < 6; ++I)
+#pragma unroll
+                        for (int J = I; J < 6; ++J) {
+                            R v = -beta * mh[I] * mh[J];
+#pragma unroll
+                            for (int i = 0; i < 5; ++i) v += (R)loc.coef[i] * B[i][I] * B[i][J];
+                            Ch[I][J] += v;
+                            if (J != I) Ch[J][I] += v;
+                        }
+                }
+            }
+            // ---- second divided differences f2(c_a, c_b, c_r)
+            R f2[3][3][3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const R cp = R(1) + s.mu[p];
+                f2[p][p][p] = R(-0.25) / (cp * cp);
+            }
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    if (r != p) {
+                        const R v = dd2_pair<R>(s.mu[p], s.mu[r], s.eh[p], s.eh[r]);
+                        f2[p][p][r] = f2[p][r][p] = f2[r][p][p] = v;
+                    }
+            {
+                const R v = dd2_triple<R>(s.mu[0], s.mu[1], s.mu[2], s.eh[0], s.eh[1], s.eh[2]);
+                f2[0][1][2] = f2[0][2][1] = f2[1][0][2] = f2[1][2][0] = f2[2][0][1] = f2[2][1][0] = v;
+            }
+            // ---- Lagrangian tangent (Mandel, eigenframe):
+            //      Cm = P^ Ch P^ + L,  P^_I = 2 f1(I),  (L:dC)_ab = 4 sum_r f2_abr (dC_ar T_rb + T_ar dC_rb)
+            R Cm[6][6];
+#pragma unroll
+            for (int J = 0; J < 6; ++J) {
+                const int c = mi(J), d = mj(J);
+                const R ev = (c == d) ? R(1) : R(kInvSqrt2);
+#pragma unroll
+                for (int I = 0; I < 6; ++I) {
+                    const int p = mi(I), r = mj(I);
+                    // L(E_J)_pr with E_J = ev (e_c e_d + e_d e_c) (or e_c e_c)
+                    R x = R(0);
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) {
+                        R Ept = R(0), Etr = R(0);
+                        if ((p == c && t == d) || (p == d && t == c)) Ept = ev;
+                        if ((t == c && r == d) || (t == d && r == c)) Etr = ev;
+                        if (c == d) {
+                            Ept = (p == c && t == c) ? R(1) : R(0);
+                            Etr = (t == c && r == c) ? R(1) : R(0);
+                        }
+                        x += f2[p][r][t] * (Ept * Th[t][r] + Th[p][t] * Etr);
+                    }
+                    const R Pi = R(2) * f1[p][r], Pj = R(2) * f1[c][d];
+                    Cm[I][J] = Pi * Ch[I][J] * Pj + R(4) * mw<R>(I) * x;
+                }
+            }
+            bool fin = true;
+#pragma unroll
+            for (int I = 0; I < 6; ++I) fin = fin && isfinite((double)Cm[I][I]);
+            if (valid && !fin) ++cnt_nan;
+
+            // ---- element tangent blocks (a <= b), reduced over the 8 Gauss points
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa) {
+                // Y[q][r][s] = sum_p f^_ap C4(p,q,r,s)
+                R Y[3][3][3];
+#pragma unroll
+                for (int qq = 0; qq < 3; ++qq)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int ss = 0; ss < 3; ++ss) {
+                            R v = R(0);
+#pragma unroll
+                            for (int p = 0; p < 3; ++p) {
+                                const int I = midx(p, qq), J = midx(r, ss);
+                                v += fh[aa][p] * Cm[I][J] / (mw<R>(I) * mw<R>(J));
+                            }
+                            Y[qq][r][ss] = v;
+                        }
+#pragma unroll
+                for (int bb = aa; bb < 3; ++bb) {
+                    R Ah[3][3];
+#pragma unroll
+                    for (int qq = 0; qq < 3; ++qq)
+#pragma unroll
+                        for (int ss = 0; ss < 3; ++ss) {
+                            R v = fh[bb][0] * Y[qq][0][ss] + fh[bb][1] * Y[qq][1][ss] + fh[bb][2] * Y[qq][2][ss];
+                            if (aa == bb) v += Sh[qq][ss];
+                            Ah[qq][ss] = wdet * v;
+                        }
+                    R Xq[3][8];
+#pragma unroll
+                    for (int qq = 0; qq < 3; ++qq)
+#pragma unroll
+                        for (int J = 0; J < 8; ++J)
+                            Xq[qq][J] = Ah[qq][0] * gh[J][0] + Ah[qq][1] * gh[J][1] + Ah[qq][2] * gh[J][2];
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+                        for (int il = 0; il < 4; ++il)
+#pragma unroll
+                            for (int J = 0; J < 8; ++J) {
+                                const int I = 4 * half + il;
+                                red[il * 8 + J][tid] = gh[I][0] * Xq[0][J] + gh[I][1] * Xq[1][J] + gh[I][2] * Xq[2][J];
+                            }
+                        __syncthreads();
+                        if (valid) {
+                            const int il = gp >> 1, I = 4 * half + il, jb = (gp & 1) * 4;
+                            const int64_t rowI = (int64_t)sRow[slot][I] + (int64_t)aa * sLen[slot][I];
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const int J = jb + j;
+                                R sum = R(0);
+#pragma unroll
+                                for (int g2 = 0; g2 < 8; ++g2) sum += red[il * 8 + J][slot * 8 + g2];
+                                R* Kp = reinterpret_cast<R*>(a.K);
+                                // a rank outside the row (pattern of another mesh) is skipped
+                                const int oIJ = 3 * (int)sRank[slot][I * 8 + J] + bb;
+                                if (oIJ < sLen[slot][I]) atomic_add<R>(Kp + rowI + oIJ, sum);
+                                if (bb != aa) {
+                                    const int64_t rowJ = (int64_t)sRow[slot][J] + (int64_t)bb * sLen[slot][J];
+                                    const int oJI = 3 * (int)sRank[slot][J * 8 + I] + aa;
+                                    if (oJI < sLen[slot][J]) atomic_add<R>(Kp + rowJ + oJI, sum);
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (a.diag) {
+        if (cnt_fail) atomicAdd(a.diag + 0, cnt_fail);
+        if (cnt_j0) atomicAdd(a.diag + 1, cnt_j0);
+        if (cnt_jf) atomicAdd(a.diag + 2, cnt_jf);
+        if (cnt_nan) atomicAdd(a.diag + 3, cnt_nan);
+    }
+}
+
+// ---- epilogue: Dirichlet rows and residual norm
+
+template <typename R>
+__global__ void dirichlet_rows(int32_t n_dof, const uint8_t* __restrict__ bc, double* __restrict__ Rv,
+                               const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                               R* __restrict__ K) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_dof || !bc[r]) return;
+    if (Rv) Rv[r] = 0.0;
+    if (K)
+        for (int32_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) K[p] = (col_idx[p] == r) ? R(1) : R(0);
+}
+
+__global__ void norm_partial(const double* __restrict__ Rv, int64_t n, double* __restrict__ part) {
+    __shared__ double sh[kNormThreads];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = Rv[i];
+        s += v * v;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kNormThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void norm_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double sh[kNormThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kNormThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+template <typename R, int BLOCK>
+hipError_t launch_fwd(const FwdArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((fwd_kernel<R, BLOCK>), dim3(grid), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fwd_block(const FwdArgs& a, int block, int grid, hipStream_t s) {
+    switch (block) {
+        case 64: return launch_fwd<R, 64>(a, grid, s);
+        case 256: return launch_fwd<R, 256>(a, grid, s);
+        default: return launch_fwd<R, 128>(a, grid, s);
+    }
+}
+
+}  // namespace
+}  // namespace fem
+
+using namespace fem;
+
+extern "C" size_t fem_forward_workspace_bytes(int32_t n_nodes, int32_t n_elems) {
+    (void)n_nodes;
+    (void)n_elems;
+    return (size_t)kNormBlocks * sizeof(double) + 256;
+}
+
+extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch, const fem_csr* csr,
+                                    const fem_params* params, const double* d, const double* hist_n,
+                                    const uint8_t* bc_mask, fem_precision prec, double* R, void* K_vals,
+                                    double* hist_np1, double* rnorm2, int32_t* diag, void* ws, size_t ws_bytes,
+                                    void* stream) {
+    clear_error();
+    if (!mesh || !params) return set_error(FEM_EINVAL, "fem_residual_tangent: mesh and params must not be NULL");
+    if (mesh->n_nodes < 0 || mesh->n_elems < 0) return set_error(FEM_EINVAL, "fem_residual_tangent: negative sizes");
+    if (prec != FEM_FP64 && prec != FEM_FP32_MIXED)
+        return set_error(FEM_EINVAL, "fem_residual_tangent: unknown precision %d", (int)prec);
+    const int64_t ne = mesh->n_elems, n_dof = 3 * (int64_t)mesh->n_nodes;
+    if (rnorm2 && !R && n_dof > 0) return set_error(FEM_EINVAL, "fem_residual_tangent: rnorm2 requires R");
+    if (ne > 0 && (!mesh->X || !mesh->conn || !d || !hist_n))
+        return set_error(FEM_EINVAL, "fem_residual_tangent: X, conn, d and hist_n must not be NULL");
+    if (K_vals && (!csr || !csr->row_ptr || !csr->col_idx || !csr->elem_rank))
+        return set_error(FEM_EINVAL, "fem_residual_tangent: K_vals requires a complete CSR pattern");
+    if (K_vals && csr->n_rows != n_dof)
+        return set_error(FEM_EINVAL, "fem_residual_tangent: csr->n_rows = %d, expected %lld", csr->n_rows,
+                         (long long)n_dof);
+    for (int k = 0; k < FEM_NPARAM; ++k)
+        if (!params->p[k]) return set_error(FEM_EINVAL, "fem_residual_tangent: parameter %d is NULL", k);
+    if (params->per_spec_mask && (!batch || batch->n_spec < 1 || !batch->elem_off))
+        return set_error(FEM_EINVAL, "fem_residual_tangent: per-specimen parameters need a batch");
+    if (batch && (batch->n_spec < 1 || !batch->elem_off))
+        return set_error(FEM_EINVAL, "fem_residual_tangent: invalid batch");
+    if (rnorm2 && (!ws || ws_bytes < fem_forward_workspace_bytes(mesh->n_nodes, mesh->n_elems)))
+        return set_error(FEM_ENOMEM, "fem_residual_tangent: workspace of %zu bytes required",
+                         fem_forward_workspace_bytes(mesh->n_nodes, mesh->n_elems));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t kb = (prec == FEM_FP64) ? sizeof(double) : sizeof(float);
+    if (R) FEM_HIP_CHECK(zero_bytes(R, sizeof(double) * n_dof, s));
+    if (K_vals) FEM_HIP_CHECK(zero_bytes(K_vals, kb * (size_t)csr->nnz, s));
+    if (diag) FEM_HIP_CHECK(zero_bytes(diag, 4 * sizeof(int32_t), s));
+
+    if (ne > 0) {
+        const fem_launch cfg = launch_config(FEM_KERNEL_FORWARD, prec);
+        FwdArgs a;
+        a.n_nodes = mesh->n_nodes;
+        a.n_elems = mesh->n_elems;
+        a.X = mesh->X;
+        a.conn = mesh->conn;
+        for (int k = 0; k < FEM_NPARAM; ++k) a.prm[k] = params->p[k];
+        a.pe_mask = params->per_elem_mask;
+        a.ps_mask = params->per_spec_mask & ~params->per_elem_mask;
+        a.n_spec = batch ? batch->n_spec : 1;
+        a.elem_off = batch ? batch->elem_off : nullptr;
+        a.row_ptr = csr ? csr->row_ptr : nullptr;
+        a.elem_rank = csr ? csr->elem_rank : nullptr;
+        a.d = d;
+        a.hist_n = hist_n;
+        a.R = R;
+        a.K = K_vals;
+        a.hist_np1 = hist_np1;
+        a.diag = diag;
+        a.n_gp = 8 * ne;
+        const int epb = cfg.block / 8;
+        a.n_tiles = (ne + epb - 1) / epb;
+        a.xcd_remap = cfg.xcd_remap;
+        const int grid = persistent_grid(cfg, a.n_tiles);
+        void* tk = timing_begin(s);
+        hipError_t e = (prec == FEM_FP64) ? launch_fwd_block<double>(a, cfg.block, grid, s)
+                                          : launch_fwd_block<float>(a, cfg.block, grid, s);
+        timing_end(tk, FEM_KERNEL_FORWARD, s);
+        if (e != hipSuccess) return set_error(FEM_EHIP, "forward kernel launch failed: %s", hipGetErrorString(e));
+    }
+    if (bc_mask && n_dof > 0 && (R || K_vals)) {
+        const int T = 256;
+        const unsigned nbk = (unsigned)((n_dof + T - 1) / T);
+        if (prec == FEM_FP64)
+            hipLaunchKernelGGL(dirichlet_rows<double>, dim3(nbk), dim3(T), 0, s, (int32_t)n_dof, bc_mask, R,
+                               csr ? csr->row_ptr : nullptr, csr ? csr->col_idx : nullptr,
+                               reinterpret_cast<double*>(K_vals));
+        else
+            hipLaunchKernelGGL(dirichlet_rows<float>, dim3(nbk), dim3(T), 0, s, (int32_t)n_dof, bc_mask, R,
+                               csr ? csr->row_ptr : nullptr, csr ? csr->col_idx : nullptr,
+                               reinterpret_cast<float*>(K_vals));
+        FEM_HIP_CHECK(hipGetLastError());
+    }
+    if (rnorm2) {
+        double* part = reinterpret_cast<double*>(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        hipLaunchKernelGGL(norm_partial, dim3(kNormBlocks), dim3(kNormThreads), 0, s, R, n_dof, part);
+        hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormThreads), 0, s, part, kNormBlocks, rnorm2);
+        FEM_HIP_CHECK(hipGetLastError());
+    }
+    return FEM_OK;
+}

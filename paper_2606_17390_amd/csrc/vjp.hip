@@ -1,0 +1,419 @@
+// vjp.hip -- parameter vector-Jacobian product g = lambda^T dR/dtheta for
+// theta = (F, G, H, N, K, eps0, n) (Alg. 1 "Evaluate VJP", Eq. (main_grad)).
+//
+// R_Ia = sum_e sum_g w detJ0 P_aA dN_I/dX_A, P = F (P_L : T), and only the
+// logarithmic stress T depends on theta, through the converged local update.
+// Per Gauss point:
+//   Lambda = sum_I lambda_I (x) grad N_I,  Tbar = P_L : sym(F^T Lambda),
+//   thetabar_k = w detJ0 Tbar : dT/dtheta_k.
+// dT/dtheta follows from differentiating the converged closest-point
+// equations (App. D); here it is applied in reverse mode, in closed form:
+//   u = Xi Tbar,  Xi = (E^-1 + dgamma dN/dT)^-1,  D = N.Xi.N + sigma_y',
+//   thetabar = -dgamma u.N_theta
+//              - (u.N / D) (-dgamma (Xi N).N_theta + phi_theta - sigma_y,theta).
+// The local state is recomputed from d and hist_n (no tape is stored).
+// Elastic Gauss points contribute exactly zero.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fem_device.h"
+#include "fem_internal.h"
+
+namespace fem {
+namespace {
+
+struct VjpArgs {
+    int32_t n_nodes, n_elems;
+    const double* X;
+    const int32_t* conn;
+    const double* prm[FEM_NPARAM];
+    uint32_t pe_mask, ps_mask;
+    int32_t n_spec;
+    const int64_t* elem_off;
+    const double* d;
+    const double* hist_n;
+    const double* lam;
+    double* g_elem;  // [7][n_elems]
+    int32_t* diag;
+    int64_t n_gp;
+    int64_t n_tiles;
+    int32_t xcd_remap;
+};
+
+__device__ inline int spec_of_v(const int64_t* __restrict__ off, int n_spec, int64_t e) {
+    int lo = 0, hi = n_spec - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline Mat load_material_v(const VjpArgs& a, int64_t e) {
+    int sp = 0;
+    if (a.ps_mask) sp = spec_of_v(a.elem_off, a.n_spec, e);
+    double v[FEM_NPARAM];
+#pragma unroll
+    for (int k = 0; k < FEM_NPARAM; ++k) {
+        const int64_t idx = ((a.pe_mask >> k) & 1u) ? e : (((a.ps_mask >> k) & 1u) ? (int64_t)sp : 0);
+        v[k] = a.prm[k][idx];
+    }
+    Mat m;
+    m.E = v[0]; m.nu = v[1]; m.F = v[2]; m.G = v[3]; m.H = v[4]; m.L = v[5];
+    m.M = v[6]; m.N = v[7]; m.K = v[8]; m.eps0 = v[9]; m.nexp = v[10];
+    return m;
+}
+
+__device__ inline void tile_range_v(int64_t n_tiles, int remap, int64_t& first, int64_t& end, int64_t& step) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    if (remap && (nb % 8) == 0 && nb >= 8) {
+        const int x = b & 7, k = b >> 3, per = nb >> 3;
+        const int64_t chunk = (n_tiles + 7) / 8;
+        first = (int64_t)x * chunk + k;
+        end = min((int64_t)(x + 1) * chunk, n_tiles);
+        step = per;
+    } else {
+        first = b;
+        end = n_tiles;
+        step = nb;
+    }
+}
+
+template <typename R>
+struct GPv {
+    R g[8][3];
+    R detJ;
+    R H[3][3];   // displacement gradient, F = I + H
+    R Q[3][3];
+    R mu[3];
+    R eh[3];
+};
+
+template <typename R>
+__device__ inline void kin_log_v(const R xs[8][3], const R ds[8][3], int gp, GPv<R>& s, double eps[6]) {
+    kinematics<R>(xs, ds, gp, s.g, s.detJ, s.H);
+    R M[3][3];
+    cauchy_green_minus_identity<R>(s.H, M);
+    eig_sym3<R>(M, s.mu, s.Q);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s.eh[a] = R(0.5) * m_log1p(s.mu[a]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int i = mi(k), j = mj(k);
+        R v = s.Q[i][0] * s.eh[0] * s.Q[j][0] + s.Q[i][1] * s.eh[1] * s.Q[j][1] + s.Q[i][2] * s.eh[2] * s.Q[j][2];
+        eps[k] = (double)(mw<R>(k) * v);
+    }
+}
+
+template <typename R, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
+    constexpr int EPB = BLOCK / 8;
+    __shared__ double sN[EPB][8][9];
+    __shared__ double red[7][BLOCK + 1];
+    const int tid = threadIdx.x;
+    const int slot = tid >> 3, gp = tid & 7;
+    int32_t cnt_fail = 0, cnt_j0 = 0;
+
+    int64_t t0, t1, ts;
+    tile_range_v(a.n_tiles, a.xcd_remap, t0, t1, ts);
+    for (int64_t tile = t0; tile < t1; tile += ts) {
+        const int64_t e_raw = tile * EPB + slot;
+        const bool valid = e_raw < a.n_elems;
+        const int64_t e = valid ? e_raw : (int64_t)a.n_elems - 1;
+        const int64_t q = e * 8 + gp;
+        int32_t node = a.conn[q];
+        if ((uint32_t)node >= (uint32_t)a.n_nodes) node = 0;  // out-of-range id: stay in bounds
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sN[slot][gp][c] = a.X[3 * (int64_t)node + c];
+            sN[slot][gp][3 + c] = a.d[3 * (int64_t)node + c];
+            sN[slot][gp][6 + c] = a.lam[3 * (int64_t)node + c];
+        }
+        double hn[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) hn[k] = a.hist_n[k * a.n_gp + q];
+        const Mat mat = load_material_v(a, e);
+        __syncthreads();
+
+        GPv<R> s;
+        double eps[6];
+        R lrel[8][3];
+        {
+            R xs[8][3], ds[8][3];
+#pragma unroll
+            for (int I = 0; I < 8; ++I)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xs[I][c] = (R)(sN[slot][I][c] - sN[slot][0][c]);
+                    ds[I][c] = (R)(sN[slot][I][3 + c] - sN[slot][0][3 + c]);
+                    lrel[I][c] = (R)(sN[slot][I][6 + c] - sN[slot][0][6 + c]);
+                }
+            kin_log_v<R>(xs, ds, gp, s, eps);
+        }
+        Modes md;
+        hill_modes(mat, md);
+        Local loc;
+        local_update(eps, hn, mat, md, loc);
+        if constexpr (std::is_same<R, float>::value) {
+            if (fabs(loc.ftr) < 2e-4 * loc.sy_n) {
+                GPv<double> sd;
+                double xs[8][3], ds[8][3];
+#pragma unroll
+                for (int I = 0; I < 8; ++I)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        xs[I][c] = sN[slot][I][c] - sN[slot][0][c];
+                        ds[I][c] = sN[slot][I][3 + c] - sN[slot][0][3 + c];
+                    }
+                kin_log_v<double>(xs, ds, gp, sd, eps);
+                local_update(eps, hn, mat, md, loc);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    s.mu[i] = (R)sd.mu[i];
+                    s.eh[i] = (R)sd.eh[i];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        s.Q[i][j] = (R)sd.Q[i][j];
+                        s.H[i][j] = (R)sd.H[i][j];
+                    }
+                }
+            }
+        }
+        if (valid) {
+            cnt_fail += loc.converged ? 0 : 1;
+            cnt_j0 += (s.detJ <= R(0)) ? 1 : 0;
+        }
+        double gbar[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (loc.plastic) {
+            // Tbar = P_L : sym(F^T Lambda) in the eigenframe of C
+            R gh[8][3];
+#pragma unroll
+            for (int I = 0; I < 8; ++I)
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+                    gh[I][p] = s.g[I][0] * s.Q[0][p] + s.g[I][1] * s.Q[1][p] + s.g[I][2] * s.Q[2][p];
+            R Lh[3][3];  // Lambda^_aq = sum_I lambda_Ia g^_Iq
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    R v = R(0);
+#pragma unroll
+                    for (int I = 1; I < 8; ++I) v += lrel[I][i] * gh[I][p];
+                    Lh[i][p] = v;
+                }
+            R fh[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+                    fh[i][p] = s.Q[i][p] + (s.H[i][0] * s.Q[0][p] + s.H[i][1] * s.Q[1][p] + s.H[i][2] * s.Q[2][p]);
+            R Tb[3][3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int r = p; r < 3; ++r) {
+                    R x = R(0.5) * (fh[0][p] * Lh[0][r] + fh[1][p] * Lh[1][r] + fh[2][p] * Lh[2][r] +
+                                    fh[0][r] * Lh[0][p] + fh[1][r] * Lh[1][p] + fh[2][r] * Lh[2][p]);
+                    const R f1 = (p == r) ? R(0.5) / (R(1) + s.mu[p]) : dd1<R>(s.mu[p], s.mu[r], s.eh[p], s.eh[r]);
+                    Tb[p][r] = Tb[r][p] = R(2) * f1 * x;
+                }
+            R tbm[6];
+            frame_to_mandel<R>(s.Q, Tb, tbm);
+            double tb[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) tb[k] = (double)tbm[k];
+
+            // ---- reverse-mode adjoint of the local update (double)
+            const double lam = loc.lam, dg = loc.dgamma, phi = loc.phi, sv = loc.svar;
+            const double om = 1.0 / (1.0 - lam * sv);
+            double tmod[5];
+            const double tbh = (tb[0] + tb[1] + tb[2]) * kInvSqrt3;
+            tmod[0] = md.v1[0] * tb[0] + md.v1[1] * tb[1] + md.v1[2] * tb[2];
+            tmod[1] = md.v2[0] * tb[0] + md.v2[1] * tb[1] + md.v2[2] * tb[2];
+            tmod[2] = tb[3];
+            tmod[3] = tb[4];
+            tmod[4] = tb[5];
+            double mT = 0.0;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) mT += loc.mvec[i] * tmod[i];
+            double u[5], xin[5], uN = 0.0;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                const double ai = md.mu2 / (1.0 + md.mu2 * lam * md.eta[i]);
+                u[i] = ai * tmod[i] + lam * loc.mvec[i] * mT * om;
+                xin[i] = loc.mvec[i] * om;
+                uN += u[i] * loc.Nm[i];
+            }
+            const double uh = md.k3 * tbh;
+            const double Dn = sv * om + loc.dsig;
+            const double xN = sv * om;
+            // Cartesian Mandel of u and Xi N
+            double uc[6], xc[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                uc[k] = uh * kInvSqrt3 + u[0] * md.v1[k] + u[1] * md.v2[k];
+                xc[k] = xin[0] * md.v1[k] + xin[1] * md.v2[k];
+            }
+            uc[3] = u[2]; uc[4] = u[3]; uc[5] = u[4];
+            xc[3] = xin[2]; xc[4] = xin[3]; xc[5] = xin[4];
+            const double* T = loc.T;
+            // Hill parameters F, G, H, N: (H_theta T) and T.H_theta.T
+            double hv[4][6] = {{0, T[1] - T[2], T[2] - T[1], 0, 0, 0},
+                               {T[0] - T[2], 0, T[2] - T[0], 0, 0, 0},
+                               {T[0] - T[1], T[1] - T[0], 0, 0, 0, 0},
+                               {0, 0, 0, 0, 0, T[5]}};
+            const double tht[4] = {(T[1] - T[2]) * (T[1] - T[2]), (T[0] - T[2]) * (T[0] - T[2]),
+                                   (T[0] - T[1]) * (T[0] - T[1]), T[5] * T[5]};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double uh_ = 0.0, xh_ = 0.0;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    uh_ += uc[c] * hv[k][c];
+                    xh_ += xc[c] * hv[k][c];
+                }
+                const double dphi = tht[k] / (2.0 * phi);
+                const double uNt = uh_ / phi - uN * dphi / phi;
+                const double xNt = xh_ / phi - xN * dphi / phi;
+                gbar[k] = -dg * uNt - (uN / Dn) * (-dg * xNt + dphi);
+            }
+            // Swift K, eps0, n at alpha_{n+1}
+            const double alpha = loc.hist[6];
+            const double base = mat.eps0 + alpha;
+            const double dK = loc.sig / mat.K;
+            const double de0 = loc.dsig;
+            const double dn = loc.sig * log(base);
+            gbar[4] = (uN / Dn) * dK;
+            gbar[5] = (uN / Dn) * de0;
+            gbar[6] = (uN / Dn) * dn;
+            const double w = (double)s.detJ;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) gbar[k] *= w;
+        }
+#pragma unroll
+        for (int k = 0; k < 7; ++k) red[k][tid] = gbar[k];
+        __syncthreads();
+        if (valid && gp < 7) {
+            double sum = 0.0;
+#pragma unroll
+            for (int g2 = 0; g2 < 8; ++g2) sum += red[gp][slot * 8 + g2];
+            a.g_elem[(int64_t)gp * a.n_elems + e] = sum;
+        }
+        __syncthreads();
+    }
+    if (a.diag) {
+        if (cnt_fail) atomicAdd(a.diag + 0, cnt_fail);
+        if (cnt_j0) atomicAdd(a.diag + 1, cnt_j0);
+    }
+}
+
+// g_uniform[s][k] = sum over the elements of specimen s of g_elem[k][e]; one
+// workgroup per (s, k), fixed summation order (deterministic).
+__global__ void reduce_uniform(const double* __restrict__ g_elem, int64_t n_elems, const int64_t* __restrict__ off,
+                               int n_spec, double* __restrict__ g_uniform) {
+    __shared__ double sh[256];
+    const int sidx = blockIdx.x / FEM_NGRAD, k = blockIdx.x % FEM_NGRAD;
+    const int64_t b = off ? off[sidx] : 0, en = off ? off[sidx + 1] : n_elems;
+    double s = 0.0;
+    for (int64_t e = b + threadIdx.x; e < en; e += blockDim.x) s += g_elem[(int64_t)k * n_elems + e];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g_uniform[(int64_t)sidx * FEM_NGRAD + k] = sh[0];
+    (void)n_spec;
+}
+
+template <typename R>
+hipError_t launch_vjp(const VjpArgs& a, int block, int grid, hipStream_t s) {
+    switch (block) {
+        case 64: hipLaunchKernelGGL((vjp_kernel<R, 64>), dim3(grid), dim3(64), 0, s, a); break;
+        case 256: hipLaunchKernelGGL((vjp_kernel<R, 256>), dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((vjp_kernel<R, 128>), dim3(grid), dim3(128), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace fem
+
+using namespace fem;
+
+extern "C" size_t fem_vjp_workspace_bytes(int32_t n_elems, int32_t n_spec) {
+    (void)n_spec;
+    if (n_elems < 0) return 0;
+    return sizeof(double) * (size_t)FEM_NGRAD * ((size_t)n_elems + 1) + 512;
+}
+
+extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, const fem_params* params,
+                                const double* d, const double* hist_n, const double* lam, fem_precision prec,
+                                double* g_uniform, double* g_elem, int32_t* diag, void* ws, size_t ws_bytes,
+                                void* stream) {
+    clear_error();
+    if (!mesh || !params) return set_error(FEM_EINVAL, "fem_residual_vjp: mesh and params must not be NULL");
+    if (mesh->n_nodes < 0 || mesh->n_elems < 0) return set_error(FEM_EINVAL, "fem_residual_vjp: negative sizes");
+    if (prec != FEM_FP64 && prec != FEM_FP32_MIXED)
+        return set_error(FEM_EINVAL, "fem_residual_vjp: unknown precision %d", (int)prec);
+    const int64_t ne = mesh->n_elems;
+    if (ne > 0 && (!mesh->X || !mesh->conn || !d || !hist_n || !lam))
+        return set_error(FEM_EINVAL, "fem_residual_vjp: X, conn, d, hist_n and lam must not be NULL");
+    for (int k = 0; k < FEM_NPARAM; ++k)
+        if (!params->p[k]) return set_error(FEM_EINVAL, "fem_residual_vjp: parameter %d is NULL", k);
+    if (batch && (batch->n_spec < 1 || !batch->elem_off))
+        return set_error(FEM_EINVAL, "fem_residual_vjp: invalid batch");
+    if (params->per_spec_mask && !batch)
+        return set_error(FEM_EINVAL, "fem_residual_vjp: per-specimen parameters need a batch");
+    const int n_spec = batch ? batch->n_spec : 1;
+    hipStream_t s = (hipStream_t)stream;
+    double* ge = g_elem;
+    if (!ge) {
+        const size_t need = fem_vjp_workspace_bytes(mesh->n_elems, n_spec);
+        if (!ws || ws_bytes < need)
+            return set_error(FEM_ENOMEM, "fem_residual_vjp: workspace of %zu bytes required", need);
+        ge = reinterpret_cast<double*>(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    }
+    if (diag) FEM_HIP_CHECK(zero_bytes(diag, 4 * sizeof(int32_t), s));
+    if (ne > 0) {
+        const fem_launch cfg = launch_config(FEM_KERNEL_VJP, prec);
+        VjpArgs a;
+        a.n_nodes = mesh->n_nodes;
+        a.n_elems = mesh->n_elems;
+        a.X = mesh->X;
+        a.conn = mesh->conn;
+        for (int k = 0; k < FEM_NPARAM; ++k) a.prm[k] = params->p[k];
+        a.pe_mask = params->per_elem_mask;
+        a.ps_mask = params->per_spec_mask & ~params->per_elem_mask;
+        a.n_spec = n_spec;
+        a.elem_off = batch ? batch->elem_off : nullptr;
+        a.d = d;
+        a.hist_n = hist_n;
+        a.lam = lam;
+        a.g_elem = ge;
+        a.diag = diag;
+        a.n_gp = 8 * ne;
+        const int epb = cfg.block / 8;
+        a.n_tiles = (ne + epb - 1) / epb;
+        a.xcd_remap = cfg.xcd_remap;
+        const int grid = persistent_grid(cfg, a.n_tiles);
+        void* tk = timing_begin(s);
+        hipError_t e = (prec == FEM_FP64) ? launch_vjp<double>(a, cfg.block, grid, s)
+                                          : launch_vjp<float>(a, cfg.block, grid, s);
+        timing_end(tk, FEM_KERNEL_VJP, s);
+        if (e != hipSuccess) return set_error(FEM_EHIP, "vjp kernel launch failed: %s", hipGetErrorString(e));
+    }
+    if (g_uniform) {
+        if (ne == 0) {
+            FEM_HIP_CHECK(zero_bytes(g_uniform, sizeof(double) * FEM_NGRAD * n_spec, s));
+        } else {
+            hipLaunchKernelGGL(reduce_uniform, dim3(n_spec * FEM_NGRAD), dim3(256), 0, s, ge, ne,
+                               batch ? batch->elem_off : nullptr, n_spec, g_uniform);
+            FEM_HIP_CHECK(hipGetLastError());
+        }
+    }
+    return FEM_OK;
+}

@@ -1,0 +1,398 @@
+"""ctypes binding of libfem.so (C ABI in include/fem.h).
+
+Only argument marshalling lives here: every step of the hot path runs in the
+HIP kernels of libfem.so.  Device buffers are torch tensors (torch is used for
+device memory and streams only).  If libfem.so is missing the first call
+raises; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfem.so")
+
+FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOMEM, FEM_EOVERFLOW, FEM_EMESH = 0, -1, -2, -3, -4, -5
+FP64, FP32_MIXED = 0, 1
+NPARAM, NGRAD = 11, 7
+KERNEL_FORWARD, KERNEL_VJP = 0, 1
+
+_c_i32, _c_i64, _c_u32, _c_p, _c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
+
+
+class FemMesh(ctypes.Structure):
+    _fields_ = [("n_nodes", _c_i32), ("n_elems", _c_i32), ("X", _c_p), ("conn", _c_p)]
+
+
+class FemParams(ctypes.Structure):
+    _fields_ = [("p", _c_p * NPARAM), ("per_elem_mask", _c_u32), ("per_spec_mask", _c_u32)]
+
+
+class FemCsr(ctypes.Structure):
+    _fields_ = [("n_rows", _c_i32), ("nnz", _c_i64), ("row_ptr", _c_p), ("col_idx", _c_p), ("elem_rank", _c_p)]
+
+
+class FemBatch(ctypes.Structure):
+    _fields_ = [("n_spec", _c_i32), ("elem_off", _c_p)]
+
+
+class FemLaunch(ctypes.Structure):
+    _fields_ = [("block", _c_i32), ("waves_per_cu", _c_i32), ("xcd_remap", _c_i32)]
+
+
+class FemError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = ("fem_version", "fem_last_error", "fem_set_launch", "fem_get_launch", "fem_csr_workspace_bytes",
+           "fem_forward_workspace_bytes", "fem_vjp_workspace_bytes", "fem_csr_pattern", "fem_residual_tangent",
+           "fem_residual_vjp", "fem_timing_enable", "fem_timing_read", "fem_graph_begin", "fem_graph_end",
+           "fem_graph_launch", "fem_graph_destroy")
+
+
+def lib():
+    """Load libfem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_2606_17390_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.fem_version.restype = ctypes.c_int
+    L.fem_last_error.restype = ctypes.c_char_p
+    L.fem_set_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(FemLaunch)]
+    L.fem_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(FemLaunch)]
+    L.fem_csr_workspace_bytes.argtypes = [_c_i32, _c_i32]
+    L.fem_csr_workspace_bytes.restype = _c_sz
+    L.fem_forward_workspace_bytes.argtypes = [_c_i32, _c_i32]
+    L.fem_forward_workspace_bytes.restype = _c_sz
+    L.fem_vjp_workspace_bytes.argtypes = [_c_i32, _c_i32]
+    L.fem_vjp_workspace_bytes.restype = _c_sz
+    L.fem_csr_pattern.argtypes = [ctypes.POINTER(FemMesh), ctypes.POINTER(FemCsr), _c_p, _c_sz, _c_p]
+    L.fem_residual_tangent.argtypes = [ctypes.POINTER(FemMesh), ctypes.POINTER(FemBatch), ctypes.POINTER(FemCsr),
+                                       ctypes.POINTER(FemParams), _c_p, _c_p, _c_p, ctypes.c_int, _c_p, _c_p, _c_p,
+                                       _c_p, _c_p, _c_p, _c_sz, _c_p]
+    L.fem_residual_vjp.argtypes = [ctypes.POINTER(FemMesh), ctypes.POINTER(FemBatch), ctypes.POINTER(FemParams),
+                                   _c_p, _c_p, _c_p, ctypes.c_int, _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p]
+    L.fem_timing_enable.argtypes = [ctypes.c_int]
+    L.fem_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_c_i32)]
+    L.fem_graph_begin.argtypes = [_c_p]
+    L.fem_graph_end.argtypes = [_c_p, ctypes.POINTER(_c_p)]
+    L.fem_graph_launch.argtypes = [_c_p, _c_p]
+    L.fem_graph_destroy.argtypes = [_c_p]
+    _lib = L
+    return L
+
+
+def _check(fn, code):
+    if code != FEM_OK:
+        raise FemError(fn, code, lib().fem_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _prec(p):
+    if p in (FP64, "fp64", "f64", torch.float64):
+        return FP64
+    if p in (FP32_MIXED, "mixed", "fp32", "fp32_mixed", torch.float32):
+        return FP32_MIXED
+    raise ValueError(f"unknown precision {p!r}")
+
+
+def version():
+    return lib().fem_version()
+
+
+def set_launch(kernel, prec, block=None, waves_per_cu=None, xcd_remap=None):
+    """Set the launch configuration of a kernel; with all None, reset it."""
+    if block is None and waves_per_cu is None and xcd_remap is None:
+        _check("fem_set_launch", lib().fem_set_launch(kernel, _prec(prec), None))
+        return
+    cur = get_launch(kernel, prec)
+    cfg = FemLaunch(block if block is not None else cur.block,
+                    waves_per_cu if waves_per_cu is not None else cur.waves_per_cu,
+                    xcd_remap if xcd_remap is not None else cur.xcd_remap)
+    _check("fem_set_launch", lib().fem_set_launch(kernel, _prec(prec), ctypes.byref(cfg)))
+
+
+def timing_enable(on=True):
+    _check("fem_timing_enable", lib().fem_timing_enable(1 if on else 0))
+
+
+def timing_read(kernel):
+    """(summed milliseconds, launch count) of the kernel since the last read."""
+    ms = ctypes.c_double()
+    n = _c_i32()
+    _check("fem_timing_read", lib().fem_timing_read(kernel, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def get_launch(kernel, prec):
+    cfg = FemLaunch()
+    _check("fem_get_launch", lib().fem_get_launch(kernel, _prec(prec), ctypes.byref(cfg)))
+    return cfg
+
+
+# ---------------------------------------------------------------------------
+# device-side containers
+# ---------------------------------------------------------------------------
+
+class Mesh:
+    """Reference coordinates [n_nodes, 3] (float64) and connectivity [n_elems, 8]
+    (int32, VTK order) resident on the device."""
+
+    def __init__(self, X, conn, device="cuda"):
+        self.X = torch.as_tensor(np.asarray(X, dtype=np.float64)).to(device).contiguous()
+        self.conn = torch.as_tensor(np.asarray(conn, dtype=np.int32)).to(device).contiguous()
+        self.n_nodes = int(self.X.shape[0])
+        self.n_elems = int(self.conn.shape[0])
+        self.device = self.X.device
+
+    def c(self):
+        return FemMesh(self.n_nodes, self.n_elems, _ptr(self.X) if self.X.numel() else None,
+                       _ptr(self.conn) if self.conn.numel() else None)
+
+
+class Params:
+    """The 11 material parameters: uniform (shape [11]), per element ([n_elems, 11])
+    or per specimen ([n_spec, 11], batched mode)."""
+
+    def __init__(self, prm, n_elems, device="cuda", per_spec=False):
+        prm = torch.as_tensor(np.asarray(prm, dtype=np.float64) if not torch.is_tensor(prm) else prm,
+                              dtype=torch.float64)
+        self.cols = []
+        self.per_elem_mask = 0
+        self.per_spec_mask = 0
+        if prm.dim() == 1:
+            for k in range(NPARAM):
+                self.cols.append(prm[k:k + 1].to(device).contiguous())
+        else:
+            if not per_spec and prm.shape[0] != n_elems:
+                raise ValueError("per-element parameters need n_elems rows")
+            for k in range(NPARAM):
+                col = prm[:, k]
+                if prm.shape[0] > 0 and bool((col == col[0]).all()):
+                    # a constant column is passed as one uniform value
+                    self.cols.append(col[:1].to(device).contiguous())
+                    continue
+                self.cols.append(col.to(device).contiguous())
+                if per_spec:
+                    self.per_spec_mask |= 1 << k
+                else:
+                    self.per_elem_mask |= 1 << k
+
+    def c(self):
+        p = FemParams()
+        for k in range(NPARAM):
+            p.p[k] = self.cols[k].data_ptr()
+        p.per_elem_mask = self.per_elem_mask
+        p.per_spec_mask = self.per_spec_mask
+        return p
+
+
+class Batch:
+    """Element offsets [n_spec + 1] of concatenated specimens."""
+
+    def __init__(self, elem_off, device="cuda"):
+        self.elem_off = torch.as_tensor(np.asarray(elem_off, dtype=np.int64)).to(device).contiguous()
+        self.n_spec = int(self.elem_off.numel() - 1)
+
+    def c(self):
+        return FemBatch(self.n_spec, _ptr(self.elem_off))
+
+
+class Csr:
+    def __init__(self, row_ptr, col_idx, elem_rank, nnz, n_rows):
+        self.row_ptr, self.col_idx, self.elem_rank = row_ptr, col_idx, elem_rank
+        self.nnz, self.n_rows = nnz, n_rows
+
+    def c(self):
+        return FemCsr(self.n_rows, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx) if self.nnz else None,
+                      _ptr(self.elem_rank) if self.elem_rank is not None and self.elem_rank.numel() else None)
+
+
+def _ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def csr_pattern(mesh, stream=None):
+    """Build the CSR pattern of the tangent (two calls of fem_csr_pattern)."""
+    L = lib()
+    dev = mesh.device
+    ws_bytes = L.fem_csr_workspace_bytes(mesh.n_nodes, mesh.n_elems)
+    ws = _ws(ws_bytes, dev)
+    row_ptr = torch.empty(3 * mesh.n_nodes + 1, dtype=torch.int32, device=dev)
+    cm = mesh.c()
+    c = FemCsr(3 * mesh.n_nodes, 0, _ptr(row_ptr), None, None)
+    s = _stream(stream)
+    _check("fem_csr_pattern", L.fem_csr_pattern(ctypes.byref(cm), ctypes.byref(c), _ptr(ws), ws_bytes, s))
+    nnz = int(c.nnz)
+    col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    elem_rank = torch.empty((max(mesh.n_elems, 1), 64), dtype=torch.uint8, device=dev)
+    c.col_idx = col_idx.data_ptr()
+    c.elem_rank = elem_rank.data_ptr()
+    if nnz:
+        _check("fem_csr_pattern", L.fem_csr_pattern(ctypes.byref(cm), ctypes.byref(c), _ptr(ws), ws_bytes, s))
+    return Csr(row_ptr, col_idx[:nnz], elem_rank[:mesh.n_elems], nnz, 3 * mesh.n_nodes)
+
+
+class Forward:
+    """Preallocated outputs of fem_residual_tangent for repeated calls."""
+
+    def __init__(self, mesh, csr, prec=FP64, want_K=True, want_hist=True, want_norm=True):
+        dev = mesh.device
+        self.prec = _prec(prec)
+        self.R = torch.empty(3 * mesh.n_nodes, dtype=torch.float64, device=dev)
+        kdt = torch.float64 if self.prec == FP64 else torch.float32
+        nnz = csr.nnz if csr is not None else 0
+        self.K = torch.empty(max(nnz, 1), dtype=kdt, device=dev)[:nnz] if (want_K and csr is not None) else None
+        self.hist = torch.empty((7, 8 * mesh.n_elems), dtype=torch.float64, device=dev) if want_hist else None
+        self.rnorm2 = torch.empty(1, dtype=torch.float64, device=dev) if want_norm else None
+        self.diag = torch.empty(4, dtype=torch.int32, device=dev)
+        nb = lib().fem_forward_workspace_bytes(mesh.n_nodes, mesh.n_elems)
+        self.ws = _ws(nb, dev)
+        self.ws_bytes = nb
+
+
+def residual_tangent(mesh, csr, params, d, hist_n, bc_mask=None, prec=FP64, out=None, batch=None,
+                     want_K=True, want_hist=True, stream=None):
+    """One residual + tangent + CSR assembly pass; returns the Forward buffers."""
+    L = lib()
+    if out is None:
+        out = Forward(mesh, csr, prec, want_K=want_K, want_hist=want_hist)
+    cm, cp = mesh.c(), params.c()
+    cc = csr.c() if csr is not None else None
+    cb = batch.c() if batch is not None else None
+    rc = L.fem_residual_tangent(ctypes.byref(cm), ctypes.byref(cb) if cb is not None else None,
+                                ctypes.byref(cc) if cc is not None else None, ctypes.byref(cp), _ptr(d), _ptr(hist_n),
+                                _ptr(bc_mask), out.prec, _ptr(out.R),
+                                _ptr(out.K) if (out.K is not None and csr is not None and csr.nnz) else None,
+                                _ptr(out.hist), _ptr(out.rnorm2), _ptr(out.diag), _ptr(out.ws), out.ws_bytes,
+                                _stream(stream))
+    _check("fem_residual_tangent", rc)
+    return out
+
+
+class Vjp:
+    def __init__(self, mesh, n_spec=1):
+        dev = mesh.device
+        self.g_uniform = torch.empty((n_spec, NGRAD), dtype=torch.float64, device=dev)
+        self.g_elem = torch.empty((NGRAD, max(mesh.n_elems, 1)), dtype=torch.float64, device=dev)[:, :mesh.n_elems]
+        self.diag = torch.empty(4, dtype=torch.int32, device=dev)
+        nb = lib().fem_vjp_workspace_bytes(mesh.n_elems, n_spec)
+        self.ws = _ws(nb, dev)
+        self.ws_bytes = nb
+
+
+def residual_vjp(mesh, params, d, hist_n, lam, prec=FP64, out=None, batch=None, want_elem=True, stream=None):
+    """g = lam^T dR/dtheta for (F, G, H, N, K, eps0, n); returns the Vjp buffers."""
+    L = lib()
+    n_spec = batch.n_spec if batch is not None else 1
+    if out is None:
+        out = Vjp(mesh, n_spec)
+    cm, cp = mesh.c(), params.c()
+    cb = batch.c() if batch is not None else None
+    ge = out.g_elem if (want_elem and mesh.n_elems) else None
+    rc = L.fem_residual_vjp(ctypes.byref(cm), ctypes.byref(cb) if cb is not None else None, ctypes.byref(cp),
+                            _ptr(d), _ptr(hist_n), _ptr(lam), _prec(prec), _ptr(out.g_uniform), _ptr(ge),
+                            _ptr(out.diag), _ptr(out.ws), out.ws_bytes, _stream(stream))
+    _check("fem_residual_vjp", rc)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# HIP graphs
+# ---------------------------------------------------------------------------
+
+class Graph:
+    """Capture the library calls made inside `with graph.capture(stream):` and
+    replay them with graph.replay().  The stream must not be the null stream."""
+
+    def __init__(self):
+        self.exec = None
+
+    def capture(self, stream):
+        g = self
+
+        class _Ctx:
+            def __enter__(self_):
+                _check("fem_graph_begin", lib().fem_graph_begin(_stream(stream)))
+                return g
+
+            def __exit__(self_, et, ev, tb):
+                h = ctypes.c_void_p()
+                rc = lib().fem_graph_end(_stream(stream), ctypes.byref(h))
+                if et is None:
+                    _check("fem_graph_end", rc)
+                    g.exec = h
+                return False
+        return _Ctx()
+
+    def replay(self, stream):
+        _check("fem_graph_launch", lib().fem_graph_launch(self.exec, _stream(stream)))
+
+    def __del__(self):
+        if self.exec is not None and _lib is not None:
+            _lib.fem_graph_destroy(self.exec)
+            self.exec = None
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+
+class ResidualFn(torch.autograd.Function):
+    """R(theta) with theta the 7 differentiated parameters (F, G, H, N, K, eps0, n),
+    either uniform (shape [7]) or per element ([7, n_elems]).  Forward runs a
+    residual-only pass of fem_residual_tangent; backward runs fem_residual_vjp
+    with lam = grad_R.  Gradients with respect to d and the history are not
+    provided (returned as None)."""
+
+    GRAD_COLS = (2, 3, 4, 7, 8, 9, 10)
+
+    @staticmethod
+    def forward(ctx, theta, base_prm, mesh, d, hist_n, prec=FP64):
+        prm = base_prm.clone().to(torch.float64)
+        per_elem = theta.dim() == 2
+        if per_elem:
+            if prm.dim() == 1:
+                prm = prm.unsqueeze(0).repeat(mesh.n_elems, 1)
+            for i, c in enumerate(ResidualFn.GRAD_COLS):
+                prm[:, c] = theta[i].detach().to(prm.device)
+        else:
+            for i, c in enumerate(ResidualFn.GRAD_COLS):
+                if prm.dim() == 1:
+                    prm[c] = theta[i].detach()
+                else:
+                    prm[:, c] = theta[i].detach()
+        params = Params(prm, mesh.n_elems, device=mesh.device)
+        out = residual_tangent(mesh, None, params, d, hist_n, prec=prec, want_K=False, want_hist=False)
+        ctx.save_for_backward(d, hist_n)
+        ctx.mesh, ctx.params, ctx.prec, ctx.per_elem = mesh, params, prec, per_elem
+        ctx.uniform_prm = prm.dim() == 1
+        ctx.theta_device = theta.device
+        return out.R.clone()
+
+    @staticmethod
+    def backward(ctx, grad_R):
+        d, hist_n = ctx.saved_tensors
+        lam = grad_R.contiguous().to(torch.float64)
+        v = residual_vjp(ctx.mesh, ctx.params, d, hist_n, lam, prec=ctx.prec, want_elem=ctx.per_elem)
+        if ctx.per_elem:
+            g = v.g_elem.clone()
+        else:
+            g = v.g_uniform[0].clone()
+        return g.to(ctx.theta_device), None, None, None, None, None

@@ -1,0 +1,176 @@
+"""Batched mode (concatenated specimens with per-specimen parameters), HIP
+graph capture/replay, and sampled parity on the 100^3 large cube."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import TOL_FP64, TOL_MIXED, gpu_problem
+from paper_2606_17390_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fem():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2606_17390_amd import fem as F
+    F.lib()
+    return F
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def batch_problem(fem, n=4, seed=4100, lo=300, hi=3000):
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(lo), np.log(hi), n)).astype(int)
+    specs = [synth.uneven_slab(seed + i, int(s)) for i, s in enumerate(sizes)]
+    merged = synth.concat(specs)
+    return specs, merged
+
+
+def test_batch_equals_separate_calls(fem):
+    specs, m = batch_problem(fem)
+    say("batch", [s.n_elems for s in specs])
+    mesh = fem.Mesh(m.X, m.conn)
+    csr = fem.csr_pattern(mesh)
+    params = fem.Params(m.meta["spec_prm"], m.n_elems, per_spec=True)
+    batch = fem.Batch(m.meta["elem_off"])
+    d = torch.as_tensor(m.d).cuda()
+    h = torch.as_tensor(m.hist_n).cuda()
+    lam = torch.as_tensor(m.lam).cuda()
+    out = fem.residual_tangent(mesh, csr, params, d, h, prec=fem.FP64, batch=batch)
+    v = fem.residual_vjp(mesh, params, d, h, lam, prec=fem.FP64, batch=batch)
+    torch.cuda.synchronize()
+    R = out.R.cpu().numpy()
+    gu = v.g_uniform.cpu().numpy()
+    no, eo = m.meta["node_off"], m.meta["elem_off"]
+    for i, s in enumerate(specs):
+        ms, ps, ds, hs, _, ls = gpu_problem(s, fem)
+        o = fem.residual_tangent(ms, fem.csr_pattern(ms), ps, ds, hs, prec=fem.FP64)
+        vs = fem.residual_vjp(ms, ps, ds, hs, ls, prec=fem.FP64)
+        torch.cuda.synchronize()
+        Ri = o.R.cpu().numpy()
+        assert np.abs(R[3 * no[i]:3 * no[i + 1]] - Ri).max() <= 1e-12 * np.abs(Ri).max()
+        gi = vs.g_uniform[0].cpu().numpy()
+        assert np.abs(gu[i] - gi).max() <= 1e-12 * np.abs(gi).max()
+        ge = vs.g_elem.cpu().numpy()
+        assert np.abs(v.g_elem.cpu().numpy()[:, eo[i]:eo[i + 1]] - ge).max() <= 1e-12 * np.abs(ge).max()
+    # per-specimen VJP against the oracle for one specimen
+    s = specs[1]
+    og, _, _ = oracle.residual_vjp(s.X, s.conn, s.prm, s.d, s.hist_n, s.lam)
+    assert np.abs(gu[1] - og).max() <= TOL_FP64 * np.abs(og).max()
+
+
+def test_graph_replay_matches_eager(fem):
+    specs, m = batch_problem(fem, n=3, seed=4200)
+    mesh = fem.Mesh(m.X, m.conn)
+    csr = fem.csr_pattern(mesh)
+    params = fem.Params(m.meta["spec_prm"], m.n_elems, per_spec=True)
+    batch = fem.Batch(m.meta["elem_off"])
+    d = torch.as_tensor(m.d).cuda()
+    h = torch.as_tensor(m.hist_n).cuda()
+    lam = torch.as_tensor(m.lam).cuda()
+    for prec in (fem.FP64, fem.FP32_MIXED):
+        eager = fem.residual_tangent(mesh, csr, params, d, h, prec=prec, batch=batch)
+        ev = fem.residual_vjp(mesh, params, d, h, lam, prec=prec, batch=batch)
+        torch.cuda.synchronize()
+        R0, K0, g0 = eager.R.cpu().numpy(), eager.K.double().cpu().numpy(), ev.g_uniform.cpu().numpy()
+        stream = torch.cuda.Stream()
+        out = fem.Forward(mesh, csr, prec)
+        vout = fem.Vjp(mesh, batch.n_spec)
+        g = fem.Graph()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            with g.capture(stream):
+                fem.residual_tangent(mesh, csr, params, d, h, prec=prec, out=out, batch=batch, stream=stream)
+                fem.residual_vjp(mesh, params, d, h, lam, prec=prec, out=vout, batch=batch, stream=stream)
+        for rep in range(3):
+            out.R.fill_(7.0)  # eager work between replays
+            vout.g_uniform.fill_(3.0)
+            torch.cuda.synchronize()
+            g.replay(stream)
+            stream.synchronize()
+            tol = 1e-12 if prec == fem.FP64 else 1e-5
+            assert np.abs(out.R.cpu().numpy() - R0).max() <= tol * np.abs(R0).max()
+            assert np.abs(out.K.double().cpu().numpy() - K0).max() <= tol * np.abs(K0).max()
+            assert np.abs(vout.g_uniform.cpu().numpy() - g0).max() <= tol * np.abs(g0).max()
+
+
+def _node_rows_from_oracle(p, nodes, prm):
+    """R_I and the K rows of the given nodes, summed element by element with
+    the oracle over the elements around each node."""
+    res = {}
+    elems_of = {}
+    for n in nodes:
+        elems_of[n] = np.nonzero((p.conn == n).any(axis=1))[0]
+    for n in nodes:
+        R = np.zeros(3)
+        Krow = {}
+        for e in elems_of[n]:
+            he = p.hist_n[:, 8 * e:8 * e + 8].T
+            Re, Ke, _, _ = oracle.element(p.X[p.conn[e]], p.d[p.conn[e]], he, prm[e])
+            i = int(np.nonzero(p.conn[e] == n)[0][0])
+            R += Re[3 * i:3 * i + 3]
+            for j in range(8):
+                nj = int(p.conn[e, j])
+                Krow[nj] = Krow.get(nj, np.zeros((3, 3))) + Ke[3 * i:3 * i + 3, 3 * j:3 * j + 3]
+        res[n] = (R, Krow)
+    return res
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "mixed"])
+def test_large_cube_sampled_parity(fem, prec_name):
+    """Full 100^3 problem (1e6 elements, nnz 245,438,109) in the launch
+    configuration the benchmark uses; residual and tangent rows of sampled
+    nodes and the history of sampled Gauss points against the oracle."""
+    p = synth.large_cube()
+    prec = fem.FP64 if prec_name == "fp64" else fem.FP32_MIXED
+    say("large cube", prec_name)
+    mesh, params, d, h, bc, lam = gpu_problem(p, fem)
+    csr = fem.csr_pattern(mesh)
+    assert csr.nnz == 245438109
+    out = fem.residual_tangent(mesh, csr, params, d, h, prec=prec)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    nodes = list(rng.choice(p.n_nodes, 40, replace=False))
+    ref = _node_rows_from_oracle(p, nodes, p.prm)
+    rp = csr.row_ptr.cpu().numpy()
+    R = out.R.cpu().numpy()
+    tol = TOL_FP64 if prec == fem.FP64 else TOL_MIXED
+    Kscale = max(np.abs(Kr).max() for _, (_, kr) in ref.items() for Kr in kr.values())
+    Rscale = max(np.abs(r).max() for _, (r, _) in ref.items())
+    for n, (Rn, Krow) in ref.items():
+        assert np.abs(R[3 * n:3 * n + 3] - Rn).max() <= tol * Rscale
+        for a in range(3):
+            r = 3 * n + a
+            cols = csr.col_idx[rp[r]:rp[r + 1]].cpu().numpy()
+            vals = out.K[rp[r]:rp[r + 1]].double().cpu().numpy()
+            expect = np.zeros_like(vals)
+            for nj, blk in Krow.items():
+                for b in range(3):
+                    k = np.searchsorted(cols, 3 * nj + b)
+                    expect[k] = blk[a, b]
+            assert np.abs(vals - expect).max() <= tol * Kscale
+    # history of sampled Gauss points
+    q = rng.choice(8 * p.n_elems, 200, replace=False)
+    hn = out.hist.cpu().numpy()[:, q]
+    elems = q // 8
+    for i, qq in enumerate(q):
+        e, g = divmod(int(qq), 8)
+        _, _, hnp, _ = oracle.element(p.X[p.conn[e]], p.d[p.conn[e]], p.hist_n[:, 8 * e:8 * e + 8].T, p.prm[e],
+                                      want_K=False)
+        ref_h = hnp[g]
+        assert np.abs(hn[6, i] - ref_h[6]) <= tol * max(abs(ref_h[6]), 1e-3)
+        assert np.abs(hn[:6, i] - ref_h[:6]).max() <= tol * max(np.abs(ref_h[:6]).max(), 1e-4)
+    del elems
+    # plastic fraction at the trial state is the calibrated 30%
+    plastic = (out.hist.cpu().numpy()[6] != p.hist_n[6]).mean()
+    say("plastic fraction", plastic)
+    assert abs(plastic - 0.30) <= 0.005
