@@ -94,13 +94,18 @@ typedef struct {
  * for every node J sharing an element with I (I included), ascending.
  * elem_rank[64*e + 8*i + j] = position of node conn[e][j] in the sorted
  * neighbour list of node conn[e][i], so that K(3I+a, 3J+b) sits at
- * row_ptr[3I+a] + 3*rank + b. */
+ * row_ptr[3I+a] + 3*rank + b.  node_elem lists, for every node I, the
+ * conn entries 8*e + i with conn[e][i] = I, in ascending order, at
+ * [node_elem_ptr[I], node_elem_ptr[I+1]) (node -> element incidence used by
+ * the row-owner assembly). */
 typedef struct {
-    int32_t n_rows;     /* 3 * n_nodes */
-    int64_t nnz;        /* set by fem_csr_pattern */
-    int32_t *row_ptr;   /* device [n_rows + 1] */
-    int32_t *col_idx;   /* device [nnz] */
-    uint8_t *elem_rank; /* device [n_elems][64] */
+    int32_t n_rows;         /* 3 * n_nodes */
+    int64_t nnz;            /* set by fem_csr_pattern */
+    int32_t *row_ptr;       /* device [n_rows + 1] */
+    int32_t *col_idx;       /* device [nnz] */
+    uint8_t *elem_rank;     /* device [n_elems][64] */
+    int32_t *node_elem_ptr; /* device [n_nodes + 1] */
+    int32_t *node_elem;     /* device [8 * n_elems] */
 } fem_csr;
 
 /* Batched mode: n_spec specimens concatenated (node ids in conn already
@@ -133,7 +138,7 @@ int fem_get_launch(int kernel, fem_precision prec, fem_launch *cfg);
 
 /* Workspace bytes for each operation (host-only query, no GPU work). */
 size_t fem_csr_workspace_bytes(int32_t n_nodes, int32_t n_elems);
-size_t fem_forward_workspace_bytes(int32_t n_nodes, int32_t n_elems);
+size_t fem_forward_workspace_bytes(int32_t n_nodes, int32_t n_elems, fem_precision prec);
 size_t fem_vjp_workspace_bytes(int32_t n_elems, int32_t n_spec);
 
 /*
@@ -142,7 +147,9 @@ size_t fem_vjp_workspace_bytes(int32_t n_elems, int32_t n_spec);
  * Two calls:
  *   csr->col_idx == NULL : fills csr->row_ptr (device, [3*n_nodes+1]) and
  *                          csr->nnz; synchronises `stream` to read nnz back.
- *   csr->col_idx != NULL : fills col_idx [nnz] and, if non-NULL, elem_rank.
+ *   csr->col_idx != NULL : fills col_idx [nnz] and, if non-NULL, elem_rank,
+ *                          node_elem_ptr and node_elem (all three are needed
+ *                          by fem_residual_tangent).
  * ws: device workspace of at least fem_csr_workspace_bytes(n_nodes, n_elems)
  * bytes.  Errors: FEM_EINVAL (NULL pointers, negative sizes), FEM_ENOMEM,
  * FEM_EMESH (node id out of range, orphan node, more than 64 neighbours),
@@ -153,7 +160,13 @@ int fem_csr_pattern(const fem_mesh *mesh, fem_csr *csr, void *ws, size_t ws_byte
 /*
  * fem_residual_tangent -- one residual + tangent + assembly pass
  * (Sec. 2.2.4 element residual and stiffness, App. C Alg. C1/C2 at every
- * Gauss point, App. E row elimination).
+ * Gauss point, App. E row elimination).  Assembly is row-owner and
+ * write-once: the element kernel stores R^e and K^e in the workspace, and
+ * every entry of R and K is then written exactly once as the sum of its
+ * element contributions in ascending element order (no atomics, no prior
+ * zeroing, bitwise reproducible for any launch configuration).
+ *   csr      complete pattern of this mesh (row_ptr, col_idx, elem_rank,
+ *            node_elem_ptr, node_elem), also for a residual-only pass
  *   d        device [n_nodes][3] current displacement
  *   hist_n   device [7][8*n_elems] history of the last converged increment
  *   bc_mask  device [3*n_nodes] uint8 (1 = constrained dof) or NULL: rows of
@@ -161,13 +174,15 @@ int fem_csr_pattern(const fem_mesh *mesh, fem_csr *csr, void *ws, size_t ws_byte
  *   prec     FEM_FP64 or FEM_FP32_MIXED
  *   R        device [3*n_nodes] residual, or NULL (then rnorm2 must be NULL)
  *   K_vals   device [nnz] double (FEM_FP64) or float (FEM_FP32_MIXED), or NULL
- *            for a residual-only pass; requires csr->row_ptr/col_idx/elem_rank
+ *            for a residual-only pass
  *   hist_np1 device [7][8*n_elems] updated history for this d (never committed
  *            by the library), or NULL
  *   rnorm2   device [1] FP64 sum of R_i^2 after row elimination, or NULL
  *   diag     device [4] int32 counters (local Newton not converged, detJ0 <= 0,
  *            det F <= 0, non-finite values), or NULL
- *   ws       device workspace of fem_forward_workspace_bytes() bytes
+ *   ws       device workspace of fem_forward_workspace_bytes(n_nodes, n_elems,
+ *            prec) bytes (element residuals and tangents: 192 + 384*sizeof(K)
+ *            bytes per element)
  * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP.
  */
 int fem_residual_tangent(const fem_mesh *mesh, const fem_batch *batch, const fem_csr *csr,

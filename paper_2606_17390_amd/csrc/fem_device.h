@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace fem {
 
 constexpr double kSqrt2 = 1.41421356237309504880168872;
@@ -55,6 +57,28 @@ template <> struct Eps<float> {
     static constexpr float series = 0.02f;
     static constexpr int terms = 6;
 };
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
+template <int B, int E, typename Fn>
+__device__ inline void static_for(Fn&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// 4 consecutive values with vector stores (16-byte aligned destination)
+template <typename R>
+__device__ inline void store4(R* p, const R v[4]);
+template <>
+__device__ inline void store4<float>(float* p, const float v[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ inline void store4<double>(double* p, const double v[4]) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
 
 // ---------------------------------------------------------------- kinematics
 
@@ -413,16 +437,18 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
     }
     o.plastic = 1;
     const double mu2 = h.mu2;
-    // initial guess from the linearisation at lambda = 0
-    double dphi0 = 0.0;
+    // Newton on psi(lambda) = (1 + 2 mu etab lambda) g(lambda): the factor is
+    // positive, so psi and g share their root, and for a single active Hill
+    // mode with linear hardening psi is linear in lambda (one step).  etab is
+    // the trial-stress weighted mean Hill eigenvalue.
+    double num = 0.0;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) dphi0 -= mu2 * h.eta[i] * h.eta[i] * s[i] * s[i];
-    dphi0 /= phi_tr;
-    double lam = o.ftr / (-(dphi0 - dsig_n * phi_tr));
-    double lo = 0.0, hi = 1e300;
+    for (int i = 0; i < 5; ++i) num += h.eta[i] * h.eta[i] * s[i] * s[i];
+    const double etab = num / phi2;
+    double lam = 0.0, lo = 0.0, hi = __builtin_inf();
     double phi = phi_tr, sig = o.sy_n, dsig = dsig_n;
     int conv = 0;
-    for (int it = 0; it < 60; ++it) {
+    for (int it = 0; it < 40; ++it) {
         double p2 = 0.0, dp = 0.0;
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
@@ -433,20 +459,18 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
         }
         phi = sqrt(p2);
         dp /= phi;
-        sig = swift(m, o.hist[6] = alpha_n + lam * phi, dsig);
+        sig = swift(m, alpha_n + lam * phi, dsig);
         const double g = phi - sig;
-        const double gp = dp - dsig * (phi + lam * dp);
         if (g > 0.0) lo = lam; else hi = lam;
-        const double step = -g / gp;
-        // converged once the Newton step is at the rounding level of lambda
-        // (tested before the bracket, which a zero step would fail)
-        if (fabs(step) <= 2e-15 * lam || g == 0.0) {
-            lam += step;
-            conv = 1;
-            break;
-        }
+        // converged at the rounding level of sigma_y
+        if (fabs(g) <= 1e-15 * sig) { conv = 1; break; }
+        const double gp = dp - dsig * (phi + lam * dp);
+        const double f = 1.0 + mu2 * etab * lam;
+        const double step = -(f * g) / (mu2 * etab * g + f * gp);
         double ln = lam + step;
-        if (!(ln > lo && ln < hi)) ln = (hi < 1e299) ? 0.5 * (lo + hi) : 2.0 * lam + 1e-300;
+        if (!(ln > lo && ln < hi)) ln = (hi < __builtin_inf()) ? 0.5 * (lo + hi) : 2.0 * lam + 1e-300;
+        // step or bracket at the rounding level of lambda
+        if (fabs(ln - lam) <= 2e-15 * lam || hi - lo <= 4e-16 * lam) { lam = ln; conv = 1; break; }
         lam = ln;
     }
     // final state at lambda

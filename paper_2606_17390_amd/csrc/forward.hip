@@ -14,8 +14,15 @@
 //   R^e_Ia  = sum_g w detJ0 P_aA dN_I/dX_A,
 //   K^e_IaJb = sum_g w detJ0 dN_I/dX_A (delta_ab S_AB + F_aC C_CADB F_bD) dN_J/dX_B
 // are formed per Gauss point in the eigenframe (g^ = Q^T grad N, f^ = F Q),
-// summed over the 8 lanes of an element through LDS and scattered into the
-// fixed CSR pattern with hardware float atomics.
+// summed over the 8 lanes of an element through LDS and stored, with
+// coalesced vector stores, as the element's 24 residual entries and the 384
+// entries of its six (a <= b) component blocks in a workspace.
+//
+// Assembly (App. E, Alg. E1, without triplets or atomics): the owner of each
+// node gathers, in ascending element order, the blocks of the elements
+// around it and writes its three CSR rows (and residual entries) exactly
+// once, applying the Dirichlet row elimination on the fly; the FP64 residual
+// norm is reduced in two fixed-order stages.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -34,12 +41,10 @@ struct FwdArgs {
     uint32_t pe_mask, ps_mask;
     int32_t n_spec;
     const int64_t* elem_off;
-    const int32_t* row_ptr;
-    const uint8_t* elem_rank;
     const double* d;
     const double* hist_n;
-    double* R;
-    void* K;
+    double* Re;      // [n_elems][24] element residuals
+    void* Ke;        // [n_elems][384] element tangent blocks (R), or null
     double* hist_np1;
     int32_t* diag;
     int64_t n_gp;
@@ -128,23 +133,15 @@ __device__ inline void kin_and_log(const R xs[8][3], const R ds[8][3], int gp, G
     }
 }
 
-template <typename R>
-__device__ inline void atomic_add(R* p, R v) {
-    unsafeAtomicAdd(p, v);
-}
-
 template <typename R, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
     constexpr int EPB = BLOCK / 8;
     __shared__ double sXD[EPB][8][6];
-    __shared__ int32_t sRow[EPB][8];
-    __shared__ int32_t sLen[EPB][8];
-    __shared__ uint8_t sRank[EPB][64];
     __shared__ R red[32][BLOCK + 1];
 
     const int tid = threadIdx.x;
     const int slot = tid >> 3, gp = tid & 7;
-    const bool want_K = a.K != nullptr;
+    const bool want_K = a.Ke != nullptr;
     int32_t cnt_fail = 0, cnt_j0 = 0, cnt_jf = 0, cnt_nan = 0;
 
     int64_t t0, t1, ts;
@@ -168,13 +165,6 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
         sXD[slot][gp][3] = a.d[3 * (int64_t)node + 0];
         sXD[slot][gp][4] = a.d[3 * (int64_t)node + 1];
         sXD[slot][gp][5] = a.d[3 * (int64_t)node + 2];
-        if (want_K) {
-            const int32_t r0 = a.row_ptr[3 * (int64_t)node];
-            sRow[slot][gp] = r0;
-            sLen[slot][gp] = a.row_ptr[3 * (int64_t)node + 1] - r0;
-            const uint64_t rk = reinterpret_cast<const uint64_t*>(a.elem_rank)[q];
-            *reinterpret_cast<uint64_t*>(&sRank[slot][gp * 8]) = rk;
-        }
         double hn[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) hn[k] = a.hist_n[k * a.n_gp + q];
@@ -297,13 +287,15 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                 for (int i = 0; i < 3; ++i)
                     red[3 * I + i][tid] = Ph[i][0] * gh[I][0] + Ph[i][1] * gh[I][1] + Ph[i][2] * gh[I][2];
             __syncthreads();
-            if (valid && a.R) {
+            if (valid) {
+                // lane gp owns node gp of the element: R^e_{gp,0..2}
+                double* dst = a.Re + e * 24 + 3 * gp;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     R sum = R(0);
 #pragma unroll
                     for (int g2 = 0; g2 < 8; ++g2) sum += red[3 * gp + i][slot * 8 + g2];
-                    atomic_add<double>(a.R + 3 * (int64_t)node + i, (double)sum);
+                    dst[i] = (double)sum;
                 }
             }
             __syncthreads();
@@ -400,8 +392,8 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
             if (valid && !fin) ++cnt_nan;
 
             // ---- element tangent blocks (a <= b), reduced over the 8 Gauss points
-#pragma unroll
-            for (int aa = 0; aa < 3; ++aa) {
+            static_for<0, 3>([&](auto AA) {
+                constexpr int aa = decltype(AA)::value;
                 // Y[q][r][s] = sum_p f^_ap C4(p,q,r,s)
                 R Y[3][3][3];
 #pragma unroll
@@ -418,8 +410,8 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                             }
                             Y[qq][r][ss] = v;
                         }
-#pragma unroll
-                for (int bb = aa; bb < 3; ++bb) {
+                static_for<aa, 3>([&](auto BB) {
+                    constexpr int bb = decltype(BB)::value;
                     R Ah[3][3];
 #pragma unroll
                     for (int qq = 0; qq < 3; ++qq)
@@ -446,29 +438,25 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                             }
                         __syncthreads();
                         if (valid) {
-                            const int il = gp >> 1, I = 4 * half + il, jb = (gp & 1) * 4;
-                            const int64_t rowI = (int64_t)sRow[slot][I] + (int64_t)aa * sLen[slot][I];
+                            // lane gp sums block entries I = 4 half + gp/2, J = 4 (gp&1) + 0..3
+                            // and stores them at ((p*2 + half)*8 + gp)*4 of the element's 384
+                            const int il = gp >> 1, jb = (gp & 1) * 4;
+                            R v4[4];
 #pragma unroll
                             for (int j = 0; j < 4; ++j) {
-                                const int J = jb + j;
                                 R sum = R(0);
 #pragma unroll
-                                for (int g2 = 0; g2 < 8; ++g2) sum += red[il * 8 + J][slot * 8 + g2];
-                                R* Kp = reinterpret_cast<R*>(a.K);
-                                // a rank outside the row (pattern of another mesh) is skipped
-                                const int oIJ = 3 * (int)sRank[slot][I * 8 + J] + bb;
-                                if (oIJ < sLen[slot][I]) atomic_add<R>(Kp + rowI + oIJ, sum);
-                                if (bb != aa) {
-                                    const int64_t rowJ = (int64_t)sRow[slot][J] + (int64_t)bb * sLen[slot][J];
-                                    const int oJI = 3 * (int)sRank[slot][J * 8 + I] + aa;
-                                    if (oJI < sLen[slot][J]) atomic_add<R>(Kp + rowJ + oJI, sum);
-                                }
+                                for (int g2 = 0; g2 < 8; ++g2) sum += red[il * 8 + jb + j][slot * 8 + g2];
+                                v4[j] = sum;
                             }
+                            constexpr int pidx = aa * 3 - (aa * (aa - 1)) / 2 + (bb - aa);
+                            R* Kd = reinterpret_cast<R*>(a.Ke) + e * 384 + ((pidx * 2 + half) * 8 + gp) * 4;
+                            store4<R>(Kd, v4);
                         }
                         __syncthreads();
                     }
-                }
-            }
+                });
+            });
         }
         __syncthreads();
     }
@@ -480,33 +468,106 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
     }
 }
 
-// ---- epilogue: Dirichlet rows and residual norm
+// ---- row-owner assembly
 
-template <typename R>
-__global__ void dirichlet_rows(int32_t n_dof, const uint8_t* __restrict__ bc, double* __restrict__ Rv,
-                               const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                               R* __restrict__ K) {
-    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_dof || !bc[r]) return;
-    if (Rv) Rv[r] = 0.0;
-    if (K)
-        for (int32_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) K[p] = (col_idx[p] == r) ? R(1) : R(0);
+// Offset of K^e_{Ia,Jb} (a <= b) in an element's 384 stored block entries.
+__device__ inline int ke_offset(int p, int I, int J) {
+    return ((p * 2 + (I >> 2)) * 8 + (((I & 3) << 1) | (J >> 2))) * 4 + (J & 3);
+}
+__host__ __device__ constexpr int pair_index(int a, int b) { return a * 3 - (a * (a - 1)) / 2 + (b - a); }
+
+// R_I = sum over the elements around node I (ascending) of R^e_i; Dirichlet
+// rows zeroed; per-workgroup partial sums of R^2 for the norm.
+__global__ void assemble_residual(int32_t n_nodes, const int32_t* __restrict__ ne_ptr,
+                                  const int32_t* __restrict__ ne_list, const double* __restrict__ Re,
+                                  const uint8_t* __restrict__ bc, double* __restrict__ Rv,
+                                  double* __restrict__ part) {
+    __shared__ double sh[256];
+    const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (n < n_nodes) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int32_t k = ne_ptr[n]; k < ne_ptr[n + 1]; ++k) {
+            const int64_t v = ne_list[k];  // 8 e + i
+            const double* src = Re + (v >> 3) * 24 + 3 * (v & 7);
+            acc[0] += src[0];
+            acc[1] += src[1];
+            acc[2] += src[2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t dof = 3 * (int64_t)n + c;
+            const double val = (bc && bc[dof]) ? 0.0 : acc[c];
+            Rv[dof] = val;
+            sq += val * val;
+        }
+    }
+    if (part) {
+        sh[threadIdx.x] = sq;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    }
 }
 
-__global__ void norm_partial(const double* __restrict__ Rv, int64_t n, double* __restrict__ part) {
-    __shared__ double sh[kNormThreads];
-    double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double v = Rv[i];
-        s += v * v;
+// Rows 3I+a of K: 32 lanes per node, lane r owns column block r (node J = the
+// r-th neighbour) and sums, in ascending element order, the 3x3 blocks (i,j)
+// of the elements around I with elem_rank(i,j) = r.  Constrained rows become
+// identity rows.  Every entry of K is written exactly once.
+template <typename R>
+__global__ void assemble_tangent(int32_t n_nodes, const int32_t* __restrict__ ne_ptr,
+                                 const int32_t* __restrict__ ne_list, const uint8_t* __restrict__ elem_rank,
+                                 const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                                 const R* __restrict__ Ke, const uint8_t* __restrict__ bc, R* __restrict__ K) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = gid >> 5;
+    const int lane = (int)(gid & 31);
+    if (n >= n_nodes) return;
+    const int32_t rs = row_ptr[3 * n];
+    const int32_t len = row_ptr[3 * n + 1] - rs;  // 3 deg
+    const int deg = len / 3;
+    const int32_t k0 = ne_ptr[n], k1 = ne_ptr[n + 1];
+    for (int r = lane; r < deg; r += 32) {
+        R acc[3][3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int y = 0; y < 3; ++y) acc[x][y] = R(0);
+        for (int32_t k = k0; k < k1; ++k) {
+            const int64_t v = ne_list[k];
+            const int64_t e = v >> 3;
+            const int i = (int)(v & 7);
+            const uint64_t rk = reinterpret_cast<const uint64_t*>(elem_rank)[v];
+            const R* blk = Ke + e * 384;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if ((int)((rk >> (8 * j)) & 0xffu) != r) continue;
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+                    for (int bb = 0; bb < 3; ++bb) {
+                        const int off = (aa <= bb) ? ke_offset(pair_index(aa, bb), i, j)
+                                                   : ke_offset(pair_index(bb, aa), j, i);
+                        acc[aa][bb] += blk[off];
+                    }
+            }
+        }
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa) {
+            const int64_t row = 3 * n + aa;
+            const int64_t o = (int64_t)rs + aa * len + 3 * r;
+            if (bc && bc[row]) {
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) K[o + bb] = (col_idx[o + bb] == row) ? R(1) : R(0);
+            } else {
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) K[o + bb] = acc[aa][bb];
+            }
+        }
     }
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = kNormThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
 __global__ void norm_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
@@ -537,15 +598,42 @@ hipError_t launch_fwd_block(const FwdArgs& a, int block, int grid, hipStream_t s
     }
 }
 
+constexpr int kAsmThreads = 256;
+
+struct FwdWs {
+    double* Re;
+    void* Ke;
+    double* part;
+};
+
+template <typename C>
+void carve_forward(C& c, int32_t n_nodes, int32_t n_elems, fem_precision prec, FwdWs* w) {
+    const size_t kb = (prec == FEM_FP64) ? sizeof(double) : sizeof(float);
+    auto re = c.template take<double>((size_t)n_elems * 24 + 1);
+    auto ke = c.template take<char>((size_t)n_elems * 384 * kb + 16);
+    auto pa = c.template take<double>((size_t)n_nodes / kAsmThreads + 2);
+    if (w) *w = FwdWs{re, (void*)ke, pa};
+}
+
+struct CountAdapterF {
+    WsCounter cnt;
+    template <typename T>
+    T* take(size_t n) {
+        cnt.take<T>(n);
+        return nullptr;
+    }
+};
+
 }  // namespace
 }  // namespace fem
 
 using namespace fem;
 
-extern "C" size_t fem_forward_workspace_bytes(int32_t n_nodes, int32_t n_elems) {
-    (void)n_nodes;
-    (void)n_elems;
-    return (size_t)kNormBlocks * sizeof(double) + 256;
+extern "C" size_t fem_forward_workspace_bytes(int32_t n_nodes, int32_t n_elems, fem_precision prec) {
+    if (n_nodes < 0 || n_elems < 0) return 0;
+    CountAdapterF c;
+    carve_forward(c, n_nodes, n_elems, prec, (FwdWs*)nullptr);
+    return c.cnt.used + 256;
 }
 
 extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch, const fem_csr* csr,
@@ -562,9 +650,12 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
     if (rnorm2 && !R && n_dof > 0) return set_error(FEM_EINVAL, "fem_residual_tangent: rnorm2 requires R");
     if (ne > 0 && (!mesh->X || !mesh->conn || !d || !hist_n))
         return set_error(FEM_EINVAL, "fem_residual_tangent: X, conn, d and hist_n must not be NULL");
-    if (K_vals && (!csr || !csr->row_ptr || !csr->col_idx || !csr->elem_rank))
+    const bool assemble = (R || K_vals) && n_dof > 0;
+    if (assemble && (!csr || !csr->row_ptr || !csr->node_elem_ptr || !csr->node_elem))
+        return set_error(FEM_EINVAL, "fem_residual_tangent: assembly needs csr row_ptr and the node incidence");
+    if (K_vals && (!csr->col_idx || !csr->elem_rank))
         return set_error(FEM_EINVAL, "fem_residual_tangent: K_vals requires a complete CSR pattern");
-    if (K_vals && csr->n_rows != n_dof)
+    if (assemble && csr->n_rows != n_dof)
         return set_error(FEM_EINVAL, "fem_residual_tangent: csr->n_rows = %d, expected %lld", csr->n_rows,
                          (long long)n_dof);
     for (int k = 0; k < FEM_NPARAM; ++k)
@@ -573,13 +664,14 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         return set_error(FEM_EINVAL, "fem_residual_tangent: per-specimen parameters need a batch");
     if (batch && (batch->n_spec < 1 || !batch->elem_off))
         return set_error(FEM_EINVAL, "fem_residual_tangent: invalid batch");
-    if (rnorm2 && (!ws || ws_bytes < fem_forward_workspace_bytes(mesh->n_nodes, mesh->n_elems)))
-        return set_error(FEM_ENOMEM, "fem_residual_tangent: workspace of %zu bytes required",
-                         fem_forward_workspace_bytes(mesh->n_nodes, mesh->n_elems));
+    const size_t need = fem_forward_workspace_bytes(mesh->n_nodes, mesh->n_elems, prec);
+    if (!ws || ws_bytes < need)
+        return set_error(FEM_ENOMEM, "fem_residual_tangent: workspace of %zu bytes required, %zu given", need,
+                         ws_bytes);
     hipStream_t s = (hipStream_t)stream;
-    const size_t kb = (prec == FEM_FP64) ? sizeof(double) : sizeof(float);
-    if (R) FEM_HIP_CHECK(zero_bytes(R, sizeof(double) * n_dof, s));
-    if (K_vals) FEM_HIP_CHECK(zero_bytes(K_vals, kb * (size_t)csr->nnz, s));
+    WsCarver cv(ws, ws_bytes);
+    FwdWs w;
+    carve_forward(cv, mesh->n_nodes, mesh->n_elems, prec, &w);
     if (diag) FEM_HIP_CHECK(zero_bytes(diag, 4 * sizeof(int32_t), s));
 
     if (ne > 0) {
@@ -594,12 +686,10 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         a.ps_mask = params->per_spec_mask & ~params->per_elem_mask;
         a.n_spec = batch ? batch->n_spec : 1;
         a.elem_off = batch ? batch->elem_off : nullptr;
-        a.row_ptr = csr ? csr->row_ptr : nullptr;
-        a.elem_rank = csr ? csr->elem_rank : nullptr;
         a.d = d;
         a.hist_n = hist_n;
-        a.R = R;
-        a.K = K_vals;
+        a.Re = w.Re;
+        a.Ke = K_vals ? w.Ke : nullptr;
         a.hist_np1 = hist_np1;
         a.diag = diag;
         a.n_gp = 8 * ne;
@@ -612,24 +702,33 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
                                           : launch_fwd_block<float>(a, cfg.block, grid, s);
         timing_end(tk, FEM_KERNEL_FORWARD, s);
         if (e != hipSuccess) return set_error(FEM_EHIP, "forward kernel launch failed: %s", hipGetErrorString(e));
+    } else if (assemble) {
+        // no elements: every residual entry and K entry is zero (or an identity row)
+        FEM_HIP_CHECK(zero_bytes(w.Re, sizeof(double) * 24, s));
     }
-    if (bc_mask && n_dof > 0 && (R || K_vals)) {
-        const int T = 256;
-        const unsigned nbk = (unsigned)((n_dof + T - 1) / T);
-        if (prec == FEM_FP64)
-            hipLaunchKernelGGL(dirichlet_rows<double>, dim3(nbk), dim3(T), 0, s, (int32_t)n_dof, bc_mask, R,
-                               csr ? csr->row_ptr : nullptr, csr ? csr->col_idx : nullptr,
-                               reinterpret_cast<double*>(K_vals));
-        else
-            hipLaunchKernelGGL(dirichlet_rows<float>, dim3(nbk), dim3(T), 0, s, (int32_t)n_dof, bc_mask, R,
-                               csr ? csr->row_ptr : nullptr, csr ? csr->col_idx : nullptr,
-                               reinterpret_cast<float*>(K_vals));
+    const int nn = mesh->n_nodes;
+    if (R && nn > 0) {
+        const unsigned nb = (unsigned)((nn + kAsmThreads - 1) / kAsmThreads);
+        hipLaunchKernelGGL(assemble_residual, dim3(nb), dim3(kAsmThreads), 0, s, nn, csr->node_elem_ptr,
+                           csr->node_elem, w.Re, bc_mask, R, rnorm2 ? w.part : nullptr);
         FEM_HIP_CHECK(hipGetLastError());
+        if (rnorm2) {
+            hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormThreads), 0, s, w.part, (int)nb, rnorm2);
+            FEM_HIP_CHECK(hipGetLastError());
+        }
+    } else if (rnorm2) {
+        FEM_HIP_CHECK(zero_bytes(rnorm2, sizeof(double), s));
     }
-    if (rnorm2) {
-        double* part = reinterpret_cast<double*>(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        hipLaunchKernelGGL(norm_partial, dim3(kNormBlocks), dim3(kNormThreads), 0, s, R, n_dof, part);
-        hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormThreads), 0, s, part, kNormBlocks, rnorm2);
+    if (K_vals && nn > 0 && csr->nnz > 0) {
+        const unsigned nb = (unsigned)(((int64_t)nn * 32 + kAsmThreads - 1) / kAsmThreads);
+        if (prec == FEM_FP64)
+            hipLaunchKernelGGL(assemble_tangent<double>, dim3(nb), dim3(kAsmThreads), 0, s, nn, csr->node_elem_ptr,
+                               csr->node_elem, csr->elem_rank, csr->row_ptr, csr->col_idx,
+                               reinterpret_cast<const double*>(w.Ke), bc_mask, reinterpret_cast<double*>(K_vals));
+        else
+            hipLaunchKernelGGL(assemble_tangent<float>, dim3(nb), dim3(kAsmThreads), 0, s, nn, csr->node_elem_ptr,
+                               csr->node_elem, csr->elem_rank, csr->row_ptr, csr->col_idx,
+                               reinterpret_cast<const float*>(w.Ke), bc_mask, reinterpret_cast<float*>(K_vals));
         FEM_HIP_CHECK(hipGetLastError());
     }
     return FEM_OK;

@@ -42,7 +42,7 @@ __global__ void fill_incidence(const int32_t* __restrict__ conn, int64_t n_entri
     const int32_t n = conn[i];
     if (n < 0 || n >= n_nodes) return;
     const int32_t pos = atomicAdd(&fillc[n], 1);
-    inc[inc_ptr[n] + pos] = (int32_t)(i >> 3);
+    inc[inc_ptr[n] + pos] = (int32_t)i;  // conn entry 8e + local index
 }
 
 // Sorted unique neighbour list of node n (n included).  Returns the count or
@@ -51,7 +51,7 @@ __device__ int node_neighbours(int32_t n, const int32_t* __restrict__ conn, cons
                                const int32_t* __restrict__ inc, int32_t* nb) {
     int cnt = 0;
     for (int64_t k = inc_ptr[n]; k < inc_ptr[n + 1]; ++k) {
-        const int64_t e = inc[k];
+        const int64_t e = inc[k] >> 3;
         for (int j = 0; j < 8; ++j) {
             const int32_t v = conn[e * 8 + j];
             // insertion into the sorted list
@@ -97,6 +97,26 @@ __global__ void node_columns(int32_t n_nodes, const int32_t* __restrict__ conn, 
             row[3 * k + 1] = 3 * nb[k] + 1;
             row[3 * k + 2] = 3 * nb[k] + 2;
         }
+    }
+}
+
+// node -> conn-entry incidence in ascending order (deterministic assembly)
+__global__ void write_incidence(int32_t n_nodes, const int64_t* __restrict__ inc_ptr,
+                                const int32_t* __restrict__ inc, int32_t* __restrict__ out_ptr,
+                                int32_t* __restrict__ out) {
+    const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > n_nodes) return;
+    out_ptr[n] = (int32_t)inc_ptr[n];
+    if (n == n_nodes) return;
+    const int64_t b = inc_ptr[n], e = inc_ptr[n + 1];
+    for (int64_t k = b; k < e; ++k) {
+        const int32_t v = inc[k];
+        int64_t p = k;
+        while (p > b && out[p - 1] > v) {
+            out[p] = out[p - 1];
+            --p;
+        }
+        out[p] = v;
     }
 }
 
@@ -296,8 +316,8 @@ extern "C" int fem_csr_pattern(const fem_mesh* mesh, fem_csr* csr, void* ws, siz
         return set_error(FEM_EINVAL, "fem_csr_pattern: negative sizes");
     if ((mesh->n_elems > 0 && !mesh->conn) || !csr->row_ptr)
         return set_error(FEM_EINVAL, "fem_csr_pattern: conn and row_ptr must not be NULL");
-    if ((int64_t)mesh->n_nodes * 3 >= INT32_MAX)
-        return set_error(FEM_EOVERFLOW, "fem_csr_pattern: 3*n_nodes does not fit in int32");
+    if ((int64_t)mesh->n_nodes * 3 >= INT32_MAX || (int64_t)mesh->n_elems * 8 >= INT32_MAX)
+        return set_error(FEM_EOVERFLOW, "fem_csr_pattern: 3*n_nodes or 8*n_elems does not fit in int32");
     hipStream_t s = (hipStream_t)stream;
     const size_t need = fem_csr_workspace_bytes(mesh->n_nodes, mesh->n_elems);
     if (!ws || ws_bytes < need)
@@ -331,6 +351,9 @@ extern "C" int fem_csr_pattern(const fem_mesh* mesh, fem_csr* csr, void* ws, siz
         hipLaunchKernelGGL(node_columns, dim3((unsigned)((nn + T - 1) / T)), dim3(T), 0, s, nn, mesh->conn, w.inc_ptr,
                            w.inc, csr->row_ptr, csr->col_idx);
     const int64_t ne8 = (int64_t)mesh->n_elems * 8;
+    if (csr->node_elem_ptr && csr->node_elem)
+        hipLaunchKernelGGL(write_incidence, dim3((unsigned)((nn + 1 + T - 1) / T)), dim3(T), 0, s, nn, w.inc_ptr,
+                           w.inc, csr->node_elem_ptr, csr->node_elem);
     if (csr->elem_rank && ne8 > 0)
         hipLaunchKernelGGL(element_rank, dim3((unsigned)((ne8 + T - 1) / T)), dim3(T), 0, s, mesh->n_elems,
                            mesh->conn, csr->row_ptr, csr->col_idx, csr->elem_rank);

@@ -31,7 +31,8 @@ class FemParams(ctypes.Structure):
 
 
 class FemCsr(ctypes.Structure):
-    _fields_ = [("n_rows", _c_i32), ("nnz", _c_i64), ("row_ptr", _c_p), ("col_idx", _c_p), ("elem_rank", _c_p)]
+    _fields_ = [("n_rows", _c_i32), ("nnz", _c_i64), ("row_ptr", _c_p), ("col_idx", _c_p), ("elem_rank", _c_p),
+                ("node_elem_ptr", _c_p), ("node_elem", _c_p)]
 
 
 class FemBatch(ctypes.Structure):
@@ -70,7 +71,7 @@ def lib():
     L.fem_get_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(FemLaunch)]
     L.fem_csr_workspace_bytes.argtypes = [_c_i32, _c_i32]
     L.fem_csr_workspace_bytes.restype = _c_sz
-    L.fem_forward_workspace_bytes.argtypes = [_c_i32, _c_i32]
+    L.fem_forward_workspace_bytes.argtypes = [_c_i32, _c_i32, ctypes.c_int]
     L.fem_forward_workspace_bytes.restype = _c_sz
     L.fem_vjp_workspace_bytes.argtypes = [_c_i32, _c_i32]
     L.fem_vjp_workspace_bytes.restype = _c_sz
@@ -160,6 +161,13 @@ class Mesh:
         self.n_nodes = int(self.X.shape[0])
         self.n_elems = int(self.conn.shape[0])
         self.device = self.X.device
+        self._pattern = None
+
+    def pattern(self):
+        """The CSR pattern of this mesh (built on first use, then cached)."""
+        if self._pattern is None:
+            self._pattern = csr_pattern(self)
+        return self._pattern
 
     def c(self):
         return FemMesh(self.n_nodes, self.n_elems, _ptr(self.X) if self.X.numel() else None,
@@ -215,13 +223,15 @@ class Batch:
 
 
 class Csr:
-    def __init__(self, row_ptr, col_idx, elem_rank, nnz, n_rows):
+    def __init__(self, row_ptr, col_idx, elem_rank, nnz, n_rows, node_elem_ptr, node_elem):
         self.row_ptr, self.col_idx, self.elem_rank = row_ptr, col_idx, elem_rank
+        self.node_elem_ptr, self.node_elem = node_elem_ptr, node_elem
         self.nnz, self.n_rows = nnz, n_rows
 
     def c(self):
         return FemCsr(self.n_rows, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx) if self.nnz else None,
-                      _ptr(self.elem_rank) if self.elem_rank is not None and self.elem_rank.numel() else None)
+                      _ptr(self.elem_rank) if self.elem_rank is not None and self.elem_rank.numel() else None,
+                      _ptr(self.node_elem_ptr), _ptr(self.node_elem) if self.node_elem.numel() else None)
 
 
 def _ws(nbytes, device):
@@ -242,11 +252,16 @@ def csr_pattern(mesh, stream=None):
     nnz = int(c.nnz)
     col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
     elem_rank = torch.empty((max(mesh.n_elems, 1), 64), dtype=torch.uint8, device=dev)
+    ne_ptr = torch.zeros(mesh.n_nodes + 1, dtype=torch.int32, device=dev)
+    ne_list = torch.empty(max(8 * mesh.n_elems, 1), dtype=torch.int32, device=dev)
     c.col_idx = col_idx.data_ptr()
     c.elem_rank = elem_rank.data_ptr()
+    c.node_elem_ptr = ne_ptr.data_ptr()
+    c.node_elem = ne_list.data_ptr()
     if nnz:
         _check("fem_csr_pattern", L.fem_csr_pattern(ctypes.byref(cm), ctypes.byref(c), _ptr(ws), ws_bytes, s))
-    return Csr(row_ptr, col_idx[:nnz], elem_rank[:mesh.n_elems], nnz, 3 * mesh.n_nodes)
+    return Csr(row_ptr, col_idx[:nnz], elem_rank[:mesh.n_elems], nnz, 3 * mesh.n_nodes, ne_ptr,
+               ne_list[:8 * mesh.n_elems])
 
 
 class Forward:
@@ -262,15 +277,21 @@ class Forward:
         self.hist = torch.empty((7, 8 * mesh.n_elems), dtype=torch.float64, device=dev) if want_hist else None
         self.rnorm2 = torch.empty(1, dtype=torch.float64, device=dev) if want_norm else None
         self.diag = torch.empty(4, dtype=torch.int32, device=dev)
-        nb = lib().fem_forward_workspace_bytes(mesh.n_nodes, mesh.n_elems)
+        nb = lib().fem_forward_workspace_bytes(mesh.n_nodes, mesh.n_elems, self.prec)
         self.ws = _ws(nb, dev)
         self.ws_bytes = nb
 
 
 def residual_tangent(mesh, csr, params, d, hist_n, bc_mask=None, prec=FP64, out=None, batch=None,
                      want_K=True, want_hist=True, stream=None):
-    """One residual + tangent + CSR assembly pass; returns the Forward buffers."""
+    """One residual + tangent + CSR assembly pass; returns the Forward buffers.
+    With csr None the mesh's cached pattern is used (it carries the node
+    incidence the assembly needs); K is then not requested."""
     L = lib()
+    if csr is None:
+        want_K = False
+        if out is None or out.R is not None:
+            csr = mesh.pattern()
     if out is None:
         out = Forward(mesh, csr, prec, want_K=want_K, want_hist=want_hist)
     cm, cp = mesh.c(), params.c()
@@ -279,7 +300,8 @@ def residual_tangent(mesh, csr, params, d, hist_n, bc_mask=None, prec=FP64, out=
     rc = L.fem_residual_tangent(ctypes.byref(cm), ctypes.byref(cb) if cb is not None else None,
                                 ctypes.byref(cc) if cc is not None else None, ctypes.byref(cp), _ptr(d), _ptr(hist_n),
                                 _ptr(bc_mask), out.prec, _ptr(out.R),
-                                _ptr(out.K) if (out.K is not None and csr is not None and csr.nnz) else None,
+                                _ptr(out.K) if (want_K and out.K is not None and csr is not None and csr.nnz)
+                                else None,
                                 _ptr(out.hist), _ptr(out.rnorm2), _ptr(out.diag), _ptr(out.ws), out.ws_bytes,
                                 _stream(stream))
     _check("fem_residual_tangent", rc)

@@ -1,0 +1,91 @@
+"""The C ABI library loads on a host without a GPU, exports every function
+declared in include/fem.h, and rejects invalid arguments before touching the
+device (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fem.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fem_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2606_17390_amd import fem
+    return fem.lib()
+
+
+def test_header_declares_the_three_calls():
+    names = declared_functions()
+    for f in ("fem_csr_pattern", "fem_residual_tangent", "fem_residual_vjp"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_lists_every_export():
+    from paper_2606_17390_amd import fem
+    assert sorted(fem.EXPORTS) == declared_functions()
+
+
+def test_version_and_workspace_queries(lib):
+    assert lib.fem_version() >= 100
+    assert lib.fem_csr_workspace_bytes(125, 64) > 0
+    assert lib.fem_csr_workspace_bytes(-1, 0) == 0
+    assert lib.fem_forward_workspace_bytes(125, 64, 1) >= 64 * (24 * 8 + 384 * 4)
+    assert lib.fem_forward_workspace_bytes(125, 64, 0) >= 64 * (24 * 8 + 384 * 8)
+    assert lib.fem_vjp_workspace_bytes(64, 1) >= 7 * 64 * 8
+
+
+def test_invalid_arguments_are_rejected_on_the_host(lib):
+    from paper_2606_17390_amd import fem
+    assert lib.fem_csr_pattern(None, None, None, 0, None) == fem.FEM_EINVAL
+    assert b"must not be NULL" in lib.fem_last_error()
+    rc = lib.fem_residual_tangent(None, None, None, None, None, None, None, 0, None, None, None, None, None,
+                                  None, 0, None)
+    assert rc == fem.FEM_EINVAL
+    rc = lib.fem_residual_vjp(None, None, None, None, None, None, 0, None, None, None, None, 0, None)
+    assert rc == fem.FEM_EINVAL
+    # negative sizes
+    m = fem.FemMesh(-1, 0, None, None)
+    c = fem.FemCsr(0, 0, None, None, None, None, None)
+    assert lib.fem_csr_pattern(ctypes.byref(m), ctypes.byref(c), None, 0, None) == fem.FEM_EINVAL
+    # bad precision with otherwise empty problem
+    m = fem.FemMesh(0, 0, None, None)
+    p = fem.FemParams()
+    assert lib.fem_residual_tangent(ctypes.byref(m), None, None, ctypes.byref(p), None, None, None, 9, None,
+                                    None, None, None, None, None, 0, None) == fem.FEM_EINVAL
+
+
+def test_launch_configuration_round_trip(lib):
+    from paper_2606_17390_amd import fem
+    cfg = fem.FemLaunch(256, 4, 0)
+    assert lib.fem_set_launch(0, 1, ctypes.byref(cfg)) == fem.FEM_OK
+    got = fem.FemLaunch()
+    assert lib.fem_get_launch(0, 1, ctypes.byref(got)) == fem.FEM_OK
+    assert (got.block, got.waves_per_cu, got.xcd_remap) == (256, 4, 0)
+    assert lib.fem_set_launch(0, 1, None) == fem.FEM_OK
+    bad = fem.FemLaunch(96, 4, 0)
+    assert lib.fem_set_launch(0, 1, ctypes.byref(bad)) == fem.FEM_EINVAL
+    assert lib.fem_set_launch(5, 1, None) == fem.FEM_EINVAL
+
+
+def test_product_path_does_not_import_the_oracle():
+    """The binding, kernels and bench's timed path never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_2606_17390_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "oracle." not in txt.replace("the oracle", ""), f
