@@ -146,6 +146,68 @@ __device__ inline void kinematics(const R xs[8][3], const R ds[8][3], int gp, R 
         }
 }
 
+// Same as kinematics(), reading the element's node coordinates and
+// displacements (nd[I][0..2] = X_I, nd[I][3..5] = d_I, FP64 in LDS) as they
+// are needed, relative to node 0.
+template <typename R, int W>
+__device__ inline void kinematics_lds(const double (*nd)[W], int gp, R g[8][3], R& detJ, R Hd[3][3]) {
+    const R r = R(kInvSqrt3);
+    const R xi = (gp & 1) ? r : -r, eta = (gp & 2) ? r : -r, zeta = (gp & 4) ? r : -r;
+    R dN[8][3];
+#pragma unroll
+    for (int I = 0; I < 8; ++I) {
+        const R a = R(1) + R(sgx(I)) * xi, b = R(1) + R(sgy(I)) * eta, c = R(1) + R(sgz(I)) * zeta;
+        dN[I][0] = R(0.125) * R(sgx(I)) * b * c;
+        dN[I][1] = R(0.125) * a * R(sgy(I)) * c;
+        dN[I][2] = R(0.125) * a * b * R(sgz(I));
+    }
+    R J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double x0 = nd[0][i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) J[i][j] = R(0);
+#pragma unroll
+        for (int I = 1; I < 8; ++I) {
+            const R x = (R)(nd[I][i] - x0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) J[i][j] += x * dN[I][j];
+        }
+    }
+    const R c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const R c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const R c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    detJ = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const R id = R(1) / detJ;
+    R Ji[3][3];
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int A = 0; A < 3; ++A) Hd[a][A] = R(0);
+#pragma unroll
+    for (int I = 0; I < 8; ++I) {
+#pragma unroll
+        for (int A = 0; A < 3; ++A) g[I][A] = Ji[0][A] * dN[I][0] + Ji[1][A] * dN[I][1] + Ji[2][A] * dN[I][2];
+        if (I > 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R dv = (R)(nd[I][3 + a] - nd[0][3 + a]);
+#pragma unroll
+                for (int A = 0; A < 3; ++A) Hd[a][A] += dv * g[I][A];
+            }
+        }
+    }
+}
+
 // C - I = H + H^T + H^T H
 template <typename R>
 __device__ inline void cauchy_green_minus_identity(const R H[3][3], R M[3][3]) {

@@ -50,6 +50,10 @@ struct FwdArgs {
     int64_t n_gp;
     int64_t n_tiles;
     int32_t xcd_remap;
+    // mixed precision: elements with a Gauss point in the guard band are
+    // appended here by the FP32 kernel and recomputed by the FP64 kernel
+    int32_t* fix_list;
+    int32_t* fix_count;
 };
 
 // specimen of element e (elem_off has n_spec + 1 prefix entries)
@@ -118,8 +122,8 @@ struct GP {
 };
 
 template <typename R>
-__device__ inline void kin_and_log(const R xs[8][3], const R ds[8][3], int gp, GP<R>& s, double eps[6]) {
-    kinematics<R>(xs, ds, gp, s.g, s.detJ, s.H);
+__device__ inline void kin_and_log(const double (*nd)[6], int gp, GP<R>& s, double eps[6]) {
+    kinematics_lds<R, 6>(nd, gp, s.g, s.detJ, s.H);
     R M[3][3];
     cauchy_green_minus_identity<R>(s.H, M);
     eig_sym3<R>(M, s.mu, s.Q);
@@ -133,11 +137,16 @@ __device__ inline void kin_and_log(const R xs[8][3], const R ds[8][3], int gp, G
     }
 }
 
-template <typename R, int BLOCK>
+// R: working type of kinematics, pull-back and contraction; RO: type of the
+// stored element tangent blocks; FIXUP: walk the element list of the guard
+// band instead of all elements (FP64 recomputation for the mixed path).
+template <typename R, typename RO, int BLOCK, bool FIXUP>
 __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
     constexpr int EPB = BLOCK / 8;
+    constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
     __shared__ double sXD[EPB][8][6];
     __shared__ R red[32][BLOCK + 1];
+    __shared__ int sFlag[EPB];
 
     const int tid = threadIdx.x;
     const int slot = tid >> 3, gp = tid & 7;
@@ -145,12 +154,23 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
     int32_t cnt_fail = 0, cnt_j0 = 0, cnt_jf = 0, cnt_nan = 0;
 
     int64_t t0, t1, ts;
-    tile_range(a.n_tiles, a.xcd_remap, t0, t1, ts);
+    int64_t n_work = a.n_elems;
+    if constexpr (FIXUP) {
+        n_work = *a.fix_count;
+        t0 = blockIdx.x;
+        t1 = (n_work + EPB - 1) / EPB;
+        ts = gridDim.x;
+    } else {
+        tile_range(a.n_tiles, a.xcd_remap, t0, t1, ts);
+    }
     for (int64_t tile = t0; tile < t1; tile += ts) {
         const int64_t e_raw = tile * EPB + slot;
-        const bool valid = e_raw < a.n_elems;
-        const int64_t e = valid ? e_raw : (int64_t)a.n_elems - 1;
+        const bool valid = e_raw < n_work;
+        int64_t e;
+        if constexpr (FIXUP) e = a.fix_list[valid ? e_raw : 0];
+        else e = valid ? e_raw : (int64_t)a.n_elems - 1;
         const int64_t q = e * 8 + gp;
+        if (FLAG && gp == 0) sFlag[slot] = 0;
 
         // ---- gather (own node through LDS); an out-of-range node id is
         // replaced by node 0 and counted, so no access leaves its buffer
@@ -174,50 +194,18 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
         // ---- kinematics, log strain (R), local update (double)
         GP<R> s;
         double eps[6];
-        {
-            R xs[8][3], ds[8][3];
-#pragma unroll
-            for (int I = 0; I < 8; ++I)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xs[I][c] = (R)(sXD[slot][I][c] - sXD[slot][0][c]);
-                    ds[I][c] = (R)(sXD[slot][I][3 + c] - sXD[slot][0][3 + c]);
-                }
-            kin_and_log<R>(xs, ds, gp, s, eps);
-        }
+        kin_and_log<R>(sXD[slot], gp, s, eps);
         Modes md;
         hill_modes(mat, md);
         Local loc;
         local_update(eps, hn, mat, md, loc);
-        if constexpr (std::is_same<R, float>::value) {
+        if constexpr (FLAG) {
             // guard band: a trial state this close to the yield surface is
-            // re-evaluated with FP64 kinematics so that the elastic/plastic
-            // decision and the stress are those of the FP64 path
-            if (fabs(loc.ftr) < 2e-4 * loc.sy_n) {
-                GP<double> sd;
-                double xs[8][3], ds[8][3];
-#pragma unroll
-                for (int I = 0; I < 8; ++I)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        xs[I][c] = sXD[slot][I][c] - sXD[slot][0][c];
-                        ds[I][c] = sXD[slot][I][3 + c] - sXD[slot][0][3 + c];
-                    }
-                kin_and_log<double>(xs, ds, gp, sd, eps);
-                local_update(eps, hn, mat, md, loc);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    s.mu[i] = (R)sd.mu[i];
-                    s.eh[i] = (R)sd.eh[i];
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        s.Q[i][j] = (R)sd.Q[i][j];
-                        s.H[i][j] = (R)sd.H[i][j];
-                    }
-                }
-            }
+            // left to the FP64 recomputation of its element, so that the
+            // elastic/plastic decision and the stress are those of FP64
+            if (valid && fabs(loc.ftr) < 2e-4 * loc.sy_n) sFlag[slot] = 1;
         }
-        if (valid) {
+        if (valid && !FIXUP) {
             cnt_fail += loc.converged ? 0 : 1;
             cnt_j0 += (s.detJ <= R(0)) ? 1 : 0;
             R F[3][3];
@@ -229,10 +217,10 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                            F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
                            F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
             cnt_jf += (detF <= R(0)) ? 1 : 0;
-            if (a.hist_np1) {
+        }
+        if (valid && a.hist_np1) {
 #pragma unroll
-                for (int k = 0; k < 7; ++k) a.hist_np1[k * a.n_gp + q] = loc.hist[k];
-            }
+            for (int k = 0; k < 7; ++k) a.hist_np1[k * a.n_gp + q] = loc.hist[k];
         }
 
         // ---- pull-back in the eigenframe of C
@@ -280,7 +268,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                     Ph[i][p] = wdet * (fh[i][0] * Sh[0][p] + fh[i][1] * Sh[1][p] + fh[i][2] * Sh[2][p]);
                     fin = fin && isfinite((double)Ph[i][p]);
                 }
-            if (valid && !fin) ++cnt_nan;
+            if (valid && !fin && !FIXUP) ++cnt_nan;
 #pragma unroll
             for (int I = 0; I < 8; ++I)
 #pragma unroll
@@ -296,6 +284,9 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
 #pragma unroll
                     for (int g2 = 0; g2 < 8; ++g2) sum += red[3 * gp + i][slot * 8 + g2];
                     dst[i] = (double)sum;
+                }
+                if constexpr (FLAG) {
+                    if (gp == 0 && sFlag[slot]) a.fix_list[atomicAdd(a.fix_count, 1)] = (int32_t)e;
                 }
             }
             __syncthreads();
@@ -367,7 +358,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                 const int c = mi(J), d = mj(J);
                 const R ev = (c == d) ? R(1) : R(kInvSqrt2);
 #pragma unroll
-                for (int I = 0; I < 6; ++I) {
+                for (int I = 0; I <= J; ++I) {
                     const int p = mi(I), r = mj(I);
                     // L(E_J)_pr with E_J = ev (e_c e_d + e_d e_c) (or e_c e_c)
                     R x = R(0);
@@ -384,12 +375,13 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                     }
                     const R Pi = R(2) * f1[p][r], Pj = R(2) * f1[c][d];
                     Cm[I][J] = Pi * Ch[I][J] * Pj + R(4) * mw<R>(I) * x;
+                    Cm[J][I] = Cm[I][J];  // the tangent is symmetric
                 }
             }
             bool fin = true;
 #pragma unroll
             for (int I = 0; I < 6; ++I) fin = fin && isfinite((double)Cm[I][I]);
-            if (valid && !fin) ++cnt_nan;
+            if (valid && !fin && !FIXUP) ++cnt_nan;
 
             // ---- element tangent blocks (a <= b), reduced over the 8 Gauss points
             static_for<0, 3>([&](auto AA) {
@@ -441,17 +433,17 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                             // lane gp sums block entries I = 4 half + gp/2, J = 4 (gp&1) + 0..3
                             // and stores them at ((p*2 + half)*8 + gp)*4 of the element's 384
                             const int il = gp >> 1, jb = (gp & 1) * 4;
-                            R v4[4];
+                            RO v4[4];
 #pragma unroll
                             for (int j = 0; j < 4; ++j) {
                                 R sum = R(0);
 #pragma unroll
                                 for (int g2 = 0; g2 < 8; ++g2) sum += red[il * 8 + jb + j][slot * 8 + g2];
-                                v4[j] = sum;
+                                v4[j] = (RO)sum;
                             }
                             constexpr int pidx = aa * 3 - (aa * (aa - 1)) / 2 + (bb - aa);
-                            R* Kd = reinterpret_cast<R*>(a.Ke) + e * 384 + ((pidx * 2 + half) * 8 + gp) * 4;
-                            store4<R>(Kd, v4);
+                            RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * 384 + ((pidx * 2 + half) * 8 + gp) * 4;
+                            store4<RO>(Kd, v4);
                         }
                         __syncthreads();
                     }
@@ -460,7 +452,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
         }
         __syncthreads();
     }
-    if (a.diag) {
+    if (a.diag && !FIXUP) {
         if (cnt_fail) atomicAdd(a.diag + 0, cnt_fail);
         if (cnt_j0) atomicAdd(a.diag + 1, cnt_j0);
         if (cnt_jf) atomicAdd(a.diag + 2, cnt_jf);
@@ -583,20 +575,24 @@ __global__ void norm_final(const double* __restrict__ part, int nb, double* __re
     if (threadIdx.x == 0) out[0] = sh[0];
 }
 
-template <typename R, int BLOCK>
+template <typename R, typename RO, int BLOCK, bool FIXUP>
 hipError_t launch_fwd(const FwdArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((fwd_kernel<R, BLOCK>), dim3(grid), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((fwd_kernel<R, RO, BLOCK, FIXUP>), dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_fwd_block(const FwdArgs& a, int block, int grid, hipStream_t s) {
     switch (block) {
-        case 64: return launch_fwd<R, 64>(a, grid, s);
-        case 256: return launch_fwd<R, 256>(a, grid, s);
-        default: return launch_fwd<R, 128>(a, grid, s);
+        case 64: return launch_fwd<R, R, 64, false>(a, grid, s);
+        case 256: return launch_fwd<R, R, 256, false>(a, grid, s);
+        default: return launch_fwd<R, R, 128, false>(a, grid, s);
     }
 }
+
+// FP64 recomputation of the guard-band elements of a mixed pass
+constexpr int kFixBlock = 64;
+constexpr int kFixGrid = 1024;
 
 constexpr int kAsmThreads = 256;
 
@@ -604,6 +600,8 @@ struct FwdWs {
     double* Re;
     void* Ke;
     double* part;
+    int32_t* fix_list;
+    int32_t* fix_count;
 };
 
 template <typename C>
@@ -612,7 +610,9 @@ void carve_forward(C& c, int32_t n_nodes, int32_t n_elems, fem_precision prec, F
     auto re = c.template take<double>((size_t)n_elems * 24 + 1);
     auto ke = c.template take<char>((size_t)n_elems * 384 * kb + 16);
     auto pa = c.template take<double>((size_t)n_nodes / kAsmThreads + 2);
-    if (w) *w = FwdWs{re, (void*)ke, pa};
+    auto fl = c.template take<int32_t>(prec == FEM_FP64 ? 1 : (size_t)n_elems + 1);
+    auto fc = c.template take<int32_t>(4);
+    if (w) *w = FwdWs{re, (void*)ke, pa, fl, fc};
 }
 
 struct CountAdapterF {
@@ -696,12 +696,19 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         const int epb = cfg.block / 8;
         a.n_tiles = (ne + epb - 1) / epb;
         a.xcd_remap = cfg.xcd_remap;
+        a.fix_list = w.fix_list;
+        a.fix_count = w.fix_count;
+        if (prec == FEM_FP32_MIXED) FEM_HIP_CHECK(zero_bytes(w.fix_count, sizeof(int32_t), s));
         const int grid = persistent_grid(cfg, a.n_tiles);
         void* tk = timing_begin(s);
         hipError_t e = (prec == FEM_FP64) ? launch_fwd_block<double>(a, cfg.block, grid, s)
                                           : launch_fwd_block<float>(a, cfg.block, grid, s);
         timing_end(tk, FEM_KERNEL_FORWARD, s);
         if (e != hipSuccess) return set_error(FEM_EHIP, "forward kernel launch failed: %s", hipGetErrorString(e));
+        if (prec == FEM_FP32_MIXED) {
+            e = launch_fwd<double, float, kFixBlock, true>(a, kFixGrid, s);
+            if (e != hipSuccess) return set_error(FEM_EHIP, "fixup kernel launch failed: %s", hipGetErrorString(e));
+        }
     } else if (assemble) {
         // no elements: every residual entry and K entry is zero (or an identity row)
         FEM_HIP_CHECK(zero_bytes(w.Re, sizeof(double) * 24, s));

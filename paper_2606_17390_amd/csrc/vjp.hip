@@ -39,6 +39,8 @@ struct VjpArgs {
     int64_t n_gp;
     int64_t n_tiles;
     int32_t xcd_remap;
+    int32_t* fix_list;   // mixed precision: guard-band elements, recomputed in FP64
+    int32_t* fix_count;
 };
 
 __device__ inline int spec_of_v(const int64_t* __restrict__ off, int n_spec, int64_t e) {
@@ -92,8 +94,8 @@ struct GPv {
 };
 
 template <typename R>
-__device__ inline void kin_log_v(const R xs[8][3], const R ds[8][3], int gp, GPv<R>& s, double eps[6]) {
-    kinematics<R>(xs, ds, gp, s.g, s.detJ, s.H);
+__device__ inline void kin_log_v(const double (*nd)[9], int gp, GPv<R>& s, double eps[6]) {
+    kinematics_lds<R, 9>(nd, gp, s.g, s.detJ, s.H);
     R M[3][3];
     cauchy_green_minus_identity<R>(s.H, M);
     eig_sym3<R>(M, s.mu, s.Q);
@@ -107,22 +109,35 @@ __device__ inline void kin_log_v(const R xs[8][3], const R ds[8][3], int gp, GPv
     }
 }
 
-template <typename R, int BLOCK>
+template <typename R, int BLOCK, bool FIXUP>
 __global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
     constexpr int EPB = BLOCK / 8;
+    constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
     __shared__ double sN[EPB][8][9];
     __shared__ double red[7][BLOCK + 1];
+    __shared__ int sFlag[EPB];
     const int tid = threadIdx.x;
     const int slot = tid >> 3, gp = tid & 7;
     int32_t cnt_fail = 0, cnt_j0 = 0;
 
     int64_t t0, t1, ts;
-    tile_range_v(a.n_tiles, a.xcd_remap, t0, t1, ts);
+    int64_t n_work = a.n_elems;
+    if constexpr (FIXUP) {
+        n_work = *a.fix_count;
+        t0 = blockIdx.x;
+        t1 = (n_work + EPB - 1) / EPB;
+        ts = gridDim.x;
+    } else {
+        tile_range_v(a.n_tiles, a.xcd_remap, t0, t1, ts);
+    }
     for (int64_t tile = t0; tile < t1; tile += ts) {
         const int64_t e_raw = tile * EPB + slot;
-        const bool valid = e_raw < a.n_elems;
-        const int64_t e = valid ? e_raw : (int64_t)a.n_elems - 1;
+        const bool valid = e_raw < n_work;
+        int64_t e;
+        if constexpr (FIXUP) e = a.fix_list[valid ? e_raw : 0];
+        else e = valid ? e_raw : (int64_t)a.n_elems - 1;
         const int64_t q = e * 8 + gp;
+        if (FLAG && gp == 0) sFlag[slot] = 0;
         int32_t node = a.conn[q];
         if ((uint32_t)node >= (uint32_t)a.n_nodes) node = 0;  // out-of-range id: stay in bounds
 #pragma unroll
@@ -139,49 +154,16 @@ __global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
 
         GPv<R> s;
         double eps[6];
-        R lrel[8][3];
-        {
-            R xs[8][3], ds[8][3];
-#pragma unroll
-            for (int I = 0; I < 8; ++I)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xs[I][c] = (R)(sN[slot][I][c] - sN[slot][0][c]);
-                    ds[I][c] = (R)(sN[slot][I][3 + c] - sN[slot][0][3 + c]);
-                    lrel[I][c] = (R)(sN[slot][I][6 + c] - sN[slot][0][6 + c]);
-                }
-            kin_log_v<R>(xs, ds, gp, s, eps);
-        }
+        kin_log_v<R>(sN[slot], gp, s, eps);
         Modes md;
         hill_modes(mat, md);
         Local loc;
         local_update(eps, hn, mat, md, loc);
-        if constexpr (std::is_same<R, float>::value) {
-            if (fabs(loc.ftr) < 2e-4 * loc.sy_n) {
-                GPv<double> sd;
-                double xs[8][3], ds[8][3];
-#pragma unroll
-                for (int I = 0; I < 8; ++I)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        xs[I][c] = sN[slot][I][c] - sN[slot][0][c];
-                        ds[I][c] = sN[slot][I][3 + c] - sN[slot][0][3 + c];
-                    }
-                kin_log_v<double>(xs, ds, gp, sd, eps);
-                local_update(eps, hn, mat, md, loc);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    s.mu[i] = (R)sd.mu[i];
-                    s.eh[i] = (R)sd.eh[i];
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        s.Q[i][j] = (R)sd.Q[i][j];
-                        s.H[i][j] = (R)sd.H[i][j];
-                    }
-                }
-            }
+        if constexpr (FLAG) {
+            // guard band: the element is recomputed in FP64 (fixup launch)
+            if (valid && fabs(loc.ftr) < 2e-4 * loc.sy_n) sFlag[slot] = 1;
         }
-        if (valid) {
+        if (valid && !FIXUP) {
             cnt_fail += loc.converged ? 0 : 1;
             cnt_j0 += (s.detJ <= R(0)) ? 1 : 0;
         }
@@ -201,7 +183,7 @@ __global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
                 for (int p = 0; p < 3; ++p) {
                     R v = R(0);
 #pragma unroll
-                    for (int I = 1; I < 8; ++I) v += lrel[I][i] * gh[I][p];
+                    for (int I = 1; I < 8; ++I) v += (R)(sN[slot][I][6 + i] - sN[slot][0][6 + i]) * gh[I][p];
                     Lh[i][p] = v;
                 }
             R fh[3][3];
@@ -302,9 +284,12 @@ __global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
             for (int g2 = 0; g2 < 8; ++g2) sum += red[gp][slot * 8 + g2];
             a.g_elem[(int64_t)gp * a.n_elems + e] = sum;
         }
+        if constexpr (FLAG) {
+            if (valid && gp == 7 && sFlag[slot]) a.fix_list[atomicAdd(a.fix_count, 1)] = (int32_t)e;
+        }
         __syncthreads();
     }
-    if (a.diag) {
+    if (a.diag && !FIXUP) {
         if (cnt_fail) atomicAdd(a.diag + 0, cnt_fail);
         if (cnt_j0) atomicAdd(a.diag + 1, cnt_j0);
     }
@@ -332,9 +317,9 @@ __global__ void reduce_uniform(const double* __restrict__ g_elem, int64_t n_elem
 template <typename R>
 hipError_t launch_vjp(const VjpArgs& a, int block, int grid, hipStream_t s) {
     switch (block) {
-        case 64: hipLaunchKernelGGL((vjp_kernel<R, 64>), dim3(grid), dim3(64), 0, s, a); break;
-        case 256: hipLaunchKernelGGL((vjp_kernel<R, 256>), dim3(grid), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((vjp_kernel<R, 128>), dim3(grid), dim3(128), 0, s, a); break;
+        case 64: hipLaunchKernelGGL((vjp_kernel<R, 64, false>), dim3(grid), dim3(64), 0, s, a); break;
+        case 256: hipLaunchKernelGGL((vjp_kernel<R, 256, false>), dim3(grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((vjp_kernel<R, 128, false>), dim3(grid), dim3(128), 0, s, a); break;
     }
     return hipGetLastError();
 }
@@ -344,10 +329,12 @@ hipError_t launch_vjp(const VjpArgs& a, int block, int grid, hipStream_t s) {
 
 using namespace fem;
 
+// workspace: [g_elem when the caller passes none][fix list][fix count]
 extern "C" size_t fem_vjp_workspace_bytes(int32_t n_elems, int32_t n_spec) {
     (void)n_spec;
     if (n_elems < 0) return 0;
-    return sizeof(double) * (size_t)FEM_NGRAD * ((size_t)n_elems + 1) + 512;
+    return sizeof(double) * (size_t)FEM_NGRAD * ((size_t)n_elems + 1) + sizeof(int32_t) * ((size_t)n_elems + 1) +
+           1024;
 }
 
 extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, const fem_params* params,
@@ -370,13 +357,14 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         return set_error(FEM_EINVAL, "fem_residual_vjp: per-specimen parameters need a batch");
     const int n_spec = batch ? batch->n_spec : 1;
     hipStream_t s = (hipStream_t)stream;
-    double* ge = g_elem;
-    if (!ge) {
-        const size_t need = fem_vjp_workspace_bytes(mesh->n_elems, n_spec);
-        if (!ws || ws_bytes < need)
-            return set_error(FEM_ENOMEM, "fem_residual_vjp: workspace of %zu bytes required", need);
-        ge = reinterpret_cast<double*>(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-    }
+    const size_t need = fem_vjp_workspace_bytes(mesh->n_elems, n_spec);
+    if (!ws || ws_bytes < need)
+        return set_error(FEM_ENOMEM, "fem_residual_vjp: workspace of %zu bytes required", need);
+    WsCarver cv(ws, ws_bytes);
+    double* ge_ws = cv.take<double>((size_t)FEM_NGRAD * ((size_t)mesh->n_elems + 1));
+    int32_t* fix_list = cv.take<int32_t>((size_t)mesh->n_elems + 1);
+    int32_t* fix_count = cv.take<int32_t>(4);
+    double* ge = g_elem ? g_elem : ge_ws;
     if (diag) FEM_HIP_CHECK(zero_bytes(diag, 4 * sizeof(int32_t), s));
     if (ne > 0) {
         const fem_launch cfg = launch_config(FEM_KERNEL_VJP, prec);
@@ -399,12 +387,19 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         const int epb = cfg.block / 8;
         a.n_tiles = (ne + epb - 1) / epb;
         a.xcd_remap = cfg.xcd_remap;
+        a.fix_list = fix_list;
+        a.fix_count = fix_count;
+        if (prec == FEM_FP32_MIXED) FEM_HIP_CHECK(zero_bytes(fix_count, sizeof(int32_t), s));
         const int grid = persistent_grid(cfg, a.n_tiles);
         void* tk = timing_begin(s);
         hipError_t e = (prec == FEM_FP64) ? launch_vjp<double>(a, cfg.block, grid, s)
                                           : launch_vjp<float>(a, cfg.block, grid, s);
         timing_end(tk, FEM_KERNEL_VJP, s);
         if (e != hipSuccess) return set_error(FEM_EHIP, "vjp kernel launch failed: %s", hipGetErrorString(e));
+        if (prec == FEM_FP32_MIXED) {
+            hipLaunchKernelGGL((vjp_kernel<double, 64, true>), dim3(1024), dim3(64), 0, s, a);
+            FEM_HIP_CHECK(hipGetLastError());
+        }
     }
     if (g_uniform) {
         if (ne == 0) {
