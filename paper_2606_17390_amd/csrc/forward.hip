@@ -505,60 +505,91 @@ __global__ void assemble_residual(int32_t n_nodes, const int32_t* __restrict__ n
     }
 }
 
-// Rows 3I+a of K: 32 lanes per node, lane r owns column block r (node J = the
-// r-th neighbour) and sums, in ascending element order, the 3x3 blocks (i,j)
-// of the elements around I with elem_rank(i,j) = r.  Constrained rows become
-// identity rows.  Every entry of K is written exactly once.
+// Orders a wave's LDS stores before loads of the same addresses by other
+// lanes of that wave.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kTanWaves = 4;  // nodes (waves) per workgroup of assemble_tangent
+
+// Rows 3I+a of K, one wave per node I.  The node's incident elements are
+// taken 8 at a time: lane (k, j) loads the 3x3 block (i_k, j) of element k
+// (i_k = local index of I in it) and parks it in LDS; then lane r, owner of
+// column block r (the r-th neighbour J of I in ascending order), adds the
+// parked block of each element whose node j has elem_rank r, in ascending
+// element order.  The node's 3 rows are 9 deg consecutive values of K; they
+// are staged in LDS and stored by all 64 lanes, constrained rows replaced by
+// identity rows.  Every entry of K is written exactly once.  Workgroups are
+// mapped to 8 contiguous node ranges, one per XCD, so the elements shared by
+// neighbouring nodes are re-read from the same L2.
 template <typename R>
-__global__ void assemble_tangent(int32_t n_nodes, const int32_t* __restrict__ ne_ptr,
-                                 const int32_t* __restrict__ ne_list, const uint8_t* __restrict__ elem_rank,
-                                 const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                                 const R* __restrict__ Ke, const uint8_t* __restrict__ bc, R* __restrict__ K) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = gid >> 5;
-    const int lane = (int)(gid & 31);
-    if (n >= n_nodes) return;
+__global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
+    int32_t n_nodes, int64_t n_chunk, const int32_t* __restrict__ ne_ptr, const int32_t* __restrict__ ne_list,
+    const uint8_t* __restrict__ elem_rank, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const R* __restrict__ Ke, const uint8_t* __restrict__ bc, R* __restrict__ K) {
+    __shared__ R sv[kTanWaves][64 * 9];
+    __shared__ uint64_t sr[kTanWaves][8];
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t grp = (int64_t)(blockIdx.x & 7) * n_chunk + (blockIdx.x >> 3);
+    const int64_t n = grp * kTanWaves + w;
+    if (n >= n_nodes) return;  // the whole wave; no workgroup barrier below
+    R* vals = sv[w];
     const int32_t rs = row_ptr[3 * n];
     const int32_t len = row_ptr[3 * n + 1] - rs;  // 3 deg
     const int deg = len / 3;
     const int32_t k0 = ne_ptr[n], k1 = ne_ptr[n + 1];
-    for (int r = lane; r < deg; r += 32) {
-        R acc[3][3];
+    const int kk = lane >> 3, j = lane & 7;
+    const uint64_t pat = 0x0101010101010101ull * (uint64_t)lane;
+    R acc[9];
 #pragma unroll
-        for (int x = 0; x < 3; ++x)
-#pragma unroll
-            for (int y = 0; y < 3; ++y) acc[x][y] = R(0);
-        for (int32_t k = k0; k < k1; ++k) {
-            const int64_t v = ne_list[k];
-            const int64_t e = v >> 3;
+    for (int q = 0; q < 9; ++q) acc[q] = R(0);
+    for (int32_t c = k0; c < k1; c += 8) {
+        if (c + kk < k1) {
+            const int64_t v = ne_list[c + kk];  // 8 e + i
             const int i = (int)(v & 7);
-            const uint64_t rk = reinterpret_cast<const uint64_t*>(elem_rank)[v];
-            const R* blk = Ke + e * 384;
+            const R* blk = Ke + (v >> 3) * 384;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if ((int)((rk >> (8 * j)) & 0xffu) != r) continue;
+            for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
-                for (int aa = 0; aa < 3; ++aa)
+                for (int bb = 0; bb < 3; ++bb) {
+                    const int off = (aa <= bb) ? ke_offset(pair_index(aa, bb), i, j)
+                                               : ke_offset(pair_index(bb, aa), j, i);
+                    vals[lane * 9 + aa * 3 + bb] = blk[off];
+                }
+            if (j == 0) sr[w][kk] = reinterpret_cast<const uint64_t*>(elem_rank)[v];
+        }
+        wave_sync();
+        if (lane < deg) {
+            const int nk = min(8, k1 - c);
+            for (int q = 0; q < nk; ++q) {
+                // byte of the rank word equal to this lane's rank (at most one)
+                const uint64_t x = sr[w][q] ^ pat;
+                const uint64_t z = (x - 0x0101010101010101ull) & ~x & 0x8080808080808080ull;
+                if (z) {
+                    const R* src = vals + (q * 8 + (__builtin_ctzll(z) >> 3)) * 9;
 #pragma unroll
-                    for (int bb = 0; bb < 3; ++bb) {
-                        const int off = (aa <= bb) ? ke_offset(pair_index(aa, bb), i, j)
-                                                   : ke_offset(pair_index(bb, aa), j, i);
-                        acc[aa][bb] += blk[off];
-                    }
+                    for (int t = 0; t < 9; ++t) acc[t] += src[t];
+                }
             }
         }
+        wave_sync();
+    }
+    if (lane < deg) {
 #pragma unroll
-        for (int aa = 0; aa < 3; ++aa) {
-            const int64_t row = 3 * n + aa;
-            const int64_t o = (int64_t)rs + aa * len + 3 * r;
-            if (bc && bc[row]) {
+        for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
-                for (int bb = 0; bb < 3; ++bb) K[o + bb] = (col_idx[o + bb] == row) ? R(1) : R(0);
-            } else {
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb) K[o + bb] = acc[aa][bb];
-            }
-        }
+            for (int bb = 0; bb < 3; ++bb) vals[aa * len + 3 * lane + bb] = acc[aa * 3 + bb];
+    }
+    wave_sync();
+    const bool b0 = bc && bc[3 * n], b1 = bc && bc[3 * n + 1], b2 = bc && bc[3 * n + 2];
+    for (int t = lane; t < 3 * len; t += 64) {
+        const int aa = (t >= len) + (t >= 2 * len);
+        R val = vals[t];
+        if (aa == 0 ? b0 : (aa == 1 ? b1 : b2)) val = (col_idx[rs + t] == 3 * n + aa) ? R(1) : R(0);
+        K[rs + t] = val;
     }
 }
 
@@ -727,14 +758,15 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         FEM_HIP_CHECK(zero_bytes(rnorm2, sizeof(double), s));
     }
     if (K_vals && nn > 0 && csr->nnz > 0) {
-        const unsigned nb = (unsigned)(((int64_t)nn * 32 + kAsmThreads - 1) / kAsmThreads);
+        const int64_t n_chunk = ((nn + kTanWaves - 1) / kTanWaves + 7) / 8;
+        const unsigned nb = (unsigned)(8 * n_chunk);
         if (prec == FEM_FP64)
-            hipLaunchKernelGGL(assemble_tangent<double>, dim3(nb), dim3(kAsmThreads), 0, s, nn, csr->node_elem_ptr,
-                               csr->node_elem, csr->elem_rank, csr->row_ptr, csr->col_idx,
+            hipLaunchKernelGGL(assemble_tangent<double>, dim3(nb), dim3(64 * kTanWaves), 0, s, nn, n_chunk,
+                               csr->node_elem_ptr, csr->node_elem, csr->elem_rank, csr->row_ptr, csr->col_idx,
                                reinterpret_cast<const double*>(w.Ke), bc_mask, reinterpret_cast<double*>(K_vals));
         else
-            hipLaunchKernelGGL(assemble_tangent<float>, dim3(nb), dim3(kAsmThreads), 0, s, nn, csr->node_elem_ptr,
-                               csr->node_elem, csr->elem_rank, csr->row_ptr, csr->col_idx,
+            hipLaunchKernelGGL(assemble_tangent<float>, dim3(nb), dim3(64 * kTanWaves), 0, s, nn, n_chunk,
+                               csr->node_elem_ptr, csr->node_elem, csr->elem_rank, csr->row_ptr, csr->col_idx,
                                reinterpret_cast<const float*>(w.Ke), bc_mask, reinterpret_cast<float*>(K_vals));
         FEM_HIP_CHECK(hipGetLastError());
     }
