@@ -7,14 +7,15 @@ Workload (synthetic, seeded): the 100x100x100 hex8 cube (1,000,000 elements,
 1,030,301 nodes, 3,090,903 dofs, 8,000,000 Gauss points, nnz 245,438,109),
 per-element Hill-48 F,G,H from smooth random fields, 30% of the Gauss points
 yielding at the trial state, x = 0 face constrained.  A step is one
-fem_residual_tangent call in FP32-mixed precision (fill of R and K, element
-kernel with return map / residual / tangent / CSR scatter, Dirichlet rows,
-FP64 residual norm), inputs resident in HBM.  Prints ONE JSON line.
+fem_residual_tangent call in FP32-mixed precision (element kernel with return
+map / residual / element tangent, FP64 re-run of the guard-band elements,
+residual assembly with Dirichlet rows and the FP64 residual norm, tangent
+assembly into the CSR values), inputs resident in HBM.  Prints ONE JSON line.
 
 Also reported (same JSON line): the plain FP64 pass on the same cube, the
 parameter VJP on the 200x200x2 voided specimen, the batched 64-specimen
-forward + VJP graph, the roofline of the dominant kernel (live HIP-event
-timing of the element kernel), and the CPU oracle on a bounded sample.
+forward + VJP graph, per-kernel rooflines (live HIP-event timing of each
+kernel on its launch stream), and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -26,6 +27,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU peak of the element kernels: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA)
+# x 2.4 GHz = 78.6 TFLOP/s, the rate of FP64 and of non-packed FP32 alike
+# (the library is built without packed FP32 instructions).
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+# Counted VALU flops per Gauss point of the main element kernel on the 100^3
+# cube: rocprofv3 --pmc SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F{32,64}, 64 lanes per
+# wave instruction, FMA = 2 flop, summed over F32 and F64, divided by the
+# 8e6 Gauss points (profiles/fwd_kernel_large_cube_valu.txt).  None until
+# counted for the kernel as it stands.
+FLOP_PER_GP = {"mixed": None, "fp64": None}
+# HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a
+# plain 1 GiB copy, profiles/hbm_traffic_large_cube.txt); None until taken
+# for the kernel as it stands.
+TRAFFIC_BYTES = {"fwd_kernel": None, "assemble_tangent": None, "assemble_residual": None}
 
 
 def log(*a):
@@ -33,7 +49,8 @@ def log(*a):
 
 
 def algorithmic_bytes(p, nnz, prec_mixed, per_elem_cols):
-    """Bytes an ideal pass moves through HBM, each array once."""
+    """Bytes an ideal residual + tangent + assembly pass moves through HBM,
+    each input and output array once (no element scratch)."""
     ne, nn = p.n_elems, p.n_nodes
     ngp = 8 * ne
     kb = 4 if prec_mixed else 8
@@ -51,11 +68,27 @@ def algorithmic_bytes(p, nnz, prec_mixed, per_elem_cols):
     return b
 
 
-def time_passes(fn, steps, warmup, torch, kernel, fem):
+def kernel_bytes(p, nnz, prec_mixed, per_elem_cols, n_bc_rows, bc_row_nnz):
+    """Algorithmic bytes of each kernel of one pass (its inputs read once, its
+    outputs written once, element scratch included where a kernel reads or
+    writes it)."""
+    ne, nn = p.n_elems, p.n_nodes
+    ngp = 8 * ne
+    kb = 4 if prec_mixed else 8
+    fwd = nn * 48 + ne * 32 + ngp * 56 + ne * 8 * per_elem_cols + ngp * 56 + ne * 24 * 8 + ne * 384 * kb
+    asm_k = (ne * 384 * kb + ne * 64 + ne * 8 * 4 + (nn + 1) * 4 + (3 * nn + 1) * 4 + 3 * nn
+             + nnz * kb + bc_row_nnz * 4)
+    asm_r = ne * 24 * 8 + ne * 8 * 4 + (nn + 1) * 4 + 3 * nn + 3 * nn * 8
+    return {"fwd_kernel": fwd, "assemble_tangent": asm_k, "assemble_residual": asm_r}
+
+
+def time_passes(fn, steps, warmup, torch, kernels, fem):
+    """Event-timed steps; returns (ms per step, wall ms per step, {kernel id: average launch ms})."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    fem.timing_read(kernel)  # drop launches of the warm-up
+    for k in kernels:
+        fem.timing_read(k)  # drop launches of the warm-up
     fem.timing_enable(True)
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -69,8 +102,11 @@ def time_passes(fn, steps, warmup, torch, kernel, fem):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fem.timing_enable(False)
-    kms, nl = fem.timing_read(kernel)
-    return e0.elapsed_time(e1) / steps, wall / steps * 1e3, (kms / nl if nl else None)
+    avg = {}
+    for k in kernels:
+        kms, nl = fem.timing_read(k)
+        avg[k] = kms / nl if nl else None
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3, avg
 
 
 def cpu_baseline(p, n_sample):
@@ -142,20 +178,25 @@ def main():
     log(f"nnz {csr.nnz}, per-element parameter columns {per_elem_cols}")
 
     # ---- headline: FP32-mixed residual + tangent + CSR pass
+    KS = (fem.KERNEL_FORWARD, fem.KERNEL_ASSEMBLE_K, fem.KERNEL_ASSEMBLE_R)
     out_m = fem.Forward(mesh, csr, fem.FP32_MIXED)
-    ms_m, wall_m, kms_m = time_passes(
+    ms_m, wall_m, kt_m = time_passes(
         lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP32_MIXED, out=out_m),
-        args.steps, args.warmup, torch, fem.KERNEL_FORWARD, fem)
+        args.steps, args.warmup, torch, KS, fem)
+    kms_m = kt_m[fem.KERNEL_FORWARD]
     plastic = float((out_m.hist[6] != h[6]).double().mean().cpu())
     diag_m = out_m.diag.cpu().tolist()
-    log(f"mixed: {ms_m:.3f} ms/pass, kernel {kms_m:.3f} ms, plastic {plastic:.4f}, diag {diag_m}")
+    log(f"mixed: {ms_m:.3f} ms/pass, element kernel {kms_m:.3f} ms, tangent assembly "
+        f"{kt_m[fem.KERNEL_ASSEMBLE_K]:.3f} ms, residual assembly {kt_m[fem.KERNEL_ASSEMBLE_R]:.3f} ms, "
+        f"plastic {plastic:.4f}, diag {diag_m}")
     result = {}
     extras = {}
     if not args.no_extras:
         out_d = fem.Forward(mesh, csr, fem.FP64)
-        ms_d, _, kms_d = time_passes(
+        ms_d, _, kt_d = time_passes(
             lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP64, out=out_d),
-            max(args.steps // 2, 3), 2, torch, fem.KERNEL_FORWARD, fem)
+            max(args.steps // 2, 3), 2, torch, KS, fem)
+        kms_d = kt_d[fem.KERNEL_FORWARD]
         # mixed vs FP64 on this very workload
         torch.cuda.synchronize()
         kd = out_d.K
@@ -164,8 +205,13 @@ def main():
         err_r = float(((out_m.R - out_d.R).abs().max() / out_d.R.abs().max()).cpu())
         del km
         log(f"fp64: {ms_d:.3f} ms/pass, kernel {kms_d:.3f} ms; mixed vs fp64 K {err_k:.2e} R {err_r:.2e}")
-        extras["fp64"] = dict(gp_updates_per_s=n_gp / (ms_d * 1e-3), ms_per_pass=ms_d, kernel_ms=kms_d,
-                              hbm_algorithmic_GBps=algorithmic_bytes(p, csr.nnz, False, per_elem_cols) / (kms_d * 1e6))
+        extras["fp64"] = dict(gp_updates_per_s=n_gp / (ms_d * 1e-3), ms_per_pass=ms_d,
+                              kernel_ms={"fwd_kernel": kms_d, "assemble_tangent": kt_d[fem.KERNEL_ASSEMBLE_K],
+                                         "assemble_residual": kt_d[fem.KERNEL_ASSEMBLE_R]},
+                              pass_hbm_algorithmic_GBps=algorithmic_bytes(p, csr.nnz, False, per_elem_cols)
+                              / (ms_d * 1e6))
+        if FLOP_PER_GP["fp64"]:
+            extras["fp64"]["fwd_kernel_TFLOPs"] = FLOP_PER_GP["fp64"] * n_gp / (kms_d * 1e-3) / 1e12
         extras["mixed_vs_fp64_rel_err"] = dict(K=err_k, R=err_r)
         del out_d, kd
         torch.cuda.empty_cache()
@@ -180,9 +226,10 @@ def main():
         vj = {}
         for name, prec in (("fp64", fem.FP64), ("mixed", fem.FP32_MIXED)):
             vo = fem.Vjp(mv)
-            ms_v, _, kms_v = time_passes(
+            ms_v, _, kt_v = time_passes(
                 lambda: fem.residual_vjp(mv, pv_params, dv, hv, lv, prec=prec, out=vo),
-                args.steps, args.warmup, torch, fem.KERNEL_VJP, fem)
+                args.steps, args.warmup, torch, (fem.KERNEL_VJP,), fem)
+            kms_v = kt_v[fem.KERNEL_VJP]
             vj[name] = dict(vjp_per_s=1e3 / ms_v, gp_vjp_per_s=8 * pv.n_elems / (ms_v * 1e-3), ms_per_vjp=ms_v,
                             kernel_ms=kms_v)
             log(f"vjp {name}: {ms_v:.3f} ms")
@@ -233,7 +280,7 @@ def main():
             for (ms_, cs, pr, dd, hh, ll, bb), (fo, vo) in zip(sep, sep_out):
                 fem.residual_tangent(ms_, cs, pr, dd, hh, bc_mask=bb, prec=fem.FP64, out=fo)
                 fem.residual_vjp(ms_, pr, dd, hh, ll, prec=fem.FP64, out=vo)
-        ms_sep, _, _ = time_passes(run_sep, max(args.steps // 4, 3), 2, torch, fem.KERNEL_FORWARD, fem)
+        ms_sep, _, _ = time_passes(run_sep, max(args.steps // 4, 3), 2, torch, (fem.KERNEL_FORWARD,), fem)
         extras["batched_64"] = dict(n_elems=mb.n_elems, ms_graph_fwd_vjp_mixed=ms_b,
                                     specimen_fwd_vjp_per_s=64 / (ms_b * 1e-3),
                                     gp_updates_per_s=8 * mb.n_elems / (ms_b * 1e-3),
@@ -242,11 +289,32 @@ def main():
         del sep, sep_out
 
     value = n_gp / (ms_m * 1e-3)
-    abytes = algorithmic_bytes(p, csr.nnz, True, per_elem_cols)
-    achieved = abytes / (kms_m * 1e6)  # GB/s
-    roof = dict(bound="hbm", kernel="fwd_kernel<float> (FP32-mixed element kernel)", achieved=achieved,
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
-                algorithmic_bytes_per_launch=abytes, kernel_ms=kms_m)
+    bc_np = p.bc_mask.astype(bool)
+    rp = csr.row_ptr.cpu().numpy()
+    bc_rows = np.nonzero(bc_np)[0]
+    bc_row_nnz = int((rp[bc_rows + 1] - rp[bc_rows]).sum())
+    kb = kernel_bytes(p, csr.nnz, True, per_elem_cols, bc_rows.size, bc_row_nnz)
+    kms = {"fwd_kernel": kms_m, "assemble_tangent": kt_m[fem.KERNEL_ASSEMBLE_K],
+           "assemble_residual": kt_m[fem.KERNEL_ASSEMBLE_R]}
+    roofs = {}
+    for name, ms_k in kms.items():
+        if name == "fwd_kernel":
+            # bound by VALU arithmetic: counted flops against the VALU peak
+            fl = FLOP_PER_GP["mixed"]
+            ach = fl * n_gp / (ms_k * 1e-3) / 1e12 if fl else None
+            roofs[name] = dict(bound="alu", achieved=ach, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                               frac=(ach / VALU_PEAK_TFLOPS) if ach else None, traffic=TRAFFIC_BYTES[name],
+                               flop_per_gp=fl, n_gp=n_gp, kernel_ms=ms_k,
+                               hbm_algorithmic_bytes=kb[name],
+                               hbm_GBps=kb[name] / (ms_k * 1e6))
+        else:
+            ach = kb[name] / (ms_k * 1e6)
+            roofs[name] = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                               traffic=TRAFFIC_BYTES[name], algorithmic_bytes=kb[name], kernel_ms=ms_k)
+    dom = max(kms, key=lambda k: kms[k])
+    roof = dict(kernel=dom, **roofs[dom])
+    extras["kernels"] = roofs
+    extras["pass_hbm_algorithmic_GBps"] = algorithmic_bytes(p, csr.nnz, True, per_elem_cols) / (ms_m * 1e6)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         result_cpu = cpu_baseline(p, args.cpu_sample)

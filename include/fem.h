@@ -123,7 +123,9 @@ typedef struct {
     int32_t xcd_remap;     /* 1: consecutive tiles stay on one XCD's L2 */
 } fem_launch;
 
-enum { FEM_KERNEL_FORWARD = 0, FEM_KERNEL_VJP = 1 };
+/* Kernel ids: the two element kernels (launch configuration and timing) and
+ * the two assembly kernels of fem_residual_tangent (timing only). */
+enum { FEM_KERNEL_FORWARD = 0, FEM_KERNEL_VJP = 1, FEM_KERNEL_ASSEMBLE_K = 2, FEM_KERNEL_ASSEMBLE_R = 3 };
 
 /* Library version (major*10000 + minor*100 + patch). */
 int fem_version(void);
@@ -131,8 +133,10 @@ int fem_version(void);
 /* Message of the last failed call on this thread ("" if none). */
 const char *fem_last_error(void);
 
-/* Set (cfg != NULL) or reset (cfg == NULL) the launch configuration of a
- * kernel for a precision; process-wide.  Returns FEM_EINVAL for bad values. */
+/* Set (cfg != NULL) or reset (cfg == NULL) the launch configuration of an
+ * element kernel (FEM_KERNEL_FORWARD or FEM_KERNEL_VJP) for a precision;
+ * process-wide.  Defaults: forward {64, 8, 1}, VJP {128, 8, 1}.  Returns
+ * FEM_EINVAL for bad values. */
 int fem_set_launch(int kernel, fem_precision prec, const fem_launch *cfg);
 int fem_get_launch(int kernel, fem_precision prec, fem_launch *cfg);
 
@@ -211,9 +215,11 @@ int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_par
                      void *stream);
 
 /*
- * Kernel timing for benchmarks: while enabled, every launch of the element
- * kernel of `kernel` (FEM_KERNEL_FORWARD / FEM_KERNEL_VJP) is bracketed by a
- * pair of HIP events recorded on the launch stream.  fem_timing_read waits
+ * Kernel timing for benchmarks: while enabled, every launch of kernel
+ * `kernel` (FEM_KERNEL_FORWARD / FEM_KERNEL_VJP: the main element kernel, not
+ * the FP64 guard-band re-run; FEM_KERNEL_ASSEMBLE_K / _R: the tangent and
+ * residual assembly kernels) is bracketed by a pair of HIP events recorded on
+ * the launch stream.  fem_timing_read waits
  * for the recorded events, returns the summed elapsed milliseconds and the
  * number of launches since the previous read, and releases the events.
  * Do not enable while capturing a graph.

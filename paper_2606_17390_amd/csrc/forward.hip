@@ -92,6 +92,12 @@ __device__ inline Mat load_material(const A& a, int64_t e) {
     return m;
 }
 
+// Element tangent blocks K^e_{Ia,Jb}, a <= b, are stored per element as 6
+// pair blocks p(a,b) (order (0,0),(0,1),(0,2),(1,1),(1,2),(2,2)) of 8x8
+// node entries: offset p*64 + 8 I + J of the element's 384.
+__host__ __device__ constexpr int pair_index(int a, int b) { return a * 3 - (a * (a - 1)) / 2 + (b - a); }
+__device__ inline int ke_offset(int p, int I, int J) { return p * 64 + 8 * I + J; }
+
 // Tile range of this workgroup in a persistent launch.  Workgroups are
 // dispatched round-robin over the 8 XCDs; with xcd_remap the tiles are cut in
 // 8 contiguous chunks and chunk x is walked by the workgroups of XCD x.
@@ -144,9 +150,21 @@ template <typename R, typename RO, int BLOCK, bool FIXUP>
 __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
     constexpr int EPB = BLOCK / 8;
     constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
+    // LDS: node coordinates and displacements of the tile; the frame
+    // gradients g^ of every Gauss point; and one buffer used in turn for H
+    // and Q across the local update, the residual reduction and the tangent
+    // hand-off (the 3 blocks A^ of one phase per Gauss point)
+    constexpr int kRed = 24 * (BLOCK + 1);
+    constexpr int kHand = EPB * 8 * 28;
+    constexpr int kPark = EPB * 8 * 18;
+    constexpr int kBuf = kRed > kHand ? (kRed > kPark ? kRed : kPark) : (kHand > kPark ? kHand : kPark);
     __shared__ double sXD[EPB][8][6];
-    __shared__ R red[32][BLOCK + 1];
+    __shared__ __attribute__((aligned(16))) R sG[EPB][8][24];  // [slot][g][3 I + q]
+    __shared__ __attribute__((aligned(16))) R sbuf[kBuf];
     __shared__ int sFlag[EPB];
+    R (*sHQ)[8][18] = reinterpret_cast<R (*)[8][18]>(sbuf);     // [slot][g][H 9, Q 9]
+    R (*red)[BLOCK + 1] = reinterpret_cast<R (*)[BLOCK + 1]>(sbuf);
+    R (*sA)[8][28] = reinterpret_cast<R (*)[8][28]>(sbuf);      // [slot][g][9 k + 3 q + s]
 
     const int tid = threadIdx.x;
     const int slot = tid >> 3, gp = tid & 7;
@@ -195,10 +213,34 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
         GP<R> s;
         double eps[6];
         kin_and_log<R>(sXD[slot], gp, s, eps);
+        // g^_Iq = grad N_IA Q_Aq, parked in LDS (read back by the residual and
+        // the tangent hand-off; keeps registers free for the local update)
+#pragma unroll
+        for (int I = 0; I < 8; ++I)
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                sG[slot][gp][3 * I + p] = s.g[I][0] * s.Q[0][p] + s.g[I][1] * s.Q[1][p] + s.g[I][2] * s.Q[2][p];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                sHQ[slot][gp][3 * i + j] = s.H[i][j];
+                sHQ[slot][gp][9 + 3 * i + j] = s.Q[i][j];
+            }
+        asm volatile("" ::: "memory");  // the parked values are re-read, not kept in registers
         Modes md;
         hill_modes(mat, md);
         Local loc;
         local_update(eps, hn, mat, md, loc);
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                s.H[i][j] = sHQ[slot][gp][3 * i + j];
+                s.Q[i][j] = sHQ[slot][gp][9 + 3 * i + j];
+            }
+        __syncthreads();  // the parking area becomes the residual buffer
         if constexpr (FLAG) {
             // guard band: a trial state this close to the yield surface is
             // left to the FP64 recomputation of its element, so that the
@@ -250,11 +292,6 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int p = 0; p < 3; ++p) fh[i][p] = s.Q[i][p] + (s.H[i][0] * s.Q[0][p] + s.H[i][1] * s.Q[1][p] + s.H[i][2] * s.Q[2][p]);
-        R gh[8][3];  // g^_Iq = grad N_IA Q_Aq
-#pragma unroll
-        for (int I = 0; I < 8; ++I)
-#pragma unroll
-            for (int p = 0; p < 3; ++p) gh[I][p] = s.g[I][0] * s.Q[0][p] + s.g[I][1] * s.Q[1][p] + s.g[I][2] * s.Q[2][p];
         const R wdet = s.detJ;
 
         // ---- residual: R_Ia = w detJ0 sum_q (f^ S^)_aq g^_Iq
@@ -273,7 +310,8 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
             for (int I = 0; I < 8; ++I)
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
-                    red[3 * I + i][tid] = Ph[i][0] * gh[I][0] + Ph[i][1] * gh[I][1] + Ph[i][2] * gh[I][2];
+                    red[3 * I + i][tid] = Ph[i][0] * sG[slot][gp][3 * I] + Ph[i][1] * sG[slot][gp][3 * I + 1] +
+                                          Ph[i][2] * sG[slot][gp][3 * I + 2];
             __syncthreads();
             if (valid) {
                 // lane gp owns node gp of the element: R^e_{gp,0..2}
@@ -383,71 +421,86 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
             for (int I = 0; I < 6; ++I) fin = fin && isfinite((double)Cm[I][I]);
             if (valid && !fin && !FIXUP) ++cnt_nan;
 
-            // ---- element tangent blocks (a <= b), reduced over the 8 Gauss points
-            static_for<0, 3>([&](auto AA) {
-                constexpr int aa = decltype(AA)::value;
-                // Y[q][r][s] = sum_p f^_ap C4(p,q,r,s)
-                R Y[3][3][3];
+            // ---- element tangent blocks K^e(a,b), a <= b:
+            //      K^e_{Ia,Jb} = sum_g w detJ0 g^_Iq A^(a,b)_qs g^_Js  (per Gauss point g)
+            // Each lane hands its g^ and A^ over through LDS, then lane I
+            // sums row I of the blocks over the element's 8 Gauss points, in
+            // order.  Two phases of 3 blocks: (0,0),(0,1),(0,2); (1,1),(1,2),(2,2).
+            static_for<0, 2>([&](auto PH) {
+                constexpr int ph = decltype(PH)::value;
+                static_for<ph, ph + 1 + ph>([&](auto AA) {
+                    constexpr int aa = decltype(AA)::value;
+                    // Y[q][r][s] = sum_p f^_ap C4(p,q,r,s)
+                    R Y[3][3][3];
 #pragma unroll
-                for (int qq = 0; qq < 3; ++qq)
+                    for (int qq = 0; qq < 3; ++qq)
 #pragma unroll
-                    for (int r = 0; r < 3; ++r)
+                        for (int r = 0; r < 3; ++r)
 #pragma unroll
-                        for (int ss = 0; ss < 3; ++ss) {
-                            R v = R(0);
+                            for (int ss = 0; ss < 3; ++ss) {
+                                R v = R(0);
 #pragma unroll
-                            for (int p = 0; p < 3; ++p) {
-                                const int I = midx(p, qq), J = midx(r, ss);
-                                v += fh[aa][p] * Cm[I][J] / (mw<R>(I) * mw<R>(J));
+                                for (int p = 0; p < 3; ++p) {
+                                    const int I = midx(p, qq), J = midx(r, ss);
+                                    v += fh[aa][p] * Cm[I][J] * (R(1) / (mw<R>(I) * mw<R>(J)));
+                                }
+                                Y[qq][r][ss] = v;
                             }
-                            Y[qq][r][ss] = v;
-                        }
-                static_for<aa, 3>([&](auto BB) {
-                    constexpr int bb = decltype(BB)::value;
-                    R Ah[3][3];
+                    static_for<aa, 3>([&](auto BB) {
+                        constexpr int bb = decltype(BB)::value;
+                        constexpr int k = pair_index(aa, bb) - 3 * ph;
 #pragma unroll
-                    for (int qq = 0; qq < 3; ++qq)
+                        for (int qq = 0; qq < 3; ++qq)
 #pragma unroll
-                        for (int ss = 0; ss < 3; ++ss) {
-                            R v = fh[bb][0] * Y[qq][0][ss] + fh[bb][1] * Y[qq][1][ss] + fh[bb][2] * Y[qq][2][ss];
-                            if (aa == bb) v += Sh[qq][ss];
-                            Ah[qq][ss] = wdet * v;
-                        }
-                    R Xq[3][8];
+                            for (int ss = 0; ss < 3; ++ss) {
+                                R v = fh[bb][0] * Y[qq][0][ss] + fh[bb][1] * Y[qq][1][ss] + fh[bb][2] * Y[qq][2][ss];
+                                if (aa == bb) v += Sh[qq][ss];
+                                sA[slot][gp][9 * k + 3 * qq + ss] = wdet * v;
+                            }
+                    });
+                });
+                __syncthreads();
+                // lane gp = row I
+                R acc[3][8];
 #pragma unroll
-                    for (int qq = 0; qq < 3; ++qq)
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int J = 0; J < 8; ++J) acc[k][J] = R(0);
+#pragma unroll 2
+                for (int g = 0; g < 8; ++g) {
+                    R G[24], A[28], gi[3];
+#pragma unroll
+                    for (int t = 0; t < 24; ++t) G[t] = sG[slot][g][t];
+#pragma unroll
+                    for (int t = 0; t < 28; ++t) A[t] = sA[slot][g][t];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) gi[q] = sG[slot][g][3 * gp + q];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        R t3[3];
+#pragma unroll
+                        for (int ss = 0; ss < 3; ++ss)
+                            t3[ss] = gi[0] * A[9 * k + ss] + gi[1] * A[9 * k + 3 + ss] + gi[2] * A[9 * k + 6 + ss];
 #pragma unroll
                         for (int J = 0; J < 8; ++J)
-                            Xq[qq][J] = Ah[qq][0] * gh[J][0] + Ah[qq][1] * gh[J][1] + Ah[qq][2] * gh[J][2];
-#pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-#pragma unroll
-                        for (int il = 0; il < 4; ++il)
-#pragma unroll
-                            for (int J = 0; J < 8; ++J) {
-                                const int I = 4 * half + il;
-                                red[il * 8 + J][tid] = gh[I][0] * Xq[0][J] + gh[I][1] * Xq[1][J] + gh[I][2] * Xq[2][J];
-                            }
-                        __syncthreads();
-                        if (valid) {
-                            // lane gp sums block entries I = 4 half + gp/2, J = 4 (gp&1) + 0..3
-                            // and stores them at ((p*2 + half)*8 + gp)*4 of the element's 384
-                            const int il = gp >> 1, jb = (gp & 1) * 4;
-                            RO v4[4];
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                R sum = R(0);
-#pragma unroll
-                                for (int g2 = 0; g2 < 8; ++g2) sum += red[il * 8 + jb + j][slot * 8 + g2];
-                                v4[j] = (RO)sum;
-                            }
-                            constexpr int pidx = aa * 3 - (aa * (aa - 1)) / 2 + (bb - aa);
-                            RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * 384 + ((pidx * 2 + half) * 8 + gp) * 4;
-                            store4<RO>(Kd, v4);
-                        }
-                        __syncthreads();
+                            acc[k][J] += t3[0] * G[3 * J] + t3[1] * G[3 * J + 1] + t3[2] * G[3 * J + 2];
                     }
-                });
+                }
+                if (valid) {
+                    // stored layout: [pair p][I][J], p = 3 ph + k
+                    RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * 384 + (3 * ph) * 64 + gp * 8;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        RO v4[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][j];
+                        store4<RO>(Kd + k * 64, v4);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][4 + j];
+                        store4<RO>(Kd + k * 64 + 4, v4);
+                    }
+                }
+                __syncthreads();
             });
         }
         __syncthreads();
@@ -462,42 +515,47 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
 
 // ---- row-owner assembly
 
-// Offset of K^e_{Ia,Jb} (a <= b) in an element's 384 stored block entries.
-__device__ inline int ke_offset(int p, int I, int J) {
-    return ((p * 2 + (I >> 2)) * 8 + (((I & 3) << 1) | (J >> 2))) * 4 + (J & 3);
-}
-__host__ __device__ constexpr int pair_index(int a, int b) { return a * 3 - (a * (a - 1)) / 2 + (b - a); }
 
-// R_I = sum over the elements around node I (ascending) of R^e_i; Dirichlet
-// rows zeroed; per-workgroup partial sums of R^2 for the norm.
-__global__ void assemble_residual(int32_t n_nodes, const int32_t* __restrict__ ne_ptr,
-                                  const int32_t* __restrict__ ne_list, const double* __restrict__ Re,
-                                  const uint8_t* __restrict__ bc, double* __restrict__ Rv,
-                                  double* __restrict__ part) {
-    __shared__ double sh[256];
-    const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-    double sq = 0.0;
+// R_I = sum of R^e_i over the elements around node I; 8 lanes per node, lane
+// k taking incident elements k, k+8, ... in ascending order, then a fixed
+// butterfly over the 8 lanes (bitwise reproducible).  Dirichlet dofs are
+// zeroed; per-workgroup partial sums of R^2 go to `part` for the norm.
+// Workgroups are mapped to 8 contiguous node ranges, one per XCD.
+constexpr int kResThreads = 256;  // 32 nodes per workgroup
+__global__ __launch_bounds__(kResThreads) void assemble_residual(
+    int32_t n_nodes, int64_t n_chunk, const int32_t* __restrict__ ne_ptr, const int32_t* __restrict__ ne_list,
+    const double* __restrict__ Re, const uint8_t* __restrict__ bc, double* __restrict__ Rv,
+    double* __restrict__ part) {
+    __shared__ double sh[kResThreads];
+    const int64_t grp = (int64_t)(blockIdx.x & 7) * n_chunk + (blockIdx.x >> 3);
+    const int64_t n = grp * (kResThreads / 8) + (threadIdx.x >> 3);
+    const int k = (int)(threadIdx.x & 7);
+    double acc[3] = {0.0, 0.0, 0.0};
     if (n < n_nodes) {
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int32_t k = ne_ptr[n]; k < ne_ptr[n + 1]; ++k) {
-            const int64_t v = ne_list[k];  // 8 e + i
+        const int32_t k1 = ne_ptr[n + 1];
+        for (int32_t c = ne_ptr[n] + k; c < k1; c += 8) {
+            const int64_t v = ne_list[c];  // 8 e + i
             const double* src = Re + (v >> 3) * 24 + 3 * (v & 7);
             acc[0] += src[0];
             acc[1] += src[1];
             acc[2] += src[2];
         }
+    }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int64_t dof = 3 * (int64_t)n + c;
-            const double val = (bc && bc[dof]) ? 0.0 : acc[c];
-            Rv[dof] = val;
-            sq += val * val;
-        }
+    for (int m = 1; m < 8; m <<= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], m, 8);
+    double sq = 0.0;
+    if (n < n_nodes && k < 3) {
+        const int64_t dof = 3 * n + k;
+        const double val = (bc && bc[dof]) ? 0.0 : (k == 0 ? acc[0] : (k == 1 ? acc[1] : acc[2]));
+        Rv[dof] = val;
+        sq = val * val;
     }
     if (part) {
         sh[threadIdx.x] = sq;
         __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
+        for (int off = kResThreads / 2; off > 0; off >>= 1) {
             if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
             __syncthreads();
         }
@@ -625,7 +683,11 @@ hipError_t launch_fwd_block(const FwdArgs& a, int block, int grid, hipStream_t s
 constexpr int kFixBlock = 64;
 constexpr int kFixGrid = 1024;
 
-constexpr int kAsmThreads = 256;
+// Workgroups of assemble_residual (= partial sums of the norm) for n nodes.
+inline int64_t residual_blocks(int64_t n_nodes) {
+    const int64_t n_chunk = ((n_nodes + kResThreads / 8 - 1) / (kResThreads / 8) + 7) / 8;
+    return 8 * n_chunk;
+}
 
 struct FwdWs {
     double* Re;
@@ -640,7 +702,7 @@ void carve_forward(C& c, int32_t n_nodes, int32_t n_elems, fem_precision prec, F
     const size_t kb = (prec == FEM_FP64) ? sizeof(double) : sizeof(float);
     auto re = c.template take<double>((size_t)n_elems * 24 + 1);
     auto ke = c.template take<char>((size_t)n_elems * 384 * kb + 16);
-    auto pa = c.template take<double>((size_t)n_nodes / kAsmThreads + 2);
+    auto pa = c.template take<double>((size_t)residual_blocks(n_nodes) + 1);
     auto fl = c.template take<int32_t>(prec == FEM_FP64 ? 1 : (size_t)n_elems + 1);
     auto fc = c.template take<int32_t>(4);
     if (w) *w = FwdWs{re, (void*)ke, pa, fl, fc};
@@ -746,9 +808,11 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
     }
     const int nn = mesh->n_nodes;
     if (R && nn > 0) {
-        const unsigned nb = (unsigned)((nn + kAsmThreads - 1) / kAsmThreads);
-        hipLaunchKernelGGL(assemble_residual, dim3(nb), dim3(kAsmThreads), 0, s, nn, csr->node_elem_ptr,
+        const int64_t nb = residual_blocks(nn), n_chunk = nb / 8;
+        void* tr = timing_begin(s);
+        hipLaunchKernelGGL(assemble_residual, dim3((unsigned)nb), dim3(kResThreads), 0, s, nn, n_chunk, csr->node_elem_ptr,
                            csr->node_elem, w.Re, bc_mask, R, rnorm2 ? w.part : nullptr);
+        timing_end(tr, FEM_KERNEL_ASSEMBLE_R, s);
         FEM_HIP_CHECK(hipGetLastError());
         if (rnorm2) {
             hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormThreads), 0, s, w.part, (int)nb, rnorm2);
@@ -760,6 +824,7 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
     if (K_vals && nn > 0 && csr->nnz > 0) {
         const int64_t n_chunk = ((nn + kTanWaves - 1) / kTanWaves + 7) / 8;
         const unsigned nb = (unsigned)(8 * n_chunk);
+        void* tk = timing_begin(s);
         if (prec == FEM_FP64)
             hipLaunchKernelGGL(assemble_tangent<double>, dim3(nb), dim3(64 * kTanWaves), 0, s, nn, n_chunk,
                                csr->node_elem_ptr, csr->node_elem, csr->elem_rank, csr->row_ptr, csr->col_idx,
@@ -768,6 +833,7 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
             hipLaunchKernelGGL(assemble_tangent<float>, dim3(nb), dim3(64 * kTanWaves), 0, s, nn, n_chunk,
                                csr->node_elem_ptr, csr->node_elem, csr->elem_rank, csr->row_ptr, csr->col_idx,
                                reinterpret_cast<const float*>(w.Ke), bc_mask, reinterpret_cast<float*>(K_vals));
+        timing_end(tk, FEM_KERNEL_ASSEMBLE_K, s);
         FEM_HIP_CHECK(hipGetLastError());
     }
     return FEM_OK;

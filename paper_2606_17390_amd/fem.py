@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfem.so")
 FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOMEM, FEM_EOVERFLOW, FEM_EMESH = 0, -1, -2, -3, -4, -5
 FP64, FP32_MIXED = 0, 1
 NPARAM, NGRAD = 11, 7
-KERNEL_FORWARD, KERNEL_VJP = 0, 1
+KERNEL_FORWARD, KERNEL_VJP, KERNEL_ASSEMBLE_K, KERNEL_ASSEMBLE_R = 0, 1, 2, 3
 
 _c_i32, _c_i64, _c_u32, _c_p, _c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
 
