@@ -75,8 +75,8 @@ def kernel_bytes(p, nnz, prec_mixed, per_elem_cols, n_bc_rows, bc_row_nnz):
     ne, nn = p.n_elems, p.n_nodes
     ngp = 8 * ne
     kb = 4 if prec_mixed else 8
-    fwd = nn * 48 + ne * 32 + ngp * 56 + ne * 8 * per_elem_cols + ngp * 56 + ne * 24 * 8 + ne * 384 * kb
-    asm_k = (ne * 384 * kb + ne * 64 + ne * 8 * 4 + (nn + 1) * 4 + (3 * nn + 1) * 4 + 3 * nn
+    fwd = nn * 48 + ne * 32 + ngp * 56 + ne * 8 * per_elem_cols + ngp * 56 + ne * 24 * 8 + ne * 300 * kb
+    asm_k = (ne * 300 * kb + ne * 64 + ne * 8 * 4 + (nn + 1) * 4 + (3 * nn + 1) * 4 + 3 * nn
              + nnz * kb + bc_row_nnz * 4)
     asm_r = ne * 24 * 8 + ne * 8 * 4 + (nn + 1) * 4 + 3 * nn + 3 * nn * 8
     return {"fwd_kernel": fwd, "assemble_tangent": asm_k, "assemble_residual": asm_r}

@@ -22,6 +22,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions disabled
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP32 division and square root by the hardware reciprocal / square-root
+    # approximations (about 1 ulp) instead of correctly rounded sequences; only
+    # the FP32 part of the mixed-precision path uses them
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function",
 ]

@@ -43,6 +43,9 @@ __device__ inline float m_abs(float x) { return __builtin_fabsf(x); }
 __device__ inline double m_abs(double x) { return __builtin_fabs(x); }
 __device__ inline float m_sinh(float x) { return sinhf(x); }
 __device__ inline double m_sinh(double x) { return sinh(x); }
+// c + a b as one fused multiply-add
+__device__ inline float m_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double m_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <typename R> struct Eps;
 template <> struct Eps<double> {

@@ -15,8 +15,8 @@
 //   K^e_IaJb = sum_g w detJ0 dN_I/dX_A (delta_ab S_AB + F_aC C_CADB F_bD) dN_J/dX_B
 // are formed per Gauss point in the eigenframe (g^ = Q^T grad N, f^ = F Q),
 // summed over the 8 lanes of an element through LDS and stored, with
-// coalesced vector stores, as the element's 24 residual entries and the 384
-// entries of its six (a <= b) component blocks in a workspace.
+// coalesced stores, as the element's 24 residual entries and the 300 distinct
+// entries of its symmetric tangent in a workspace.
 //
 // Assembly (App. E, Alg. E1, without triplets or atomics): the owner of each
 // node gathers, in ascending element order, the blocks of the elements
@@ -44,7 +44,7 @@ struct FwdArgs {
     const double* d;
     const double* hist_n;
     double* Re;      // [n_elems][24] element residuals
-    void* Ke;        // [n_elems][384] element tangent blocks (R), or null
+    void* Ke;        // [n_elems][300] element tangent entries (RO), or null
     double* hist_np1;
     int32_t* diag;
     int64_t n_gp;
@@ -92,11 +92,28 @@ __device__ inline Mat load_material(const A& a, int64_t e) {
     return m;
 }
 
-// Element tangent blocks K^e_{Ia,Jb}, a <= b, are stored per element as 6
-// pair blocks p(a,b) (order (0,0),(0,1),(0,2),(1,1),(1,2),(2,2)) of 8x8
-// node entries: offset p*64 + 8 I + J of the element's 384.
+// The symmetric element tangent is stored as its 300 distinct entries: the 6
+// component-pair blocks K^e_{Ia,Jb}, a <= b, in the order (0,0),(0,1),(0,2),
+// (1,1),(1,2),(2,2); a diagonal block (a = b) as the upper triangle J >= I of
+// its 8x8 node entries, row by row (36), an off-diagonal block as the full
+// 8x8, row-major (64).
+constexpr int kKeStride = 300;
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * 3 - (a * (a - 1)) / 2 + (b - a); }
-__device__ inline int ke_offset(int p, int I, int J) { return p * 64 + 8 * I + J; }
+__host__ __device__ constexpr int pair_base(int p) {
+    // 36 for p = 0, 3, 5 (diagonal), 64 for p = 1, 2, 4
+    return p == 0 ? 0 : p == 1 ? 36 : p == 2 ? 100 : p == 3 ? 164 : p == 4 ? 200 : 264;
+}
+__host__ __device__ constexpr bool pair_diag(int p) { return p == 0 || p == 3 || p == 5; }
+// start of row I of a diagonal block's triangle (entries J = I..7)
+__host__ __device__ constexpr int tri_row(int I) { return 8 * I - (I * (I - 1)) / 2; }
+// offset of K^e_{Ia,Jb} for the pair block p = p(a,b), a <= b, any I, J
+__device__ inline int ke_offset(int p, int I, int J) {
+    if (pair_diag(p)) {
+        const int lo = I < J ? I : J, hi = I < J ? J : I;
+        return pair_base(p) + tri_row(lo) + (hi - lo);
+    }
+    return pair_base(p) + 8 * I + J;
+}
 
 // Tile range of this workgroup in a persistent launch.  Workgroups are
 // dispatched round-robin over the 8 XCDs; with xcd_remap the tiles are cut in
@@ -420,6 +437,16 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
 #pragma unroll
             for (int I = 0; I < 6; ++I) fin = fin && isfinite((double)Cm[I][I]);
             if (valid && !fin && !FIXUP) ++cnt_nan;
+            // tensor components C4(p,q,r,s) = Cm[I][J] / (w_I w_J) (Mandel weights)
+            R C4[6][6];
+#pragma unroll
+            for (int I = 0; I < 6; ++I)
+#pragma unroll
+                for (int J = I; J < 6; ++J) {
+                    constexpr R h = R(0.5), r2 = R(kInvSqrt2);
+                    const R sc = (I < 3 && J < 3) ? R(1) : ((I < 3 || J < 3) ? r2 : h);
+                    C4[I][J] = C4[J][I] = (I < 3 && J < 3) ? Cm[I][J] : sc * Cm[I][J];
+                }
 
             // ---- element tangent blocks K^e(a,b), a <= b:
             //      K^e_{Ia,Jb} = sum_g w detJ0 g^_Iq A^(a,b)_qs g^_Js  (per Gauss point g)
@@ -430,7 +457,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                 constexpr int ph = decltype(PH)::value;
                 static_for<ph, ph + 1 + ph>([&](auto AA) {
                     constexpr int aa = decltype(AA)::value;
-                    // Y[q][r][s] = sum_p f^_ap C4(p,q,r,s)
+                    // Y[q][r][s] = sum_p f^_ap C4(p,q,r,s), C4 = the tensor components of Cm
                     R Y[3][3][3];
 #pragma unroll
                     for (int qq = 0; qq < 3; ++qq)
@@ -438,13 +465,10 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                         for (int r = 0; r < 3; ++r)
 #pragma unroll
                             for (int ss = 0; ss < 3; ++ss) {
-                                R v = R(0);
-#pragma unroll
-                                for (int p = 0; p < 3; ++p) {
-                                    const int I = midx(p, qq), J = midx(r, ss);
-                                    v += fh[aa][p] * Cm[I][J] * (R(1) / (mw<R>(I) * mw<R>(J)));
-                                }
-                                Y[qq][r][ss] = v;
+                                const int J = midx(r, ss);
+                                R v = fh[aa][0] * C4[midx(0, qq)][J];
+                                v = m_fma(fh[aa][1], C4[midx(1, qq)][J], v);
+                                Y[qq][r][ss] = m_fma(fh[aa][2], C4[midx(2, qq)][J], v);
                             }
                     static_for<aa, 3>([&](auto BB) {
                         constexpr int bb = decltype(BB)::value;
@@ -480,25 +504,36 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                         R t3[3];
 #pragma unroll
                         for (int ss = 0; ss < 3; ++ss)
-                            t3[ss] = gi[0] * A[9 * k + ss] + gi[1] * A[9 * k + 3 + ss] + gi[2] * A[9 * k + 6 + ss];
+                            t3[ss] = m_fma(gi[2], A[9 * k + 6 + ss], m_fma(gi[1], A[9 * k + 3 + ss], gi[0] * A[9 * k + ss]));
 #pragma unroll
-                        for (int J = 0; J < 8; ++J)
-                            acc[k][J] += t3[0] * G[3 * J] + t3[1] * G[3 * J + 1] + t3[2] * G[3 * J + 2];
+                        for (int J = 0; J < 8; ++J) {
+                            R v = m_fma(t3[0], G[3 * J], acc[k][J]);
+                            v = m_fma(t3[1], G[3 * J + 1], v);
+                            acc[k][J] = m_fma(t3[2], G[3 * J + 2], v);
+                        }
                     }
                 }
                 if (valid) {
-                    // stored layout: [pair p][I][J], p = 3 ph + k
-                    RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * 384 + (3 * ph) * 64 + gp * 8;
+                    // row I = gp of the pair blocks p = 3 ph + k
+                    RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * kKeStride;
+                    static_for<0, 3>([&](auto KK) {
+                        constexpr int k = decltype(KK)::value;
+                        constexpr int p = 3 * ph + k;
+                        if constexpr (pair_diag(p)) {
+                            RO* row = Kd + pair_base(p) + tri_row(gp) - gp;  // + J for J >= I
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        RO v4[4];
+                            for (int J = 0; J < 8; ++J)
+                                if (J >= gp) row[J] = (RO)acc[k][J];
+                        } else {
+                            RO v4[4];
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][j];
-                        store4<RO>(Kd + k * 64, v4);
+                            for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][j];
+                            store4<RO>(Kd + pair_base(p) + 8 * gp, v4);
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][4 + j];
-                        store4<RO>(Kd + k * 64 + 4, v4);
-                    }
+                            for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][4 + j];
+                            store4<RO>(Kd + pair_base(p) + 8 * gp + 4, v4);
+                        }
+                    });
                 }
                 __syncthreads();
             });
@@ -608,7 +643,7 @@ __global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
         if (c + kk < k1) {
             const int64_t v = ne_list[c + kk];  // 8 e + i
             const int i = (int)(v & 7);
-            const R* blk = Ke + (v >> 3) * 384;
+            const R* blk = Ke + (v >> 3) * kKeStride;
 #pragma unroll
             for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
@@ -701,7 +736,7 @@ template <typename C>
 void carve_forward(C& c, int32_t n_nodes, int32_t n_elems, fem_precision prec, FwdWs* w) {
     const size_t kb = (prec == FEM_FP64) ? sizeof(double) : sizeof(float);
     auto re = c.template take<double>((size_t)n_elems * 24 + 1);
-    auto ke = c.template take<char>((size_t)n_elems * 384 * kb + 16);
+    auto ke = c.template take<char>((size_t)n_elems * kKeStride * kb + 16);
     auto pa = c.template take<double>((size_t)residual_blocks(n_nodes) + 1);
     auto fl = c.template take<int32_t>(prec == FEM_FP64 ? 1 : (size_t)n_elems + 1);
     auto fc = c.template take<int32_t>(4);
