@@ -33,15 +33,15 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # Counted VALU flops per Gauss point of the main element kernel on the 100^3
-# cube: rocprofv3 --pmc SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F{32,64}, 64 lanes per
-# wave instruction, FMA = 2 flop, summed over F32 and F64, divided by the
-# 8e6 Gauss points (profiles/fwd_kernel_large_cube_valu.txt).  None until
+# cube: rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP32/_FP64/_FP32_TRANS/_FP64_TRANS
+# (per wave instruction; x 64 lanes), summed over one launch, divided by the
+# 8e6 Gauss points (profiles/fwd_kernel_large_cube_valu.md).  None where not
 # counted for the kernel as it stands.
-FLOP_PER_GP = {"mixed": None, "fp64": None}
+FLOP_PER_GP = {"mixed": 7756.7, "fp64": None}
 # HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a
-# plain 1 GiB copy, profiles/hbm_traffic_large_cube.txt); None until taken
-# for the kernel as it stands.
-TRAFFIC_BYTES = {"fwd_kernel": None, "assemble_tangent": None, "assemble_residual": None}
+# plain 1 GiB copy), profiles/hbm_traffic_large_cube_mixed.md; None where not
+# taken for the kernel as it stands.
+TRAFFIC_BYTES = {"fwd_kernel": 2.638e9, "assemble_tangent": 3.571e9, "assemble_residual": 3.664e8}
 
 
 def log(*a):

@@ -66,8 +66,4 @@ bool timing_on();
 void* timing_begin(hipStream_t s);
 void timing_end(void* token, int kernel, hipStream_t s);
 
-// Fixed grid of the deterministic two-stage norm reduction.
-constexpr int kNormBlocks = 512;
-constexpr int kNormThreads = 256;
-
 }  // namespace fem

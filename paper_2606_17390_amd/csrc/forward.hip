@@ -686,17 +686,29 @@ __global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
     }
 }
 
-__global__ void norm_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
-    __shared__ double sh[kNormThreads];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
-    sh[threadIdx.x] = s;
+// ||R||^2 = sum of the residual workgroups' partial sums: each thread adds a
+// fixed strided subset (4 independent chains), then a fixed tree.
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void norm_final(const double* __restrict__ part, int nb,
+                                                         double* __restrict__ out) {
+    __shared__ double sh[kFinThreads];
+    const int t = (int)threadIdx.x;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = t;
+    for (; i + 3 * kFinThreads < nb; i += 4 * kFinThreads) {
+        s0 += part[i];
+        s1 += part[i + kFinThreads];
+        s2 += part[i + 2 * kFinThreads];
+        s3 += part[i + 3 * kFinThreads];
+    }
+    for (; i < nb; i += kFinThreads) s0 += part[i];
+    sh[t] = (s0 + s1) + (s2 + s3);
     __syncthreads();
-    for (int off = kNormThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    for (int off = kFinThreads / 2; off > 0; off >>= 1) {
+        if (t < off) sh[t] += sh[t + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = sh[0];
+    if (t == 0) out[0] = sh[0];
 }
 
 template <typename R, typename RO, int BLOCK, bool FIXUP>
@@ -850,7 +862,7 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         timing_end(tr, FEM_KERNEL_ASSEMBLE_R, s);
         FEM_HIP_CHECK(hipGetLastError());
         if (rnorm2) {
-            hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormThreads), 0, s, w.part, (int)nb, rnorm2);
+            hipLaunchKernelGGL(norm_final, dim3(1), dim3(kFinThreads), 0, s, w.part, (int)nb, rnorm2);
             FEM_HIP_CHECK(hipGetLastError());
         }
     } else if (rnorm2) {
