@@ -37,11 +37,11 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # (per wave instruction; x 64 lanes), summed over one launch, divided by the
 # 8e6 Gauss points (profiles/fwd_kernel_large_cube_valu.md).  None where not
 # counted for the kernel as it stands.
-FLOP_PER_GP = {"mixed": 7756.7, "fp64": None}
+FLOP_PER_GP = {"mixed": None, "fp64": None}
 # HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a
 # plain 1 GiB copy), profiles/hbm_traffic_large_cube_mixed.md; None where not
 # taken for the kernel as it stands.
-TRAFFIC_BYTES = {"fwd_kernel": 2.638e9, "assemble_tangent": 3.571e9, "assemble_residual": 3.664e8}
+TRAFFIC_BYTES = {"fwd_kernel": None, "assemble_tangent": None, "assemble_residual": 3.664e8}
 
 
 def log(*a):
@@ -75,8 +75,8 @@ def kernel_bytes(p, nnz, prec_mixed, per_elem_cols, n_bc_rows, bc_row_nnz):
     ne, nn = p.n_elems, p.n_nodes
     ngp = 8 * ne
     kb = 4 if prec_mixed else 8
-    fwd = nn * 48 + ne * 32 + ngp * 56 + ne * 8 * per_elem_cols + ngp * 56 + ne * 24 * 8 + ne * 300 * kb
-    asm_k = (ne * 300 * kb + ne * 64 + ne * 8 * 4 + (nn + 1) * 4 + (3 * nn + 1) * 4 + 3 * nn
+    fwd = nn * 48 + ne * 32 + ngp * 56 + ne * 8 * per_elem_cols + ngp * 56 + ne * 24 * 8 + ne * 576 * kb
+    asm_k = (ne * 576 * kb + ne * 64 + ne * 8 * 4 + (nn + 1) * 4 + (3 * nn + 1) * 4 + 3 * nn
              + nnz * kb + bc_row_nnz * 4)
     asm_r = ne * 24 * 8 + ne * 8 * 4 + (nn + 1) * 4 + 3 * nn + 3 * nn * 8
     return {"fwd_kernel": fwd, "assemble_tangent": asm_k, "assemble_residual": asm_r}

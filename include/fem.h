@@ -185,7 +185,7 @@ int fem_csr_pattern(const fem_mesh *mesh, fem_csr *csr, void *ws, size_t ws_byte
  *   diag     device [4] int32 counters (local Newton not converged, detJ0 <= 0,
  *            det F <= 0, non-finite values), or NULL
  *   ws       device workspace of fem_forward_workspace_bytes(n_nodes, n_elems,
- *            prec) bytes (element residuals and tangents: 192 + 300*sizeof(K)
+ *            prec) bytes (element residuals and tangents: 192 + 576*sizeof(K)
  *            bytes per element)
  * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP.
  */

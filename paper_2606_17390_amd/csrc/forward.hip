@@ -15,8 +15,8 @@
 //   K^e_IaJb = sum_g w detJ0 dN_I/dX_A (delta_ab S_AB + F_aC C_CADB F_bD) dN_J/dX_B
 // are formed per Gauss point in the eigenframe (g^ = Q^T grad N, f^ = F Q),
 // summed over the 8 lanes of an element through LDS and stored, with
-// coalesced stores, as the element's 24 residual entries and the 300 distinct
-// entries of its symmetric tangent in a workspace.
+// coalesced stores, as the element's 24 residual entries and its 24x24
+// tangent, row by row, in a workspace.
 //
 // Assembly (App. E, Alg. E1, without triplets or atomics): the owner of each
 // node gathers, in ascending element order, the blocks of the elements
@@ -44,7 +44,7 @@ struct FwdArgs {
     const double* d;
     const double* hist_n;
     double* Re;      // [n_elems][24] element residuals
-    void* Ke;        // [n_elems][300] element tangent entries (RO), or null
+    void* Ke;        // [n_elems][576] element tangent rows (RO), or null
     double* hist_np1;
     int32_t* diag;
     int64_t n_gp;
@@ -92,28 +92,19 @@ __device__ inline Mat load_material(const A& a, int64_t e) {
     return m;
 }
 
-// The symmetric element tangent is stored as its 300 distinct entries: the 6
-// component-pair blocks K^e_{Ia,Jb}, a <= b, in the order (0,0),(0,1),(0,2),
-// (1,1),(1,2),(2,2); a diagonal block (a = b) as the upper triangle J >= I of
-// its 8x8 node entries, row by row (36), an off-diagonal block as the full
-// 8x8, row-major (64).
-constexpr int kKeStride = 300;
+// The element tangent is stored per element as its 9 component blocks
+// K^e_{Ia,Jb}, (a, b) row-major, each an 8x8 node block, row-major: offset
+// 64 (3a + b) + 8 I + J of the element's 576.  Both triangles are stored, so
+// the assembly of node I's rows reads, for each block, 8 consecutive entries
+// of row I per incident element (and no entry twice); the element kernel
+// writes each block as 8 consecutive rows.
+constexpr int kKeStride = 576;
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * 3 - (a * (a - 1)) / 2 + (b - a); }
-__host__ __device__ constexpr int pair_base(int p) {
-    // 36 for p = 0, 3, 5 (diagonal), 64 for p = 1, 2, 4
-    return p == 0 ? 0 : p == 1 ? 36 : p == 2 ? 100 : p == 3 ? 164 : p == 4 ? 200 : 264;
-}
-__host__ __device__ constexpr bool pair_diag(int p) { return p == 0 || p == 3 || p == 5; }
-// start of row I of a diagonal block's triangle (entries J = I..7)
-__host__ __device__ constexpr int tri_row(int I) { return 8 * I - (I * (I - 1)) / 2; }
-// offset of K^e_{Ia,Jb} for the pair block p = p(a,b), a <= b, any I, J
-__device__ inline int ke_offset(int p, int I, int J) {
-    if (pair_diag(p)) {
-        const int lo = I < J ? I : J, hi = I < J ? J : I;
-        return pair_base(p) + tri_row(lo) + (hi - lo);
-    }
-    return pair_base(p) + 8 * I + J;
-}
+__host__ __device__ constexpr int pair_a(int p) { return p < 3 ? 0 : (p < 5 ? 1 : 2); }
+__host__ __device__ constexpr int pair_b(int p) { return p < 3 ? p : (p < 5 ? p - 2 : 2); }
+__host__ __device__ constexpr int ke_offset(int I, int a, int b, int J) { return 64 * (3 * a + b) + 8 * I + J; }
+// slot of an off-diagonal pair (0,1), (0,2), (1,2) in the transpose hand-off
+__host__ __device__ constexpr int offdiag_slot(int p) { return p == 1 ? 0 : (p == 2 ? 1 : 2); }
 
 // Tile range of this workgroup in a persistent launch.  Workgroups are
 // dispatched round-robin over the 8 XCDs; with xcd_remap the tiles are cut in
@@ -453,6 +444,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
             // Each lane hands its g^ and A^ over through LDS, then lane I
             // sums row I of the blocks over the element's 8 Gauss points, in
             // order.  Two phases of 3 blocks: (0,0),(0,1),(0,2); (1,1),(1,2),(2,2).
+            R keep[3][8];  // rows I of the blocks (0,1), (0,2), (1,2)
             static_for<0, 2>([&](auto PH) {
                 constexpr int ph = decltype(PH)::value;
                 static_for<ph, ph + 1 + ph>([&](auto AA) {
@@ -514,29 +506,55 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                     }
                 }
                 if (valid) {
-                    // row I = gp of the pair blocks p = 3 ph + k
+                    // row I = gp of the blocks (a, b), a <= b, p = 3 ph + k
                     RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * kKeStride;
                     static_for<0, 3>([&](auto KK) {
                         constexpr int k = decltype(KK)::value;
                         constexpr int p = 3 * ph + k;
-                        if constexpr (pair_diag(p)) {
-                            RO* row = Kd + pair_base(p) + tri_row(gp) - gp;  // + J for J >= I
+                        RO* row = Kd + ke_offset(gp, pair_a(p), pair_b(p), 0);
+                        RO v4[4];
 #pragma unroll
-                            for (int J = 0; J < 8; ++J)
-                                if (J >= gp) row[J] = (RO)acc[k][J];
-                        } else {
-                            RO v4[4];
+                        for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][j];
+                        store4<RO>(row, v4);
 #pragma unroll
-                            for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][j];
-                            store4<RO>(Kd + pair_base(p) + 8 * gp, v4);
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][4 + j];
-                            store4<RO>(Kd + pair_base(p) + 8 * gp + 4, v4);
-                        }
+                        for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][4 + j];
+                        store4<RO>(row + 4, v4);
                     });
                 }
+                // the off-diagonal rows are kept for the transpose below
+                static_for<0, 3>([&](auto KK) {
+                    constexpr int k = decltype(KK)::value;
+                    constexpr int p = 3 * ph + k;
+                    if constexpr (pair_a(p) != pair_b(p)) {
+#pragma unroll
+                        for (int J = 0; J < 8; ++J) keep[offdiag_slot(p)][J] = acc[k][J];
+                    }
+                });
                 __syncthreads();
             });
+            // blocks (b, a), a < b: row I of (b, a) is column I of (a, b),
+            // handed over through the g^ area (free after the two phases)
+            R* tt = &sG[slot][0][0];  // [3][8 I][8 J]
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+#pragma unroll
+                for (int J = 0; J < 8; ++J) tt[64 * t + 8 * gp + J] = keep[t][J];
+            __syncthreads();
+            if (valid) {
+                RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * kKeStride;
+                static_for<0, 3>([&](auto TT) {
+                    constexpr int t = decltype(TT)::value;
+                    constexpr int p = t == 0 ? 1 : (t == 1 ? 2 : 4);
+                    RO* row = Kd + ke_offset(gp, pair_b(p), pair_a(p), 0);
+                    RO v4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v4[j] = (RO)tt[64 * t + 8 * j + gp];
+                    store4<RO>(row, v4);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v4[j] = (RO)tt[64 * t + 8 * (4 + j) + gp];
+                    store4<RO>(row + 4, v4);
+                });
+            }
         }
         __syncthreads();
     }
@@ -610,7 +628,8 @@ constexpr int kTanWaves = 4;  // nodes (waves) per workgroup of assemble_tangent
 
 // Rows 3I+a of K, one wave per node I.  The node's incident elements are
 // taken 8 at a time: lane (k, j) loads the 3x3 block (i_k, j) of element k
-// (i_k = local index of I in it) and parks it in LDS; then lane r, owner of
+// (i_k = local index of I in it; per load, the 8 lanes of an element read 8
+// consecutive entries of row i_k of one component block) and parks it in LDS; then lane r, owner of
 // column block r (the r-th neighbour J of I in ascending order), adds the
 // parked block of each element whose node j has elem_rank r, in ascending
 // element order.  The node's 3 rows are 9 deg consecutive values of K; they
@@ -634,6 +653,9 @@ __global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
     const int32_t len = row_ptr[3 * n + 1] - rs;  // 3 deg
     const int deg = len / 3;
     const int32_t k0 = ne_ptr[n], k1 = ne_ptr[n + 1];
+    // constrained rows of the node (bit a: row 3n + a), fetched up front
+    uint32_t bcm = 0;
+    if (bc) bcm = (bc[3 * n] ? 1u : 0u) | (bc[3 * n + 1] ? 2u : 0u) | (bc[3 * n + 2] ? 4u : 0u);
     const int kk = lane >> 3, j = lane & 7;
     const uint64_t pat = 0x0101010101010101ull * (uint64_t)lane;
     R acc[9];
@@ -643,15 +665,9 @@ __global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
         if (c + kk < k1) {
             const int64_t v = ne_list[c + kk];  // 8 e + i
             const int i = (int)(v & 7);
-            const R* blk = Ke + (v >> 3) * kKeStride;
+            const R* row = Ke + (v >> 3) * kKeStride + ke_offset(i, 0, 0, j);
 #pragma unroll
-            for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb) {
-                    const int off = (aa <= bb) ? ke_offset(pair_index(aa, bb), i, j)
-                                               : ke_offset(pair_index(bb, aa), j, i);
-                    vals[lane * 9 + aa * 3 + bb] = blk[off];
-                }
+            for (int ab = 0; ab < 9; ++ab) vals[lane * 9 + ab] = row[64 * ab];
             if (j == 0) sr[w][kk] = reinterpret_cast<const uint64_t*>(elem_rank)[v];
         }
         wave_sync();
@@ -677,11 +693,10 @@ __global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
             for (int bb = 0; bb < 3; ++bb) vals[aa * len + 3 * lane + bb] = acc[aa * 3 + bb];
     }
     wave_sync();
-    const bool b0 = bc && bc[3 * n], b1 = bc && bc[3 * n + 1], b2 = bc && bc[3 * n + 2];
     for (int t = lane; t < 3 * len; t += 64) {
         const int aa = (t >= len) + (t >= 2 * len);
         R val = vals[t];
-        if (aa == 0 ? b0 : (aa == 1 ? b1 : b2)) val = (col_idx[rs + t] == 3 * n + aa) ? R(1) : R(0);
+        if ((bcm >> aa) & 1u) val = (col_idx[rs + t] == 3 * n + aa) ? R(1) : R(0);
         K[rs + t] = val;
     }
 }

@@ -43,8 +43,8 @@ def test_version_and_workspace_queries(lib):
     assert lib.fem_version() >= 100
     assert lib.fem_csr_workspace_bytes(125, 64) > 0
     assert lib.fem_csr_workspace_bytes(-1, 0) == 0
-    assert lib.fem_forward_workspace_bytes(125, 64, 1) >= 64 * (24 * 8 + 300 * 4)
-    assert lib.fem_forward_workspace_bytes(125, 64, 0) >= 64 * (24 * 8 + 300 * 8)
+    assert lib.fem_forward_workspace_bytes(125, 64, 1) >= 64 * (24 * 8 + 576 * 4)
+    assert lib.fem_forward_workspace_bytes(125, 64, 0) >= 64 * (24 * 8 + 576 * 8)
     assert lib.fem_vjp_workspace_bytes(64, 1) >= 7 * 64 * 8
 
 
