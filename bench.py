@@ -41,7 +41,7 @@ FLOP_PER_GP = {"mixed": 7756.7, "fp64": None}
 # HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a
 # plain 1 GiB copy), profiles/hbm_traffic_large_cube_mixed.md; None where not
 # taken for the kernel as it stands.
-TRAFFIC_BYTES = {"fwd_kernel": 3.768e9, "assemble_tangent": 3.474e9, "assemble_residual": 3.664e8}
+TRAFFIC_BYTES = {"fwd_kernel": 3.769e9, "assemble_tangent": 3.475e9, "assemble_residual": 3.661e8}
 
 
 def log(*a):
