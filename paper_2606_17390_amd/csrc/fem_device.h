@@ -43,6 +43,23 @@ __device__ inline float m_abs(float x) { return __builtin_fabsf(x); }
 __device__ inline double m_abs(double x) { return __builtin_fabs(x); }
 __device__ inline float m_sinh(float x) { return sinhf(x); }
 __device__ inline double m_sinh(double x) { return sinh(x); }
+// 1/x and 1/sqrt(x) in FP64 for the local update: the hardware estimate
+// refined by two Newton-Raphson steps (quadratic convergence; the result is
+// within about an ulp, for the finite positive normal arguments used here).
+__device__ inline double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ inline double rsqrt_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    double e = __builtin_fma(-x * r, r, 1.0);  // 1 - x r^2
+    r = __builtin_fma(0.5 * r, e, r);
+    e = __builtin_fma(-x * r, r, 1.0);
+    return __builtin_fma(0.5 * r, e, r);
+}
 // c + a b as one fused multiply-add
 __device__ inline float m_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double m_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -425,7 +442,7 @@ __device__ inline void hill_modes(const Mat& m, Modes& h) {
 __device__ inline double swift(const Mat& m, double alpha, double& dsig) {
     const double base = m.eps0 + alpha;
     const double s = m.K * exp(m.nexp * log(base));
-    dsig = m.nexp * s / base;
+    dsig = m.nexp * s * recip(base);
     return s;
 }
 
@@ -473,7 +490,8 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
     double phi2 = 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) phi2 += h.eta[i] * s[i] * s[i];
-    const double phi_tr = sqrt(phi2);
+    // phi_tr = sqrt(phi2) (phi2 = 0 only for a zero deviatoric trial stress)
+    const double phi_tr = phi2 > 0.0 ? phi2 * rsqrt_nr(phi2) : 0.0;
     double dsig_n;
     const double alpha_n = hist_n[6];
     o.sy_n = swift(m, alpha_n, dsig_n);
@@ -509,21 +527,24 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
     double num = 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) num += h.eta[i] * h.eta[i] * s[i] * s[i];
-    const double etab = num / phi2;
+    const double etab = num * recip(phi2);
     double lam = 0.0, lo = 0.0, hi = __builtin_inf();
     double phi = phi_tr, sig = o.sy_n, dsig = dsig_n;
     int conv = 0;
     for (int it = 0; it < 40; ++it) {
         double p2 = 0.0, dp = 0.0;
+        const double c = mu2 * lam;
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
-            const double den = 1.0 / (1.0 + mu2 * lam * h.eta[i]);
+            const double den = recip(1.0 + c * h.eta[i]);
             const double ti = s[i] * den;
-            p2 += h.eta[i] * ti * ti;
-            dp -= mu2 * h.eta[i] * h.eta[i] * ti * ti * den;
+            const double e2 = h.eta[i] * ti * ti;
+            p2 += e2;
+            dp -= mu2 * h.eta[i] * e2 * den;
         }
-        phi = sqrt(p2);
-        dp /= phi;
+        const double iphi = rsqrt_nr(p2);
+        phi = p2 * iphi;
+        dp *= iphi;
         sig = swift(m, alpha_n + lam * phi, dsig);
         const double g = phi - sig;
         if (g > 0.0) lo = lam; else hi = lam;
@@ -531,7 +552,7 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
         if (fabs(g) <= 1e-15 * sig) { conv = 1; break; }
         const double gp = dp - dsig * (phi + lam * dp);
         const double f = 1.0 + mu2 * etab * lam;
-        const double step = -(f * g) / (mu2 * etab * g + f * gp);
+        const double step = -(f * g) * recip(mu2 * etab * g + f * gp);
         double ln = lam + step;
         if (!(ln > lo && ln < hi)) ln = (hi < __builtin_inf()) ? 0.5 * (lo + hi) : 2.0 * lam + 1e-300;
         // step or bracket at the rounding level of lambda
@@ -539,13 +560,15 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
         lam = ln;
     }
     // final state at lambda
-    double tau[5], p2 = 0.0;
+    double tau[5], den[5], p2 = 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        tau[i] = s[i] / (1.0 + mu2 * lam * h.eta[i]);
+        den[i] = recip(1.0 + mu2 * lam * h.eta[i]);
+        tau[i] = s[i] * den[i];
         p2 += h.eta[i] * tau[i] * tau[i];
     }
-    phi = sqrt(p2);
+    const double iphi = rsqrt_nr(p2);
+    phi = p2 * iphi;
     const double dg = lam * phi;
     const double alpha = alpha_n + dg;
     sig = swift(m, alpha, dsig);
@@ -557,7 +580,7 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
     o.dsig = dsig;
     double N[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) N[i] = h.eta[i] * tau[i] / phi;
+    for (int i = 0; i < 5; ++i) N[i] = h.eta[i] * tau[i] * iphi;
     // stress (Cartesian Mandel)
 #pragma unroll
     for (int k = 0; k < 3; ++k) o.T[k] = th * kInvSqrt3 + tau[0] * h.v1[k] + tau[1] * h.v2[k];
@@ -577,15 +600,14 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
     double sv = 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        const double den = 1.0 / (1.0 + mu2 * lam * h.eta[i]);
-        const double a = mu2 * den;
-        o.coef[i] = -mu2 * (mu2 * lam * h.eta[i]) * den;
+        const double a = mu2 * den[i];
+        o.coef[i] = -mu2 * (mu2 * lam * h.eta[i]) * den[i];
         o.mvec[i] = a * N[i];
         o.Nm[i] = N[i];
         sv += o.mvec[i] * N[i];
     }
     o.svar = sv;
-    o.beta = (1.0 - lam * dsig) / (sv + dsig * (1.0 - lam * sv));
+    o.beta = (1.0 - lam * dsig) * recip(sv + dsig * (1.0 - lam * sv));
 }
 
 // ---------------------------------------------------------------- frame helpers

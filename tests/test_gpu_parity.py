@@ -128,6 +128,20 @@ def test_residual_only_and_no_bc(fem):
     assert abs(g["rnorm2"] - o["rnorm2"][1]) <= 1e-10 * o["rnorm2"][1]
 
 
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
+@pytest.mark.parametrize("bc", [True, False])
+def test_residual_same_with_and_without_tangent(fem, prec_name, bc):
+    """R and ||R||^2 are assembled by the tangent kernel when K is requested
+    and by the residual kernel otherwise: the two are bitwise equal."""
+    p = CASES["ragged_13x5x3"]()
+    prec = getattr(fem, prec_name)
+    say(f"residual with/without K: {prec_name} bc={bc}")
+    full = gpu_forward(p, fem, prec, bc=bc, want_K=True)
+    ronly = gpu_forward(p, fem, prec, bc=bc, want_K=False)
+    assert np.array_equal(full["R"], ronly["R"])
+    assert full["rnorm2"] == ronly["rnorm2"]
+
+
 def test_empty_mesh(fem):
     X = np.zeros((0, 3))
     conn = np.zeros((0, 8), dtype=np.int32)
