@@ -182,8 +182,10 @@ int fem_csr_pattern(const fem_mesh *mesh, fem_csr *csr, void *ws, size_t ws_byte
  *   hist_np1 device [7][8*n_elems] updated history for this d (never committed
  *            by the library), or NULL
  *   rnorm2   device [1] FP64 sum of R_i^2 after row elimination, or NULL
- *   diag     device [4] int32 counters (local Newton not converged, detJ0 <= 0,
- *            det F <= 0, non-finite values), or NULL
+ *   diag     device [4] int32 counters of Gauss points (zeroed by the call):
+ *            local Newton not converged, detJ0 <= 0, det F <= 0,
+ *            non-finite stress or tangent (also counted: a node id out of
+ *            range, replaced by node 0); or NULL
  *   ws       device workspace of fem_forward_workspace_bytes(n_nodes, n_elems,
  *            prec) bytes (element residuals and tangents: 192 + 576*sizeof(K)
  *            bytes per element)

@@ -303,6 +303,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
         const R wdet = s.detJ;
 
         // ---- residual: R_Ia = w detJ0 sum_q (f^ S^)_aq g^_Iq
+        bool finite_gp = true;  // P (and the tangent) of this Gauss point finite
         {
             R Ph[3][3];
             bool fin = true;
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                     Ph[i][p] = wdet * (fh[i][0] * Sh[0][p] + fh[i][1] * Sh[1][p] + fh[i][2] * Sh[2][p]);
                     fin = fin && isfinite((double)Ph[i][p]);
                 }
-            if (valid && !fin && !FIXUP) ++cnt_nan;
+            finite_gp = fin;
 #pragma unroll
             for (int I = 0; I < 8; ++I)
 #pragma unroll
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
             bool fin = true;
 #pragma unroll
             for (int I = 0; I < 6; ++I) fin = fin && isfinite((double)Cm[I][I]);
-            if (valid && !fin && !FIXUP) ++cnt_nan;
+            finite_gp = finite_gp && fin;
             // tensor components C4(p,q,r,s) = Cm[I][J] / (w_I w_J) (Mandel weights)
             R C4[6][6];
 #pragma unroll
@@ -556,6 +557,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                 });
             }
         }
+        if (valid && !finite_gp && !FIXUP) ++cnt_nan;
         __syncthreads();
     }
     if (a.diag && !FIXUP) {
