@@ -627,13 +627,16 @@ __device__ inline void wave_sync() {
 }
 
 constexpr int kTanWaves = 4;  // nodes (waves) per workgroup of assemble_tangent
+constexpr int kSlot = 12;     // LDS slot of a parked 3x3 block (padded for 16-byte reads)
 
 // Rows 3I+a of K, one wave per node I.  The node's incident elements are
 // taken 8 at a time: lane (k, j) loads the 3x3 block (i_k, j) of element k
 // (i_k = local index of I in it; per load, the 8 lanes of an element read 8
-// consecutive entries of row i_k of one component block) and parks it in LDS; then lane r, owner of
-// column block r (the r-th neighbour J of I in ascending order), adds the
-// parked block of each element whose node j has elem_rank r, in ascending
+// consecutive entries of row i_k of one component block) and parks it in
+// LDS, and records j in a table at [r][k], r = elem_rank of node j in
+// element k (the column block of node j in row I).  Lane r, owner of column
+// block r (the r-th neighbour J of I in ascending order), then reads its 8
+// table entries at once and adds the parked blocks they name, in ascending
 // element order.  The node's 3 rows are 9 deg consecutive values of K; they
 // are staged in LDS and stored by all 64 lanes, constrained rows replaced by
 // identity rows.  Every entry of K is written exactly once.  Workgroups are
@@ -644,13 +647,14 @@ __global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
     int32_t n_nodes, int64_t n_chunk, const int32_t* __restrict__ ne_ptr, const int32_t* __restrict__ ne_list,
     const uint8_t* __restrict__ elem_rank, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const R* __restrict__ Ke, const uint8_t* __restrict__ bc, R* __restrict__ K) {
-    __shared__ R sv[kTanWaves][64 * 9];
-    __shared__ uint64_t sr[kTanWaves][8];
+    __shared__ __attribute__((aligned(16))) R sv[kTanWaves][64 * kSlot];
+    __shared__ uint64_t stab[kTanWaves][64];  // [r]: byte k = j of element k with rank r, 0xff if none
     const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int64_t grp = (int64_t)(blockIdx.x & 7) * n_chunk + (blockIdx.x >> 3);
     const int64_t n = grp * kTanWaves + w;
     if (n >= n_nodes) return;  // the whole wave; no workgroup barrier below
     R* vals = sv[w];
+    uint8_t* tab = reinterpret_cast<uint8_t*>(stab[w]);
     const int32_t rs = row_ptr[3 * n];
     const int32_t len = row_ptr[3 * n + 1] - rs;  // 3 deg
     const int deg = len / 3;
@@ -659,28 +663,29 @@ __global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
     uint32_t bcm = 0;
     if (bc) bcm = (bc[3 * n] ? 1u : 0u) | (bc[3 * n + 1] ? 2u : 0u) | (bc[3 * n + 2] ? 4u : 0u);
     const int kk = lane >> 3, j = lane & 7;
-    const uint64_t pat = 0x0101010101010101ull * (uint64_t)lane;
     R acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = R(0);
     for (int32_t c = k0; c < k1; c += 8) {
+        stab[w][lane] = ~0ull;
+        wave_sync();
         if (c + kk < k1) {
             const int64_t v = ne_list[c + kk];  // 8 e + i
             const int i = (int)(v & 7);
             const R* row = Ke + (v >> 3) * kKeStride + ke_offset(i, 0, 0, j);
+            R* dst = vals + lane * kSlot;
 #pragma unroll
-            for (int ab = 0; ab < 9; ++ab) vals[lane * 9 + ab] = row[64 * ab];
-            if (j == 0) sr[w][kk] = reinterpret_cast<const uint64_t*>(elem_rank)[v];
+            for (int ab = 0; ab < 9; ++ab) dst[ab] = row[64 * ab];
+            tab[8 * elem_rank[8 * v + j] + kk] = (uint8_t)j;
         }
         wave_sync();
         if (lane < deg) {
             const int nk = min(8, k1 - c);
+            const uint64_t word = stab[w][lane];
             for (int q = 0; q < nk; ++q) {
-                // byte of the rank word equal to this lane's rank (at most one)
-                const uint64_t x = sr[w][q] ^ pat;
-                const uint64_t z = (x - 0x0101010101010101ull) & ~x & 0x8080808080808080ull;
-                if (z) {
-                    const R* src = vals + (q * 8 + (__builtin_ctzll(z) >> 3)) * 9;
+                const uint32_t jj = (uint32_t)(word >> (8 * q)) & 0xffu;
+                if (jj != 0xffu) {
+                    const R* src = vals + (q * 8 + (int)jj) * kSlot;
 #pragma unroll
                     for (int t = 0; t < 9; ++t) acc[t] += src[t];
                 }
