@@ -700,11 +700,18 @@ __global__ __launch_bounds__(64 * kTanWaves) void assemble_tangent(
             for (int bb = 0; bb < 3; ++bb) vals[aa * len + 3 * lane + bb] = acc[aa * 3 + bb];
     }
     wave_sync();
-    for (int t = lane; t < 3 * len; t += 64) {
-        const int aa = (t >= len) + (t >= 2 * len);
-        R val = vals[t];
-        if ((bcm >> aa) & 1u) val = (col_idx[rs + t] == 3 * n + aa) ? R(1) : R(0);
-        K[rs + t] = val;
+    R* __restrict__ Kn = K + rs;  // the node's 3 rows, wave-uniform base
+    const int tot = 3 * len;
+    if (bcm == 0) {
+        for (int t = lane; t < tot; t += 64) Kn[t] = vals[t];
+    } else {
+        const int32_t* __restrict__ cn = col_idx + rs;
+        for (int t = lane; t < tot; t += 64) {
+            const int aa = (t >= len) + (t >= 2 * len);
+            R val = vals[t];
+            if ((bcm >> aa) & 1u) val = (cn[t] == 3 * n + aa) ? R(1) : R(0);
+            Kn[t] = val;
+        }
     }
 }
 
