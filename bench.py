@@ -37,11 +37,11 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # (per wave instruction; x 64 lanes), summed over one launch, divided by the
 # 8e6 Gauss points (profiles/fwd_kernel_large_cube_valu.md).  None where not
 # counted for the kernel as it stands.
-FLOP_PER_GP = {"mixed": 7756.7, "fp64": None}
+FLOP_PER_GP = {"mixed": 7516.4, "fp64": None}
 # HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a
 # plain 1 GiB copy), profiles/hbm_traffic_large_cube_mixed.md; None where not
 # taken for the kernel as it stands.
-TRAFFIC_BYTES = {"fwd_kernel": 3.769e9, "assemble_tangent": 3.475e9, "assemble_residual": 3.661e8}
+TRAFFIC_BYTES = {"fwd_kernel": 3.764e9, "assemble_tangent": 3.475e9, "assemble_residual": 3.661e8}
 
 
 def log(*a):
