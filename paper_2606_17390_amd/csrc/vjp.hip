@@ -109,13 +109,20 @@ __device__ inline void kin_log_v(const double (*nd)[9], int gp, GPv<R>& s, doubl
     }
 }
 
+// The FP32 form is held to two waves per SIMD (a few registers spill; measured
+// faster than one wave per SIMD without spills).
 template <typename R, int BLOCK, bool FIXUP>
-__global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value && !FIXUP ? 2 : 1)))
+void vjp_kernel(const VjpArgs a) {
     constexpr int EPB = BLOCK / 8;
     constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
     __shared__ double sN[EPB][8][9];
     __shared__ double red[7][BLOCK + 1];
     __shared__ int sFlag[EPB];
+    // per lane, across the local update (registers are the limit there): the
+    // frame gradients g^ = Q^T grad N and H, Q
+    __shared__ R sG[EPB][8][24];
+    __shared__ R sHQ[EPB][8][18];
     const int tid = threadIdx.x;
     const int slot = tid >> 3, gp = tid & 7;
     int32_t cnt_fail = 0, cnt_j0 = 0;
@@ -155,10 +162,31 @@ __global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
         GPv<R> s;
         double eps[6];
         kin_log_v<R>(sN[slot], gp, s, eps);
+#pragma unroll
+        for (int I = 0; I < 8; ++I)
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                sG[slot][gp][3 * I + p] = s.g[I][0] * s.Q[0][p] + s.g[I][1] * s.Q[1][p] + s.g[I][2] * s.Q[2][p];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                sHQ[slot][gp][3 * i + j] = s.H[i][j];
+                sHQ[slot][gp][9 + 3 * i + j] = s.Q[i][j];
+            }
+        asm volatile("" ::: "memory");  // the parked values are re-read, not kept in registers
         Modes md;
         hill_modes(mat, md);
         Local loc;
         local_update(eps, hn, mat, md, loc);
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                s.H[i][j] = sHQ[slot][gp][3 * i + j];
+                s.Q[i][j] = sHQ[slot][gp][9 + 3 * i + j];
+            }
         if constexpr (FLAG) {
             // guard band: the element is recomputed in FP64 (fixup launch)
             if (valid && fabs(loc.ftr) < 2e-4 * loc.sy_n) sFlag[slot] = 1;
@@ -170,12 +198,7 @@ __global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
         double gbar[7] = {0, 0, 0, 0, 0, 0, 0};
         if (loc.plastic) {
             // Tbar = P_L : sym(F^T Lambda) in the eigenframe of C
-            R gh[8][3];
-#pragma unroll
-            for (int I = 0; I < 8; ++I)
-#pragma unroll
-                for (int p = 0; p < 3; ++p)
-                    gh[I][p] = s.g[I][0] * s.Q[0][p] + s.g[I][1] * s.Q[1][p] + s.g[I][2] * s.Q[2][p];
+            const R* gh = sG[slot][gp];  // g^_Iq at 3 I + q
             R Lh[3][3];  // Lambda^_aq = sum_I lambda_Ia g^_Iq
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -183,7 +206,7 @@ __global__ __launch_bounds__(BLOCK) void vjp_kernel(const VjpArgs a) {
                 for (int p = 0; p < 3; ++p) {
                     R v = R(0);
 #pragma unroll
-                    for (int I = 1; I < 8; ++I) v += (R)(sN[slot][I][6 + i] - sN[slot][0][6 + i]) * gh[I][p];
+                    for (int I = 1; I < 8; ++I) v += (R)(sN[slot][I][6 + i] - sN[slot][0][6 + i]) * gh[3 * I + p];
                     Lh[i][p] = v;
                 }
             R fh[3][3];
