@@ -135,7 +135,7 @@ const char *fem_last_error(void);
 
 /* Set (cfg != NULL) or reset (cfg == NULL) the launch configuration of an
  * element kernel (FEM_KERNEL_FORWARD or FEM_KERNEL_VJP) for a precision;
- * process-wide.  Defaults: forward {64, 8, 1}, VJP {128, 8, 1}.  Returns
+ * process-wide.  Defaults: {64, 8, 1} for both.  Returns
  * FEM_EINVAL for bad values. */
 int fem_set_launch(int kernel, fem_precision prec, const fem_launch *cfg);
 int fem_get_launch(int kernel, fem_precision prec, fem_launch *cfg);

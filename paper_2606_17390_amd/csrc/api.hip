@@ -80,12 +80,13 @@ int device_cu_count() {
 }
 
 static fem_launch default_launch(int kernel, int prec) {
-    // measured on MI355X (100^3 cube): the forward kernel is fastest with one
-    // wave per workgroup in both precisions
+    // measured on MI355X (100^3 cube, 200x200x2 voided specimen): both element
+    // kernels are fastest with one wave per workgroup in both precisions
     fem_launch c;
-    c.block = (kernel == FEM_KERNEL_FORWARD) ? 64 : 128;
+    c.block = 64;
     c.waves_per_cu = 8;
     c.xcd_remap = 1;
+    (void)kernel;
     (void)prec;
     return c;
 }
@@ -113,6 +114,18 @@ __global__ void zero_kernel(uint4* p16, size_t n16, unsigned char* tail, size_t 
     for (; i < n16; i += stride) p16[i] = z;
     if (blockIdx.x == 0)
         for (size_t t = threadIdx.x; t < ntail; t += blockDim.x) tail[t] = 0;
+}
+
+__global__ void zero_counters_kernel(int32_t* a, int na, int32_t* b, int nb) {
+    const int t = (int)threadIdx.x;
+    if (a && t < na) a[t] = 0;
+    if (b && t < nb) b[t] = 0;
+}
+
+hipError_t zero_counters(int32_t* a, int na, int32_t* b, int nb, hipStream_t s) {
+    if ((!a || na <= 0) && (!b || nb <= 0)) return hipSuccess;
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, s, a, na, b, nb);
+    return hipGetLastError();
 }
 
 hipError_t zero_bytes(void* p, size_t bytes, hipStream_t s) {

@@ -60,6 +60,10 @@ struct WsCounter {
 // captured graph may replay it).
 hipError_t zero_bytes(void* p, size_t bytes, hipStream_t s);
 
+// Zero two small int32 arrays (up to 64 entries each; either may be null) in
+// one launch.
+hipError_t zero_counters(int32_t* a, int na, int32_t* b, int nb, hipStream_t s);
+
 // Kernel timing (fem_timing_enable): returns true if enabled; then
 // timing_begin / timing_end bracket one launch on stream s.
 bool timing_on();

@@ -841,7 +841,8 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
     WsCarver cv(ws, ws_bytes);
     FwdWs w;
     carve_forward(cv, mesh->n_nodes, mesh->n_elems, prec, &w);
-    if (diag) FEM_HIP_CHECK(zero_bytes(diag, 4 * sizeof(int32_t), s));
+    // diag, and the guard-band counter of a mixed pass, start at zero
+    FEM_HIP_CHECK(zero_counters(diag, 4, (ne > 0 && prec == FEM_FP32_MIXED) ? w.fix_count : nullptr, 1, s));
 
     if (ne > 0) {
         const fem_launch cfg = launch_config(FEM_KERNEL_FORWARD, prec);
@@ -867,7 +868,6 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         a.xcd_remap = cfg.xcd_remap;
         a.fix_list = w.fix_list;
         a.fix_count = w.fix_count;
-        if (prec == FEM_FP32_MIXED) FEM_HIP_CHECK(zero_bytes(w.fix_count, sizeof(int32_t), s));
         const int grid = persistent_grid(cfg, a.n_tiles);
         void* tk = timing_begin(s);
         hipError_t e = (prec == FEM_FP64) ? launch_fwd_block<double>(a, cfg.block, grid, s)

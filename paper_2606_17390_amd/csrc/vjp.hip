@@ -319,22 +319,33 @@ void vjp_kernel(const VjpArgs a) {
 }
 
 // g_uniform[s][k] = sum over the elements of specimen s of g_elem[k][e]; one
-// workgroup per (s, k), fixed summation order (deterministic).
-__global__ void reduce_uniform(const double* __restrict__ g_elem, int64_t n_elems, const int64_t* __restrict__ off,
-                               int n_spec, double* __restrict__ g_uniform) {
-    __shared__ double sh[256];
+// workgroup per (s, k): thread t adds elements t, t + T, t + 2T, ... of the
+// specimen into 8 chains (element t + mT into chain m mod 8), then a fixed
+// tree (deterministic).
+constexpr int kRedThreads = 1024;
+__global__ __launch_bounds__(kRedThreads) void reduce_uniform(const double* __restrict__ g_elem, int64_t n_elems,
+                                                              const int64_t* __restrict__ off,
+                                                              double* __restrict__ g_uniform) {
+    __shared__ double sh[kRedThreads];
     const int sidx = blockIdx.x / FEM_NGRAD, k = blockIdx.x % FEM_NGRAD;
     const int64_t b = off ? off[sidx] : 0, en = off ? off[sidx + 1] : n_elems;
-    double s = 0.0;
-    for (int64_t e = b + threadIdx.x; e < en; e += blockDim.x) s += g_elem[(int64_t)k * n_elems + e];
-    sh[threadIdx.x] = s;
+    const double* __restrict__ gk = g_elem + (int64_t)k * n_elems;
+    double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t e = b + threadIdx.x;
+    for (; e + 7 * kRedThreads < en; e += 8 * kRedThreads) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) c[m] += gk[e + m * kRedThreads];
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        if (e + m * kRedThreads < en) c[m] += gk[e + m * kRedThreads];
+    sh[threadIdx.x] = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) g_uniform[(int64_t)sidx * FEM_NGRAD + k] = sh[0];
-    (void)n_spec;
 }
 
 template <typename R>
@@ -388,7 +399,8 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
     int32_t* fix_list = cv.take<int32_t>((size_t)mesh->n_elems + 1);
     int32_t* fix_count = cv.take<int32_t>(4);
     double* ge = g_elem ? g_elem : ge_ws;
-    if (diag) FEM_HIP_CHECK(zero_bytes(diag, 4 * sizeof(int32_t), s));
+    // diag, and the guard-band counter of a mixed call, start at zero
+    FEM_HIP_CHECK(zero_counters(diag, 4, (ne > 0 && prec == FEM_FP32_MIXED) ? fix_count : nullptr, 1, s));
     if (ne > 0) {
         const fem_launch cfg = launch_config(FEM_KERNEL_VJP, prec);
         VjpArgs a;
@@ -412,7 +424,6 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         a.xcd_remap = cfg.xcd_remap;
         a.fix_list = fix_list;
         a.fix_count = fix_count;
-        if (prec == FEM_FP32_MIXED) FEM_HIP_CHECK(zero_bytes(fix_count, sizeof(int32_t), s));
         const int grid = persistent_grid(cfg, a.n_tiles);
         void* tk = timing_begin(s);
         hipError_t e = (prec == FEM_FP64) ? launch_vjp<double>(a, cfg.block, grid, s)
@@ -428,8 +439,8 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         if (ne == 0) {
             FEM_HIP_CHECK(zero_bytes(g_uniform, sizeof(double) * FEM_NGRAD * n_spec, s));
         } else {
-            hipLaunchKernelGGL(reduce_uniform, dim3(n_spec * FEM_NGRAD), dim3(256), 0, s, ge, ne,
-                               batch ? batch->elem_off : nullptr, n_spec, g_uniform);
+            hipLaunchKernelGGL(reduce_uniform, dim3(n_spec * FEM_NGRAD), dim3(kRedThreads), 0, s, ge, ne,
+                               batch ? batch->elem_off : nullptr, g_uniform);
             FEM_HIP_CHECK(hipGetLastError());
         }
     }
