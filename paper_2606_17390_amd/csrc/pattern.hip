@@ -4,10 +4,13 @@
 //
 // Steps, all on the device:
 //   1. node -> element incidence by counting and a prefix scan;
-//   2. per node, the sorted unique list of nodes sharing an element (<= 64);
+//   2. per node, the sorted unique list of nodes sharing an element (<= 64):
+//      one wave per node sorts the (element, node) candidates of up to 8
+//      incident elements across its lanes and keeps the first of equal ones;
 //   3. row_ptr from a scan of the neighbour counts (rows of one node have
 //      equal length 3*deg);
-//   4. col_idx rows and elem_rank (position of node J in node I's list).
+//   4. col_idx rows and elem_rank (position of node J in node I's list),
+//      written by the same wave per node.
 #include <hip/hip_runtime.h>
 
 #include "fem_internal.h"
@@ -67,19 +70,148 @@ __device__ int node_neighbours(int32_t n, const int32_t* __restrict__ conn, cons
     return cnt;
 }
 
-__global__ void node_degree(int32_t n_nodes, const int32_t* __restrict__ conn, const int64_t* __restrict__ inc_ptr,
-                            const int32_t* __restrict__ inc, int32_t* __restrict__ deg, int32_t* __restrict__ err) {
-    int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+// ---- one wave per node (nodes with at most 8 incident elements; a node with
+// more takes the serial node_neighbours in lane 0)
+
+constexpr int kPatWaves = 4;  // nodes (waves) per workgroup
+
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ascending bitonic sort of one 64-bit key per lane across the wave.
+__device__ inline uint64_t wave_sort64(uint64_t key, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t other = __shfl_xor(key, j, 64);
+            const bool keep_min = (((lane & j) == 0) == ((lane & k) == 0));
+            key = keep_min ? (other < key ? other : key) : (other > key ? other : key);
+        }
+    return key;
+}
+
+// Lane (k, j) proposes node j of incident element k (k < 8); after the sort,
+// the sorted position p knows whether it starts a new value and that value's
+// index among the unique ones.  Returns the number of unique neighbours.
+struct WaveNbr {
+    int deg;
+    bool first;     // sorted position p holds the first copy of its value
+    int32_t value;  // value at sorted position p
+    int uidx;       // its index among the unique values
+    int origin;     // lane whose candidate sits at position p (-1: none)
+};
+__device__ inline WaveNbr wave_neighbours(uint64_t key, int lane) {
+    key = wave_sort64(key, lane);
+    const bool valid = key != ~0ull;
+    const uint64_t prev = __shfl_up(key, 1, 64);
+    const bool first = valid && (lane == 0 || (prev >> 32) != (key >> 32));
+    const uint64_t mask = __ballot(first);
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    WaveNbr r;
+    r.deg = __popcll(mask);
+    r.first = first;
+    r.value = (int32_t)(key >> 32);
+    r.uidx = __popcll(mask & upto) - 1;
+    r.origin = valid ? (int)(key & 63) : -1;
+    return r;
+}
+
+__global__ __launch_bounds__(64 * kPatWaves) void node_degree_w(int32_t n_nodes, const int32_t* __restrict__ conn,
+                                                                 const int64_t* __restrict__ inc_ptr,
+                                                                 const int32_t* __restrict__ inc,
+                                                                 int32_t* __restrict__ deg, int32_t* __restrict__ err) {
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t n = (int64_t)blockIdx.x * kPatWaves + w;
     if (n >= n_nodes) return;
-    int32_t nb[kMaxNbr];
-    int c = node_neighbours(n, conn, inc_ptr, inc, nb);
-    if (c < 0) {
-        atomicOr(err, ERR_DEGREE);
-        c = 0;
-    } else if (c == 0) {
-        atomicOr(err, ERR_ORPHAN);
+    const int64_t k0 = inc_ptr[n], cnt = inc_ptr[n + 1] - k0;
+    int c;
+    if (cnt <= 8) {
+        const int kk = lane >> 3, j = lane & 7;
+        uint64_t key = ~0ull;
+        if (kk < cnt) key = ((uint64_t)(uint32_t)conn[(int64_t)(inc[k0 + kk] >> 3) * 8 + j] << 32) | (uint64_t)lane;
+        c = wave_neighbours(key, lane).deg;
+    } else {
+        int32_t nb[kMaxNbr];
+        c = (lane == 0) ? node_neighbours((int32_t)n, conn, inc_ptr, inc, nb) : 0;
     }
-    deg[n] = c;
+    if (lane == 0) {
+        if (c < 0) {
+            atomicOr(err, ERR_DEGREE);
+            c = 0;
+        } else if (c == 0) {
+            atomicOr(err, ERR_ORPHAN);
+        }
+        deg[n] = c;
+    }
+}
+
+// Column indices of node n's three rows and the elem_rank entries of every
+// (element, local index) pair that is node n.
+__global__ __launch_bounds__(64 * kPatWaves) void node_fill_w(int32_t n_nodes, const int32_t* __restrict__ conn,
+                                                               const int64_t* __restrict__ inc_ptr,
+                                                               const int32_t* __restrict__ inc,
+                                                               const int32_t* __restrict__ row_ptr,
+                                                               int32_t* __restrict__ col_idx,
+                                                               uint8_t* __restrict__ rank) {
+    __shared__ int32_t snb[kPatWaves][kMaxNbr];
+    __shared__ int32_t srk[kPatWaves][64];
+    __shared__ int32_t sdeg[kPatWaves];
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t n = (int64_t)blockIdx.x * kPatWaves + w;
+    if (n >= n_nodes) return;
+    const int64_t k0 = inc_ptr[n], k1 = inc_ptr[n + 1], cnt = k1 - k0;
+    const int kk = lane >> 3, j = lane & 7;
+    int deg;
+    if (cnt <= 8) {
+        int32_t entry = -1;
+        uint64_t key = ~0ull;
+        if (kk < cnt) {
+            entry = inc[k0 + kk];
+            key = ((uint64_t)(uint32_t)conn[(int64_t)(entry >> 3) * 8 + j] << 32) | (uint64_t)lane;
+        }
+        const WaveNbr r = wave_neighbours(key, lane);
+        deg = r.deg;
+        if (r.first) snb[w][r.uidx] = r.value;
+        if (r.origin >= 0) srk[w][r.origin] = r.uidx;
+        wave_sync_lds();
+        if (entry >= 0) rank[(int64_t)entry * 8 + j] = (uint8_t)srk[w][lane];
+    } else {
+        if (lane == 0) {
+            int32_t nb[kMaxNbr];
+            const int c = node_neighbours((int32_t)n, conn, inc_ptr, inc, nb);
+            for (int t = 0; t < c; ++t) snb[w][t] = nb[t];
+            sdeg[w] = c;
+        }
+        wave_sync_lds();
+        deg = sdeg[w];
+        if (deg <= 0) return;  // reported by the counting call
+        for (int64_t c = k0; c < k1; c += 8) {
+            if (c + kk < k1) {
+                const int32_t entry = inc[c + kk];
+                const int32_t v = conn[(int64_t)(entry >> 3) * 8 + j];
+                int lo = 0, hi = deg - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (snb[w][mid] < v) lo = mid + 1;
+                    else hi = mid;
+                }
+                rank[(int64_t)entry * 8 + j] = (uint8_t)lo;
+            }
+        }
+    }
+    int32_t* row = col_idx + row_ptr[3 * n];
+    const int32_t len = 3 * deg;
+    for (int u = lane; u < deg; u += 64) {
+        const int32_t v = snb[w][u];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) row[a * len + 3 * u + b] = 3 * v + b;
+    }
 }
 
 __global__ void node_columns(int32_t n_nodes, const int32_t* __restrict__ conn, const int64_t* __restrict__ inc_ptr,
@@ -118,30 +250,6 @@ __global__ void write_incidence(int32_t n_nodes, const int64_t* __restrict__ inc
         }
         out[p] = v;
     }
-}
-
-__global__ void element_rank(int32_t n_elems, const int32_t* __restrict__ conn, const int32_t* __restrict__ row_ptr,
-                             const int32_t* __restrict__ col_idx, uint8_t* __restrict__ rank) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n_elems * 8) return;
-    const int64_t e = t >> 3;
-    const int i = (int)(t & 7);
-    const int32_t ni = conn[t];
-    const int32_t start = row_ptr[3 * ni];
-    const int32_t deg = (row_ptr[3 * ni + 1] - start) / 3;
-    uint8_t out[8];
-    for (int j = 0; j < 8; ++j) {
-        const int32_t target = 3 * conn[e * 8 + j];
-        int lo = 0, hi = deg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (col_idx[start + 3 * mid] < target) lo = mid + 1;
-            else hi = mid;
-        }
-        out[j] = (uint8_t)lo;
-    }
-    uint8_t* dst = rank + e * 64 + i * 8;
-    for (int j = 0; j < 8; ++j) dst[j] = out[j];
 }
 
 __global__ void write_row_ptr(int32_t n_nodes, const int32_t* __restrict__ deg, const int64_t* __restrict__ dscan,
@@ -290,8 +398,8 @@ int build_incidence(const fem_mesh* m, const PatternWs& w, hipStream_t s) {
         hipLaunchKernelGGL(fill_incidence, dim3((unsigned)((ne8 + T - 1) / T)), dim3(T), 0, s, m->conn, ne8, nn,
                            w.inc_ptr, w.fillc, w.inc);
     if (nn > 0)
-        hipLaunchKernelGGL(node_degree, dim3((unsigned)((nn + T - 1) / T)), dim3(T), 0, s, nn, m->conn, w.inc_ptr,
-                           w.inc, w.deg, w.err);
+        hipLaunchKernelGGL(node_degree_w, dim3((unsigned)((nn + kPatWaves - 1) / kPatWaves)), dim3(64 * kPatWaves), 0,
+                           s, nn, m->conn, w.inc_ptr, w.inc, w.deg, w.err);
     FEM_HIP_CHECK(exclusive_scan(w.deg, nn, w.dscan, w.bsum, s));
     FEM_HIP_CHECK(hipGetLastError());
     return FEM_OK;
@@ -347,16 +455,17 @@ extern "C" int fem_csr_pattern(const fem_mesh* mesh, fem_csr* csr, void* ws, siz
         csr->nnz = 9 * total;
         return FEM_OK;
     }
-    if (nn > 0)
-        hipLaunchKernelGGL(node_columns, dim3((unsigned)((nn + T - 1) / T)), dim3(T), 0, s, nn, mesh->conn, w.inc_ptr,
-                           w.inc, csr->row_ptr, csr->col_idx);
-    const int64_t ne8 = (int64_t)mesh->n_elems * 8;
+    if (nn > 0) {
+        if (csr->elem_rank)
+            hipLaunchKernelGGL(node_fill_w, dim3((unsigned)((nn + kPatWaves - 1) / kPatWaves)), dim3(64 * kPatWaves),
+                               0, s, nn, mesh->conn, w.inc_ptr, w.inc, csr->row_ptr, csr->col_idx, csr->elem_rank);
+        else
+            hipLaunchKernelGGL(node_columns, dim3((unsigned)((nn + T - 1) / T)), dim3(T), 0, s, nn, mesh->conn,
+                               w.inc_ptr, w.inc, csr->row_ptr, csr->col_idx);
+    }
     if (csr->node_elem_ptr && csr->node_elem)
         hipLaunchKernelGGL(write_incidence, dim3((unsigned)((nn + 1 + T - 1) / T)), dim3(T), 0, s, nn, w.inc_ptr,
                            w.inc, csr->node_elem_ptr, csr->node_elem);
-    if (csr->elem_rank && ne8 > 0)
-        hipLaunchKernelGGL(element_rank, dim3((unsigned)((ne8 + T - 1) / T)), dim3(T), 0, s, mesh->n_elems,
-                           mesh->conn, csr->row_ptr, csr->col_idx, csr->elem_rank);
     FEM_HIP_CHECK(hipGetLastError());
     return FEM_OK;
 }

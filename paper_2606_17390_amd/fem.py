@@ -238,30 +238,39 @@ def _ws(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def csr_pattern(mesh, stream=None):
-    """Build the CSR pattern of the tangent (two calls of fem_csr_pattern)."""
+def csr_pattern(mesh, stream=None, out=None):
+    """Build the CSR pattern of the tangent (two calls of fem_csr_pattern).
+    With `out` (a Csr of the same mesh) its buffers are filled again instead
+    of allocating new ones."""
     L = lib()
     dev = mesh.device
     ws_bytes = L.fem_csr_workspace_bytes(mesh.n_nodes, mesh.n_elems)
-    ws = _ws(ws_bytes, dev)
-    row_ptr = torch.empty(3 * mesh.n_nodes + 1, dtype=torch.int32, device=dev)
+    if out is not None and getattr(out, "_ws", None) is not None and out._ws.numel() >= ws_bytes:
+        ws = out._ws
+    else:
+        ws = _ws(ws_bytes, dev)
+    row_ptr = out.row_ptr if out is not None else torch.empty(3 * mesh.n_nodes + 1, dtype=torch.int32, device=dev)
     cm = mesh.c()
     c = FemCsr(3 * mesh.n_nodes, 0, _ptr(row_ptr), None, None)
     s = _stream(stream)
     _check("fem_csr_pattern", L.fem_csr_pattern(ctypes.byref(cm), ctypes.byref(c), _ptr(ws), ws_bytes, s))
     nnz = int(c.nnz)
-    col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
-    elem_rank = torch.empty((max(mesh.n_elems, 1), 64), dtype=torch.uint8, device=dev)
-    ne_ptr = torch.zeros(mesh.n_nodes + 1, dtype=torch.int32, device=dev)
-    ne_list = torch.empty(max(8 * mesh.n_elems, 1), dtype=torch.int32, device=dev)
+    if out is not None and out.nnz == nnz and out.n_rows == 3 * mesh.n_nodes:
+        col_idx, elem_rank, ne_ptr, ne_list = out.col_idx, out.elem_rank, out.node_elem_ptr, out.node_elem
+    else:
+        col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
+        elem_rank = torch.empty((max(mesh.n_elems, 1), 64), dtype=torch.uint8, device=dev)[:mesh.n_elems]
+        ne_ptr = torch.zeros(mesh.n_nodes + 1, dtype=torch.int32, device=dev)
+        ne_list = torch.empty(max(8 * mesh.n_elems, 1), dtype=torch.int32, device=dev)[:8 * mesh.n_elems]
     c.col_idx = col_idx.data_ptr()
     c.elem_rank = elem_rank.data_ptr()
     c.node_elem_ptr = ne_ptr.data_ptr()
     c.node_elem = ne_list.data_ptr()
     if nnz:
         _check("fem_csr_pattern", L.fem_csr_pattern(ctypes.byref(cm), ctypes.byref(c), _ptr(ws), ws_bytes, s))
-    return Csr(row_ptr, col_idx[:nnz], elem_rank[:mesh.n_elems], nnz, 3 * mesh.n_nodes, ne_ptr,
-               ne_list[:8 * mesh.n_elems])
+    csr = Csr(row_ptr, col_idx, elem_rank, nnz, 3 * mesh.n_nodes, ne_ptr, ne_list)
+    csr._ws = ws
+    return csr
 
 
 class Forward:

@@ -63,6 +63,30 @@ def test_pattern_void_specimen_bit_exact(fem):
     assert np.array_equal(csr.elem_rank.cpu().numpy(), rank)
 
 
+def test_pattern_incidence_and_rebuild_in_place(fem):
+    """The node -> element incidence (entries 8 e + i, ascending per node) is
+    the one read off the connectivity, and a rebuild into the buffers of an
+    existing pattern reproduces every array bit for bit."""
+    p = synth.void_specimen()
+    mesh, *_ = gpu_problem(p, fem)
+    csr = fem.csr_pattern(mesh)
+    flat = p.conn.ravel().astype(np.int64)
+    order = np.argsort(flat, kind="stable")  # entries 8 e + i grouped by node, ascending
+    ptr = np.concatenate([[0], np.cumsum(np.bincount(flat, minlength=p.n_nodes))])
+    assert np.array_equal(csr.node_elem_ptr.cpu().numpy(), ptr)
+    assert np.array_equal(csr.node_elem.cpu().numpy(), order)
+    before = [t.cpu().numpy().copy() for t in (csr.row_ptr, csr.col_idx, csr.elem_rank, csr.node_elem_ptr,
+                                                csr.node_elem)]
+    for t in (csr.col_idx, csr.elem_rank, csr.node_elem):
+        t.fill_(0)
+    again = fem.csr_pattern(mesh, out=csr)
+    assert again.col_idx.data_ptr() == csr.col_idx.data_ptr()
+    after = [t.cpu().numpy() for t in (again.row_ptr, again.col_idx, again.elem_rank, again.node_elem_ptr,
+                                       again.node_elem)]
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+
+
 def test_pattern_rejects_bad_meshes(fem):
     X, conn = synth.hex_grid(2, 1, 1)
     mesh = fem.Mesh(np.vstack([X, [[9.0, 9.0, 9.0]]]), conn)  # orphan node
