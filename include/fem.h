@@ -57,7 +57,8 @@ typedef enum {
     FEM_EHIP = -2,      /* a HIP runtime call failed */
     FEM_ENOMEM = -3,    /* workspace smaller than required */
     FEM_EOVERFLOW = -4, /* nnz does not fit in int32 */
-    FEM_EMESH = -5      /* node index out of range, orphan node, more than 64 neighbours */
+    FEM_EMESH = -5,     /* node index out of range, orphan node, more than 64 neighbours */
+    FEM_ENOCONV = -6    /* fem_solve: the relative residual did not reach rtol */
 } fem_status;
 
 typedef enum {
@@ -215,6 +216,35 @@ int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_par
                      const double *d, const double *hist_n, const double *lam, fem_precision prec,
                      double *g_uniform, double *g_elem, int32_t *diag, void *ws, size_t ws_bytes,
                      void *stream);
+
+/*
+ * Linear solve of the global Newton iteration (Sec. 2.2.4: K du = -R, with
+ * the Dirichlet rows of App. E as identity rows, so K is not symmetric).
+ *
+ * fem_csr_spmv -- y = K x for the pattern csr (row_ptr, col_idx, n_rows) and
+ * values K_vals (double for FEM_FP64, float for FEM_FP32_MIXED, as written by
+ * fem_residual_tangent); x, y device [n_rows] doubles (not aliased).  Errors:
+ * FEM_EINVAL, FEM_EHIP.
+ *
+ * fem_solve -- K x = b by BiCGSTAB preconditioned with the inverse diagonal
+ * of K; vectors and scalars in FP64 whatever the type of K.
+ *   b        device [n_rows]
+ *   x        device [n_rows], initial guess in, solution out
+ *   max_iter iteration limit (>= 0); rtol: stop at ||b - K x|| <= rtol ||b||
+ *   iters, rel_res  host outputs (iterations done, final relative residual),
+ *            or NULL
+ *   ws       device workspace of fem_solver_workspace_bytes(n_rows) bytes
+ * The reductions are fixed-order (bitwise reproducible).  Synchronises the
+ * stream once per iteration (the convergence test reads one double back).
+ * Returns FEM_ENOCONV if rtol is not reached (x holds the last iterate).
+ * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOCONV.
+ */
+size_t fem_solver_workspace_bytes(int32_t n_rows);
+int fem_csr_spmv(const fem_csr *csr, const void *K_vals, fem_precision prec, const double *x, double *y,
+                 void *stream);
+int fem_solve(const fem_csr *csr, const void *K_vals, fem_precision prec, const double *b, double *x,
+              int32_t max_iter, double rtol, int32_t *iters, double *rel_res, void *ws, size_t ws_bytes,
+              void *stream);
 
 /*
  * Kernel timing for benchmarks: while enabled, every launch of kernel

@@ -14,7 +14,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfem.so")
 
-FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOMEM, FEM_EOVERFLOW, FEM_EMESH = 0, -1, -2, -3, -4, -5
+FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOMEM, FEM_EOVERFLOW, FEM_EMESH, FEM_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_MIXED = 0, 1
 NPARAM, NGRAD = 11, 7
 KERNEL_FORWARD, KERNEL_VJP, KERNEL_ASSEMBLE_K, KERNEL_ASSEMBLE_R = 0, 1, 2, 3
@@ -54,7 +54,7 @@ _lib = None
 EXPORTS = ("fem_version", "fem_last_error", "fem_set_launch", "fem_get_launch", "fem_csr_workspace_bytes",
            "fem_forward_workspace_bytes", "fem_vjp_workspace_bytes", "fem_csr_pattern", "fem_residual_tangent",
            "fem_residual_vjp", "fem_timing_enable", "fem_timing_read", "fem_graph_begin", "fem_graph_end",
-           "fem_graph_launch", "fem_graph_destroy")
+           "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes", "fem_csr_spmv", "fem_solve")
 
 
 def lib():
@@ -87,6 +87,11 @@ def lib():
     L.fem_graph_end.argtypes = [_c_p, ctypes.POINTER(_c_p)]
     L.fem_graph_launch.argtypes = [_c_p, _c_p]
     L.fem_graph_destroy.argtypes = [_c_p]
+    L.fem_solver_workspace_bytes.argtypes = [_c_i32]
+    L.fem_solver_workspace_bytes.restype = _c_sz
+    L.fem_csr_spmv.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
+    L.fem_solve.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_i32, ctypes.c_double,
+                            ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double), _c_p, _c_sz, _c_p]
     _lib = L
     return L
 
@@ -427,3 +432,42 @@ class ResidualFn(torch.autograd.Function):
         else:
             g = v.g_uniform[0].clone()
         return g.to(ctx.theta_device), None, None, None, None, None
+
+
+# ---------------------------------------------------------------------------
+# linear solve of the Newton iteration
+# ---------------------------------------------------------------------------
+
+def _kprec(K):
+    return FP64 if K.dtype == torch.float64 else FP32_MIXED
+
+
+def csr_spmv(csr, K, x, y=None, stream=None):
+    """y = K x for the CSR values K (float64 or float32) of pattern csr."""
+    if y is None:
+        y = torch.empty(csr.n_rows, dtype=torch.float64, device=x.device)
+    _check("fem_csr_spmv", lib().fem_csr_spmv(ctypes.byref(csr.c()), _ptr(K), _kprec(K), _ptr(x), _ptr(y),
+                                              _stream(stream)))
+    return y
+
+
+class Solver:
+    """Workspace of fem_solve for a pattern (reused across solves)."""
+
+    def __init__(self, csr, device="cuda"):
+        self.csr = csr
+        self.ws_bytes = lib().fem_solver_workspace_bytes(csr.n_rows)
+        self.ws = _ws(self.ws_bytes, device)
+
+    def solve(self, K, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True):
+        """Solve K x = b (BiCGSTAB, Jacobi preconditioner); returns (x, iterations, relative residual)."""
+        if x is None:
+            x = torch.zeros(self.csr.n_rows, dtype=torch.float64, device=b.device)
+        it = _c_i32(0)
+        res = ctypes.c_double(0.0)
+        rc = lib().fem_solve(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), _ptr(b), _ptr(x), int(max_iter),
+                             float(rtol), ctypes.byref(it), ctypes.byref(res), _ptr(self.ws), self.ws_bytes,
+                             _stream(stream))
+        if check:
+            _check("fem_solve", rc)
+        return x, int(it.value), float(res.value)

@@ -1,0 +1,116 @@
+"""The linear solve and the global Newton iteration on the GPU (through the C
+ABI): the CSR product against scipy's, BiCGSTAB against a dense solve, and
+the 4x4x4 uniaxial tension run of 10 load steps against the one-dimensional
+Swift solution (ln(1.02) = sigma/E + alpha, sigma = K (eps0 + alpha)^n; the
+x = 1 face reaction equals sigma / 1.02)."""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import gpu_problem
+from paper_2606_17390_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fem():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2606_17390_amd import fem as F
+    F.lib()
+    return F
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dense(csr, K):
+    import scipy.sparse as sp
+    n = csr.n_rows
+    return sp.csr_matrix((K.double().cpu().numpy(), csr.col_idx.cpu().numpy(), csr.row_ptr.cpu().numpy()),
+                         shape=(n, n))
+
+
+def system(fem, prec):
+    p = synth.small_slab(51, 5, 4, 3)
+    mesh, params, d, h, bc, _ = gpu_problem(p, fem)
+    csr = fem.csr_pattern(mesh)
+    out = fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=prec)
+    torch.cuda.synchronize()
+    return csr, out
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
+def test_spmv_matches_scipy(fem, prec_name):
+    csr, out = system(fem, getattr(fem, prec_name))
+    say(f"spmv {prec_name}: n {csr.n_rows}, nnz {csr.nnz}")
+    x = torch.as_tensor(np.random.default_rng(3).standard_normal(csr.n_rows)).cuda()
+    y = fem.csr_spmv(csr, out.K, x)
+    torch.cuda.synchronize()
+    ref = dense(csr, out.K) @ x.cpu().numpy()
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
+def test_solve_matches_dense_solve(fem, prec_name):
+    csr, out = system(fem, getattr(fem, prec_name))
+    A = dense(csr, out.K).toarray()
+    b = np.random.default_rng(4).standard_normal(csr.n_rows)
+    say(f"solve {prec_name}: n {csr.n_rows}")
+    s = fem.Solver(csr)
+    x, its, res = s.solve(out.K, torch.as_tensor(b).cuda(), rtol=1e-12)
+    torch.cuda.synchronize()
+    ref = np.linalg.solve(A, b)
+    assert res <= 1e-12 and its > 0
+    assert np.abs(x.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
+    # the same solve again is bitwise the same (fixed-order reductions)
+    x2, its2, _ = s.solve(out.K, torch.as_tensor(b).cuda(), rtol=1e-12)
+    assert its2 == its and torch.equal(x, x2)
+
+
+def test_solve_reports_no_convergence(fem):
+    csr, out = system(fem, fem.FP64)
+    b = torch.ones(csr.n_rows, dtype=torch.float64, device="cuda")
+    with pytest.raises(fem.FemError) as ei:
+        fem.Solver(csr).solve(out.K, b, rtol=1e-14, max_iter=2)
+    assert ei.value.code == fem.FEM_ENOCONV
+    x, its, res = fem.Solver(csr).solve(out.K, b, rtol=1e-14, max_iter=2, check=False)
+    assert its == 2 and res > 1e-14
+
+
+@pytest.mark.parametrize("prec_name,tol,atol", [("FP64", 1e-10, 1e-9), ("FP32_MIXED", 1e-6, 1e-5)])
+def test_uniaxial_tension_newton_matches_one_dimensional_swift(fem, prec_name, tol, atol):
+    from scipy.optimize import brentq
+
+    from paper_2606_17390_amd import newton
+    prec = getattr(fem, prec_name)
+    p = synth.tiny_cube(step=0)
+    mesh, params, _, _, bc, _ = gpu_problem(p, fem)
+    csr = fem.csr_pattern(mesh)
+    face = np.isclose(p.X[:, 0], 1.0)
+    d = torch.zeros((p.n_nodes, 3), dtype=torch.float64, device="cuda")
+    hist = torch.zeros_like(torch.as_tensor(p.hist_n)).cuda()
+    out = fem.Forward(mesh, csr, prec)
+    solver = fem.Solver(csr)
+    face_t = torch.as_tensor(face).cuda()
+    for step in range(1, 11):
+        d[face_t, 0] = 0.002 * step
+        hist, its, norms = newton.solve_step(mesh, csr, params, d, hist, bc, prec=prec, tol=tol, out=out,
+                                             solver=solver)
+        say(f"newton {prec_name} step {step}: {its} iterations, ||R|| {norms[0]:.2e} -> {norms[-1]:.2e}")
+    Kc, e0, n, E = p.prm[8], p.prm[9], p.prm[10], p.prm[0]
+    abar = brentq(lambda a: Kc * (e0 + a) ** n / E + a - np.log(1.02), 0.0, 0.1, xtol=1e-16)
+    sig = Kc * (e0 + abar) ** n
+    alpha = hist[6].cpu().numpy()
+    assert np.abs(alpha - abar).max() <= atol
+    # reaction on the x = 1 face: residual without the constraints
+    r = fem.residual_tangent(mesh, csr, params, d, hist * 0 + hist, bc_mask=None, prec=fem.FP64, want_K=False)
+    torch.cuda.synchronize()
+    reac = r.R.cpu().numpy().reshape(-1, 3)[face, 0].sum()
+    assert abs(reac - sig / 1.02) <= atol * 10 * sig
