@@ -199,6 +199,34 @@ def main():
     result = {}
     extras = {"csr_pattern_ms": ms_pattern}
     if not args.no_extras:
+        # ---- linear solve of a Newton iteration on the same system (FP32 K)
+        solver = fem.Solver(csr)
+        xv = torch.ones(csr.n_rows, dtype=torch.float64, device="cuda")
+        yv = torch.empty_like(xv)
+        for _ in range(3):
+            fem.csr_spmv(csr, out_m.K, xv, yv)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fem.csr_spmv(csr, out_m.K, xv, yv)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_spmv = e0.elapsed_time(e1) / 10
+        # FP32 values, the column list once per node (shared by its 3 rows), row_ptr, x and y once
+        spmv_bytes = csr.nnz * 4 + csr.nnz // 3 * 4 + (csr.n_rows + 1) * 4 + 2 * csr.n_rows * 8
+        rhs = -out_m.R
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, its, res = solver.solve(out_m.K, rhs, rtol=0.0, max_iter=50, check=False)
+        torch.cuda.synchronize()
+        ms_it = (time.perf_counter() - t0) * 1e3 / max(its, 1)
+        extras["linear_solve"] = dict(spmv_ms=ms_spmv, spmv_GBps=spmv_bytes / (ms_spmv * 1e6),
+                                      spmv_hbm_frac=spmv_bytes / (ms_spmv * 1e6) / HBM_PEAK_GBS,
+                                      bicgstab_ms_per_iteration=ms_it, bicgstab_rel_res_after_50=res)
+        log(f"spmv {ms_spmv:.3f} ms ({spmv_bytes / (ms_spmv * 1e6):.0f} GB/s), bicgstab {ms_it:.3f} ms/iteration")
+        del solver, xv, yv, rhs
         out_d = fem.Forward(mesh, csr, fem.FP64)
         ms_d, _, kt_d = time_passes(
             lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP64, out=out_d),

@@ -221,7 +221,9 @@ int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_par
  * Linear solve of the global Newton iteration (Sec. 2.2.4: K du = -R, with
  * the Dirichlet rows of App. E as identity rows, so K is not symmetric).
  *
- * fem_csr_spmv -- y = K x for the pattern csr (row_ptr, col_idx, n_rows) and
+ * fem_csr_spmv -- y = K x for a pattern csr made by fem_csr_pattern (the three
+ * rows 3I, 3I+1, 3I+2 of a node are consecutive and share their columns; only
+ * row_ptr, col_idx and n_rows are read) and
  * values K_vals (double for FEM_FP64, float for FEM_FP32_MIXED, as written by
  * fem_residual_tangent); x, y device [n_rows] doubles (not aliased).  Errors:
  * FEM_EINVAL, FEM_EHIP.

@@ -3,6 +3,8 @@
 // K is not symmetric): CSR matrix-vector product and BiCGSTAB with a Jacobi
 // preconditioner (the inverse of the diagonal of K).
 //
+// The matrix is the CSR pattern of fem_csr_pattern (rows 3I+a; the three
+// rows of a node are consecutive and share their sorted column list).
 // Vectors are FP64; the matrix values are FP64 or FP32 (the mixed form keeps
 // K in FP32 and solves in FP64).  Every reduction is a fixed two-stage tree,
 // so a solve is bitwise reproducible.  The iteration runs on the host: the
@@ -17,26 +19,40 @@
 namespace fem {
 namespace {
 
-constexpr int kSpmvLanes = 16;    // lanes per row of the matrix-vector product
+constexpr int kSpmvLanes = 32;    // lanes per node (3 rows) of the matrix-vector product
 constexpr int kVecThreads = 256;  // vector kernels
 constexpr int kDotBlocks = 256;   // fixed grid of the first reduction stage
 
-// y = K x, 16 lanes per row: lane l adds entries l, l + 16, ... of the row,
-// then a butterfly over the 16 lanes (fixed order).
+// y = K x over the pattern of fem_csr_pattern, where the three rows of a node
+// are consecutive, equally long and share their column list: 32 lanes per
+// node, lane l takes columns l, l + 32, ... of the node's rows, reading each
+// column index and x value once for the three rows, then a butterfly over
+// the 32 lanes (fixed order).
 template <typename RV>
-__global__ __launch_bounds__(256) void spmv_kernel(int32_t n_rows, const int32_t* __restrict__ row_ptr,
+__global__ __launch_bounds__(256) void spmv_kernel(int32_t n_nodes, const int32_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ col_idx, const RV* __restrict__ val,
                                                    const double* __restrict__ x, double* __restrict__ y) {
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSpmvLanes;
+    const int64_t node = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSpmvLanes;
     const int l = (int)(threadIdx.x & (kSpmvLanes - 1));
-    double s = 0.0;
-    if (row < n_rows) {
-        const int32_t b = row_ptr[row], e = row_ptr[row + 1];
-        for (int32_t k = b + l; k < e; k += kSpmvLanes) s += (double)val[k] * x[col_idx[k]];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (node < n_nodes) {
+        const int32_t b = row_ptr[3 * node], len = row_ptr[3 * node + 1] - b;
+        const int32_t* __restrict__ ci = col_idx + b;
+        const RV* __restrict__ v = val + b;
+        for (int32_t k = l; k < len; k += kSpmvLanes) {
+            const double xv = x[ci[k]];
+            s0 += (double)v[k] * xv;
+            s1 += (double)v[len + k] * xv;
+            s2 += (double)v[2 * len + k] * xv;
+        }
     }
 #pragma unroll
-    for (int m = 1; m < kSpmvLanes; m <<= 1) s += __shfl_xor(s, m, kSpmvLanes);
-    if (row < n_rows && l == 0) y[row] = s;
+    for (int m = 1; m < kSpmvLanes; m <<= 1) {
+        s0 += __shfl_xor(s0, m, kSpmvLanes);
+        s1 += __shfl_xor(s1, m, kSpmvLanes);
+        s2 += __shfl_xor(s2, m, kSpmvLanes);
+    }
+    if (node < n_nodes && l < 3) y[3 * node + l] = (l == 0 ? s0 : (l == 1 ? s1 : s2));
 }
 
 // dinv[i] = 1 / K_ii (1 where the diagonal entry is absent or zero)
@@ -178,14 +194,14 @@ struct CountAdapterS {
 
 hipError_t spmv(const fem_csr* csr, const void* vals, fem_precision prec, const double* x, double* y,
                 hipStream_t s) {
-    const int32_t n = csr->n_rows;
-    if (n <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)(((int64_t)n * kSpmvLanes + 255) / 256);
+    const int32_t nn = csr->n_rows / 3;
+    if (nn <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)(((int64_t)nn * kSpmvLanes + 255) / 256);
     if (prec == FEM_FP64)
-        hipLaunchKernelGGL(spmv_kernel<double>, dim3(nb), dim3(256), 0, s, n, csr->row_ptr, csr->col_idx,
+        hipLaunchKernelGGL(spmv_kernel<double>, dim3(nb), dim3(256), 0, s, nn, csr->row_ptr, csr->col_idx,
                            static_cast<const double*>(vals), x, y);
     else
-        hipLaunchKernelGGL(spmv_kernel<float>, dim3(nb), dim3(256), 0, s, n, csr->row_ptr, csr->col_idx,
+        hipLaunchKernelGGL(spmv_kernel<float>, dim3(nb), dim3(256), 0, s, nn, csr->row_ptr, csr->col_idx,
                            static_cast<const float*>(vals), x, y);
     return hipGetLastError();
 }
@@ -198,7 +214,7 @@ hipError_t dot(int64_t n, const double* a, const double* b, double* part, double
 
 int check_csr(const fem_csr* csr, const void* vals, const char* who) {
     if (!csr || !vals) return set_error(FEM_EINVAL, "%s: csr and K values must not be NULL", who);
-    if (csr->n_rows < 0) return set_error(FEM_EINVAL, "%s: negative n_rows", who);
+    if (csr->n_rows < 0 || csr->n_rows % 3) return set_error(FEM_EINVAL, "%s: n_rows must be 3 n_nodes", who);
     if (csr->n_rows > 0 && (!csr->row_ptr || !csr->col_idx))
         return set_error(FEM_EINVAL, "%s: row_ptr and col_idx must not be NULL", who);
     return FEM_OK;
