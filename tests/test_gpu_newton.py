@@ -58,6 +58,29 @@ def test_spmv_matches_scipy(fem, prec_name):
 
 
 @pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
+def test_spmv_long_rows_matches_scipy(fem, prec_name):
+    """Rows longer than 96 columns (a node coupled to more than 32 nodes):
+    extra elements join node 0 to random nodes of the slab; random values."""
+    p = synth.small_slab(52, 6, 5, 4)
+    rng = np.random.default_rng(5)
+    extra = np.stack([np.concatenate([[0], rng.choice(np.arange(1, p.n_nodes), 7, replace=False)])
+                      for _ in range(6)]).astype(np.int32)  # node 0: 47 neighbours (at most 64)
+    mesh = fem.Mesh(p.X, np.concatenate([p.conn, extra]))
+    csr = fem.csr_pattern(mesh)
+    torch.cuda.synchronize()
+    lens = np.diff(csr.row_ptr.cpu().numpy())
+    assert lens.max() > 96
+    say(f"spmv long rows {prec_name}: n {csr.n_rows}, longest row {lens.max()}")
+    dt = torch.float64 if prec_name == "FP64" else torch.float32
+    K = torch.as_tensor(rng.standard_normal(csr.nnz)).to(dt).cuda()
+    x = torch.as_tensor(rng.standard_normal(csr.n_rows)).cuda()
+    y = fem.csr_spmv(csr, K, x)
+    torch.cuda.synchronize()
+    ref = dense(csr, K) @ x.cpu().numpy()
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
 def test_solve_matches_dense_solve(fem, prec_name):
     csr, out = system(fem, getattr(fem, prec_name))
     A = dense(csr, out.K).toarray()
