@@ -19,6 +19,9 @@ _lib = None
 
 NPARAM = 11
 NGRAD = 7
+# model option flags (oracle.h)
+MODEL_VOCE = 1
+MODEL_FBAR = 2
 
 
 def build(force=True):
@@ -44,15 +47,16 @@ def _load():
     i32, i64 = ctypes.c_int32, ctypes.c_int64
     lib.oracle_eig_sym3.argtypes = [P, P, P]
     lib.oracle_log_strain.argtypes = [P, P]
-    lib.oracle_material_point.argtypes = [P] * 3 + [P] * 9
+    ci = ctypes.c_int
+    lib.oracle_material_point.argtypes = [P] * 3 + [ci, P] + [P] * 9
     lib.oracle_material_point.restype = ctypes.c_int
-    lib.oracle_element.argtypes = [P] * 8
+    lib.oracle_element.argtypes = [P] * 4 + [ci, P] + [P] * 4
     lib.oracle_csr_pattern.argtypes = [i32, i32, P, P, P, P, P]
     lib.oracle_csr_pattern.restype = ctypes.c_int
-    lib.oracle_residual_tangent.argtypes = [i32, i32] + [P] * 13 + [ctypes.c_int]
+    lib.oracle_residual_tangent.argtypes = [i32, i32] + [P] * 5 + [ci, P] + [P] * 8 + [ci]
     lib.oracle_residual_tangent.restype = ctypes.c_int
-    lib.oracle_trial_yield.argtypes = [i32, i32] + [P] * 6 + [ctypes.c_int]
-    lib.oracle_residual_vjp.argtypes = [i32, i32] + [P] * 9 + [ctypes.c_int]
+    lib.oracle_trial_yield.argtypes = [i32, i32] + [P] * 3 + [ci, P] + [P] * 3 + [ci]
+    lib.oracle_residual_vjp.argtypes = [i32, i32] + [P] * 3 + [ci, P] + [P] * 6 + [ci]
     lib.oracle_residual_vjp.restype = ctypes.c_int
     _lib = lib
     del i64
@@ -86,35 +90,54 @@ def log_strain(F):
     return eps
 
 
-def material_point(F, hist_n, prm):
+def _theta(Theta):
+    return None if Theta is None else _f64(Theta).reshape(9)
+
+
+def expand_orient(orient, n_elems):
+    """None, one rotation (3x3) or per-element rotations [n_elems, 3, 3] -> [n_elems, 9]."""
+    if orient is None:
+        return None
+    o = _f64(orient)
+    if o.size == 9:
+        return np.ascontiguousarray(np.broadcast_to(o.reshape(9), (n_elems, 9)))
+    return _f64(o.reshape(n_elems, 9))
+
+
+def material_point(F, hist_n, prm, model=0, Theta=None):
     """Return a dict with S, P, T (3x3), hist (7), A (3,3,3,3), Cep, Cep_implicit,
-    Cmat (6x6 Mandel), plastic, iters, converged, dgamma, ftr, sy_n."""
+    Cmat (6x6 Mandel), plastic, iters, converged, dgamma, ftr, sy_n.  model:
+    MODEL_* flags (Voce hardening); Theta: orientation (3x3 rotation) or None."""
     F = _f64(F).reshape(3, 3)
     h = _f64(hist_n).reshape(7)
     p = _f64(prm).reshape(NPARAM)
+    th = _theta(Theta)
     S, P, T = np.zeros((3, 3)), np.zeros((3, 3)), np.zeros((3, 3))
     hn = np.zeros(7)
     A = np.zeros(81)
     Cep, CepI, Cm = np.zeros((6, 6)), np.zeros((6, 6)), np.zeros((6, 6))
     info = np.zeros(6)
-    rc = _load().oracle_material_point(_p(F), _p(h), _p(p), _p(S), _p(P), _p(T), _p(hn), _p(A),
-                                       _p(Cep), _p(CepI), _p(Cm), _p(info))
+    rc = _load().oracle_material_point(_p(F), _p(h), _p(p), int(model), _p(th), _p(S), _p(P), _p(T),
+                                       _p(hn), _p(A), _p(Cep), _p(CepI), _p(Cm), _p(info))
     return dict(S=S, P=P, T=T, hist=hn, A=A.reshape(3, 3, 3, 3), Cep=Cep, Cep_implicit=CepI,
                 Cmat=Cm, plastic=bool(info[0]), iters=int(info[1]), converged=bool(info[2]),
                 dgamma=info[3], ftr=info[4], sy_n=info[5], rc=rc)
 
 
-def element(Xe, de, he, prm, want_K=True):
-    """Element residual (24), tangent (24x24), updated history (8x7), diag (4)."""
+def element(Xe, de, he, prm, want_K=True, model=0, Theta=None):
+    """Element residual (24), tangent (24x24), updated history (8x7), diag (4);
+    model: MODEL_* flags (Voce, F-bar); Theta: orientation or None."""
     Xe = _f64(Xe).reshape(8, 3)
     de = _f64(de).reshape(8, 3)
     he = _f64(he).reshape(8, 7)
     p = _f64(prm).reshape(NPARAM)
+    th = _theta(Theta)
     R = np.zeros(24)
     K = np.zeros((24, 24)) if want_K else None
     hn = np.zeros((8, 7))
     diag = np.zeros(4, dtype=np.int32)
-    _load().oracle_element(_p(Xe), _p(de), _p(he), _p(p), _p(R), _p(K), _p(hn), _p(diag))
+    _load().oracle_element(_p(Xe), _p(de), _p(he), _p(p), int(model), _p(th), _p(R), _p(K), _p(hn),
+                           _p(diag))
     return R, K, hn, diag
 
 
@@ -145,13 +168,14 @@ def expand_params(prm, n_elems):
 
 
 def residual_tangent(X, conn, row_ptr, col_idx, prm, d, hist_n, bc_mask=None, want_K=True,
-                     n_threads=0):
+                     n_threads=0, model=0, orient=None):
     """Assembled residual R [3n], CSR values K [nnz] (or None), hist_np1 [7, 8ne],
     rnorm2 (double, long double), diag [4]."""
     X = _f64(X).reshape(-1, 3)
     conn = _i32(conn).reshape(-1, 8)
     nn, ne = X.shape[0], conn.shape[0]
     prm = expand_params(prm, ne)
+    ori = expand_orient(orient, ne)
     d = _f64(d).reshape(nn, 3)
     hist_n = _f64(hist_n).reshape(7, 8 * ne)
     bc = None if bc_mask is None else np.ascontiguousarray(bc_mask, dtype=np.uint8)
@@ -162,39 +186,41 @@ def residual_tangent(X, conn, row_ptr, col_idx, prm, d, hist_n, bc_mask=None, wa
     diag = np.zeros(4, dtype=np.int32)
     rp = _i32(row_ptr)
     ci = _i32(col_idx)
-    rc = _load().oracle_residual_tangent(nn, ne, _p(X), _p(conn), _p(rp), _p(ci), _p(prm), _p(d),
-                                         _p(hist_n), _p(bc), _p(R), _p(K), _p(hn), _p(rn), _p(diag),
-                                         int(n_threads))
+    rc = _load().oracle_residual_tangent(nn, ne, _p(X), _p(conn), _p(rp), _p(ci), _p(prm), int(model),
+                                         _p(ori), _p(d), _p(hist_n), _p(bc), _p(R), _p(K), _p(hn), _p(rn),
+                                         _p(diag), int(n_threads))
     if rc != 0:
         raise RuntimeError("oracle_residual_tangent: element entry missing from the CSR pattern")
     return R, K, hn, rn, diag
 
 
-def trial_yield(X, conn, prm, d, hist_n, n_threads=0):
+def trial_yield(X, conn, prm, d, hist_n, n_threads=0, model=0, orient=None):
     X = _f64(X).reshape(-1, 3)
     conn = _i32(conn).reshape(-1, 8)
     nn, ne = X.shape[0], conn.shape[0]
     prm = expand_params(prm, ne)
+    ori = expand_orient(orient, ne)
     d = _f64(d).reshape(nn, 3)
     hist_n = _f64(hist_n).reshape(7, 8 * ne)
     flag = np.zeros(8 * ne, dtype=np.uint8)
-    _load().oracle_trial_yield(nn, ne, _p(X), _p(conn), _p(prm), _p(d), _p(hist_n), _p(flag),
-                               int(n_threads))
+    _load().oracle_trial_yield(nn, ne, _p(X), _p(conn), _p(prm), int(model), _p(ori), _p(d), _p(hist_n),
+                               _p(flag), int(n_threads))
     return flag
 
 
-def residual_vjp(X, conn, prm, d, hist_n, lam, n_threads=0):
+def residual_vjp(X, conn, prm, d, hist_n, lam, n_threads=0, model=0, orient=None):
     """Return (g_uniform [7], g_elem [7, n_elems], diag [4])."""
     X = _f64(X).reshape(-1, 3)
     conn = _i32(conn).reshape(-1, 8)
     nn, ne = X.shape[0], conn.shape[0]
     prm = expand_params(prm, ne)
+    ori = expand_orient(orient, ne)
     d = _f64(d).reshape(nn, 3)
     hist_n = _f64(hist_n).reshape(7, 8 * ne)
     lam = _f64(lam).reshape(nn, 3)
     gu = np.zeros(7)
     ge = np.zeros((7, ne))
     diag = np.zeros(4, dtype=np.int32)
-    _load().oracle_residual_vjp(nn, ne, _p(X), _p(conn), _p(prm), _p(d), _p(hist_n), _p(lam),
-                                _p(gu), _p(ge), _p(diag), int(n_threads))
+    _load().oracle_residual_vjp(nn, ne, _p(X), _p(conn), _p(prm), int(model), _p(ori), _p(d), _p(hist_n),
+                                _p(lam), _p(gu), _p(ge), _p(diag), int(n_threads))
     return gu, ge, diag

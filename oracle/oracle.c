@@ -22,12 +22,17 @@
  *   App. E Alg. E1: CSR assembly, Dirichlet rows set to identity
  *   Sec. 2.3 Eq. (main_grad), Alg. 1: the VJP term lambda^T dR/dtheta
  *
+ *   Eq. (Hard): Voce hardening (model option); App. A: orientation of the
+ *       Hill tensor; Sec. 2.2.4: F-bar deformation gradient (model option)
+ *
  * Readings where the paper is silent or inconsistent (listed in the design
- * notes): Swift hardening sigma_y = K (eps0+alpha)^n replaces Voce; the Hill
+ * notes): Swift hardening sigma_y = K (eps0+alpha)^n by default, Voce as
+ * sigma_y = sig0 + Q (1 - exp(-b alpha)) in uniaxial-stress units; the Hill
  * function is written with F,G,H,L,M,N so that it reduces to von Mises at
  * F=G=H=1/2, L=M=N=3/2, with W = 1 in alpha_{n+1} = alpha_n + W dgamma;
- * isotropic elasticity; no F-bar; eps = sum 1/2 ln(c_a) N_a (x) N_a with c_a
- * the eigenvalues of C.
+ * isotropic elasticity; eps = sum 1/2 ln(c_a) N_a (x) N_a with c_a the
+ * eigenvalues of C; F-bar as R^e_I = int P(Fbar) . grad N_I dV with K^e its
+ * exact derivative (not symmetric).
  */
 #include "oracle.h"
 
@@ -304,12 +309,62 @@ static double hill_phi(const double Hm[36], const double t[6]) {
     return sqrt(s);
 }
 
-/* Swift law sigma_y = K (eps0 + alpha)^n and its derivative. */
-static double swift(const double prm[11], double alpha, double *dsig) {
+/* Hardening law and its derivative: Swift sigma_y = K (eps0 + alpha)^n, or
+ * (voce != 0) Voce sigma_y = sig0 + Q (1 - exp(-b alpha)) of Eq. (Hard) with
+ * (sig0, Q, b) in the slots of (K, eps0, n). */
+static double hardening(const double prm[11], int voce, double alpha, double *dsig) {
+    if (voce) {
+        double ex = exp(-prm[P_NEXP] * alpha);
+        if (dsig) *dsig = prm[P_EPS0] * prm[P_NEXP] * ex;
+        return prm[P_K] + prm[P_EPS0] * (1.0 - ex);
+    }
     double base = prm[P_EPS0] + alpha;
     double s = prm[P_K] * pow(base, prm[P_NEXP]);
     if (dsig) *dsig = prm[P_NEXP] * s / base;
     return s;
+}
+
+/* Mandel 6x6 <-> fourth-order tensor with both minor symmetries
+ * (T[27a+9b+3c+d]); Mandel weights 1 on normal and sqrt2 on shear slots. */
+static void mandel_to_4th(const double Mm[36], double T4[81]) {
+    for (int I = 0; I < 6; ++I)
+        for (int J = 0; J < 6; ++J) {
+            double v = Mm[6 * I + J] / ((I < 3 ? 1.0 : SQRT2) * (J < 3 ? 1.0 : SQRT2));
+            int a = MI[I], b = MJ[I], c = MI[J], d = MJ[J];
+            T4[27 * a + 9 * b + 3 * c + d] = v;
+            T4[27 * b + 9 * a + 3 * c + d] = v;
+            T4[27 * a + 9 * b + 3 * d + c] = v;
+            T4[27 * b + 9 * a + 3 * d + c] = v;
+        }
+}
+
+static void fourth_to_mandel(const double T4[81], double Mm[36]) {
+    for (int I = 0; I < 6; ++I)
+        for (int J = 0; J < 6; ++J)
+            Mm[6 * I + J] = (I < 3 ? 1.0 : SQRT2) * (J < 3 ? 1.0 : SQRT2) *
+                            T4[27 * MI[I] + 9 * MJ[I] + 3 * MI[J] + MJ[J]];
+}
+
+/* App. A: H_global = Theta Theta : H_local : Theta^T Theta^T, i.e.
+ * H_ijkl = sum Theta_ia Theta_jb Theta_kc Theta_ld H_abcd (in place, Mandel). */
+static void rotate_hill(const double *Theta, double Hm[36]) {
+    if (!Theta) return;
+    double L4[81], G4[81];
+    mandel_to_4th(Hm, L4);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) {
+                    double v = 0.0;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b)
+                            for (int c = 0; c < 3; ++c)
+                                for (int d = 0; d < 3; ++d)
+                                    v += Theta[3 * i + a] * Theta[3 * j + b] * Theta[3 * k + c] *
+                                         Theta[3 * l + d] * L4[27 * a + 9 * b + 3 * c + d];
+                    G4[27 * i + 9 * j + 3 * k + l] = v;
+                }
+    fourth_to_mandel(G4, Hm);
 }
 
 /* ------------------------------------------------------------------ */
@@ -321,6 +376,8 @@ typedef struct {
     double ee_tr[6]; /* Mandel eps_{n+1} - eps^p_n */
     double alpha_n;
     const double *prm;
+    int voce;
+    const double *Theta; /* orientation, or NULL */
 } cpp_ctx;
 
 static void cpp_residual(const cpp_ctx *c, const double y[8], double G[8]) {
@@ -339,7 +396,7 @@ static void cpp_residual(const cpp_ctx *c, const double y[8], double G[8]) {
         G[i] = t[i] - s;
     }
     G[6] = alpha - c->alpha_n - dg;
-    G[7] = phi - swift(c->prm, alpha, NULL);
+    G[7] = phi - hardening(c->prm, c->voce, alpha, NULL);
 }
 
 /* analytic J^G = dG/dy */
@@ -369,7 +426,7 @@ static void cpp_jacobian(const cpp_ctx *c, const double y[8], double J[64]) {
     J[8 * 6 + 6] = 1.0;
     J[8 * 6 + 7] = -1.0;
     double dsig;
-    swift(c->prm, alpha, &dsig);
+    hardening(c->prm, c->voce, alpha, &dsig);
     for (int j = 0; j < 6; ++j) J[8 * 7 + j] = N[j];
     J[8 * 7 + 6] = -dsig;
 }
@@ -387,7 +444,7 @@ static double cpp_merit(const cpp_ctx *c, const double y[8], const double D[8]) 
  * count (negative if not converged). */
 static int cpp_solve(const cpp_ctx *c, double y[8]) {
     double mu = c->Em[35] / 2.0;
-    double sy_n = swift(c->prm, c->alpha_n, NULL);
+    double sy_n = hardening(c->prm, c->voce, c->alpha_n, NULL);
     double D[8] = {1 / mu, 1 / mu, 1 / mu, 1 / mu, 1 / mu, 1 / mu, 1.0, 1.0 / sy_n};
     double prev = INFINITY;
     for (int k = 0; k <= KMAX; ++k) {
@@ -449,8 +506,8 @@ typedef struct {
     double y[8];
 } mp_state;
 
-static void mp_update(const double F[9], const double hist_n[7], const double prm[11],
-                      mp_state *s) {
+static void mp_update(const double F[9], const double hist_n[7], const double prm[11], int model,
+                      const double *Theta, mp_state *s) {
     memcpy(s->F, F, 9 * sizeof(double));
     /* C - I = H + H^T + H^T H with H = F - I (no cancellation against I) */
     double H[9], M[9];
@@ -484,7 +541,10 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
     cpp_ctx *c = &s->ctx;
     elastic_mandel(prm, c->Em);
     hill_mandel(prm, c->Hm);
+    rotate_hill(Theta, c->Hm);
     c->prm = prm;
+    c->voce = (model & ORACLE_MODEL_VOCE) != 0;
+    c->Theta = Theta;
     c->alpha_n = hist_n[6];
     for (int i = 0; i < 6; ++i) c->ee_tr[i] = eps_m[i] - epsp_n[i];
 
@@ -495,7 +555,7 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
         for (int j = 0; j < 6; ++j) acc += c->Em[6 * i + j] * c->ee_tr[j];
         ttr[i] = acc;
     }
-    s->sy_n = swift(prm, c->alpha_n, NULL);
+    s->sy_n = hardening(prm, c->voce, c->alpha_n, NULL);
     s->ftr = hill_phi(c->Hm, ttr) - s->sy_n;
 
     double epsp_np1[6];
@@ -547,7 +607,7 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
                 Am[6 * i + j] = Einv[6 * i + j] + s->dgamma * (c->Hm[6 * i + j] - N[i] * N[j]) / phi;
         invert_dense(6, Am, Xi);
         double v[6], nxn = 0.0, dsig;
-        swift(prm, alpha_np1, &dsig);
+        hardening(prm, c->voce, alpha_np1, &dsig);
         for (int i = 0; i < 6; ++i) {
             double acc = 0.0;
             for (int j = 0; j < 6; ++j) acc += Xi[6 * i + j] * N[j];
@@ -661,10 +721,11 @@ static void mp_nominal_tangent(const mp_state *s, const double Cm[36], double A[
 }
 
 int oracle_material_point(const double F[9], const double hist_n[7], const double prm[11],
-                          double *S, double *P, double *T, double *hist_np1, double *A,
-                          double *Cep, double *Cep_implicit, double *Cmat, double *info) {
+                          int model, const double *Theta, double *S, double *P, double *T,
+                          double *hist_np1, double *A, double *Cep, double *Cep_implicit,
+                          double *Cmat, double *info) {
     mp_state s;
-    mp_update(F, hist_n, prm, &s);
+    mp_update(F, hist_n, prm, model, Theta, &s);
     double Cm[36];
     mp_lagrangian_tangent(&s, Cm);
     if (S) memcpy(S, s.S, 9 * sizeof(double));
@@ -747,54 +808,104 @@ static int all_finite(const double *v, int n) {
     return 1;
 }
 
-void oracle_element(const double X[24], const double d[24], const double hist[56],
-                    const double prm[11], double R[24], double K[576], double hist_np1[56],
-                    int32_t diag[4]) {
-    memset(R, 0, 24 * sizeof(double));
-    if (K) memset(K, 0, 576 * sizeof(double));
+/* Deformation gradients of the element's Gauss points and, with F-bar
+ * (Sec. 2.2.4), the modified gradients Fbar_g = (Jbar / J_g)^(1/3) F_g with
+ * Jbar = sum_g w detJ0_g J_g / sum_g w detJ0_g, and their derivatives
+ * dFm[g][9 * 24] = dFbar_g(cD) / dd(Jb) (the plain dF/dd without F-bar). */
+static void element_kinematics(const double X[24], const double d[24], int fbar,
+                               double gradN[8][24], double detJ0[8], double F[8][9],
+                               double Fm[8][9], double *dFm) {
+    double Jg[8], Ve = 0.0, VJ = 0.0;
     for (int g = 0; g < 8; ++g) {
-        double gradN[24];
-        double detJ0 = gp_gradients(X, g, gradN);
-        if (detJ0 <= 0.0) diag[1]++;
-        double F[9];
+        detJ0[g] = gp_gradients(X, g, gradN[g]);
         for (int a = 0; a < 3; ++a)
             for (int A = 0; A < 3; ++A) {
                 double s = (a == A) ? 1.0 : 0.0;
-                for (int I = 0; I < 8; ++I) s += d[3 * I + a] * gradN[3 * I + A];
-                F[3 * a + A] = s;
+                for (int I = 0; I < 8; ++I) s += d[3 * I + a] * gradN[g][3 * I + A];
+                F[g][3 * a + A] = s;
             }
-        if (det3(F) <= 0.0) diag[2]++;
+        Jg[g] = det3(F[g]);
+        Ve += detJ0[g]; /* Gauss weight 1 */
+        VJ += detJ0[g] * Jg[g];
+    }
+    double Jbar = VJ / Ve;
+    /* dJ_g/dd_Jb = J_g (F_g^-T)_bE dN_J/dX_E; dJbar/dd = sum_g w detJ0_g dJ_g/dd / V_e */
+    double dJ[8][24], dJbar[24] = {0};
+    if (fbar)
+        for (int g = 0; g < 8; ++g) {
+            double Fi[9];
+            inv3(F[g], Fi);
+            for (int J = 0; J < 8; ++J)
+                for (int b = 0; b < 3; ++b) {
+                    double v = 0.0;
+                    for (int E = 0; E < 3; ++E) v += Fi[3 * E + b] * gradN[g][3 * J + E];
+                    dJ[g][3 * J + b] = Jg[g] * v;
+                    dJbar[3 * J + b] += detJ0[g] * Jg[g] * v / Ve;
+                }
+        }
+    for (int g = 0; g < 8; ++g) {
+        double beta = fbar ? cbrt(Jbar / Jg[g]) : 1.0;
+        for (int i = 0; i < 9; ++i) Fm[g][i] = beta * F[g][i];
+        if (!dFm) continue;
+        double *D = dFm + 216 * g;
+        for (int c = 0; c < 3; ++c)
+            for (int Dd = 0; Dd < 3; ++Dd)
+                for (int J = 0; J < 8; ++J)
+                    for (int b = 0; b < 3; ++b) {
+                        double v = (c == b) ? gradN[g][3 * J + Dd] : 0.0;
+                        if (fbar)
+                            v += F[g][3 * c + Dd] / 3.0 *
+                                 (dJbar[3 * J + b] / Jbar - dJ[g][3 * J + b] / Jg[g]);
+                        D[24 * (3 * c + Dd) + 3 * J + b] = beta * v;
+                    }
+    }
+}
+
+void oracle_element(const double X[24], const double d[24], const double hist[56],
+                    const double prm[11], int model, const double *Theta, double R[24],
+                    double K[576], double hist_np1[56], int32_t diag[4]) {
+    memset(R, 0, 24 * sizeof(double));
+    if (K) memset(K, 0, 576 * sizeof(double));
+    double gradN[8][24], detJ0[8], F[8][9], Fm[8][9];
+    double *dFm = K ? malloc(sizeof(double) * 8 * 216) : NULL;
+    element_kinematics(X, d, (model & ORACLE_MODEL_FBAR) != 0, gradN, detJ0, F, Fm, dFm);
+    for (int g = 0; g < 8; ++g) {
+        if (detJ0[g] <= 0.0) diag[1]++;
+        if (det3(F[g]) <= 0.0) diag[2]++;
         mp_state s;
-        mp_update(F, hist + 7 * g, prm, &s);
+        mp_update(Fm[g], hist + 7 * g, prm, model, Theta, &s);
         if (!s.converged) diag[0]++;
         if (hist_np1) memcpy(hist_np1 + 7 * g, s.hist, 7 * sizeof(double));
-        double w = detJ0; /* Gauss weight 1 */
+        double w = detJ0[g]; /* Gauss weight 1 */
         for (int I = 0; I < 8; ++I)
             for (int a = 0; a < 3; ++a) {
                 double r = 0.0;
-                for (int A = 0; A < 3; ++A) r += s.P[3 * a + A] * gradN[3 * I + A];
+                for (int A = 0; A < 3; ++A) r += s.P[3 * a + A] * gradN[g][3 * I + A];
                 R[3 * I + a] += w * r;
             }
         int fin = all_finite(s.P, 9);
         if (K) {
+            /* K^e_IaJb = sum_g w detJ0 dN_I/dX_A A_aAcD dF_cD/dd_Jb */
             double Cm[36], A4[81];
             mp_lagrangian_tangent(&s, Cm);
             mp_nominal_tangent(&s, Cm, A4);
             fin = fin && all_finite(A4, 81);
+            const double *D = dFm + 216 * g;
             for (int I = 0; I < 8; ++I)
                 for (int a = 0; a < 3; ++a)
-                    for (int J = 0; J < 8; ++J)
-                        for (int b = 0; b < 3; ++b) {
-                            double k = 0.0;
-                            for (int A = 0; A < 3; ++A)
-                                for (int B = 0; B < 3; ++B)
-                                    k += gradN[3 * I + A] * A4[27 * a + 9 * A + 3 * b + B] *
-                                         gradN[3 * J + B];
-                            K[24 * (3 * I + a) + 3 * J + b] += w * k;
-                        }
+                    for (int col = 0; col < 24; ++col) {
+                        double k = 0.0;
+                        for (int A = 0; A < 3; ++A)
+                            for (int c = 0; c < 3; ++c)
+                                for (int Dd = 0; Dd < 3; ++Dd)
+                                    k += gradN[g][3 * I + A] * A4[27 * a + 9 * A + 3 * c + Dd] *
+                                         D[24 * (3 * c + Dd) + col];
+                        K[24 * (3 * I + a) + col] += w * k;
+                    }
         }
         if (!fin) diag[3]++;
     }
+    free(dFm);
 }
 
 /* ------------------------------------------------------------------ */
@@ -929,8 +1040,8 @@ static void gather_element(int64_t e, const double *X, const int32_t *conn, cons
 
 int oracle_residual_tangent(int32_t n_nodes, int32_t n_elems, const double *X,
                             const int32_t *conn, const int32_t *row_ptr, const int32_t *col_idx,
-                            const double *prm, const double *d, const double *hist_n,
-                            const uint8_t *bc_mask, double *R, double *K, double *hist_np1,
+                            const double *prm, int model, const double *orient,
+                            const double *d, const double *hist_n, const uint8_t *bc_mask, double *R, double *K, double *hist_np1,
                             double *rnorm2, int32_t *diag, int n_threads) {
     int64_t n_dof = 3 * (int64_t)n_nodes, n_gp = 8 * (int64_t)n_elems;
     int64_t nnz = row_ptr ? row_ptr[n_dof] : 0;
@@ -954,7 +1065,8 @@ int oracle_residual_tangent(int32_t n_nodes, int32_t n_elems, const double *X,
             double Xe[24], de[24], he[56], hn[56];
             int32_t dl[4] = {0, 0, 0, 0};
             gather_element(e, X, conn, d, hist_n, n_gp, Xe, de, he);
-            oracle_element(Xe, de, he, prm + 11 * e, Rb + 24 * k, Kb ? Kb + 576 * k : NULL, hn, dl);
+            oracle_element(Xe, de, he, prm + 11 * e, model, orient ? orient + 9 * e : NULL,
+                           Rb + 24 * k, Kb ? Kb + 576 * k : NULL, hn, dl);
             for (int i = 0; i < 4; ++i) dg[i] += dl[i];
             if (hist_np1)
                 for (int g = 0; g < 8; ++g)
@@ -1007,8 +1119,8 @@ int oracle_residual_tangent(int32_t n_nodes, int32_t n_elems, const double *X,
 }
 
 void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *conn,
-                        const double *prm, const double *d, const double *hist_n, uint8_t *flag,
-                        int n_threads) {
+                        const double *prm, int model, const double *orient, const double *d,
+                        const double *hist_n, uint8_t *flag, int n_threads) {
     (void)n_nodes;
     int64_t n_gp = 8 * (int64_t)n_elems;
 #ifdef _OPENMP
@@ -1024,16 +1136,12 @@ void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const
         double Em[36], Hm[36];
         elastic_mandel(p, Em);
         hill_mandel(p, Hm);
+        rotate_hill(orient ? orient + 9 * e : NULL, Hm);
+        double gradN[8][24], detJ0[8], F[8][9], Fm[8][9];
+        element_kinematics(Xe, de, (model & ORACLE_MODEL_FBAR) != 0, gradN, detJ0, F, Fm, NULL);
         for (int g = 0; g < 8; ++g) {
-            double gradN[24], F[9], eps[9], em[6], hp[9], pm[6], t[6];
-            gp_gradients(Xe, g, gradN);
-            for (int a = 0; a < 3; ++a)
-                for (int A = 0; A < 3; ++A) {
-                    double s = (a == A) ? 1.0 : 0.0;
-                    for (int I = 0; I < 8; ++I) s += de[3 * I + a] * gradN[3 * I + A];
-                    F[3 * a + A] = s;
-                }
-            oracle_log_strain(F, eps);
+            double eps[9], em[6], hp[9], pm[6], t[6];
+            oracle_log_strain(Fm[g], eps);
             sym_to_mandel(eps, em);
             const double *h = he + 7 * g;
             hp[0] = h[0];
@@ -1048,7 +1156,7 @@ void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const
                 for (int j = 0; j < 6; ++j) s += Em[6 * i + j] * (em[j] - pm[j]);
                 t[i] = s;
             }
-            double ftr = hill_phi(Hm, t) - swift(p, h[6], NULL);
+            double ftr = hill_phi(Hm, t) - hardening(p, (model & ORACLE_MODEL_VOCE) != 0, h[6], NULL);
             flag[8 * e + g] = ftr > 0.0;
         }
     }
@@ -1058,7 +1166,8 @@ void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const
 /* parameter VJP: forward-mode implicit differentiation (App. D)       */
 /* ------------------------------------------------------------------ */
 
-/* dG/dtheta_k at the converged local solution, k in (F, G, H, N, K, eps0, n) */
+/* dG/dtheta_k at the converged local solution, k in (F, G, H, N, K, eps0, n)
+ * or, with Voce hardening, (F, G, H, N, sig0, Q, b) */
 static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[8]) {
     const double *t = y;
     double alpha = y[6], dg = y[7];
@@ -1084,6 +1193,7 @@ static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[
         } else { /* N: shear 12 */
             dH[35] = 1.0;
         }
+        rotate_hill(c->Theta, dH); /* the rotation of App. A is linear in H */
         double dHt[6], tdHt = 0.0;
         for (int i = 0; i < 6; ++i) {
             double s = 0.0;
@@ -1100,6 +1210,18 @@ static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[
             dG[i] = dg * s;
         }
         dG[7] = dphi;
+    } else if (c->voce) {
+        /* sigma_y = sig0 + Q (1 - exp(-b alpha)): d/dsig0, d/dQ, d/db */
+        const double *p = c->prm;
+        double ex = exp(-p[P_NEXP] * alpha);
+        double dsy;
+        if (k == 4)
+            dsy = 1.0;
+        else if (k == 5)
+            dsy = 1.0 - ex;
+        else
+            dsy = p[P_EPS0] * alpha * ex;
+        dG[7] = -dsy;
     } else {
         const double *p = c->prm;
         double base = p[P_EPS0] + alpha;
@@ -1116,9 +1238,9 @@ static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[
 }
 
 int oracle_residual_vjp(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *conn,
-                        const double *prm, const double *d, const double *hist_n,
-                        const double *lam, double *g_uniform, double *g_elem, int32_t *diag,
-                        int n_threads) {
+                        const double *prm, int model, const double *orient, const double *d,
+                        const double *hist_n, const double *lam, double *g_uniform,
+                        double *g_elem, int32_t *diag, int n_threads) {
     (void)n_nodes;
     int64_t n_gp = 8 * (int64_t)n_elems;
     double *ge = malloc(sizeof(double) * 7 * ((size_t)n_elems + 1));
@@ -1135,25 +1257,25 @@ int oracle_residual_vjp(int32_t n_nodes, int32_t n_elems, const double *X, const
         for (int I = 0; I < 8; ++I)
             for (int a = 0; a < 3; ++a) le[3 * I + a] = lam[3 * (int64_t)conn[8 * e + I] + a];
         double acc[7] = {0};
+        double gradNe[8][24], detJ0e[8], Fe[8][9], Fme[8][9];
+        element_kinematics(Xe, de, (model & ORACLE_MODEL_FBAR) != 0, gradNe, detJ0e, Fe, Fme, NULL);
+        const double *Th = orient ? orient + 9 * e : NULL;
         for (int g = 0; g < 8; ++g) {
-            double gradN[24], F[9], Lg[9];
-            double detJ0 = gp_gradients(Xe, g, gradN);
+            const double *gradN = gradNe[g], *F = Fme[g]; /* the material sees Fbar */
+            double Lg[9];
+            double detJ0 = detJ0e[g];
             if (detJ0 <= 0.0) dgc[1]++;
             for (int a = 0; a < 3; ++a)
                 for (int A = 0; A < 3; ++A) {
-                    double s = (a == A) ? 1.0 : 0.0, l = 0.0;
-                    for (int I = 0; I < 8; ++I) {
-                        s += de[3 * I + a] * gradN[3 * I + A];
-                        l += le[3 * I + a] * gradN[3 * I + A];
-                    }
-                    F[3 * a + A] = s;
+                    double l = 0.0;
+                    for (int I = 0; I < 8; ++I) l += le[3 * I + a] * gradN[3 * I + A];
                     Lg[3 * a + A] = l;
                 }
             mp_state s;
-            mp_update(F, he + 7 * g, prm + 11 * e, &s);
+            mp_update(F, he + 7 * g, prm + 11 * e, model, Th, &s);
             if (!s.converged) dgc[0]++;
             if (!s.plastic) continue; /* elastic T does not depend on theta */
-            /* Tbar = P_L : sym(F^T Lambda) */
+            /* Tbar = P_L : sym(F^T Lambda) (F = Fbar with F-bar: lambda^T R = sum w detJ0 Lambda : P(Fbar)) */
             double FtL[9], X9[9], Xh[9], Tbh[9], Tb[9], Tbm[6];
             for (int A = 0; A < 3; ++A)
                 for (int B = 0; B < 3; ++B) {

@@ -28,6 +28,21 @@ extern "C" {
 #define ORACLE_NPARAM 11
 #define ORACLE_NGRAD 7
 
+/* Model options (bit flags, argument `model`):
+ *   ORACLE_MODEL_VOCE  Voce hardening sigma_y = sig0 + Q (1 - exp(-b alpha)),
+ *                      Eq. (Hard) in uniaxial-stress units; parameter slots
+ *                      (K, eps0, n) hold (sig0, Q, b) and so do the last three
+ *                      VJP entries.  Otherwise Swift sigma_y = K (eps0 + alpha)^n.
+ *   ORACLE_MODEL_FBAR  F-bar element (Sec. 2.2.4): the material sees
+ *                      Fbar = (Jbar / J)^(1/3) F, Jbar = (1/V_e) int J dV.
+ * Orientation (argument `Theta`, or `orient` per element): NULL for the
+ * identity, else a row-major 3x3 rotation whose columns are the orthotropy
+ * axes in global coordinates; the Hill tensor is rotated as in App. A,
+ * H_global,ijkl = Theta_ia Theta_jb Theta_kc Theta_ld H_local,abcd.  The
+ * plastic strain history is kept in global components. */
+#define ORACLE_MODEL_VOCE 1
+#define ORACLE_MODEL_FBAR 2
+
 /* Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations. */
 void oracle_eig_sym3(const double A[9], double w[3], double Q[9]);
 
@@ -46,7 +61,7 @@ void oracle_log_strain(const double F[9], double eps[9]);
  *                 [3]=delta gamma, [4]=trial yield value f_tr, [5]=sigma_y(alpha_n)
  * Returns 0 on success, 1 if the local Newton did not converge. */
 int oracle_material_point(const double F[9], const double hist_n[7], const double prm[11],
-                          double *S, double *P, double *T, double *hist_np1, double *A,
+                          int model, const double *Theta, double *S, double *P, double *T, double *hist_np1, double *A,
                           double *Cep, double *Cep_implicit, double *Cmat, double *info);
 
 /* Element residual R[24] (index 3*I+a) and tangent K[576] (row 3*I+a, col 3*J+b)
@@ -54,7 +69,7 @@ int oracle_material_point(const double F[9], const double hist_n[7], const doubl
  * hist[8][7] (GP-major).  hist_np1[8][7] may be NULL.  diag[4] accumulates
  * (local Newton failures, detJ0<=0, detF<=0, non-finite). */
 void oracle_element(const double X[24], const double d[24], const double hist[56],
-                    const double prm[11], double R[24], double K[576], double hist_np1[56],
+                    const double prm[11], int model, const double *Theta, double R[24], double K[576], double hist_np1[56],
                     int32_t diag[4]);
 
 /* CSR pattern.  Phase 1 (col_idx == NULL): fills row_ptr[3*n_nodes+1] and *nnz.
@@ -70,20 +85,20 @@ int oracle_csr_pattern(int32_t n_nodes, int32_t n_elems, const int32_t *conn,
  * diag[4] (may be NULL).  n_threads <= 0 uses the OpenMP default. */
 int oracle_residual_tangent(int32_t n_nodes, int32_t n_elems, const double *X,
                             const int32_t *conn, const int32_t *row_ptr, const int32_t *col_idx,
-                            const double *prm, const double *d, const double *hist_n,
-                            const uint8_t *bc_mask, double *R, double *K, double *hist_np1,
+                            const double *prm, int model, const double *orient,
+                            const double *d, const double *hist_n, const uint8_t *bc_mask, double *R, double *K, double *hist_np1,
                             double *rnorm2, int32_t *diag, int n_threads);
 
 /* Trial-state yield test only: flag[q] = 1 if f_tr > 0 at Gauss point q. */
 void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *conn,
-                        const double *prm, const double *d, const double *hist_n,
+                        const double *prm, int model, const double *orient, const double *d, const double *hist_n,
                         uint8_t *flag, int n_threads);
 
 /* Parameter VJP  g_elem[7][n_elems] = lam^T dR/dtheta_e for the 7 parameters
- * (F, G, H, N, K, eps0, n), by forward-mode implicit differentiation of the
+ * (F, G, H, N, K, eps0, n) (Voce: F, G, H, N, sig0, Q, b), by forward-mode implicit differentiation of the
  * local update; g_uniform[7] = sum over elements (either may be NULL). */
 int oracle_residual_vjp(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *conn,
-                        const double *prm, const double *d, const double *hist_n,
+                        const double *prm, int model, const double *orient, const double *d, const double *hist_n,
                         const double *lam, double *g_uniform, double *g_elem, int32_t *diag,
                         int n_threads);
 

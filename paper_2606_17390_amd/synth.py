@@ -26,6 +26,9 @@ GRAD_PARAM_INDEX = (2, 3, 4, 7, 8, 9, 10)  # position of each GRAD_NAMES entry i
 
 E_DEFAULT, NU_DEFAULT = 200000.0, 0.3
 SWIFT_DEFAULT = (500.0, 0.01, 0.2)  # K [MPa], eps0, n
+# Voce law sigma_y = sig0 + Q (1 - exp(-b alpha)); its three parameters take
+# the slots of (K, eps0, n) in a parameter row
+VOCE_DEFAULT = (200.0, 150.0, 20.0)  # sig0 [MPa], Q [MPa], b
 # Trial-state amplitude of the large_cube displacement field: the value for
 # which 30% of the Gauss points have f_tr > 0 (tests/golden/calibrate_large_cube.py).
 LARGE_CUBE_AMPLITUDE = 0.0041015625
@@ -46,6 +49,9 @@ class Problem:
     bc_mask: Optional[np.ndarray] = None  # [3*n_nodes] uint8
     lam: Optional[np.ndarray] = None      # [n_nodes, 3] cotangent
     meta: dict = field(default_factory=dict)
+    hardening: str = "swift"              # "swift" or "voce" (slots 8-10: K, eps0, n or sig0, Q, b)
+    fbar: bool = False                    # F-bar element formulation
+    orient: Optional[np.ndarray] = None   # None, [9] or [n_elems, 9] rotations (row-major)
 
     @property
     def n_nodes(self):
@@ -63,6 +69,54 @@ class Problem:
 def params(F=0.5, G=0.5, H=0.5, L=1.5, M=1.5, N=1.5, K=SWIFT_DEFAULT[0], eps0=SWIFT_DEFAULT[1],
            n=SWIFT_DEFAULT[2], E=E_DEFAULT, nu=NU_DEFAULT):
     return np.array([E, nu, F, G, H, L, M, N, K, eps0, n], dtype=np.float64)
+
+
+def voce_params(F=0.5, G=0.5, H=0.5, L=1.5, M=1.5, N=1.5, sig0=VOCE_DEFAULT[0], Q=VOCE_DEFAULT[1],
+                b=VOCE_DEFAULT[2], E=E_DEFAULT, nu=NU_DEFAULT):
+    return np.array([E, nu, F, G, H, L, M, N, sig0, Q, b], dtype=np.float64)
+
+
+def random_rotation(rng):
+    """A rotation drawn from the QR factors of a Gaussian matrix (det +1)."""
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def rotation_z(angle):
+    """Rotation by `angle` (radians) about the z axis; its columns are the rotated x, y, z axes."""
+    c, s = np.cos(angle), np.sin(angle)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def with_model(p, seed, hardening="swift", fbar=False, orient=None):
+    """Problem p with another hardening law, the F-bar element and/or an
+    orientation: "voce" replaces slots 8-10 of the parameters by Voce values
+    (per element draws if p is per element); orient is None, "uniform" (one
+    random rotation) or "per_element" (one random in-plane angle per element)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    prm = p.prm.copy()
+    if hardening == "voce":
+        if prm.ndim == 2:
+            ne = prm.shape[0]
+            prm[:, 8] = rng.uniform(180.0, 220.0, ne)
+            prm[:, 9] = rng.uniform(100.0, 200.0, ne)
+            prm[:, 10] = rng.uniform(10.0, 30.0, ne)
+        else:
+            prm[8:11] = VOCE_DEFAULT
+    ori = None
+    if orient == "uniform":
+        ori = random_rotation(rng).ravel()
+    elif orient == "per_element":
+        ang = rng.uniform(0.0, np.pi, p.n_elems)
+        ori = np.stack([rotation_z(a).ravel() for a in ang])
+    elif orient is not None:
+        ori = np.asarray(orient, dtype=np.float64)
+    import dataclasses
+    return dataclasses.replace(p, prm=prm, hardening=hardening, fbar=fbar, orient=ori,
+                               name=f"{p.name}_{hardening}{'_fbar' if fbar else ''}{'_' + orient if isinstance(orient, str) else ''}")
 
 
 def hex_grid(nx, ny, nz, lx=None, ly=None, lz=None):

@@ -27,14 +27,23 @@ def hist_rel(a, b):
     return max(float(np.abs(a[:6] - b[:6]).max() / se), float(np.abs(a[6] - b[6]).max() / sa))
 
 
+def oracle_model(p):
+    """Model flags and per-element orientation of a synth.Problem for the oracle."""
+    flags = (oracle.MODEL_VOCE if p.hardening == "voce" else 0) | (oracle.MODEL_FBAR if p.fbar else 0)
+    return flags, p.orient
+
+
 def residual_scale(p):
     """|| sum_e |R^e| ||_inf : assembled absolute element contributions (robust
     to cancellation near equilibrium)."""
     acc = np.zeros(3 * p.n_nodes)
     prm = oracle.expand_params(p.prm, p.n_elems)
+    model, orient = oracle_model(p)
+    ori = oracle.expand_orient(orient, p.n_elems)
     for e in range(p.n_elems):
         he = p.hist_n[:, 8 * e:8 * e + 8].T
-        Re, _, _, _ = oracle.element(p.X[p.conn[e]], p.d[p.conn[e]], he, prm[e], want_K=False)
+        Re, _, _, _ = oracle.element(p.X[p.conn[e]], p.d[p.conn[e]], he, prm[e], want_K=False, model=model,
+                                     Theta=None if ori is None else ori[e])
         dofs = (3 * p.conn[e][:, None] + np.arange(3)).ravel()
         np.add.at(acc, dofs, np.abs(Re))
     return float(acc.max())
@@ -42,8 +51,10 @@ def residual_scale(p):
 
 def oracle_forward(p, bc=True, want_K=True):
     rp, ci, rank = oracle.csr_pattern(p.conn, p.n_nodes)
+    model, orient = oracle_model(p)
     R, K, hn, rn, diag = oracle.residual_tangent(p.X, p.conn, rp, ci, p.prm, p.d, p.hist_n,
-                                                 bc_mask=p.bc_mask if bc else None, want_K=want_K)
+                                                 bc_mask=p.bc_mask if bc else None, want_K=want_K,
+                                                 model=model, orient=orient)
     return dict(row_ptr=rp, col_idx=ci, rank=rank, R=R, K=K, hist=hn, rnorm2=rn, diag=diag)
 
 
