@@ -3,7 +3,8 @@
  * a finite-strain anisotropic-plasticity finite-element step:
  *
  *   per hex8 element and each of its 2x2x2 Gauss points: logarithmic strain
- *   from C = F^T F, Hill-48 return mapping with Swift isotropic hardening,
+ *   from C = F^T F (or the F-bar gradient), Hill-48 return mapping (optional
+ *   orientation) with Swift or Voce isotropic hardening,
  *   second and first Piola-Kirchhoff stress, element residual R^e and
  *   consistent tangent K^e = dR^e/dd^e, assembled into a fixed CSR pattern;
  *   and the vector-Jacobian product lambda^T dR/dtheta for material parameters.
@@ -39,7 +40,8 @@
  *   params       : FEM_P_* below; Hill-48 in the F,G,H,L,M,N form
  *                  phi^2 = F(T22-T33)^2 + G(T33-T11)^2 + H(T11-T22)^2
  *                          + 2L T23^2 + 2M T13^2 + 2N T12^2,
- *                  Swift sigma_y = K (eps0 + alpha)^n, alpha_{n+1} = alpha_n + dgamma
+ *                  Swift sigma_y = K (eps0 + alpha)^n (or Voce, FEM_MODEL_VOCE),
+ *                  alpha_{n+1} = alpha_n + dgamma
  */
 #ifndef FEM_H
 #define FEM_H
@@ -73,8 +75,21 @@ enum {
     FEM_P_E, FEM_P_NU, FEM_P_F, FEM_P_G, FEM_P_H, FEM_P_L, FEM_P_M, FEM_P_N,
     FEM_P_K, FEM_P_EPS0, FEM_P_NEXP, FEM_NPARAM
 };
-/* differentiated parameters, in this order */
+/* with FEM_MODEL_VOCE the three hardening slots hold (sig0, Q, b) */
+enum { FEM_P_SIG0 = FEM_P_K, FEM_P_Q = FEM_P_EPS0, FEM_P_B = FEM_P_NEXP };
+/* differentiated parameters, in this order (Voce: F, G, H, N, sig0, Q, b) */
 enum { FEM_G_F, FEM_G_G, FEM_G_H, FEM_G_N, FEM_G_K, FEM_G_EPS0, FEM_G_NEXP, FEM_NGRAD };
+enum { FEM_G_SIG0 = FEM_G_K, FEM_G_Q = FEM_G_EPS0, FEM_G_B = FEM_G_NEXP };
+
+/* Model options (fem_params.model, bit flags; 0 = Swift hardening, plain hex8):
+ *   FEM_MODEL_VOCE  Voce isotropic hardening of Eq. (Hard), read in
+ *                   uniaxial-stress units as sigma_y = sig0 + Q (1 - exp(-b alpha))
+ *                   (the same normalisation as phi and the Swift law).
+ *   FEM_MODEL_FBAR  F-bar element of Sec. 2.2.4: the material sees
+ *                   Fbar = (Jbar / J)^(1/3) F at each Gauss point, with
+ *                   Jbar = (1/V_e) int J dV over the element; R^e_I =
+ *                   int P(Fbar) . grad N_I dV and K^e = dR^e/dd^e (not symmetric). */
+enum { FEM_MODEL_VOCE = 1u, FEM_MODEL_FBAR = 2u };
 
 typedef struct {
     int32_t n_nodes, n_elems;
@@ -84,11 +99,21 @@ typedef struct {
 
 /* Parameter k is read from p[k] (device): one value, or n_elems values if
  * bit k of per_elem_mask is set, or n_spec values indexed by specimen if bit k
- * of per_spec_mask is set (batched calls).  per_elem wins if both are set. */
+ * of per_spec_mask is set (batched calls).  per_elem wins if both are set.
+ * model: FEM_MODEL_* flags.  orient: material orientation Theta of the Hill
+ * tensor (App. A: H_global = Theta Theta : H_local : Theta^T Theta^T), NULL
+ * for the identity, else device row-major 3x3 rotations whose columns are
+ * the orthotropy axes in global coordinates: one ([9]) or, if
+ * orient_per_elem is nonzero, one per element ([n_elems][9]).  Theta must be
+ * a proper rotation (not checked).  The plastic strain history is always in
+ * global components. */
 typedef struct {
     const double *p[FEM_NPARAM];
     uint32_t per_elem_mask;
     uint32_t per_spec_mask;
+    uint32_t model;
+    uint32_t orient_per_elem;
+    const double *orient;
 } fem_params;
 
 /* CSR matrix of the tangent, 3x3 node blocks: row 3I+a holds columns 3J+b

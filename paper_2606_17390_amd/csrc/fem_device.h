@@ -390,7 +390,8 @@ __device__ inline R dd2_triple(R m0, R m1, R m2, R e0, R e1, R e2) {
 // ---------------------------------------------------------------- material
 
 struct Mat {
-    double E, nu, F, G, H, L, M, N, K, eps0, nexp;
+    double E, nu, F, G, H, L, M, N, K, eps0, nexp;  // Voce: (K, eps0, nexp) = (sig0, Q, b)
+    int voce;
 };
 
 // Hill-48 in its eigen-modes: hydrostatic direction (eigenvalue 0), two
@@ -439,7 +440,16 @@ __device__ inline void hill_modes(const Mat& m, Modes& h) {
     }
 }
 
-__device__ inline double swift(const Mat& m, double alpha, double& dsig) {
+// Isotropic hardening sigma_y(alpha) and its slope: Swift K (eps0 + alpha)^n,
+// or Voce sig0 + Q (1 - exp(-b alpha)) (Eq. Hard, in uniaxial-stress units)
+// with (sig0, Q, b) in the slots of (K, eps0, n).  The law is the same for
+// every element of a launch, so the branch is uniform.
+__device__ inline double hardening(const Mat& m, double alpha, double& dsig) {
+    if (m.voce) {
+        const double ex = exp(-m.nexp * alpha);
+        dsig = m.eps0 * m.nexp * ex;
+        return m.K + m.eps0 * (1.0 - ex);
+    }
     const double base = m.eps0 + alpha;
     const double s = m.K * exp(m.nexp * log(base));
     dsig = m.nexp * s * recip(base);
@@ -494,7 +504,7 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
     const double phi_tr = phi2 > 0.0 ? phi2 * rsqrt_nr(phi2) : 0.0;
     double dsig_n;
     const double alpha_n = hist_n[6];
-    o.sy_n = swift(m, alpha_n, dsig_n);
+    o.sy_n = hardening(m, alpha_n, dsig_n);
     o.ftr = phi_tr - o.sy_n;
     o.tb_h = th;
     if (!(o.ftr > 0.0)) {
@@ -545,7 +555,7 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
         const double iphi = rsqrt_nr(p2);
         phi = p2 * iphi;
         dp *= iphi;
-        sig = swift(m, alpha_n + lam * phi, dsig);
+        sig = hardening(m, alpha_n + lam * phi, dsig);
         const double g = phi - sig;
         if (g > 0.0) lo = lam; else hi = lam;
         // converged at the rounding level of sigma_y
@@ -571,7 +581,7 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
     phi = p2 * iphi;
     const double dg = lam * phi;
     const double alpha = alpha_n + dg;
-    sig = swift(m, alpha, dsig);
+    sig = hardening(m, alpha, dsig);
     o.converged = conv;
     o.lam = lam;
     o.dgamma = dg;
@@ -608,6 +618,61 @@ __device__ inline void local_update(const double eps[6], const double* hist_n, c
     }
     o.svar = sv;
     o.beta = (1.0 - lam * dsig) * recip(sv + dsig * (1.0 - lam * sv));
+}
+
+// ---------------------------------------------------------------- orientation (App. A)
+
+// Theta: row-major rotation whose columns are the orthotropy axes in global
+// coordinates; a symmetric tensor A has material-frame components
+// Theta^T A Theta.  The Hill tensor is given in the material frame, so the
+// local update runs there (isotropic elasticity is unchanged by the
+// rotation) and its results are rotated back.
+__device__ inline void load_rotation(const double* __restrict__ orient, int64_t idx, double Th[3][3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Th[i][j] = orient[9 * idx + 3 * i + j];
+}
+
+// Symmetric tensor with components v = (11, 22, 33, 23, 13, 12) scaled by w on
+// the shear entries (w = 1: tensor components, w = sqrt2: Mandel), rotated:
+// Theta^T A Theta (TO_MAT) or Theta A Theta^T.
+template <bool TO_MAT>
+__device__ inline void rotate_sym(const double Th[3][3], double v[6], double w) {
+    const double iw = 1.0 / w;
+    const double A[3][3] = {{v[0], v[5] * iw, v[4] * iw}, {v[5] * iw, v[1], v[3] * iw}, {v[4] * iw, v[3] * iw, v[2]}};
+    double W[3][3];  // A R with R = Theta (TO_MAT) or Theta^T
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double x = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) x += A[i][k] * (TO_MAT ? Th[k][q] : Th[q][k]);
+            W[i][q] = x;
+        }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int p = mi(k), q = mj(k);
+        double x = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) x += (TO_MAT ? Th[i][p] : Th[p][i]) * W[i][q];
+        v[k] = (k < 3) ? x : w * x;
+    }
+}
+
+// Qm = Theta^T Q: the eigenvectors of C in material-frame components
+template <typename R>
+__device__ inline void material_frame(const double* __restrict__ orient, int64_t idx, const R Q[3][3], R Qm[3][3]) {
+    R Th[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Th[i][j] = (R)orient[9 * idx + 3 * i + j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Qm[i][j] = Th[0][i] * Q[0][j] + Th[1][i] * Q[1][j] + Th[2][i] * Q[2][j];
 }
 
 // ---------------------------------------------------------------- frame helpers

@@ -39,6 +39,9 @@ struct FwdArgs {
     const int32_t* conn;
     const double* prm[FEM_NPARAM];
     uint32_t pe_mask, ps_mask;
+    uint32_t model;          // FEM_MODEL_* flags
+    const double* orient;    // material orientation(s), or null
+    int32_t orient_pe;       // orient holds one rotation per element
     int32_t n_spec;
     const int64_t* elem_off;
     const double* d;
@@ -89,8 +92,16 @@ __device__ inline Mat load_material(const A& a, int64_t e) {
     m.K = v[8];
     m.eps0 = v[9];
     m.nexp = v[10];
+    m.voce = 0;  // set by the kernel from its variant
     return m;
 }
+
+// Compile-time element variants (bit flags): kVarOrient (a material
+// orientation is given), kVarFbar (F-bar element), kVarVoce (Voce hardening).
+// Variant 0 is the plain Swift / hex8 kernel.
+constexpr int kVarOrient = 1;
+constexpr int kVarFbar = 2;
+constexpr int kVarVoce = 4;
 
 // The element tangent is stored per element as its 9 component blocks
 // K^e_{Ia,Jb}, (a, b) row-major, each an 8x8 node block, row-major: offset
@@ -154,10 +165,11 @@ __device__ inline void kin_and_log(const double (*nd)[6], int gp, GP<R>& s, doub
 // R: working type of kinematics, pull-back and contraction; RO: type of the
 // stored element tangent blocks; FIXUP: walk the element list of the guard
 // band instead of all elements (FP64 recomputation for the mixed path).
-template <typename R, typename RO, int BLOCK, bool FIXUP>
+template <typename R, typename RO, int BLOCK, bool FIXUP, int VAR>
 __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
     constexpr int EPB = BLOCK / 8;
     constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
+    constexpr bool ORIENT = (VAR & kVarOrient) != 0;
     // LDS: node coordinates and displacements of the tile; the frame
     // gradients g^ of every Gauss point; and one buffer used in turn for H
     // and Q across the local update, the residual reduction and the tangent
@@ -214,7 +226,8 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
         double hn[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) hn[k] = a.hist_n[k * a.n_gp + q];
-        const Mat mat = load_material(a, e);
+        Mat mat = load_material(a, e);
+        mat.voce = (VAR & kVarVoce) ? 1 : 0;
         __syncthreads();
 
         // ---- kinematics, log strain (R), local update (double)
@@ -236,10 +249,24 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                 sHQ[slot][gp][9 + 3 * i + j] = s.Q[i][j];
             }
         asm volatile("" ::: "memory");  // the parked values are re-read, not kept in registers
+        const int64_t oidx = a.orient_pe ? e : 0;
+        if constexpr (ORIENT) {
+            // the local update runs in the material frame
+            double Th[3][3];
+            load_rotation(a.orient, oidx, Th);
+            rotate_sym<true>(Th, eps, kSqrt2);
+            rotate_sym<true>(Th, hn, 1.0);
+        }
         Modes md;
         hill_modes(mat, md);
         Local loc;
         local_update(eps, hn, mat, md, loc);
+        if constexpr (ORIENT) {
+            double Th[3][3];
+            load_rotation(a.orient, oidx, Th);
+            rotate_sym<false>(Th, loc.T, kSqrt2);
+            rotate_sym<false>(Th, loc.hist, 1.0);
+        }
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -349,14 +376,18 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
 #pragma unroll
                     for (int J = 0; J < 6; ++J) Ch[I][J] = ((I < 3 && J < 3) ? lamL : R(0)) + ((I == J) ? mu2 : R(0));
                 if (loc.plastic) {
+                    // Hill eigen-basis (material frame) in the eigenframe of C
+                    R Qm[3][3];
+                    if constexpr (ORIENT) material_frame<R>(a.orient, oidx, s.Q, Qm);
+                    const R(*Qb)[3] = ORIENT ? Qm : s.Q;
                     R B[5][6];
                     R v1[3] = {(R)md.v1[0], (R)md.v1[1], (R)md.v1[2]};
                     R v2[3] = {(R)md.v2[0], (R)md.v2[1], (R)md.v2[2]};
-                    rot_diag<R>(s.Q, v1, B[0]);
-                    rot_diag<R>(s.Q, v2, B[1]);
-                    rot_shear<R, 1, 2>(s.Q, B[2]);
-                    rot_shear<R, 0, 2>(s.Q, B[3]);
-                    rot_shear<R, 0, 1>(s.Q, B[4]);
+                    rot_diag<R>(Qb, v1, B[0]);
+                    rot_diag<R>(Qb, v2, B[1]);
+                    rot_shear<R, 1, 2>(Qb, B[2]);
+                    rot_shear<R, 0, 2>(Qb, B[3]);
+                    rot_shear<R, 0, 1>(Qb, B[4]);
                     R mh[6];
 #pragma unroll
                     for (int k = 0; k < 6; ++k) {
@@ -740,24 +771,50 @@ __global__ __launch_bounds__(kFinThreads) void norm_final(const double* __restri
     if (t == 0) out[0] = sh[0];
 }
 
-template <typename R, typename RO, int BLOCK, bool FIXUP>
+template <typename R, typename RO, int BLOCK, bool FIXUP, int VAR>
 hipError_t launch_fwd(const FwdArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((fwd_kernel<R, RO, BLOCK, FIXUP>), dim3(grid), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((fwd_kernel<R, RO, BLOCK, FIXUP, VAR>), dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_fwd_block(const FwdArgs& a, int block, int grid, hipStream_t s) {
-    switch (block) {
-        case 64: return launch_fwd<R, R, 64, false>(a, grid, s);
-        case 256: return launch_fwd<R, R, 256, false>(a, grid, s);
-        default: return launch_fwd<R, R, 128, false>(a, grid, s);
+// element variant of a call
+inline int variant_of(const FwdArgs& a) {
+    return (a.orient ? kVarOrient : 0) | ((a.model & FEM_MODEL_FBAR) ? kVarFbar : 0) |
+           ((a.model & FEM_MODEL_VOCE) ? kVarVoce : 0);
+}
+
+// Variant 0 in every tuned workgroup size; the model variants with 64 threads.
+template <typename R, typename RO, bool FIXUP>
+hipError_t launch_fwd_variant(const FwdArgs& a, int block, int grid, hipStream_t s) {
+    switch (variant_of(a)) {
+        case 0:
+            if (FIXUP || block == 64) return launch_fwd<R, RO, 64, FIXUP, 0>(a, grid, s);
+            if (block == 256) return launch_fwd<R, RO, 256, FIXUP, 0>(a, grid, s);
+            return launch_fwd<R, RO, 128, FIXUP, 0>(a, grid, s);
+        case 1: return launch_fwd<R, RO, 64, FIXUP, 1>(a, grid, s);
+        case 2: return launch_fwd<R, RO, 64, FIXUP, 2>(a, grid, s);
+        case 3: return launch_fwd<R, RO, 64, FIXUP, 3>(a, grid, s);
+        case 4: return launch_fwd<R, RO, 64, FIXUP, 4>(a, grid, s);
+        case 5: return launch_fwd<R, RO, 64, FIXUP, 5>(a, grid, s);
+        case 6: return launch_fwd<R, RO, 64, FIXUP, 6>(a, grid, s);
+        default: return launch_fwd<R, RO, 64, FIXUP, 7>(a, grid, s);
     }
 }
+
+template <typename R>
+hipError_t launch_fwd_main(const FwdArgs& a, int block, int grid, hipStream_t s) {
+    return launch_fwd_variant<R, R, false>(a, block, grid, s);
+}
+
+hipError_t launch_fixup(const FwdArgs& a, int grid, hipStream_t s);
 
 // FP64 recomputation of the guard-band elements of a mixed pass
 constexpr int kFixBlock = 64;
 constexpr int kFixGrid = 1024;
+
+hipError_t launch_fixup(const FwdArgs& a, int grid, hipStream_t s) {
+    return launch_fwd_variant<double, float, true>(a, kFixBlock, grid, s);
+}
 
 // Workgroups of assemble_residual (= partial sums of the norm) for n nodes.
 inline int64_t residual_blocks(int64_t n_nodes) {
@@ -831,6 +888,10 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         if (!params->p[k]) return set_error(FEM_EINVAL, "fem_residual_tangent: parameter %d is NULL", k);
     if (params->per_spec_mask && (!batch || batch->n_spec < 1 || !batch->elem_off))
         return set_error(FEM_EINVAL, "fem_residual_tangent: per-specimen parameters need a batch");
+    if (params->model & ~(uint32_t)(FEM_MODEL_VOCE | FEM_MODEL_FBAR))
+        return set_error(FEM_EINVAL, "fem_residual_tangent: unknown model flags 0x%x", params->model);
+    if (params->model & FEM_MODEL_FBAR)
+        return set_error(FEM_EINVAL, "fem_residual_tangent: F-bar is not available in this build");
     if (batch && (batch->n_spec < 1 || !batch->elem_off))
         return set_error(FEM_EINVAL, "fem_residual_tangent: invalid batch");
     const size_t need = fem_forward_workspace_bytes(mesh->n_nodes, mesh->n_elems, prec);
@@ -845,7 +906,8 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
     FEM_HIP_CHECK(zero_counters(diag, 4, (ne > 0 && prec == FEM_FP32_MIXED) ? w.fix_count : nullptr, 1, s));
 
     if (ne > 0) {
-        const fem_launch cfg = launch_config(FEM_KERNEL_FORWARD, prec);
+        fem_launch cfg = launch_config(FEM_KERNEL_FORWARD, prec);
+        if (params->model || params->orient) cfg.block = 64;  // model variants: 64-thread workgroups
         FwdArgs a;
         a.n_nodes = mesh->n_nodes;
         a.n_elems = mesh->n_elems;
@@ -854,6 +916,9 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         for (int k = 0; k < FEM_NPARAM; ++k) a.prm[k] = params->p[k];
         a.pe_mask = params->per_elem_mask;
         a.ps_mask = params->per_spec_mask & ~params->per_elem_mask;
+        a.model = params->model;
+        a.orient = params->orient;
+        a.orient_pe = params->orient_per_elem ? 1 : 0;
         a.n_spec = batch ? batch->n_spec : 1;
         a.elem_off = batch ? batch->elem_off : nullptr;
         a.d = d;
@@ -870,12 +935,12 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         a.fix_count = w.fix_count;
         const int grid = persistent_grid(cfg, a.n_tiles);
         void* tk = timing_begin(s);
-        hipError_t e = (prec == FEM_FP64) ? launch_fwd_block<double>(a, cfg.block, grid, s)
-                                          : launch_fwd_block<float>(a, cfg.block, grid, s);
+        hipError_t e = (prec == FEM_FP64) ? launch_fwd_main<double>(a, cfg.block, grid, s)
+                                          : launch_fwd_main<float>(a, cfg.block, grid, s);
         timing_end(tk, FEM_KERNEL_FORWARD, s);
         if (e != hipSuccess) return set_error(FEM_EHIP, "forward kernel launch failed: %s", hipGetErrorString(e));
         if (prec == FEM_FP32_MIXED) {
-            e = launch_fwd<double, float, kFixBlock, true>(a, kFixGrid, s);
+            e = launch_fixup(a, kFixGrid, s);
             if (e != hipSuccess) return set_error(FEM_EHIP, "fixup kernel launch failed: %s", hipGetErrorString(e));
         }
     } else if (assemble) {

@@ -1,5 +1,6 @@
 // vjp.hip -- parameter vector-Jacobian product g = lambda^T dR/dtheta for
-// theta = (F, G, H, N, K, eps0, n) (Alg. 1 "Evaluate VJP", Eq. (main_grad)).
+// theta = (F, G, H, N, K, eps0, n), or (F, G, H, N, sig0, Q, b) with Voce
+// hardening (Alg. 1 "Evaluate VJP", Eq. (main_grad)).
 //
 // R_Ia = sum_e sum_g w detJ0 P_aA dN_I/dX_A, P = F (P_L : T), and only the
 // logarithmic stress T depends on theta, through the converged local update.
@@ -29,6 +30,9 @@ struct VjpArgs {
     const int32_t* conn;
     const double* prm[FEM_NPARAM];
     uint32_t pe_mask, ps_mask;
+    uint32_t model;          // FEM_MODEL_* flags
+    const double* orient;    // material orientation(s), or null
+    int32_t orient_pe;       // orient holds one rotation per element
     int32_t n_spec;
     const int64_t* elem_off;
     const double* d;
@@ -65,8 +69,14 @@ __device__ inline Mat load_material_v(const VjpArgs& a, int64_t e) {
     Mat m;
     m.E = v[0]; m.nu = v[1]; m.F = v[2]; m.G = v[3]; m.H = v[4]; m.L = v[5];
     m.M = v[6]; m.N = v[7]; m.K = v[8]; m.eps0 = v[9]; m.nexp = v[10];
+    m.voce = 0;  // set by the kernel from its variant
     return m;
 }
+
+// compile-time variants (bit flags, as in the forward kernel)
+constexpr int kVarOrientV = 1;
+constexpr int kVarFbarV = 2;
+constexpr int kVarVoceV = 4;
 
 __device__ inline void tile_range_v(int64_t n_tiles, int remap, int64_t& first, int64_t& end, int64_t& step) {
     const int nb = gridDim.x, b = blockIdx.x;
@@ -111,11 +121,12 @@ __device__ inline void kin_log_v(const double (*nd)[9], int gp, GPv<R>& s, doubl
 
 // The FP32 form is held to two waves per SIMD (a few registers spill; measured
 // faster than one wave per SIMD without spills).
-template <typename R, int BLOCK, bool FIXUP>
+template <typename R, int BLOCK, bool FIXUP, int VAR>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value && !FIXUP ? 2 : 1)))
 void vjp_kernel(const VjpArgs a) {
     constexpr int EPB = BLOCK / 8;
     constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
+    constexpr bool ORIENT = (VAR & kVarOrientV) != 0;
     __shared__ double sN[EPB][8][9];
     __shared__ double red[7][BLOCK + 1];
     __shared__ int sFlag[EPB];
@@ -156,7 +167,8 @@ void vjp_kernel(const VjpArgs a) {
         double hn[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) hn[k] = a.hist_n[k * a.n_gp + q];
-        const Mat mat = load_material_v(a, e);
+        Mat mat = load_material_v(a, e);
+        mat.voce = (VAR & kVarVoceV) ? 1 : 0;
         __syncthreads();
 
         GPv<R> s;
@@ -175,6 +187,14 @@ void vjp_kernel(const VjpArgs a) {
                 sHQ[slot][gp][9 + 3 * i + j] = s.Q[i][j];
             }
         asm volatile("" ::: "memory");  // the parked values are re-read, not kept in registers
+        const int64_t oidx = a.orient_pe ? e : 0;
+        if constexpr (ORIENT) {
+            // local update and adjoint in the material frame
+            double Th[3][3];
+            load_rotation(a.orient, oidx, Th);
+            rotate_sym<true>(Th, eps, kSqrt2);
+            rotate_sym<true>(Th, hn, 1.0);
+        }
         Modes md;
         hill_modes(mat, md);
         Local loc;
@@ -230,6 +250,11 @@ void vjp_kernel(const VjpArgs a) {
             double tb[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) tb[k] = (double)tbm[k];
+            if constexpr (ORIENT) {
+                double Th[3][3];
+                load_rotation(a.orient, oidx, Th);
+                rotate_sym<true>(Th, tb, kSqrt2);
+            }
 
             // ---- reverse-mode adjoint of the local update (double)
             const double lam = loc.lam, dg = loc.dgamma, phi = loc.phi, sv = loc.svar;
@@ -285,15 +310,22 @@ void vjp_kernel(const VjpArgs a) {
                 const double xNt = xh_ / phi - xN * dphi / phi;
                 gbar[k] = -dg * uNt - (uN / Dn) * (-dg * xNt + dphi);
             }
-            // Swift K, eps0, n at alpha_{n+1}
+            // hardening parameters at alpha_{n+1}: Swift (K, eps0, n) or Voce (sig0, Q, b)
             const double alpha = loc.hist[6];
-            const double base = mat.eps0 + alpha;
-            const double dK = loc.sig / mat.K;
-            const double de0 = loc.dsig;
-            const double dn = loc.sig * log(base);
-            gbar[4] = (uN / Dn) * dK;
-            gbar[5] = (uN / Dn) * de0;
-            gbar[6] = (uN / Dn) * dn;
+            double d0, d1, d2;
+            if (mat.voce) {
+                const double ex = exp(-mat.nexp * alpha);
+                d0 = 1.0;
+                d1 = 1.0 - ex;
+                d2 = mat.eps0 * alpha * ex;
+            } else {
+                d0 = loc.sig / mat.K;
+                d1 = loc.dsig;
+                d2 = loc.sig * log(mat.eps0 + alpha);
+            }
+            gbar[4] = (uN / Dn) * d0;
+            gbar[5] = (uN / Dn) * d1;
+            gbar[6] = (uN / Dn) * d2;
             const double w = (double)s.detJ;
 #pragma unroll
             for (int k = 0; k < 7; ++k) gbar[k] *= w;
@@ -348,15 +380,42 @@ __global__ __launch_bounds__(kRedThreads) void reduce_uniform(const double* __re
     if (threadIdx.x == 0) g_uniform[(int64_t)sidx * FEM_NGRAD + k] = sh[0];
 }
 
-template <typename R>
-hipError_t launch_vjp(const VjpArgs& a, int block, int grid, hipStream_t s) {
-    switch (block) {
-        case 64: hipLaunchKernelGGL((vjp_kernel<R, 64, false>), dim3(grid), dim3(64), 0, s, a); break;
-        case 256: hipLaunchKernelGGL((vjp_kernel<R, 256, false>), dim3(grid), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((vjp_kernel<R, 128, false>), dim3(grid), dim3(128), 0, s, a); break;
-    }
+template <typename R, int BLOCK, bool FIXUP, int VAR>
+hipError_t launch_vjp_one(const VjpArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((vjp_kernel<R, BLOCK, FIXUP, VAR>), dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
+
+inline int variant_of_v(const VjpArgs& a) {
+    return (a.orient ? kVarOrientV : 0) | ((a.model & FEM_MODEL_FBAR) ? kVarFbarV : 0) |
+           ((a.model & FEM_MODEL_VOCE) ? kVarVoceV : 0);
+}
+
+// Variant 0 in every tuned workgroup size; the model variants with 64 threads.
+template <typename R, bool FIXUP>
+hipError_t launch_vjp_variant(const VjpArgs& a, int block, int grid, hipStream_t s) {
+    switch (variant_of_v(a)) {
+        case 0:
+            if (FIXUP || block == 64) return launch_vjp_one<R, 64, FIXUP, 0>(a, grid, s);
+            if (block == 256) return launch_vjp_one<R, 256, FIXUP, 0>(a, grid, s);
+            return launch_vjp_one<R, 128, FIXUP, 0>(a, grid, s);
+        case 1: return launch_vjp_one<R, 64, FIXUP, 1>(a, grid, s);
+        case 2: return launch_vjp_one<R, 64, FIXUP, 2>(a, grid, s);
+        case 3: return launch_vjp_one<R, 64, FIXUP, 3>(a, grid, s);
+        case 4: return launch_vjp_one<R, 64, FIXUP, 4>(a, grid, s);
+        case 5: return launch_vjp_one<R, 64, FIXUP, 5>(a, grid, s);
+        case 6: return launch_vjp_one<R, 64, FIXUP, 6>(a, grid, s);
+        default: return launch_vjp_one<R, 64, FIXUP, 7>(a, grid, s);
+    }
+}
+
+template <typename R>
+hipError_t launch_vjp(const VjpArgs& a, int block, int grid, hipStream_t s) {
+    return launch_vjp_variant<R, false>(a, block, grid, s);
+}
+
+// FP64 recomputation of the guard-band elements of a mixed call
+hipError_t launch_vjp_fixup(const VjpArgs& a, hipStream_t s) { return launch_vjp_variant<double, true>(a, 64, 1024, s); }
 
 }  // namespace
 }  // namespace fem
@@ -389,6 +448,10 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         return set_error(FEM_EINVAL, "fem_residual_vjp: invalid batch");
     if (params->per_spec_mask && !batch)
         return set_error(FEM_EINVAL, "fem_residual_vjp: per-specimen parameters need a batch");
+    if (params->model & ~(uint32_t)(FEM_MODEL_VOCE | FEM_MODEL_FBAR))
+        return set_error(FEM_EINVAL, "fem_residual_vjp: unknown model flags 0x%x", params->model);
+    if (params->model & FEM_MODEL_FBAR)
+        return set_error(FEM_EINVAL, "fem_residual_vjp: F-bar is not available in this build");
     const int n_spec = batch ? batch->n_spec : 1;
     hipStream_t s = (hipStream_t)stream;
     const size_t need = fem_vjp_workspace_bytes(mesh->n_elems, n_spec);
@@ -402,7 +465,8 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
     // diag, and the guard-band counter of a mixed call, start at zero
     FEM_HIP_CHECK(zero_counters(diag, 4, (ne > 0 && prec == FEM_FP32_MIXED) ? fix_count : nullptr, 1, s));
     if (ne > 0) {
-        const fem_launch cfg = launch_config(FEM_KERNEL_VJP, prec);
+        fem_launch cfg = launch_config(FEM_KERNEL_VJP, prec);
+        if (params->model || params->orient) cfg.block = 64;  // model variants: 64-thread workgroups
         VjpArgs a;
         a.n_nodes = mesh->n_nodes;
         a.n_elems = mesh->n_elems;
@@ -411,6 +475,9 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         for (int k = 0; k < FEM_NPARAM; ++k) a.prm[k] = params->p[k];
         a.pe_mask = params->per_elem_mask;
         a.ps_mask = params->per_spec_mask & ~params->per_elem_mask;
+        a.model = params->model;
+        a.orient = params->orient;
+        a.orient_pe = params->orient_per_elem ? 1 : 0;
         a.n_spec = n_spec;
         a.elem_off = batch ? batch->elem_off : nullptr;
         a.d = d;
@@ -430,10 +497,7 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
                                           : launch_vjp<float>(a, cfg.block, grid, s);
         timing_end(tk, FEM_KERNEL_VJP, s);
         if (e != hipSuccess) return set_error(FEM_EHIP, "vjp kernel launch failed: %s", hipGetErrorString(e));
-        if (prec == FEM_FP32_MIXED) {
-            hipLaunchKernelGGL((vjp_kernel<double, 64, true>), dim3(1024), dim3(64), 0, s, a);
-            FEM_HIP_CHECK(hipGetLastError());
-        }
+        if (prec == FEM_FP32_MIXED) FEM_HIP_CHECK(launch_vjp_fixup(a, s));
     }
     if (g_uniform) {
         if (ne == 0) {

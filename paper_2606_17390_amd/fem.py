@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfem.so")
 FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOMEM, FEM_EOVERFLOW, FEM_EMESH, FEM_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_MIXED = 0, 1
 NPARAM, NGRAD = 11, 7
+MODEL_VOCE, MODEL_FBAR = 1, 2  # fem_params.model flags
 KERNEL_FORWARD, KERNEL_VJP, KERNEL_ASSEMBLE_K, KERNEL_ASSEMBLE_R = 0, 1, 2, 3
 
 _c_i32, _c_i64, _c_u32, _c_p, _c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
@@ -27,7 +28,8 @@ class FemMesh(ctypes.Structure):
 
 
 class FemParams(ctypes.Structure):
-    _fields_ = [("p", _c_p * NPARAM), ("per_elem_mask", _c_u32), ("per_spec_mask", _c_u32)]
+    _fields_ = [("p", _c_p * NPARAM), ("per_elem_mask", _c_u32), ("per_spec_mask", _c_u32), ("model", _c_u32),
+                ("orient_per_elem", _c_u32), ("orient", _c_p)]
 
 
 class FemCsr(ctypes.Structure):
@@ -181,9 +183,27 @@ class Mesh:
 
 class Params:
     """The 11 material parameters: uniform (shape [11]), per element ([n_elems, 11])
-    or per specimen ([n_spec, 11], batched mode)."""
+    or per specimen ([n_spec, 11], batched mode); the model options: hardening
+    "swift" or "voce" (slots 8-10 then hold sig0, Q, b), fbar (F-bar element),
+    orient (None, one rotation [3, 3] / [9], or per element [n_elems, 3, 3] /
+    [n_elems, 9]; columns = orthotropy axes)."""
 
-    def __init__(self, prm, n_elems, device="cuda", per_spec=False):
+    def __init__(self, prm, n_elems, device="cuda", per_spec=False, hardening="swift", fbar=False, orient=None):
+        if hardening not in ("swift", "voce"):
+            raise ValueError(f"unknown hardening law {hardening!r}")
+        self.model = (MODEL_VOCE if hardening == "voce" else 0) | (MODEL_FBAR if fbar else 0)
+        self.orient = None
+        self.orient_per_elem = 0
+        if orient is not None:
+            o = torch.as_tensor(np.asarray(orient, dtype=np.float64) if not torch.is_tensor(orient) else orient,
+                                dtype=torch.float64)
+            if o.numel() == 9:
+                self.orient = o.reshape(9).to(device).contiguous()
+            elif o.numel() == 9 * n_elems:
+                self.orient = o.reshape(n_elems, 9).to(device).contiguous()
+                self.orient_per_elem = 1
+            else:
+                raise ValueError("orient must hold one rotation or one per element")
         prm = torch.as_tensor(np.asarray(prm, dtype=np.float64) if not torch.is_tensor(prm) else prm,
                               dtype=torch.float64)
         self.cols = []
@@ -213,6 +233,9 @@ class Params:
             p.p[k] = self.cols[k].data_ptr()
         p.per_elem_mask = self.per_elem_mask
         p.per_spec_mask = self.per_spec_mask
+        p.model = self.model
+        p.orient_per_elem = self.orient_per_elem
+        p.orient = _ptr(self.orient) if self.orient is not None else None
         return p
 
 

@@ -107,11 +107,14 @@ def with_model(p, seed, hardening="swift", fbar=False, orient=None):
         else:
             prm[8:11] = VOCE_DEFAULT
     ori = None
-    if orient == "uniform":
-        ori = random_rotation(rng).ravel()
-    elif orient == "per_element":
-        ang = rng.uniform(0.0, np.pi, p.n_elems)
-        ori = np.stack([rotation_z(a).ravel() for a in ang])
+    if isinstance(orient, str):
+        if orient == "uniform":
+            ori = random_rotation(rng).ravel()
+        elif orient == "per_element":
+            ang = rng.uniform(0.0, np.pi, p.n_elems)
+            ori = np.stack([rotation_z(a).ravel() for a in ang])
+        else:
+            raise ValueError(f"unknown orientation {orient!r}")
     elif orient is not None:
         ori = np.asarray(orient, dtype=np.float64)
     import dataclasses

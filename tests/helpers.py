@@ -62,7 +62,7 @@ def gpu_problem(p, fem, device="cuda"):
     """Device copies of a synth.Problem for the binding."""
     import torch
     mesh = fem.Mesh(p.X, p.conn, device)
-    params = fem.Params(p.prm, p.n_elems, device)
+    params = fem.Params(p.prm, p.n_elems, device, hardening=p.hardening, fbar=p.fbar, orient=p.orient)
     d = torch.as_tensor(np.ascontiguousarray(p.d, dtype=np.float64)).to(device)
     h = torch.as_tensor(np.ascontiguousarray(p.hist_n, dtype=np.float64)).to(device)
     bc = torch.as_tensor(np.ascontiguousarray(p.bc_mask, dtype=np.uint8)).to(device) if p.bc_mask is not None else None
