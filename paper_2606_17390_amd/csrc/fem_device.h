@@ -43,6 +43,10 @@ __device__ inline float m_abs(float x) { return __builtin_fabsf(x); }
 __device__ inline double m_abs(double x) { return __builtin_fabs(x); }
 __device__ inline float m_sinh(float x) { return sinhf(x); }
 __device__ inline double m_sinh(double x) { return sinh(x); }
+__device__ inline float m_expm1(float x) { return expm1f(x); }
+__device__ inline double m_expm1(double x) { return expm1(x); }
+__device__ inline float m_cbrt(float x) { return cbrtf(x); }
+__device__ inline double m_cbrt(double x) { return cbrt(x); }
 // 1/x and 1/sqrt(x) in FP64 for the local update: the hardware estimate
 // refined by two Newton-Raphson steps (quadratic convergence; the result is
 // within about an ulp, for the finite positive normal arguments used here).
@@ -226,6 +230,52 @@ __device__ inline void kinematics_lds(const double (*nd)[W], int gp, R g[8][3], 
             }
         }
     }
+}
+
+// ---------------------------------------------------------------- F-bar (Sec. 2.2.4)
+
+// det(I + H) - 1 as tr H + (sum of principal 2x2 minors) + det H (no
+// cancellation against 1 at small strain)
+template <typename R>
+__device__ inline R det_minus_one(const R H[3][3]) {
+    const R m2 = (H[0][0] * H[1][1] - H[0][1] * H[1][0]) + (H[0][0] * H[2][2] - H[0][2] * H[2][0]) +
+                 (H[1][1] * H[2][2] - H[1][2] * H[2][1]);
+    const R d3 = H[0][0] * (H[1][1] * H[2][2] - H[1][2] * H[2][1]) - H[0][1] * (H[1][0] * H[2][2] - H[1][2] * H[2][0]) +
+                 H[0][2] * (H[1][0] * H[2][1] - H[1][1] * H[2][0]);
+    return (H[0][0] + H[1][1] + H[2][2]) + m2 + d3;
+}
+
+// Sum over the 8 lanes of an element (xor butterfly; every lane gets the
+// same bits, as each stage adds the same two values in either order).
+template <typename R>
+__device__ inline R sum8(R v) {
+    v += __shfl_xor(v, 1, 8);
+    v += __shfl_xor(v, 2, 8);
+    v += __shfl_xor(v, 4, 8);
+    return v;
+}
+
+// Per Gauss point of the F-bar element: Fbar = beta F with
+// beta = (Jbar / J)^(1/3), Jbar = sum_g w detJ0_g J_g / sum_g w detJ0_g
+// (weights 1).  Replaces H by Hbar = Fbar - I = beta H + (beta - 1) I and
+// returns beta and cw = w detJ0 J / (V_e Jbar), the weight of this Gauss
+// point's dJ in dJbar / Jbar.  Called by all 8 lanes of the element.
+// beta - 1 comes from logarithms of J and Jbar (accurate at small volume
+// change); a non-positive J or Jbar takes the plain cube root.
+template <typename R>
+__device__ inline void fbar_gradient(R detJ0, R H[3][3], R& beta, R& cw, R& jm1) {
+    jm1 = det_minus_one(H);
+    const R V = sum8(detJ0);
+    const R jbm1 = sum8(detJ0 * jm1) / V;
+    R bm1;
+    if (jm1 > R(-1) && jbm1 > R(-1)) bm1 = m_expm1((m_log1p(jbm1) - m_log1p(jm1)) * R(1.0 / 3.0));
+    else bm1 = m_cbrt((R(1) + jbm1) / (R(1) + jm1)) - R(1);
+    beta = R(1) + bm1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) H[i][j] = beta * H[i][j] + ((i == j) ? bm1 : R(0));
+    cw = detJ0 * (R(1) + jm1) / (V * (R(1) + jbm1));
 }
 
 // C - I = H + H^T + H^T H

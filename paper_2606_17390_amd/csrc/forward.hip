@@ -146,9 +146,12 @@ struct GP {
     R eh[3];     // 1/2 ln c_a
 };
 
-template <typename R>
-__device__ inline void kin_and_log(const double (*nd)[6], int gp, GP<R>& s, double eps[6]) {
+// FBAR: the material sees Fbar = beta F (fbar_gradient); s.H becomes
+// Fbar - I and beta, cw, jm1 = J - 1 are returned for the tangent.
+template <typename R, bool FBAR>
+__device__ inline void kin_and_log(const double (*nd)[6], int gp, GP<R>& s, double eps[6], R& beta, R& cw, R& jm1) {
     kinematics_lds<R, 6>(nd, gp, s.g, s.detJ, s.H);
+    if constexpr (FBAR) fbar_gradient<R>(s.detJ, s.H, beta, cw, jm1);
     R M[3][3];
     cauchy_green_minus_identity<R>(s.H, M);
     eig_sym3<R>(M, s.mu, s.Q);
@@ -170,19 +173,23 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
     constexpr int EPB = BLOCK / 8;
     constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
     constexpr bool ORIENT = (VAR & kVarOrient) != 0;
+    constexpr bool FBAR = (VAR & kVarFbar) != 0;
     // LDS: node coordinates and displacements of the tile; the frame
     // gradients g^ of every Gauss point; and one buffer used in turn for H
-    // and Q across the local update, the residual reduction and the tangent
-    // hand-off (the 3 blocks A^ of one phase per Gauss point)
+    // and Q (F-bar: and beta, cw) across the local update, the residual
+    // reduction and the tangent hand-off (the 3 blocks A^ of one phase per
+    // Gauss point; F-bar: first the element sums of the rank-one term)
+    constexpr int kHQ = FBAR ? 20 : 18;
     constexpr int kRed = 24 * (BLOCK + 1);
     constexpr int kHand = EPB * 8 * 28;
-    constexpr int kPark = EPB * 8 * 18;
+    constexpr int kPark = EPB * 8 * kHQ;
     constexpr int kBuf = kRed > kHand ? (kRed > kPark ? kRed : kPark) : (kHand > kPark ? kHand : kPark);
     __shared__ double sXD[EPB][8][6];
     __shared__ __attribute__((aligned(16))) R sG[EPB][8][24];  // [slot][g][3 I + q]
     __shared__ __attribute__((aligned(16))) R sbuf[kBuf];
     __shared__ int sFlag[EPB];
-    R (*sHQ)[8][18] = reinterpret_cast<R (*)[8][18]>(sbuf);     // [slot][g][H 9, Q 9]
+    __shared__ R sQb[FBAR ? EPB : 1][24];                      // F-bar: qbar of the element
+    R (*sHQ)[8][kHQ] = reinterpret_cast<R (*)[8][kHQ]>(sbuf);   // [slot][g][H 9, Q 9 (, beta, cw)]
     R (*red)[BLOCK + 1] = reinterpret_cast<R (*)[BLOCK + 1]>(sbuf);
     R (*sA)[8][28] = reinterpret_cast<R (*)[8][28]>(sbuf);      // [slot][g][9 k + 3 q + s]
 
@@ -233,7 +240,14 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
         // ---- kinematics, log strain (R), local update (double)
         GP<R> s;
         double eps[6];
-        kin_and_log<R>(sXD[slot], gp, s, eps);
+        R fb_beta = R(1), fb_cw = R(0), fb_jm1 = R(0);
+        kin_and_log<R, FBAR>(sXD[slot], gp, s, eps, fb_beta, fb_cw, fb_jm1);
+        if constexpr (FBAR) {
+            // det F <= 0 is counted on F (s.H now holds Fbar - I)
+            if (valid && !FIXUP) cnt_jf += (fb_jm1 <= R(-1)) ? 1 : 0;
+            sHQ[slot][gp][18] = fb_beta;
+            sHQ[slot][gp][19] = fb_cw;
+        }
         // g^_Iq = grad N_IA Q_Aq, parked in LDS (read back by the residual and
         // the tangent hand-off; keeps registers free for the local update)
 #pragma unroll
@@ -275,6 +289,10 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                 s.H[i][j] = sHQ[slot][gp][3 * i + j];
                 s.Q[i][j] = sHQ[slot][gp][9 + 3 * i + j];
             }
+        if constexpr (FBAR) {
+            fb_beta = sHQ[slot][gp][18];
+            fb_cw = sHQ[slot][gp][19];
+        }
         __syncthreads();  // the parking area becomes the residual buffer
         if constexpr (FLAG) {
             // guard band: a trial state this close to the yield surface is
@@ -293,7 +311,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
             const R detF = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
                            F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
                            F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-            cnt_jf += (detF <= R(0)) ? 1 : 0;
+            if constexpr (!FBAR) cnt_jf += (detF <= R(0)) ? 1 : 0;
         }
         if (valid && a.hist_np1) {
 #pragma unroll
@@ -471,6 +489,151 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                     C4[I][J] = C4[J][I] = (I < 3 && J < 3) ? Cm[I][J] : sc * Cm[I][J];
                 }
 
+            if constexpr (FBAR) {
+            // ---- F-bar tangent, all 9 blocks (not symmetric):
+            //   K^e_{Ia,Jb} = sum_g g^_Iq A~(a,b)_qs g^_Js + Ubar_Ia qbar_Jb
+            //   A~(a,b)_qs = beta w detJ0 (A^(a,b)_qs - Y^_aq (f^_bs / c_s) / 3)
+            // in the eigenframe of Cbar (c_s its eigenvalues), with
+            //   Y^ = f^ (S^ + (C:Cbar)^)      (Abar : Fbar = Fbar S + Fbar (C : Cbar)),
+            //   Ubar_Ia = sum_g w detJ0 / 3 Y^_ap g^_Ip,
+            //   qbar_Jb = sum_g cw beta g^_Js f^_bs / c_s   (= dJbar/dd_Jb / Jbar);
+            // the A~ part carries d(Fbar)/dd at fixed Jbar and the per-point
+            // -dJ/J term, Ubar qbar the element's dJbar/Jbar term.
+            const R wK = wdet * fb_beta;
+            R Yh[3][3], fc[3][3];
+            {
+                R Wc[6];
+#pragma unroll
+                for (int I = 0; I < 6; ++I)
+                    Wc[I] = Cm[I][0] * (R(1) + s.mu[0]) + Cm[I][1] * (R(1) + s.mu[1]) + Cm[I][2] * (R(1) + s.mu[2]);
+                const R r2 = R(kInvSqrt2);
+                const R Wm[3][3] = {{Wc[0], Wc[5] * r2, Wc[4] * r2}, {Wc[5] * r2, Wc[1], Wc[3] * r2},
+                                    {Wc[4] * r2, Wc[3] * r2, Wc[2]}};
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) {
+                        Yh[i][p] = fh[i][0] * (Sh[0][p] + Wm[0][p]) + fh[i][1] * (Sh[1][p] + Wm[1][p]) +
+                                   fh[i][2] * (Sh[2][p] + Wm[2][p]);
+                        fc[i][p] = fh[i][p] / (R(1) + s.mu[p]);
+                    }
+            }
+            // element sums Ubar (row gp) and qbar through the hand-off area, in
+            // Gauss point order
+            R (*sU)[8][24] = reinterpret_cast<R (*)[8][24]>(sbuf);
+            {
+                const R w3 = wdet * R(1.0 / 3.0);
+#pragma unroll
+                for (int I = 0; I < 8; ++I)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        sU[slot][gp][3 * I + i] = w3 * (Yh[i][0] * sG[slot][gp][3 * I] + Yh[i][1] * sG[slot][gp][3 * I + 1] +
+                                                         Yh[i][2] * sG[slot][gp][3 * I + 2]);
+            }
+            __syncthreads();
+            R ub[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                R x = R(0);
+#pragma unroll
+                for (int g = 0; g < 8; ++g) x += sU[slot][g][3 * gp + i];
+                ub[i] = x;
+            }
+            __syncthreads();
+            {
+                const R cb = fb_cw * fb_beta;
+#pragma unroll
+                for (int J = 0; J < 8; ++J)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        sU[slot][gp][3 * J + b] = cb * (sG[slot][gp][3 * J] * fc[b][0] + sG[slot][gp][3 * J + 1] * fc[b][1] +
+                                                        sG[slot][gp][3 * J + 2] * fc[b][2]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                R x = R(0);
+#pragma unroll
+                for (int g = 0; g < 8; ++g) x += sU[slot][g][3 * gp + b];
+                sQb[slot][3 * gp + b] = x;
+            }
+            __syncthreads();
+            // three phases: blocks (a, 0), (a, 1), (a, 2) for a = 0, 1, 2
+            static_for<0, 3>([&](auto AA) {
+                constexpr int aa = decltype(AA)::value;
+                R Y[3][3][3];
+#pragma unroll
+                for (int qq = 0; qq < 3; ++qq)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int ss = 0; ss < 3; ++ss) {
+                            const int J = midx(r, ss);
+                            R v = fh[aa][0] * C4[midx(0, qq)][J];
+                            v = m_fma(fh[aa][1], C4[midx(1, qq)][J], v);
+                            Y[qq][r][ss] = m_fma(fh[aa][2], C4[midx(2, qq)][J], v);
+                        }
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                    for (int qq = 0; qq < 3; ++qq)
+#pragma unroll
+                        for (int ss = 0; ss < 3; ++ss) {
+                            R v = fh[bb][0] * Y[qq][0][ss] + fh[bb][1] * Y[qq][1][ss] + fh[bb][2] * Y[qq][2][ss];
+                            if (aa == bb) v += Sh[qq][ss];
+                            v -= R(1.0 / 3.0) * Yh[aa][qq] * fc[bb][ss];
+                            sA[slot][gp][9 * bb + 3 * qq + ss] = wK * v;
+                        }
+                __syncthreads();
+                R acc[3][8];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int J = 0; J < 8; ++J) acc[k][J] = R(0);
+#pragma unroll 2
+                for (int g = 0; g < 8; ++g) {
+                    R G[24], A[28], gi[3];
+#pragma unroll
+                    for (int t = 0; t < 24; ++t) G[t] = sG[slot][g][t];
+#pragma unroll
+                    for (int t = 0; t < 28; ++t) A[t] = sA[slot][g][t];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) gi[q] = sG[slot][g][3 * gp + q];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        R t3[3];
+#pragma unroll
+                        for (int ss = 0; ss < 3; ++ss)
+                            t3[ss] = m_fma(gi[2], A[9 * k + 6 + ss], m_fma(gi[1], A[9 * k + 3 + ss], gi[0] * A[9 * k + ss]));
+#pragma unroll
+                        for (int J = 0; J < 8; ++J) {
+                            R v = m_fma(t3[0], G[3 * J], acc[k][J]);
+                            v = m_fma(t3[1], G[3 * J + 1], v);
+                            acc[k][J] = m_fma(t3[2], G[3 * J + 2], v);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int J = 0; J < 8; ++J) acc[k][J] = m_fma(ub[aa], sQb[slot][3 * J + k], acc[k][J]);
+                if (valid) {
+                    RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * kKeStride;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        RO* row = Kd + ke_offset(gp, aa, k, 0);
+                        RO v4[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][j];
+                        store4<RO>(row, v4);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) v4[j] = (RO)acc[k][4 + j];
+                        store4<RO>(row + 4, v4);
+                    }
+                }
+                __syncthreads();
+            });
+            } else {
             // ---- element tangent blocks K^e(a,b), a <= b:
             //      K^e_{Ia,Jb} = sum_g w detJ0 g^_Iq A^(a,b)_qs g^_Js  (per Gauss point g)
             // Each lane hands its g^ and A^ over through LDS, then lane I
@@ -587,6 +750,7 @@ __global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
                     store4<RO>(row + 4, v4);
                 });
             }
+            }  // F-bar / symmetric tangent
         }
         if (valid && !finite_gp && !FIXUP) ++cnt_nan;
         __syncthreads();
@@ -890,8 +1054,6 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         return set_error(FEM_EINVAL, "fem_residual_tangent: per-specimen parameters need a batch");
     if (params->model & ~(uint32_t)(FEM_MODEL_VOCE | FEM_MODEL_FBAR))
         return set_error(FEM_EINVAL, "fem_residual_tangent: unknown model flags 0x%x", params->model);
-    if (params->model & FEM_MODEL_FBAR)
-        return set_error(FEM_EINVAL, "fem_residual_tangent: F-bar is not available in this build");
     if (batch && (batch->n_spec < 1 || !batch->elem_off))
         return set_error(FEM_EINVAL, "fem_residual_tangent: invalid batch");
     const size_t need = fem_forward_workspace_bytes(mesh->n_nodes, mesh->n_elems, prec);

@@ -3,7 +3,8 @@
 // hardening (Alg. 1 "Evaluate VJP", Eq. (main_grad)).
 //
 // R_Ia = sum_e sum_g w detJ0 P_aA dN_I/dX_A, P = F (P_L : T), and only the
-// logarithmic stress T depends on theta, through the converged local update.
+// logarithmic stress T depends on theta, through the converged local update
+// (F-bar: F is Fbar throughout, which does not depend on theta).
 // Per Gauss point:
 //   Lambda = sum_I lambda_I (x) grad N_I,  Tbar = P_L : sym(F^T Lambda),
 //   thetabar_k = w detJ0 Tbar : dT/dtheta_k.
@@ -103,9 +104,14 @@ struct GPv {
     R eh[3];
 };
 
-template <typename R>
+// FBAR: the material sees Fbar = beta F (fbar_gradient); s.H becomes Fbar - I.
+template <typename R, bool FBAR>
 __device__ inline void kin_log_v(const double (*nd)[9], int gp, GPv<R>& s, double eps[6]) {
     kinematics_lds<R, 9>(nd, gp, s.g, s.detJ, s.H);
+    if constexpr (FBAR) {
+        R beta, cw, jm1;
+        fbar_gradient<R>(s.detJ, s.H, beta, cw, jm1);
+    }
     R M[3][3];
     cauchy_green_minus_identity<R>(s.H, M);
     eig_sym3<R>(M, s.mu, s.Q);
@@ -173,7 +179,7 @@ void vjp_kernel(const VjpArgs a) {
 
         GPv<R> s;
         double eps[6];
-        kin_log_v<R>(sN[slot], gp, s, eps);
+        kin_log_v<R, (VAR & kVarFbarV) != 0>(sN[slot], gp, s, eps);
 #pragma unroll
         for (int I = 0; I < 8; ++I)
 #pragma unroll
@@ -450,8 +456,6 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         return set_error(FEM_EINVAL, "fem_residual_vjp: per-specimen parameters need a batch");
     if (params->model & ~(uint32_t)(FEM_MODEL_VOCE | FEM_MODEL_FBAR))
         return set_error(FEM_EINVAL, "fem_residual_vjp: unknown model flags 0x%x", params->model);
-    if (params->model & FEM_MODEL_FBAR)
-        return set_error(FEM_EINVAL, "fem_residual_vjp: F-bar is not available in this build");
     const int n_spec = batch ? batch->n_spec : 1;
     hipStream_t s = (hipStream_t)stream;
     const size_t need = fem_vjp_workspace_bytes(mesh->n_elems, n_spec);

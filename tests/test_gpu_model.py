@@ -38,13 +38,10 @@ MODELS = {
     "fbar": ("swift", True, None),
     "fbar_voce_orient": ("voce", True, "uniform"),
 }
-FBAR_READY = False
 
 
 def problem(name, per_element):
     hard, fbar, orient = MODELS[name]
-    if fbar and not FBAR_READY:
-        pytest.skip("F-bar element not built")
     base = synth.small_slab(61 if per_element else 62, 7, 4, 3, per_element=per_element)
     return synth.with_model(base, 8, hard, fbar, orient)
 
