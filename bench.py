@@ -251,6 +251,25 @@ def main():
         del out_d, kd
         torch.cuda.empty_cache()
 
+        # ---- model variants on the same cube: Voce hardening, one orientation
+        # per element (in-plane angles), the F-bar element, and all three
+        variants = {}
+        for vname, hard, fbar, orient in (("voce", "voce", False, None), ("orient_per_elem", "swift", False, "per_element"),
+                                          ("fbar", "swift", True, None),
+                                          ("fbar_voce_orient", "voce", True, "per_element")):
+            pm = synth.with_model(p, 11, hard, fbar, orient)
+            vparams = fem.Params(pm.prm, pm.n_elems, hardening=hard, fbar=fbar, orient=pm.orient)
+            ms_v, _, kt_v = time_passes(
+                lambda: fem.residual_tangent(mesh, csr, vparams, d, h, bc_mask=bc, prec=fem.FP32_MIXED, out=out_m),
+                max(args.steps // 2, 3), 2, torch, KS, fem)
+            variants[vname] = dict(ms_per_pass=ms_v, gp_updates_per_s=n_gp / (ms_v * 1e-3),
+                                   fwd_kernel_ms=kt_v[fem.KERNEL_FORWARD],
+                                   plastic_fraction=float((out_m.hist[6] != h[6]).double().mean().cpu()))
+            log(f"mixed {vname}: {ms_v:.3f} ms/pass, element kernel {kt_v[fem.KERNEL_FORWARD]:.3f} ms")
+            del vparams, pm
+        extras["mixed_model_variants"] = variants
+        torch.cuda.empty_cache()
+
         # ---- VJP on the voided specimen
         pv = synth.void_specimen()
         mv = fem.Mesh(pv.X, pv.conn)

@@ -168,8 +168,11 @@ __device__ inline void kin_and_log(const double (*nd)[6], int gp, GP<R>& s, doub
 // R: working type of kinematics, pull-back and contraction; RO: type of the
 // stored element tangent blocks; FIXUP: walk the element list of the guard
 // band instead of all elements (FP64 recomputation for the mixed path).
+// The FP32 model variants are held to two waves per SIMD (the plain kernel
+// fits there by itself).
 template <typename R, typename RO, int BLOCK, bool FIXUP, int VAR>
-__global__ __launch_bounds__(BLOCK) void fwd_kernel(const FwdArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value && !FIXUP && VAR != 0 ? 2 : 1)))
+void fwd_kernel(const FwdArgs a) {
     constexpr int EPB = BLOCK / 8;
     constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
     constexpr bool ORIENT = (VAR & kVarOrient) != 0;

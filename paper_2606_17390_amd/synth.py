@@ -112,7 +112,9 @@ def with_model(p, seed, hardening="swift", fbar=False, orient=None):
             ori = random_rotation(rng).ravel()
         elif orient == "per_element":
             ang = rng.uniform(0.0, np.pi, p.n_elems)
-            ori = np.stack([rotation_z(a).ravel() for a in ang])
+            c, s_ = np.cos(ang), np.sin(ang)
+            ori = np.zeros((p.n_elems, 9))
+            ori[:, 0], ori[:, 1], ori[:, 3], ori[:, 4], ori[:, 8] = c, -s_, s_, c, 1.0  # rotation_z(ang)
         else:
             raise ValueError(f"unknown orientation {orient!r}")
     elif orient is not None:

@@ -1,8 +1,8 @@
 """The linear solve and the global Newton iteration on the GPU (through the C
 ABI): the CSR product against scipy's, BiCGSTAB against a dense solve, and
 the 4x4x4 uniaxial tension run of 10 load steps against the one-dimensional
-Swift solution (ln(1.02) = sigma/E + alpha, sigma = K (eps0 + alpha)^n; the
-x = 1 face reaction equals sigma / 1.02)."""
+solution (ln(1.02) = sigma/E + alpha, sigma = sigma_y(alpha), Swift or Voce;
+the x = 1 face reaction equals sigma / 1.02)."""
 import sys
 
 import numpy as np
@@ -107,13 +107,19 @@ def test_solve_reports_no_convergence(fem):
     assert its == 2 and res > 1e-14
 
 
-@pytest.mark.parametrize("prec_name,tol,atol", [("FP64", 1e-10, 1e-9), ("FP32_MIXED", 1e-6, 1e-5)])
-def test_uniaxial_tension_newton_matches_one_dimensional_swift(fem, prec_name, tol, atol):
+@pytest.mark.parametrize("prec_name,tol,atol,variant", [("FP64", 1e-10, 1e-9, "plain"),
+                                                        ("FP32_MIXED", 1e-6, 1e-5, "plain"),
+                                                        ("FP64", 1e-10, 1e-9, "fbar_voce")])
+def test_uniaxial_tension_newton_matches_one_dimensional_solution(fem, prec_name, tol, atol, variant):
+    """The homogeneous field makes F-bar reduce to the plain element (its
+    tangent is still unsymmetric); Voce replaces Swift in the 1-D root."""
     from scipy.optimize import brentq
 
     from paper_2606_17390_amd import newton
     prec = getattr(fem, prec_name)
     p = synth.tiny_cube(step=0)
+    if variant == "fbar_voce":
+        p = synth.with_model(p, 12, "voce", True, None)
     mesh, params, _, _, bc, _ = gpu_problem(p, fem)
     csr = fem.csr_pattern(mesh)
     face = np.isclose(p.X[:, 0], 1.0)
@@ -126,10 +132,15 @@ def test_uniaxial_tension_newton_matches_one_dimensional_swift(fem, prec_name, t
         d[face_t, 0] = 0.002 * step
         hist, its, norms = newton.solve_step(mesh, csr, params, d, hist, bc, prec=prec, tol=tol, out=out,
                                              solver=solver)
-        say(f"newton {prec_name} step {step}: {its} iterations, ||R|| {norms[0]:.2e} -> {norms[-1]:.2e}")
-    Kc, e0, n, E = p.prm[8], p.prm[9], p.prm[10], p.prm[0]
-    abar = brentq(lambda a: Kc * (e0 + a) ** n / E + a - np.log(1.02), 0.0, 0.1, xtol=1e-16)
-    sig = Kc * (e0 + abar) ** n
+        say(f"newton {prec_name} {variant} step {step}: {its} iterations, ||R|| {norms[0]:.2e} -> {norms[-1]:.2e}")
+        assert its <= 15
+    E = p.prm[0]
+    if p.hardening == "voce":
+        sy = lambda a: p.prm[8] + p.prm[9] * (1.0 - np.exp(-p.prm[10] * a))  # noqa: E731
+    else:
+        sy = lambda a: p.prm[8] * (p.prm[9] + a) ** p.prm[10]  # noqa: E731
+    abar = brentq(lambda a: sy(a) / E + a - np.log(1.02), 0.0, 0.1, xtol=1e-16)
+    sig = sy(abar)
     alpha = hist[6].cpu().numpy()
     assert np.abs(alpha - abar).max() <= atol
     # reaction on the x = 1 face: residual without the constraints
