@@ -58,6 +58,9 @@ def _load():
     lib.oracle_trial_yield.argtypes = [i32, i32] + [P] * 3 + [ci, P] + [P] * 3 + [ci]
     lib.oracle_residual_vjp.argtypes = [i32, i32] + [P] * 3 + [ci, P] + [P] * 6 + [ci]
     lib.oracle_residual_vjp.restype = ctypes.c_int
+    lib.oracle_local_jacobian.argtypes = [P] * 3 + [ci, P, P]
+    lib.oracle_local_jacobian.restype = ctypes.c_int
+    lib.oracle_element_adjoint.argtypes = [P] * 4 + [ci] + [P] * 6
     _lib = lib
     del i64
     return lib
@@ -224,3 +227,30 @@ def residual_vjp(X, conn, prm, d, hist_n, lam, n_threads=0, model=0, orient=None
     _load().oracle_residual_vjp(nn, ne, _p(X), _p(conn), _p(prm), int(model), _p(ori), _p(d), _p(hist_n),
                                 _p(lam), _p(gu), _p(ge), _p(diag), int(n_threads))
     return gu, ge, diag
+
+
+def local_jacobian(F, hist_n, prm, model=0, Theta=None):
+    """dz/dp [13, 20] of the local update: z = (T Mandel 6, hist_{n+1} 7),
+    p = (eps Mandel 6, hist_n 7, theta 7)."""
+    F = _f64(F).reshape(3, 3)
+    h = _f64(hist_n).reshape(7)
+    p = _f64(prm).reshape(NPARAM)
+    th = _theta(Theta)
+    Jz = np.zeros((13, 20))
+    rc = _load().oracle_local_jacobian(_p(F), _p(h), _p(p), int(model), _p(th), _p(Jz))
+    return Jz, rc
+
+
+def element_adjoint(Xe, de, he, prm, lam=None, mu=None, model=0, Theta=None):
+    """(theta_bar [7], hbar [8, 7], ubar [24]) of one element for the cotangents
+    lam [8, 3] of R^e and mu [8, 7] of hist_{n+1} (either may be None)."""
+    Xe = _f64(Xe).reshape(8, 3)
+    de = _f64(de).reshape(8, 3)
+    he = _f64(he).reshape(8, 7)
+    p = _f64(prm).reshape(NPARAM)
+    lm = None if lam is None else _f64(lam).reshape(24)
+    mm = None if mu is None else _f64(mu).reshape(56)
+    tb, hb, ub = np.zeros(7), np.zeros((8, 7)), np.zeros(24)
+    _load().oracle_element_adjoint(_p(Xe), _p(de), _p(he), _p(p), int(model), _p(_theta(Theta)), _p(lm), _p(mm),
+                                   _p(tb), _p(hb), _p(ub))
+    return tb, hb, ub

@@ -1166,11 +1166,9 @@ void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const
 /* parameter VJP: forward-mode implicit differentiation (App. D)       */
 /* ------------------------------------------------------------------ */
 
-/* dG/dtheta_k at the converged local solution, k in (F, G, H, N, K, eps0, n)
- * or, with Voce hardening, (F, G, H, N, sig0, Q, b) */
-static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[8]) {
-    const double *t = y;
-    double alpha = y[6], dg = y[7];
+/* Derivatives of phi(T) and N(T) = H T / phi with respect to the Hill
+ * parameter k in (F, G, H, N) at fixed T (Mandel t). */
+static void hill_param_derivative(const cpp_ctx *c, const double t[6], int k, double dNv[6], double *dphi_out) {
     double phi = hill_phi(c->Hm, t);
     double N[6], dH[36] = {0};
     for (int i = 0; i < 6; ++i) {
@@ -1178,32 +1176,41 @@ static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[
         for (int j = 0; j < 6; ++j) s += c->Hm[6 * i + j] * t[j];
         N[i] = s / phi;
     }
+    if (k == 0) { /* F: H22 = F+H, H33 = F+G, H23 = -F */
+        dH[7] = dH[14] = 1.0;
+        dH[8] = dH[13] = -1.0;
+    } else if (k == 1) { /* G: H11 = G+H, H33 = F+G, H13 = -G */
+        dH[0] = dH[14] = 1.0;
+        dH[2] = dH[12] = -1.0;
+    } else if (k == 2) { /* H: H11, H22, H12 = -H */
+        dH[0] = dH[7] = 1.0;
+        dH[1] = dH[6] = -1.0;
+    } else { /* N: shear 12 */
+        dH[35] = 1.0;
+    }
+    rotate_hill(c->Theta, dH); /* the rotation of App. A is linear in H */
+    double dHt[6], tdHt = 0.0;
+    for (int i = 0; i < 6; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 6; ++j) s += dH[6 * i + j] * t[j];
+        dHt[i] = s;
+        tdHt += t[i] * s;
+    }
+    double dphi = tdHt / (2.0 * phi);
+    for (int i = 0; i < 6; ++i) dNv[i] = dHt[i] / phi - N[i] * dphi / phi;
+    *dphi_out = dphi;
+}
+
+/* dG/dtheta_k at the converged local solution, k in (F, G, H, N, K, eps0, n)
+ * or, with Voce hardening, (F, G, H, N, sig0, Q, b) */
+static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[8]) {
+    const double *t = y;
+    double alpha = y[6], dg = y[7];
     memset(dG, 0, 8 * sizeof(double));
     if (k <= 3) {
         /* derivative of the Hill matrix with respect to F, G, H or N */
-        if (k == 0) { /* F: H22 = F+H, H33 = F+G, H23 = -F */
-            dH[7] = dH[14] = 1.0;
-            dH[8] = dH[13] = -1.0;
-        } else if (k == 1) { /* G: H11 = G+H, H33 = F+G, H13 = -G */
-            dH[0] = dH[14] = 1.0;
-            dH[2] = dH[12] = -1.0;
-        } else if (k == 2) { /* H: H11, H22, H12 = -H */
-            dH[0] = dH[7] = 1.0;
-            dH[1] = dH[6] = -1.0;
-        } else { /* N: shear 12 */
-            dH[35] = 1.0;
-        }
-        rotate_hill(c->Theta, dH); /* the rotation of App. A is linear in H */
-        double dHt[6], tdHt = 0.0;
-        for (int i = 0; i < 6; ++i) {
-            double s = 0.0;
-            for (int j = 0; j < 6; ++j) s += dH[6 * i + j] * t[j];
-            dHt[i] = s;
-            tdHt += t[i] * s;
-        }
-        double dphi = tdHt / (2.0 * phi);
-        double dNv[6];
-        for (int i = 0; i < 6; ++i) dNv[i] = dHt[i] / phi - N[i] * dphi / phi;
+        double dNv[6], dphi;
+        hill_param_derivative(c, t, k, dNv, &dphi);
         for (int i = 0; i < 6; ++i) {
             double s = 0.0;
             for (int j = 0; j < 6; ++j) s += c->Em[6 * i + j] * dNv[j];
@@ -1235,6 +1242,159 @@ static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[
             dsy = sy * log(base);
         dG[7] = -dsy;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Jacobian of the local update and the element adjoint (App. D)        */
+/* ------------------------------------------------------------------ */
+
+/* dz/dp of the local update at a material point, forward mode of App. D:
+ * one solve J_y ydot = -dG/dp pdot per input direction, then the output
+ * formulas.  Inputs p (20): eps (Mandel 6), hist_n (7 stored components:
+ * eps^p 11,22,33,23,13,12 and alpha), theta (7).  Outputs z (13): T (Mandel
+ * 6), hist_{n+1} (7 stored components).  Jz is row-major [13][20]. */
+static void mp_local_jacobian(const mp_state *s, const double hist_n[7], double Jz[260]) {
+    (void)hist_n;
+    static const double W[6] = {1.0, 1.0, 1.0, SQRT2, SQRT2, SQRT2}; /* stored -> Mandel */
+    const cpp_ctx *c = &s->ctx;
+    memset(Jz, 0, 260 * sizeof(double));
+    if (!s->plastic) {
+        /* T = E : (eps - eps^p_n), history unchanged */
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                Jz[20 * i + j] = c->Em[6 * i + j];
+                Jz[20 * i + 6 + j] = -c->Em[6 * i + j] * W[j];
+            }
+        for (int r = 0; r < 7; ++r) Jz[20 * (6 + r) + 6 + r] = 1.0;
+        return;
+    }
+    const double *y = s->y;
+    double dg = y[7];
+    double phi = hill_phi(c->Hm, y);
+    double N[6], dNdT[36];
+    for (int i = 0; i < 6; ++i) {
+        double a = 0.0;
+        for (int j = 0; j < 6; ++j) a += c->Hm[6 * i + j] * y[j];
+        N[i] = a / phi;
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) dNdT[6 * i + j] = (c->Hm[6 * i + j] - N[i] * N[j]) / phi;
+    double J[64];
+    cpp_jacobian(c, y, J);
+    for (int k = 0; k < 20; ++k) {
+        double Gd[8] = {0}, ep_dot[6] = {0}, dNth[6] = {0};
+        if (k < 6) {
+            for (int i = 0; i < 6; ++i) Gd[i] = -c->Em[6 * i + k];
+        } else if (k < 12) {
+            int j = k - 6;
+            for (int i = 0; i < 6; ++i) Gd[i] = c->Em[6 * i + j] * W[j];
+            ep_dot[j] = W[j];
+        } else if (k == 12) {
+            Gd[6] = -1.0;
+        } else {
+            cpp_dG_dparam(c, y, k - 13, Gd);
+            if (k - 13 <= 3) {
+                double dphi;
+                hill_param_derivative(c, y, k - 13, dNth, &dphi);
+            }
+        }
+        double Wm[64], yd[8];
+        memcpy(Wm, J, sizeof Wm);
+        for (int i = 0; i < 8; ++i) yd[i] = -Gd[i];
+        solve_dense(8, Wm, yd);
+        for (int i = 0; i < 6; ++i) Jz[20 * i + k] = yd[i];
+        /* eps^p_{n+1} = eps^p_n + dgamma N(T; theta) */
+        for (int i = 0; i < 6; ++i) {
+            double v = ep_dot[i] + yd[7] * N[i] + dg * dNth[i];
+            for (int j = 0; j < 6; ++j) v += dg * dNdT[6 * i + j] * yd[j];
+            Jz[20 * (6 + i) + k] = v / W[i];
+        }
+        Jz[20 * 12 + k] = yd[6];
+    }
+}
+
+int oracle_local_jacobian(const double F[9], const double hist_n[7], const double prm[11], int model,
+                          const double *Theta, double Jz[260]) {
+    mp_state s;
+    mp_update(F, hist_n, prm, model, Theta, &s);
+    mp_local_jacobian(&s, hist_n, Jz);
+    return s.converged ? 0 : 1;
+}
+
+/* P_L : X for a symmetric X, in the eigenframe of C: (P_L : X)^_ab = 2 f1(c_a, c_b) X^_ab */
+static void apply_PL(const mp_state *s, const double X[9], double Y[9]) {
+    double Xh[9], Yh[9];
+    rot_to_frame(s->Q, X, Xh);
+    for (int i = 0; i < 9; ++i) Yh[i] = 2.0 * s->f1[i] * Xh[i];
+    rot_from_frame(s->Q, Yh, Y);
+}
+
+void oracle_element_adjoint(const double X[24], const double d[24], const double hist[56],
+                            const double prm[11], int model, const double *Theta, const double *lam,
+                            const double *mu, double theta_bar[7], double hbar[56], double ubar[24]) {
+    double gradN[8][24], detJ0[8], F[8][9], Fm[8][9];
+    double *dFm = malloc(sizeof(double) * 8 * 216);
+    element_kinematics(X, d, (model & ORACLE_MODEL_FBAR) != 0, gradN, detJ0, F, Fm, dFm);
+    for (int k = 0; k < 7; ++k) theta_bar[k] = 0.0;
+    for (int i = 0; i < 24; ++i) ubar[i] = 0.0;
+    for (int g = 0; g < 8; ++g) {
+        mp_state s;
+        mp_update(Fm[g], hist + 7 * g, prm, model, Theta, &s);
+        double Jz[260];
+        mp_local_jacobian(&s, hist + 7 * g, Jz);
+        /* output cotangent: Tbar from lambda^T R = sum_g w detJ0 Lambda : P(Fm) with
+         * P = Fm (P_L : T):  Tbar = w detJ0 P_L : sym(Fm^T Lambda); mu for the history */
+        double zb[13] = {0};
+        if (lam) {
+            double Lg[9], FtL[9], Xs[9], Tb[9];
+            for (int a = 0; a < 3; ++a)
+                for (int A = 0; A < 3; ++A) {
+                    double l = 0.0;
+                    for (int I = 0; I < 8; ++I) l += lam[3 * I + a] * gradN[g][3 * I + A];
+                    Lg[3 * a + A] = l;
+                }
+            for (int A = 0; A < 3; ++A)
+                for (int B = 0; B < 3; ++B) {
+                    double v = 0.0;
+                    for (int a = 0; a < 3; ++a) v += Fm[g][3 * a + A] * Lg[3 * a + B];
+                    FtL[3 * A + B] = v;
+                }
+            for (int A = 0; A < 3; ++A)
+                for (int B = 0; B < 3; ++B) Xs[3 * A + B] = 0.5 * (FtL[3 * A + B] + FtL[3 * B + A]);
+            apply_PL(&s, Xs, Tb);
+            sym_to_mandel(Tb, zb);
+            for (int i = 0; i < 6; ++i) zb[i] *= detJ0[g];
+        }
+        if (mu)
+            for (int r = 0; r < 7; ++r) zb[6 + r] = mu[7 * g + r];
+        /* input cotangent p_bar = Jz^T z_bar */
+        double pb[20] = {0}, eb_mu[6] = {0};
+        for (int k = 0; k < 20; ++k) {
+            double v = 0.0;
+            for (int r = 0; r < 13; ++r) v += Jz[20 * r + k] * zb[r];
+            pb[k] = v;
+        }
+        for (int k = 0; k < 6; ++k) {
+            double v = 0.0;
+            for (int r = 6; r < 13; ++r) v += Jz[20 * r + k] * zb[r];
+            eb_mu[k] = v;
+        }
+        for (int k = 0; k < 7; ++k) theta_bar[k] += pb[13 + k];
+        for (int r = 0; r < 7; ++r) hbar[7 * g + r] = pb[6 + r];
+        /* u_bar from the history cotangent only: eps_bar -> Fm_bar = Fm (P_L : eps_bar)
+         * -> u_bar = dFm/dd^T Fm_bar (the F-bar chain is in dFm) */
+        double Xe[9], Ye[9], Fb[9];
+        mandel_to_sym(eb_mu, Xe);
+        apply_PL(&s, Xe, Ye);
+        matmul3(Fm[g], Ye, Fb);
+        const double *D = dFm + 216 * g;
+        for (int col = 0; col < 24; ++col) {
+            double v = 0.0;
+            for (int i = 0; i < 9; ++i) v += Fb[i] * D[24 * i + col];
+            ubar[col] += v;
+        }
+    }
+    free(dFm);
 }
 
 int oracle_residual_vjp(int32_t n_nodes, int32_t n_elems, const double *X, const int32_t *conn,

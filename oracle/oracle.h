@@ -102,6 +102,22 @@ int oracle_residual_vjp(int32_t n_nodes, int32_t n_elems, const double *X, const
                         const double *lam, double *g_uniform, double *g_elem, int32_t *diag,
                         int n_threads);
 
+/* Jacobian of the local update at a material point (App. D, forward mode):
+ * Jz[13][20] = dz/dp, z = (T Mandel 6, hist_{n+1} stored 7), p = (eps Mandel
+ * 6, hist_n stored 7, theta 7).  Returns 0, or 1 if the local Newton did not
+ * converge. */
+int oracle_local_jacobian(const double F[9], const double hist_n[7], const double prm[11], int model,
+                          const double *Theta, double Jz[260]);
+
+/* Element adjoint of one load step for cotangents lam[24] (of R^e, node-major,
+ * may be NULL) and mu[8][7] (of hist_{n+1}, GP-major, may be NULL):
+ *   theta_bar[7] = lam^T dR^e/dtheta + mu^T dH/dtheta,
+ *   hbar[8][7]   = lam^T dR^e/dh_n + mu^T dH/dh_n   (cotangent of hist_n),
+ *   ubar[24]     = mu^T dH/dd^e                      (the lam part, K^T lam, is not included). */
+void oracle_element_adjoint(const double X[24], const double d[24], const double hist[56],
+                            const double prm[11], int model, const double *Theta, const double *lam,
+                            const double *mu, double theta_bar[7], double hbar[56], double ubar[24]);
+
 #ifdef __cplusplus
 }
 #endif
