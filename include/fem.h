@@ -274,6 +274,43 @@ int fem_solve(const fem_csr *csr, const void *K_vals, fem_precision prec, const 
               void *stream);
 
 /*
+ * fem_csr_transpose -- KT_vals = values of K^T on the same pattern (the
+ * pattern of fem_csr_pattern is structurally symmetric), the matrix of the
+ * adjoint solve of Alg. 1 / Eq. (dR_u).  If bc_mask (device [n_rows], may be
+ * NULL) marks a dof, row i of KT becomes an identity row, so that solving
+ * KT lambda = v with v_i = 0 there gives lambda_i = 0 and the free-free block
+ * of K^T for the rest (for a K whose constrained rows are identity rows).
+ * K_vals / KT_vals: device [nnz], double (FEM_FP64) or float
+ * (FEM_FP32_MIXED), must not alias.  Asynchronous on `stream`.
+ */
+int fem_csr_transpose(const fem_csr *csr, const void *K_vals, fem_precision prec, const uint8_t *bc_mask,
+                      void *KT_vals, void *stream);
+
+/*
+ * fem_history_adjoint -- one load step of the time-history adjoint (Sec. 2.3,
+ * Eqs. (Lagrangian)-(dR_u), Alg. 1) of the time-discrete problem whose
+ * history h^n is produced by the local update H^n(u^n, h^{n-1}, theta) of
+ * the converged step.  For the state (d = u^n, hist_n = h^{n-1}) of step n
+ * and the cotangents lam (of R^n, device [n_nodes][3], or NULL = 0) and mu
+ * (of h^n, device [7][8 n_elems] in the hist layout, or NULL = 0):
+ *   g_elem [7][n_elems], g_uniform [7]: lam^T dR^n/dtheta + mu^T dH^n/dtheta
+ *   hbar [7][8 n_elems]: lam^T dR^n/dh^{n-1} + mu^T dH^n/dh^{n-1} (the mu of
+ *                        step n-1)
+ *   ubar [n_nodes][3]:   mu^T dH^n/du^n (the lam part is K^T lam; apply it
+ *                        with fem_csr_transpose and the assembled tangent)
+ * Any output may be NULL (ubar needs csr's node incidence).  FP64 only;
+ * model options and orientation as in fem_residual_tangent; no per-specimen
+ * parameters.  diag[4] as in fem_residual_vjp (zeroed by the call) or NULL.
+ * ws: device workspace of fem_history_adjoint_workspace_bytes bytes.
+ * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP.
+ */
+size_t fem_history_adjoint_workspace_bytes(int32_t n_nodes, int32_t n_elems);
+int fem_history_adjoint(const fem_mesh *mesh, const fem_csr *csr, const fem_params *params, const double *d,
+                        const double *hist_n, const double *lam, const double *mu, double *g_uniform,
+                        double *g_elem, double *hbar, double *ubar, int32_t *diag, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/*
  * Kernel timing for benchmarks: while enabled, every launch of kernel
  * `kernel` (FEM_KERNEL_FORWARD / FEM_KERNEL_VJP: the main element kernel, not
  * the FP64 guard-band re-run; FEM_KERNEL_ASSEMBLE_K / _R: the tangent and

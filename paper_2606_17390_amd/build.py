@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfem.so")
-SOURCES = ["api.hip", "pattern.hip", "forward.hip", "vjp.hip", "solver.hip"]
+SOURCES = ["api.hip", "pattern.hip", "forward.hip", "vjp.hip", "solver.hip", "adjoint.hip"]
 ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -51,7 +51,7 @@ def compile_one(src, extra, verbose):
 
 def build(verbose=False, extra=()):
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         results = list(ex.map(lambda s: compile_one(s, list(extra), verbose), SOURCES))
     objs = [o for o, _ in results]
     for _, err in results:

@@ -70,4 +70,14 @@ bool timing_on();
 void* timing_begin(hipStream_t s);
 void timing_end(void* token, int kernel, hipStream_t s);
 
+// out[3I + c] = sum of the element vectors Re[e][3i + c] over the incident
+// entries 8e + i of node I (the residual assembly without constraints or norm)
+hipError_t gather_node_vectors(int32_t n_nodes, const int32_t* ne_ptr, const int32_t* ne_list, const double* Re,
+                               double* out, hipStream_t s);
+
+// g_uniform[s][k] = sum over the elements of specimen s of g_elem[k][e]
+// (fixed order; off = NULL for one specimen)
+hipError_t reduce_g_uniform(const double* g_elem, int64_t n_elems, const int64_t* off, int n_spec,
+                            double* g_uniform, hipStream_t s);
+
 }  // namespace fem

@@ -1018,6 +1018,16 @@ struct CountAdapterF {
 };
 
 }  // namespace
+
+hipError_t gather_node_vectors(int32_t n_nodes, const int32_t* ne_ptr, const int32_t* ne_list, const double* Re,
+                               double* out, hipStream_t s) {
+    if (n_nodes <= 0) return hipSuccess;
+    const int64_t nb = residual_blocks(n_nodes), n_chunk = nb / 8;
+    hipLaunchKernelGGL(assemble_residual, dim3((unsigned)nb), dim3(kResThreads), 0, s, n_nodes, n_chunk, ne_ptr,
+                       ne_list, Re, (const uint8_t*)nullptr, out, (double*)nullptr);
+    return hipGetLastError();
+}
+
 }  // namespace fem
 
 using namespace fem;

@@ -55,6 +55,39 @@ __global__ __launch_bounds__(256) void spmv_kernel(int32_t n_nodes, const int32_
     if (node < n_nodes && l < 3) y[3 * node + l] = (l == 0 ? s0 : (l == 1 ? s1 : s2));
 }
 
+// KT = K^T on the same (structurally symmetric) pattern: one wave per node I,
+// lane r < deg(I) copies the 3x3 block (J, I)^T of the r-th neighbour J, whose
+// slot in J's sorted column list comes from a binary search; rows of
+// constrained dofs become identity rows.
+template <typename RV>
+__global__ __launch_bounds__(256) void transpose_kernel(int32_t n_nodes, const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col_idx,
+                                                        const RV* __restrict__ K, const uint8_t* __restrict__ bc,
+                                                        RV* __restrict__ KT) {
+    const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int32_t r = (int32_t)(threadIdx.x & 63);
+    if (I >= n_nodes) return;
+    const int32_t bI = row_ptr[3 * I], degI = (row_ptr[3 * I + 1] - bI) / 3;
+    if (r >= degI) return;
+    const int32_t J = col_idx[bI + 3 * r] / 3;
+    const int32_t bJ = row_ptr[3 * J], degJ = (row_ptr[3 * J + 1] - bJ) / 3;
+    int32_t a0 = 0, a1 = degJ - 1;
+    while (a0 < a1) {
+        const int32_t mid = (a0 + a1) >> 1;
+        if (col_idx[bJ + 3 * mid] < 3 * I) a0 = mid + 1;
+        else a1 = mid;
+    }
+    // a0 = slot of I in J's list (present: the pattern is symmetric)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            RV v = K[(int64_t)bJ + (int64_t)b * 3 * degJ + 3 * a0 + a];
+            if (bc && bc[3 * I + a]) v = (J == I && a == b) ? RV(1) : RV(0);
+            KT[(int64_t)bI + (int64_t)a * 3 * degI + 3 * r + b] = v;
+        }
+}
+
 // dinv[i] = 1 / K_ii (1 where the diagonal entry is absent or zero)
 template <typename RV>
 __global__ void diag_inv_kernel(int32_t n_rows, const int32_t* __restrict__ row_ptr,
@@ -239,6 +272,28 @@ extern "C" int fem_csr_spmv(const fem_csr* csr, const void* K_vals, fem_precisio
     if (prec != FEM_FP64 && prec != FEM_FP32_MIXED) return set_error(FEM_EINVAL, "fem_csr_spmv: bad precision");
     if (csr->n_rows > 0 && (!x || !y)) return set_error(FEM_EINVAL, "fem_csr_spmv: x and y must not be NULL");
     FEM_HIP_CHECK(spmv(csr, K_vals, prec, x, y, (hipStream_t)stream));
+    return FEM_OK;
+}
+
+extern "C" int fem_csr_transpose(const fem_csr* csr, const void* K_vals, fem_precision prec, const uint8_t* bc_mask,
+                                 void* KT_vals, void* stream) {
+    clear_error();
+    if (int rc = check_csr(csr, K_vals, "fem_csr_transpose")) return rc;
+    if (prec != FEM_FP64 && prec != FEM_FP32_MIXED) return set_error(FEM_EINVAL, "fem_csr_transpose: bad precision");
+    if (csr->n_rows > 0 && !KT_vals) return set_error(FEM_EINVAL, "fem_csr_transpose: KT_vals must not be NULL");
+    if (KT_vals == K_vals && csr->n_rows > 0)
+        return set_error(FEM_EINVAL, "fem_csr_transpose: KT_vals must not alias K_vals");
+    const int32_t nn = csr->n_rows / 3;
+    if (nn == 0) return FEM_OK;
+    const unsigned nb = (unsigned)(((int64_t)nn * 64 + 255) / 256);
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == FEM_FP64)
+        hipLaunchKernelGGL(transpose_kernel<double>, dim3(nb), dim3(256), 0, s, nn, csr->row_ptr, csr->col_idx,
+                           static_cast<const double*>(K_vals), bc_mask, static_cast<double*>(KT_vals));
+    else
+        hipLaunchKernelGGL(transpose_kernel<float>, dim3(nb), dim3(256), 0, s, nn, csr->row_ptr, csr->col_idx,
+                           static_cast<const float*>(K_vals), bc_mask, static_cast<float*>(KT_vals));
+    FEM_HIP_CHECK(hipGetLastError());
     return FEM_OK;
 }
 

@@ -424,6 +424,14 @@ hipError_t launch_vjp(const VjpArgs& a, int block, int grid, hipStream_t s) {
 hipError_t launch_vjp_fixup(const VjpArgs& a, hipStream_t s) { return launch_vjp_variant<double, true>(a, 64, 1024, s); }
 
 }  // namespace
+
+hipError_t reduce_g_uniform(const double* g_elem, int64_t n_elems, const int64_t* off, int n_spec,
+                            double* g_uniform, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_uniform, dim3(n_spec * FEM_NGRAD), dim3(kRedThreads), 0, s, g_elem, n_elems, off,
+                       g_uniform);
+    return hipGetLastError();
+}
+
 }  // namespace fem
 
 using namespace fem;

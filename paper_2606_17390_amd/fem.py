@@ -56,7 +56,8 @@ _lib = None
 EXPORTS = ("fem_version", "fem_last_error", "fem_set_launch", "fem_get_launch", "fem_csr_workspace_bytes",
            "fem_forward_workspace_bytes", "fem_vjp_workspace_bytes", "fem_csr_pattern", "fem_residual_tangent",
            "fem_residual_vjp", "fem_timing_enable", "fem_timing_read", "fem_graph_begin", "fem_graph_end",
-           "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes", "fem_csr_spmv", "fem_solve")
+           "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes", "fem_csr_spmv", "fem_solve",
+           "fem_csr_transpose", "fem_history_adjoint_workspace_bytes", "fem_history_adjoint")
 
 
 def lib():
@@ -94,6 +95,11 @@ def lib():
     L.fem_csr_spmv.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
     L.fem_solve.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_i32, ctypes.c_double,
                             ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double), _c_p, _c_sz, _c_p]
+    L.fem_csr_transpose.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
+    L.fem_history_adjoint_workspace_bytes.argtypes = [_c_i32, _c_i32]
+    L.fem_history_adjoint_workspace_bytes.restype = _c_sz
+    L.fem_history_adjoint.argtypes = [ctypes.POINTER(FemMesh), ctypes.POINTER(FemCsr), ctypes.POINTER(FemParams)] + \
+        [_c_p] * 9 + [_c_p, _c_sz, _c_p]
     _lib = L
     return L
 
@@ -369,6 +375,51 @@ def residual_vjp(mesh, params, d, hist_n, lam, prec=FP64, out=None, batch=None, 
                             _ptr(d), _ptr(hist_n), _ptr(lam), _prec(prec), _ptr(out.g_uniform), _ptr(ge),
                             _ptr(out.diag), _ptr(out.ws), out.ws_bytes, _stream(stream))
     _check("fem_residual_vjp", rc)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# time-history adjoint
+# ---------------------------------------------------------------------------
+
+def csr_transpose(csr, K, bc_mask=None, out=None, stream=None):
+    """K^T on the same pattern (float64 or float32 like K); rows of dofs marked in
+    bc_mask become identity rows (the matrix of the adjoint solve)."""
+    if out is None:
+        out = torch.empty_like(K)
+    _check("fem_csr_transpose", lib().fem_csr_transpose(ctypes.byref(csr.c()), _ptr(K), _kprec(K), _ptr(bc_mask),
+                                                        _ptr(out), _stream(stream)))
+    return out
+
+
+class HistoryAdjoint:
+    """Outputs and workspace of fem_history_adjoint for a mesh."""
+
+    def __init__(self, mesh):
+        dev = mesh.device
+        ne, nn = mesh.n_elems, mesh.n_nodes
+        self.g_uniform = torch.zeros(NGRAD, dtype=torch.float64, device=dev)
+        self.g_elem = torch.zeros((NGRAD, ne), dtype=torch.float64, device=dev)
+        self.hbar = torch.zeros((7, 8 * ne), dtype=torch.float64, device=dev)
+        self.ubar = torch.zeros((nn, 3), dtype=torch.float64, device=dev)
+        self.diag = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.ws_bytes = lib().fem_history_adjoint_workspace_bytes(nn, ne)
+        self.ws = _ws(self.ws_bytes, dev)
+
+
+def history_adjoint(mesh, csr, params, d, hist_n, lam=None, mu=None, out=None, want_hbar=True, want_ubar=True,
+                    stream=None):
+    """One load step of the time-history adjoint: g = lam^T dR/dtheta + mu^T dH/dtheta,
+    hbar = lam^T dR/dh_n + mu^T dH/dh_n and ubar = mu^T dH/dd (FP64)."""
+    if out is None:
+        out = HistoryAdjoint(mesh)
+    rc = lib().fem_history_adjoint(ctypes.byref(mesh.c()), ctypes.byref(csr.c()), ctypes.byref(params.c()), _ptr(d),
+                                   _ptr(hist_n), _ptr(lam), _ptr(mu), _ptr(out.g_uniform),
+                                   _ptr(out.g_elem) if mesh.n_elems else None,
+                                   _ptr(out.hbar) if want_hbar and mesh.n_elems else None,
+                                   _ptr(out.ubar) if want_ubar and mesh.n_nodes else None, _ptr(out.diag),
+                                   _ptr(out.ws), out.ws_bytes, _stream(stream))
+    _check("fem_history_adjoint", rc)
     return out
 
 
