@@ -270,6 +270,37 @@ def main():
         extras["mixed_model_variants"] = variants
         torch.cuda.empty_cache()
 
+        # ---- one step of the time-history adjoint on the same cube (FP64):
+        # the local-adjoint kernel for (lambda, mu), and K^T for the adjoint solve
+        gen = torch.Generator(device="cuda").manual_seed(5)
+        lam_c = torch.randn((p.n_nodes, 3), dtype=torch.float64, device="cuda", generator=gen)
+        mu_c = torch.randn((7, n_gp), dtype=torch.float64, device="cuda", generator=gen)
+        adj = fem.HistoryAdjoint(mesh)
+
+        def timed(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        ms_adj = timed(lambda: fem.history_adjoint(mesh, csr, params, d, h, lam=lam_c, mu=mu_c, out=adj))
+        ms_adj_mu = timed(lambda: fem.history_adjoint(mesh, csr, params, d, h, lam=None, mu=mu_c, out=adj,
+                                                      want_hbar=False))
+        KT = torch.empty_like(out_m.K)
+        ms_tr = timed(lambda: fem.csr_transpose(csr, out_m.K, bc_mask=bc, out=KT))
+        extras["history_adjoint_step"] = dict(
+            ms_lambda_mu=ms_adj, gp_per_s=n_gp / (ms_adj * 1e-3), ms_mu_ubar=ms_adj_mu, ms_transpose_f32=ms_tr,
+            transpose_GBps=(2 * csr.nnz * 4 + csr.nnz // 3 * 4) / (ms_tr * 1e6))
+        log(f"history adjoint step: {ms_adj:.3f} ms (lambda, mu -> g, hbar), {ms_adj_mu:.3f} ms (mu -> ubar), "
+            f"K^T {ms_tr:.3f} ms")
+        del lam_c, mu_c, adj, KT
+        torch.cuda.empty_cache()
+
         # ---- VJP on the voided specimen
         pv = synth.void_specimen()
         mv = fem.Mesh(pv.X, pv.conn)
