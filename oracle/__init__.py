@@ -22,6 +22,7 @@ NGRAD = 7
 # model option flags (oracle.h)
 MODEL_VOCE = 1
 MODEL_FBAR = 2
+MODEL_BARLAT = 4
 
 
 def build(force=True):
@@ -61,6 +62,9 @@ def _load():
     lib.oracle_local_jacobian.argtypes = [P] * 3 + [ci, P, P]
     lib.oracle_local_jacobian.restype = ctypes.c_int
     lib.oracle_element_adjoint.argtypes = [P] * 4 + [ci] + [P] * 6
+    lib.oracle_set_barlat.argtypes = [P]
+    lib.oracle_effective_stress.argtypes = [P, P, ci, P, P]
+    lib.oracle_effective_stress.restype = ctypes.c_double
     _lib = lib
     del i64
     return lib
@@ -254,3 +258,19 @@ def element_adjoint(Xe, de, he, prm, lam=None, mu=None, model=0, Theta=None):
     _load().oracle_element_adjoint(_p(Xe), _p(de), _p(he), _p(p), int(model), _p(_theta(Theta)), _p(lm), _p(mm),
                                    _p(tb), _p(hb), _p(ub))
     return tb, hb, ub
+
+
+def set_barlat(coef):
+    """Barlat Yld2004-18p coefficients (c'12 c'13 c'21 c'23 c'31 c'32 c'44 c'55
+    c'66, c''..., m) used by every call with MODEL_BARLAT."""
+    c = _f64(coef).reshape(19)
+    _load().oracle_set_barlat(_p(c))
+
+
+def effective_stress(T, prm, model=0, Theta=None):
+    """(phi, N [3, 3]) of the model's yield function at the stress T [3, 3]."""
+    T = _f64(T).reshape(3, 3)
+    p = _f64(prm).reshape(NPARAM)
+    N = np.zeros((3, 3))
+    phi = _load().oracle_effective_stress(_p(T), _p(p), int(model), _p(_theta(Theta)), _p(N))
+    return phi, N

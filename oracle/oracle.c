@@ -24,6 +24,8 @@
  *
  *   Eq. (Hard): Voce hardening (model option); App. A: orientation of the
  *       Hill tensor; Sec. 2.2.4: F-bar deformation gradient (model option)
+ *   Eq. (Phi_barlat), App. A: Barlat Yld2004-18p yield function (model
+ *       option), phi from the principal values of two transformed deviators
  *
  * Readings where the paper is silent or inconsistent (listed in the design
  * notes): Swift hardening sigma_y = K (eps0+alpha)^n by default, Voce as
@@ -368,6 +370,179 @@ static void rotate_hill(const double *Theta, double Hm[36]) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Barlat Yld2004-18p, Eq. (Phi_barlat) and App. A                      */
+/* ------------------------------------------------------------------ */
+
+/* coefficients c'12 c'13 c'21 c'23 c'31 c'32 c'44 c'55 c'66, the same for
+ * c'', and the exponent m (set by oracle_set_barlat; read-only during calls) */
+static double g_barlat[19];
+
+void oracle_set_barlat(const double coef[19]) { memcpy(g_barlat, coef, sizeof g_barlat); }
+
+/* L = C : P (Mandel; C and P are block diagonal, so their Voigt and Mandel
+ * matrices coincide): s' = L' t, s'' = L'' t for the Mandel stress t. */
+static void barlat_transform(const double *c9, double L[36]) {
+    double C[36] = {0}, P[36] = {0};
+    C[1] = -c9[0];
+    C[2] = -c9[1];
+    C[6] = -c9[2];
+    C[8] = -c9[3];
+    C[12] = -c9[4];
+    C[13] = -c9[5];
+    C[21] = c9[6];
+    C[28] = c9[7];
+    C[35] = c9[8];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) P[6 * i + j] = (i == j ? 2.0 : -1.0) / 3.0;
+    for (int i = 3; i < 6; ++i) P[6 * i + i] = 1.0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < 6; ++k) v += C[6 * i + k] * P[6 * k + j];
+            L[6 * i + j] = v;
+        }
+}
+
+/* phi and, optionally, its gradient g[6] and Hessian h[36] with respect to the
+ * principal values lam = (s'_1..3, s''_1..3):
+ *   Phi = 1/4 sum_ij |s'_i - s''_j|^m,  phi = Phi^(1/m) */
+static double barlat_principal(const double lam[6], double m, double *g, double *h) {
+    double Phi = 0.0, dPhi[6] = {0}, d2Phi[36] = {0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double d = lam[i] - lam[3 + j], ad = fabs(d);
+            Phi += 0.25 * pow(ad, m);
+            double t1 = 0.25 * m * d * pow(ad, m - 2.0);       /* d/dlam'_i of |d|^m / 4 */
+            double t2 = 0.25 * m * (m - 1.0) * pow(ad, m - 2.0); /* second derivative */
+            dPhi[i] += t1;
+            dPhi[3 + j] -= t1;
+            d2Phi[6 * i + i] += t2;
+            d2Phi[6 * (3 + j) + 3 + j] += t2;
+            d2Phi[6 * i + 3 + j] -= t2;
+            d2Phi[6 * (3 + j) + i] -= t2;
+        }
+    double phi = pow(Phi, 1.0 / m);
+    if (g)
+        for (int a = 0; a < 6; ++a) g[a] = phi / (m * Phi) * dPhi[a];
+    if (h)
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b)
+                h[6 * a + b] = phi / (m * Phi) * (d2Phi[6 * a + b] + (1.0 / m - 1.0) * dPhi[a] * dPhi[b] / Phi);
+    return phi;
+}
+
+/* Gradient (tensor) of a spectral function with principal derivatives g over
+ * the eigen-basis Q (columns): sum_i g_i q_i (x) q_i, as a Mandel vector. */
+static void spectral_gradient(const double Q[9], const double g[3], double out[6]) {
+    double M[9] = {0}, D[9] = {0};
+    for (int i = 0; i < 3; ++i) D[4 * i] = g[i];
+    rot_from_frame(Q, D, M);
+    sym_to_mandel(M, out);
+}
+
+/* Mandel 6x6 of the derivative of sum_i g_i q_i (x) q_i (the eigenvalues of
+ * the first argument A, basis QA) with respect to the second argument B
+ * (basis QB, eigenvalues lb), where g depends on the principal values:
+ *   d/dB = sum_ik dg_i/dlb_k (q_k . dB q_k) P_i  [+ for A = B: sum_{i!=k}
+ *   theta_ik P_i dB P_k, theta_ik = (g_i - g_k)/(l_i - l_k), or dg_i/dl_i -
+ *   dg_i/dl_k where the two values coincide] */
+static void spectral_block(const double QA[9], const double QB[9], const double la[3], const double ga[3],
+                           const double hab[9], int same, double out[36]) {
+    for (int K = 0; K < 6; ++K) {
+        double e[6] = {0}, dB[9], dBh[9], R[9] = {0}, Rh[9] = {0}, v[6];
+        e[K] = 1.0;
+        mandel_to_sym(e, dB);
+        rot_to_frame(QB, dB, dBh); /* dBh_kk = q_k . dB q_k */
+        for (int i = 0; i < 3; ++i) {
+            double x = 0.0;
+            for (int k = 0; k < 3; ++k) x += hab[3 * i + k] * dBh[4 * k];
+            Rh[4 * i] = x;
+        }
+        if (same) {
+            double scale = fabs(la[0]) + fabs(la[1]) + fabs(la[2]) + 1e-300;
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    if (i == k) continue;
+                    double th;
+                    if (fabs(la[i] - la[k]) > 1e-9 * scale) th = (ga[i] - ga[k]) / (la[i] - la[k]);
+                    else th = hab[3 * i + i] - hab[3 * i + k];
+                    Rh[3 * i + k] += th * dBh[3 * i + k];
+                }
+        }
+        memcpy(R, Rh, sizeof R);
+        double Rg[9];
+        rot_from_frame(QA, R, Rg);
+        sym_to_mandel(Rg, v);
+        for (int I = 0; I < 6; ++I) out[6 * I + K] = v[I];
+    }
+}
+
+/* Barlat phi(t), N = dphi/dt and dN/dt (Mandel), with L1 = L', L2 = L'' */
+static double barlat_eval(const double L1[36], const double L2[36], double m, const double t[6], double *N,
+                          double *dNdT) {
+    double s1[6], s2[6], S1[9], S2[9], Q1[9], Q2[9], lam[6];
+    for (int i = 0; i < 6; ++i) {
+        double a = 0.0, b = 0.0;
+        for (int j = 0; j < 6; ++j) {
+            a += L1[6 * i + j] * t[j];
+            b += L2[6 * i + j] * t[j];
+        }
+        s1[i] = a;
+        s2[i] = b;
+    }
+    mandel_to_sym(s1, S1);
+    mandel_to_sym(s2, S2);
+    oracle_eig_sym3(S1, lam, Q1);
+    oracle_eig_sym3(S2, lam + 3, Q2);
+    double g[6], h[36];
+    double phi = barlat_principal(lam, m, g, h);
+    if (N) {
+        double n1[6], n2[6];
+        spectral_gradient(Q1, g, n1);
+        spectral_gradient(Q2, g + 3, n2);
+        for (int i = 0; i < 6; ++i) {
+            double v = 0.0;
+            for (int j = 0; j < 6; ++j) v += L1[6 * j + i] * n1[j] + L2[6 * j + i] * n2[j];
+            N[i] = v;
+        }
+    }
+    if (dNdT) {
+        double H11[36], H12[36], H21[36], H22[36], hb[9];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) hb[3 * i + k] = h[6 * i + k];
+        spectral_block(Q1, Q1, lam, g, hb, 1, H11);
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) hb[3 * i + k] = h[6 * i + 3 + k];
+        spectral_block(Q1, Q2, lam, g, hb, 0, H12);
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) hb[3 * i + k] = h[6 * (3 + i) + k];
+        spectral_block(Q2, Q1, lam + 3, g + 3, hb, 0, H21);
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) hb[3 * i + k] = h[6 * (3 + i) + 3 + k];
+        spectral_block(Q2, Q2, lam + 3, g + 3, hb, 1, H22);
+        /* dN/dt = L1^T (H11 L1 + H12 L2) + L2^T (H21 L1 + H22 L2) */
+        double A1[36], A2[36];
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                double a = 0.0, b = 0.0;
+                for (int k = 0; k < 6; ++k) {
+                    a += H11[6 * i + k] * L1[6 * k + j] + H12[6 * i + k] * L2[6 * k + j];
+                    b += H21[6 * i + k] * L1[6 * k + j] + H22[6 * i + k] * L2[6 * k + j];
+                }
+                A1[6 * i + j] = a;
+                A2[6 * i + j] = b;
+            }
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                double v = 0.0;
+                for (int k = 0; k < 6; ++k) v += L1[6 * k + i] * A1[6 * k + j] + L2[6 * k + i] * A2[6 * k + j];
+                dNdT[6 * i + j] = v;
+            }
+    }
+    return phi;
+}
+
+/* ------------------------------------------------------------------ */
 /* closest-point projection, Eq. (local_cpp): y = [T(6), alpha, dgamma] */
 /* ------------------------------------------------------------------ */
 
@@ -378,18 +553,33 @@ typedef struct {
     const double *prm;
     int voce;
     const double *Theta; /* orientation, or NULL */
+    int barlat;          /* Barlat Yld2004-18p instead of Hill-48 */
+    double L1[36], L2[36], mexp;
 } cpp_ctx;
+
+/* Effective stress phi(t), flow direction N = dphi/dt and dN/dt (the last two
+ * may be NULL) of the context's yield function. */
+static double yield_eval(const cpp_ctx *c, const double t[6], double *N, double *dNdT) {
+    if (c->barlat) return barlat_eval(c->L1, c->L2, c->mexp, t, N, dNdT);
+    double phi = hill_phi(c->Hm, t);
+    double Nl[6];
+    for (int i = 0; i < 6; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 6; ++j) s += c->Hm[6 * i + j] * t[j];
+        Nl[i] = s / phi;
+    }
+    if (N) memcpy(N, Nl, sizeof Nl);
+    if (dNdT)
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) dNdT[6 * i + j] = (c->Hm[6 * i + j] - Nl[i] * Nl[j]) / phi;
+    return phi;
+}
 
 static void cpp_residual(const cpp_ctx *c, const double y[8], double G[8]) {
     const double *t = y;
     double alpha = y[6], dg = y[7];
-    double phi = hill_phi(c->Hm, t);
     double N[6];
-    for (int i = 0; i < 6; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < 6; ++j) s += c->Hm[6 * i + j] * t[j];
-        N[i] = s / phi;
-    }
+    double phi = yield_eval(c, t, N, NULL);
     for (int i = 0; i < 6; ++i) {
         double s = 0.0;
         for (int j = 0; j < 6; ++j) s += c->Em[6 * i + j] * (c->ee_tr[j] - dg * N[j]);
@@ -401,17 +591,9 @@ static void cpp_residual(const cpp_ctx *c, const double y[8], double G[8]) {
 
 /* analytic J^G = dG/dy */
 static void cpp_jacobian(const cpp_ctx *c, const double y[8], double J[64]) {
-    const double *t = y;
     double alpha = y[6], dg = y[7];
-    double phi = hill_phi(c->Hm, t);
     double N[6], dN[36];
-    for (int i = 0; i < 6; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < 6; ++j) s += c->Hm[6 * i + j] * t[j];
-        N[i] = s / phi;
-    }
-    for (int i = 0; i < 6; ++i)
-        for (int j = 0; j < 6; ++j) dN[6 * i + j] = (c->Hm[6 * i + j] - N[i] * N[j]) / phi;
+    yield_eval(c, y, N, dN);
     memset(J, 0, 64 * sizeof(double));
     for (int i = 0; i < 6; ++i) {
         for (int j = 0; j < 6; ++j) {
@@ -545,6 +727,14 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
     c->prm = prm;
     c->voce = (model & ORACLE_MODEL_VOCE) != 0;
     c->Theta = Theta;
+    c->barlat = (model & ORACLE_MODEL_BARLAT) != 0;
+    if (c->barlat) {
+        barlat_transform(g_barlat, c->L1);
+        barlat_transform(g_barlat + 9, c->L2);
+        rotate_hill(Theta, c->L1); /* the same rotation of a fourth-order tensor */
+        rotate_hill(Theta, c->L2);
+        c->mexp = g_barlat[18];
+    }
     c->alpha_n = hist_n[6];
     for (int i = 0; i < 6; ++i) c->ee_tr[i] = eps_m[i] - epsp_n[i];
 
@@ -556,7 +746,7 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
         ttr[i] = acc;
     }
     s->sy_n = hardening(prm, c->voce, c->alpha_n, NULL);
-    s->ftr = hill_phi(c->Hm, ttr) - s->sy_n;
+    s->ftr = yield_eval(c, ttr, NULL, NULL) - s->sy_n;
 
     double epsp_np1[6];
     double alpha_np1;
@@ -585,13 +775,8 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
         s->dgamma = y[7];
         alpha_np1 = y[6];
         /* recovery step of Alg. C2 */
-        double phi = hill_phi(c->Hm, y);
-        double N[6];
-        for (int i = 0; i < 6; ++i) {
-            double acc = 0.0;
-            for (int j = 0; j < 6; ++j) acc += c->Hm[6 * i + j] * y[j];
-            N[i] = acc / phi;
-        }
+        double N[6], dNdT[36];
+        yield_eval(c, y, N, dNdT);
         for (int i = 0; i < 6; ++i) epsp_np1[i] = epsp_n[i] + s->dgamma * N[i];
         for (int i = 0; i < 6; ++i) {
             double acc = 0.0;
@@ -604,7 +789,7 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
         invert_dense(6, c->Em, Einv);
         for (int i = 0; i < 6; ++i)
             for (int j = 0; j < 6; ++j)
-                Am[6 * i + j] = Einv[6 * i + j] + s->dgamma * (c->Hm[6 * i + j] - N[i] * N[j]) / phi;
+                Am[6 * i + j] = Einv[6 * i + j] + s->dgamma * dNdT[6 * i + j];
         invert_dense(6, Am, Xi);
         double v[6], nxn = 0.0, dsig;
         hardening(prm, c->voce, alpha_np1, &dsig);
@@ -745,6 +930,18 @@ int oracle_material_point(const double F[9], const double hist_n[7], const doubl
         info[5] = s.sy_n;
     }
     return s.converged ? 0 : 1;
+}
+
+double oracle_effective_stress(const double T[9], const double prm[11], int model, const double *Theta,
+                               double N[9]) {
+    mp_state ref;
+    double F0[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, h0[7] = {0, 0, 0, 0, 0, 0, 0};
+    mp_update(F0, h0, prm, model, Theta, &ref); /* sets up the yield function */
+    double t[6], Nm[6];
+    sym_to_mandel(T, t);
+    double phi = yield_eval(&ref.ctx, t, Nm, NULL);
+    if (N) mandel_to_sym(Nm, N);
+    return phi;
 }
 
 void oracle_log_strain(const double F[9], double eps[9]) {
@@ -1133,10 +1330,12 @@ void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const
         double Xe[24], de[24], he[56];
         gather_element(e, X, conn, d, hist_n, n_gp, Xe, de, he);
         const double *p = prm + 11 * e;
-        double Em[36], Hm[36];
+        double Em[36];
         elastic_mandel(p, Em);
-        hill_mandel(p, Hm);
-        rotate_hill(orient ? orient + 9 * e : NULL, Hm);
+        /* the yield function of the material point update, at alpha_n */
+        mp_state ref;
+        double F0[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, h0[7] = {0, 0, 0, 0, 0, 0, 0};
+        mp_update(F0, h0, p, model, orient ? orient + 9 * e : NULL, &ref);
         double gradN[8][24], detJ0[8], F[8][9], Fm[8][9];
         element_kinematics(Xe, de, (model & ORACLE_MODEL_FBAR) != 0, gradN, detJ0, F, Fm, NULL);
         for (int g = 0; g < 8; ++g) {
@@ -1156,7 +1355,7 @@ void oracle_trial_yield(int32_t n_nodes, int32_t n_elems, const double *X, const
                 for (int j = 0; j < 6; ++j) s += Em[6 * i + j] * (em[j] - pm[j]);
                 t[i] = s;
             }
-            double ftr = hill_phi(Hm, t) - hardening(p, (model & ORACLE_MODEL_VOCE) != 0, h[6], NULL);
+            double ftr = yield_eval(&ref.ctx, t, NULL, NULL) - hardening(p, (model & ORACLE_MODEL_VOCE) != 0, h[6], NULL);
             flag[8 * e + g] = ftr > 0.0;
         }
     }
@@ -1207,6 +1406,7 @@ static void cpp_dG_dparam(const cpp_ctx *c, const double y[8], int k, double dG[
     const double *t = y;
     double alpha = y[6], dg = y[7];
     memset(dG, 0, 8 * sizeof(double));
+    if (k <= 3 && c->barlat) return; /* the Hill parameters do not enter Barlat's function */
     if (k <= 3) {
         /* derivative of the Hill matrix with respect to F, G, H or N */
         double dNv[6], dphi;
@@ -1270,15 +1470,8 @@ static void mp_local_jacobian(const mp_state *s, const double hist_n[7], double 
     }
     const double *y = s->y;
     double dg = y[7];
-    double phi = hill_phi(c->Hm, y);
     double N[6], dNdT[36];
-    for (int i = 0; i < 6; ++i) {
-        double a = 0.0;
-        for (int j = 0; j < 6; ++j) a += c->Hm[6 * i + j] * y[j];
-        N[i] = a / phi;
-    }
-    for (int i = 0; i < 6; ++i)
-        for (int j = 0; j < 6; ++j) dNdT[6 * i + j] = (c->Hm[6 * i + j] - N[i] * N[j]) / phi;
+    yield_eval(c, y, N, dNdT);
     double J[64];
     cpp_jacobian(c, y, J);
     for (int k = 0; k < 20; ++k) {

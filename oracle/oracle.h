@@ -42,9 +42,23 @@ extern "C" {
  * plastic strain history is kept in global components. */
 #define ORACLE_MODEL_VOCE 1
 #define ORACLE_MODEL_FBAR 2
+/*   ORACLE_MODEL_BARLAT  Barlat Yld2004-18p yield function (Eq. Phi_barlat,
+ *                      App. A) instead of Hill-48, with the coefficients of
+ *                      oracle_set_barlat; the Hill slots are ignored and their
+ *                      gradient entries are zero. */
+#define ORACLE_MODEL_BARLAT 4
+
+/* Barlat coefficients c'12 c'13 c'21 c'23 c'31 c'32 c'44 c'55 c'66, the same
+ * nine for c'', and the exponent m (process-wide; set before the calls). */
+void oracle_set_barlat(const double coef[19]);
 
 /* Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations. */
 void oracle_eig_sym3(const double A[9], double w[3], double Q[9]);
+
+/* Effective stress phi(T) of the model's yield function (Hill-48 or Barlat,
+ * with the orientation) and its gradient N = dphi/dT (tensor, may be NULL). */
+double oracle_effective_stress(const double T[9], const double prm[11], int model, const double *Theta,
+                               double N[9]);
 
 /* Logarithmic strain eps = 1/2 ln(F^T F). */
 void oracle_log_strain(const double F[9], double eps[9]);

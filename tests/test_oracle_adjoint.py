@@ -134,13 +134,18 @@ def test_time_history_adjoint_matches_fd(variant):
     grad, _ = adjoint.adjoint_gradient(X, conn, prm, bc, ds, hs, u_gt, w, model=model, orient=orient)
 
     def J(pr):
-        d2, _ = adjoint.simulate(X, conn, pr, bc, steps, hist0, model=model, orient=orient)
+        d2, _ = adjoint.simulate(X, conn, pr, bc, steps, hist0, model=model, orient=orient, tol=1e-13)
         return adjoint.objective(d2, u_gt, w)
 
+    # fourth-order central differences with step 1e-3 |theta_k| (truncation
+    # O(h^4)); small steps are limited by the Newton tolerance of the forward
+    # runs (~1e-13 relative in J) in the smallest components
+    def shifted(col, x):
+        q = prm.copy()
+        q[col] += x
+        return J(q)
+
     for k, col in enumerate(synth.GRAD_PARAM_INDEX):
-        st = 1e-5 * abs(prm[col])
-        a, b = prm.copy(), prm.copy()
-        a[col] += st
-        b[col] -= st
-        fd = (J(a) - J(b)) / (2 * st)
+        st = 1e-3 * abs(prm[col])
+        fd = (-shifted(col, 2 * st) + 8 * shifted(col, st) - 8 * shifted(col, -st) + shifted(col, -2 * st)) / (12 * st)
         assert abs(grad[k] - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(grad).max()), (variant, k, grad[k], fd)
