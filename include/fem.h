@@ -89,7 +89,16 @@ enum { FEM_G_SIG0 = FEM_G_K, FEM_G_Q = FEM_G_EPS0, FEM_G_B = FEM_G_NEXP };
  *                   Fbar = (Jbar / J)^(1/3) F at each Gauss point, with
  *                   Jbar = (1/V_e) int J dV over the element; R^e_I =
  *                   int P(Fbar) . grad N_I dV and K^e = dR^e/dd^e (not symmetric). */
-enum { FEM_MODEL_VOCE = 1u, FEM_MODEL_FBAR = 2u };
+enum { FEM_MODEL_VOCE = 1u, FEM_MODEL_FBAR = 2u, FEM_MODEL_BARLAT = 4u };
+/*   FEM_MODEL_BARLAT Barlat Yld2004-18p yield function (Eq. Phi_barlat, App. A)
+ *                   instead of Hill-48: phi = [1/4 sum_ij |s'_i - s''_j|^m]^(1/m)
+ *                   over the principal values of C':P:T and C'':P:T, with the
+ *                   coefficients of fem_params.barlat (the Hill slots are
+ *                   ignored); closest-point Newton iteration with the line
+ *                   search of App. B; FP64 local update and tangent in both
+ *                   precision forms (FP32_MIXED stores K in FP32).  Forward
+ *                   call only (fem_residual_vjp and fem_history_adjoint
+ *                   reject it). */
 
 typedef struct {
     int32_t n_nodes, n_elems;
@@ -114,6 +123,8 @@ typedef struct {
     uint32_t model;
     uint32_t orient_per_elem;
     const double *orient;
+    const double *barlat; /* device [19]: c'12 c'13 c'21 c'23 c'31 c'32 c'44 c'55 c'66,
+                             the same nine for c'', m; required with FEM_MODEL_BARLAT */
 } fem_params;
 
 /* CSR matrix of the tangent, 3x3 node blocks: row 3I+a holds columns 3J+b

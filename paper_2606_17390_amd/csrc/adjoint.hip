@@ -433,6 +433,8 @@ extern "C" int fem_history_adjoint(const fem_mesh* mesh, const fem_csr* csr, con
     for (int k = 0; k < FEM_NPARAM; ++k)
         if (!params->p[k]) return set_error(FEM_EINVAL, "fem_history_adjoint: parameter %d is NULL", k);
     if (params->per_spec_mask) return set_error(FEM_EINVAL, "fem_history_adjoint: per-specimen parameters unsupported");
+    if (params->model & FEM_MODEL_BARLAT)
+        return set_error(FEM_EINVAL, "fem_history_adjoint: the Barlat yield function is available in the forward call only");
     if (params->model & ~(uint32_t)(FEM_MODEL_VOCE | FEM_MODEL_FBAR))
         return set_error(FEM_EINVAL, "fem_history_adjoint: unknown model flags 0x%x", params->model);
     if (ubar && mesh->n_nodes > 0 && (!csr || !csr->node_elem_ptr || !csr->node_elem))

@@ -27,6 +27,7 @@
 
 #include <type_traits>
 
+#include "barlat.h"
 #include "fem_device.h"
 #include "fem_internal.h"
 
@@ -42,6 +43,7 @@ struct FwdArgs {
     uint32_t model;          // FEM_MODEL_* flags
     const double* orient;    // material orientation(s), or null
     int32_t orient_pe;       // orient holds one rotation per element
+    const double* barlat;    // Yld2004-18p coefficients (Barlat variant)
     int32_t n_spec;
     const int64_t* elem_off;
     const double* d;
@@ -102,6 +104,7 @@ __device__ inline Mat load_material(const A& a, int64_t e) {
 constexpr int kVarOrient = 1;
 constexpr int kVarFbar = 2;
 constexpr int kVarVoce = 4;
+constexpr int kVarBarlat = 8;  // FP64 kernel only (R = double)
 
 // The element tangent is stored per element as its 9 component blocks
 // K^e_{Ia,Jb}, (a, b) row-major, each an 8x8 node block, row-major: offset
@@ -177,6 +180,8 @@ void fwd_kernel(const FwdArgs a) {
     constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
     constexpr bool ORIENT = (VAR & kVarOrient) != 0;
     constexpr bool FBAR = (VAR & kVarFbar) != 0;
+    constexpr bool BARLAT = (VAR & kVarBarlat) != 0;
+    static_assert(!BARLAT || std::is_same<R, double>::value, "the Barlat variant runs in FP64");
     // LDS: node coordinates and displacements of the tile; the frame
     // gradients g^ of every Gauss point; and one buffer used in turn for H
     // and Q (F-bar: and beta, cw) across the local update, the residual
@@ -192,6 +197,7 @@ void fwd_kernel(const FwdArgs a) {
     __shared__ __attribute__((aligned(16))) R sbuf[kBuf];
     __shared__ int sFlag[EPB];
     __shared__ R sQb[FBAR ? EPB : 1][24];                      // F-bar: qbar of the element
+    __shared__ double sCep[BARLAT ? EPB : 1][8][BARLAT ? 21 : 1];  // Barlat: Cep (upper triangle, material frame)
     R (*sHQ)[8][kHQ] = reinterpret_cast<R (*)[8][kHQ]>(sbuf);   // [slot][g][H 9, Q 9 (, beta, cw)]
     R (*red)[BLOCK + 1] = reinterpret_cast<R (*)[BLOCK + 1]>(sbuf);
     R (*sA)[8][28] = reinterpret_cast<R (*)[8][28]>(sbuf);      // [slot][g][9 k + 3 q + s]
@@ -277,7 +283,27 @@ void fwd_kernel(const FwdArgs a) {
         Modes md;
         hill_modes(mat, md);
         Local loc;
-        local_update(eps, hn, mat, md, loc);
+        if constexpr (BARLAT) {
+            BarlatCoef bco;
+            load_barlat(a.barlat, bco);
+            LocalB lb;
+            local_update_barlat(eps, hn, mat, md, bco, lb);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) loc.T[k] = lb.T[k];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) loc.hist[k] = lb.hist[k];
+            loc.plastic = lb.plastic;
+            loc.converged = lb.converged;
+            loc.ftr = lb.ftr;
+            loc.sy_n = lb.sy_n;
+            int c = 0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                for (int j = i; j < 6; ++j) sCep[slot][gp][c++] = lb.Cep[i][j];
+        } else {
+            local_update(eps, hn, mat, md, loc);
+        }
         if constexpr (ORIENT) {
             double Th[3][3];
             load_rotation(a.orient, oidx, Th);
@@ -396,7 +422,52 @@ void fwd_kernel(const FwdArgs a) {
                 for (int I = 0; I < 6; ++I)
 #pragma unroll
                     for (int J = 0; J < 6; ++J) Ch[I][J] = ((I < 3 && J < 3) ? lamL : R(0)) + ((I == J) ? mu2 : R(0));
-                if (loc.plastic) {
+                if constexpr (BARLAT) {
+                    // dense Cep (material frame) to the eigenframe of C: Ch = M Cep M^T,
+                    // column k of M the eigenframe image of Mandel basis tensor k
+                    R Qm[3][3];
+                    if constexpr (ORIENT) material_frame<R>(a.orient, oidx, s.Q, Qm);
+                    const R(*Qb)[3] = ORIENT ? Qm : s.Q;
+                    R Mb[6][6];
+                    const R u0[3] = {R(1), R(0), R(0)}, u1[3] = {R(0), R(1), R(0)}, u2[3] = {R(0), R(0), R(1)};
+                    rot_diag<R>(Qb, u0, Mb[0]);
+                    rot_diag<R>(Qb, u1, Mb[1]);
+                    rot_diag<R>(Qb, u2, Mb[2]);
+                    rot_shear<R, 1, 2>(Qb, Mb[3]);
+                    rot_shear<R, 0, 2>(Qb, Mb[4]);
+                    rot_shear<R, 0, 1>(Qb, Mb[5]);
+                    R Cp[6][6];
+                    {
+                        int c = 0;
+#pragma unroll
+                        for (int i = 0; i < 6; ++i)
+#pragma unroll
+                            for (int j = i; j < 6; ++j) {
+                                const R v = (R)sCep[slot][gp][c++];
+                                Cp[i][j] = v;
+                                Cp[j][i] = v;
+                            }
+                    }
+                    R W[6][6];  // Cep M^T
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+#pragma unroll
+                        for (int J = 0; J < 6; ++J) {
+                            R x = R(0);
+#pragma unroll
+                            for (int l = 0; l < 6; ++l) x += Cp[k][l] * Mb[l][J];
+                            W[k][J] = x;
+                        }
+#pragma unroll
+                    for (int I = 0; I < 6; ++I)
+#pragma unroll
+                        for (int J = 0; J < 6; ++J) {
+                            R x = R(0);
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) x += Mb[k][I] * W[k][J];
+                            Ch[I][J] = x;
+                        }
+                } else if (loc.plastic) {
                     // Hill eigen-basis (material frame) in the eigenframe of C
                     R Qm[3][3];
                     if constexpr (ORIENT) material_frame<R>(a.orient, oidx, s.Q, Qm);
@@ -947,12 +1018,31 @@ hipError_t launch_fwd(const FwdArgs& a, int grid, hipStream_t s) {
 // element variant of a call
 inline int variant_of(const FwdArgs& a) {
     return (a.orient ? kVarOrient : 0) | ((a.model & FEM_MODEL_FBAR) ? kVarFbar : 0) |
-           ((a.model & FEM_MODEL_VOCE) ? kVarVoce : 0);
+           ((a.model & FEM_MODEL_VOCE) ? kVarVoce : 0) | ((a.model & FEM_MODEL_BARLAT) ? kVarBarlat : 0);
 }
 
 // Variant 0 in every tuned workgroup size; the model variants with 64 threads.
+// Barlat variants: FP64 element kernel, K stored in the call's type RO
+template <typename RO>
+hipError_t launch_fwd_barlat(const FwdArgs& a, int grid, hipStream_t s) {
+    switch (variant_of(a) & ~kVarBarlat) {
+        case 0: return launch_fwd<double, RO, 64, false, 8>(a, grid, s);
+        case 1: return launch_fwd<double, RO, 64, false, 9>(a, grid, s);
+        case 2: return launch_fwd<double, RO, 64, false, 10>(a, grid, s);
+        case 3: return launch_fwd<double, RO, 64, false, 11>(a, grid, s);
+        case 4: return launch_fwd<double, RO, 64, false, 12>(a, grid, s);
+        case 5: return launch_fwd<double, RO, 64, false, 13>(a, grid, s);
+        case 6: return launch_fwd<double, RO, 64, false, 14>(a, grid, s);
+        default: return launch_fwd<double, RO, 64, false, 15>(a, grid, s);
+    }
+}
+
 template <typename R, typename RO, bool FIXUP>
 hipError_t launch_fwd_variant(const FwdArgs& a, int block, int grid, hipStream_t s) {
+    if (variant_of(a) & kVarBarlat) {
+        if constexpr (FIXUP) return hipSuccess;  // no guard band: the Barlat kernel is FP64
+        else return launch_fwd_barlat<RO>(a, grid, s);
+    }
     switch (variant_of(a)) {
         case 0:
             if (FIXUP || block == 64) return launch_fwd<R, RO, 64, FIXUP, 0>(a, grid, s);
@@ -1065,8 +1155,10 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         if (!params->p[k]) return set_error(FEM_EINVAL, "fem_residual_tangent: parameter %d is NULL", k);
     if (params->per_spec_mask && (!batch || batch->n_spec < 1 || !batch->elem_off))
         return set_error(FEM_EINVAL, "fem_residual_tangent: per-specimen parameters need a batch");
-    if (params->model & ~(uint32_t)(FEM_MODEL_VOCE | FEM_MODEL_FBAR))
+    if (params->model & ~(uint32_t)(FEM_MODEL_VOCE | FEM_MODEL_FBAR | FEM_MODEL_BARLAT))
         return set_error(FEM_EINVAL, "fem_residual_tangent: unknown model flags 0x%x", params->model);
+    if ((params->model & FEM_MODEL_BARLAT) && !params->barlat)
+        return set_error(FEM_EINVAL, "fem_residual_tangent: FEM_MODEL_BARLAT needs the coefficients");
     if (batch && (batch->n_spec < 1 || !batch->elem_off))
         return set_error(FEM_EINVAL, "fem_residual_tangent: invalid batch");
     const size_t need = fem_forward_workspace_bytes(mesh->n_nodes, mesh->n_elems, prec);
@@ -1094,6 +1186,7 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         a.model = params->model;
         a.orient = params->orient;
         a.orient_pe = params->orient_per_elem ? 1 : 0;
+        a.barlat = params->barlat;
         a.n_spec = batch ? batch->n_spec : 1;
         a.elem_off = batch ? batch->elem_off : nullptr;
         a.d = d;

@@ -462,6 +462,8 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         return set_error(FEM_EINVAL, "fem_residual_vjp: invalid batch");
     if (params->per_spec_mask && !batch)
         return set_error(FEM_EINVAL, "fem_residual_vjp: per-specimen parameters need a batch");
+    if (params->model & FEM_MODEL_BARLAT)
+        return set_error(FEM_EINVAL, "fem_residual_vjp: the Barlat yield function is available in the forward call only");
     if (params->model & ~(uint32_t)(FEM_MODEL_VOCE | FEM_MODEL_FBAR))
         return set_error(FEM_EINVAL, "fem_residual_vjp: unknown model flags 0x%x", params->model);
     const int n_spec = batch ? batch->n_spec : 1;

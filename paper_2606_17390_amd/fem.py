@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfem.so")
 FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOMEM, FEM_EOVERFLOW, FEM_EMESH, FEM_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_MIXED = 0, 1
 NPARAM, NGRAD = 11, 7
-MODEL_VOCE, MODEL_FBAR = 1, 2  # fem_params.model flags
+MODEL_VOCE, MODEL_FBAR, MODEL_BARLAT = 1, 2, 4  # fem_params.model flags
 KERNEL_FORWARD, KERNEL_VJP, KERNEL_ASSEMBLE_K, KERNEL_ASSEMBLE_R = 0, 1, 2, 3
 
 _c_i32, _c_i64, _c_u32, _c_p, _c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
@@ -29,7 +29,7 @@ class FemMesh(ctypes.Structure):
 
 class FemParams(ctypes.Structure):
     _fields_ = [("p", _c_p * NPARAM), ("per_elem_mask", _c_u32), ("per_spec_mask", _c_u32), ("model", _c_u32),
-                ("orient_per_elem", _c_u32), ("orient", _c_p)]
+                ("orient_per_elem", _c_u32), ("orient", _c_p), ("barlat", _c_p)]
 
 
 class FemCsr(ctypes.Structure):
@@ -192,12 +192,22 @@ class Params:
     or per specimen ([n_spec, 11], batched mode); the model options: hardening
     "swift" or "voce" (slots 8-10 then hold sig0, Q, b), fbar (F-bar element),
     orient (None, one rotation [3, 3] / [9], or per element [n_elems, 3, 3] /
-    [n_elems, 9]; columns = orthotropy axes)."""
+    [n_elems, 9]; columns = orthotropy axes), barlat (19 Yld2004-18p values:
+    c'12 c'13 c'21 c'23 c'31 c'32 c'44 c'55 c'66, the same for c'', m; replaces
+    the Hill-48 function)."""
 
-    def __init__(self, prm, n_elems, device="cuda", per_spec=False, hardening="swift", fbar=False, orient=None):
+    def __init__(self, prm, n_elems, device="cuda", per_spec=False, hardening="swift", fbar=False, orient=None,
+                 barlat=None):
         if hardening not in ("swift", "voce"):
             raise ValueError(f"unknown hardening law {hardening!r}")
         self.model = (MODEL_VOCE if hardening == "voce" else 0) | (MODEL_FBAR if fbar else 0)
+        self.barlat = None
+        if barlat is not None:
+            b = torch.as_tensor(np.asarray(barlat, dtype=np.float64)).reshape(-1)
+            if b.numel() != 19:
+                raise ValueError("barlat needs 19 values (18 coefficients and m)")
+            self.barlat = b.to(device).contiguous()
+            self.model |= MODEL_BARLAT
         self.orient = None
         self.orient_per_elem = 0
         if orient is not None:
@@ -242,6 +252,7 @@ class Params:
         p.model = self.model
         p.orient_per_elem = self.orient_per_elem
         p.orient = _ptr(self.orient) if self.orient is not None else None
+        p.barlat = _ptr(self.barlat) if self.barlat is not None else None
         return p
 
 

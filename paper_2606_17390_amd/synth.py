@@ -52,6 +52,7 @@ class Problem:
     hardening: str = "swift"              # "swift" or "voce" (slots 8-10: K, eps0, n or sig0, Q, b)
     fbar: bool = False                    # F-bar element formulation
     orient: Optional[np.ndarray] = None   # None, [9] or [n_elems, 9] rotations (row-major)
+    barlat: Optional[np.ndarray] = None   # Yld2004-18p coefficients [19] (replaces Hill-48), or None
 
     @property
     def n_nodes(self):
@@ -91,9 +92,18 @@ def rotation_z(angle):
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
 
 
-def with_model(p, seed, hardening="swift", fbar=False, orient=None):
-    """Problem p with another hardening law, the F-bar element and/or an
-    orientation: "voce" replaces slots 8-10 of the parameters by Voce values
+# Yld2004-18p coefficients c'12 c'13 c'21 c'23 c'31 c'32 c'44 c'55 c'66, the
+# same for c'', and m: the AA6111-T4 set of the paper's Barlat verification
+# table (tests/golden/barlat_yld2004_aa6111.json holds the same values)
+BARLAT_AA6111 = np.array([-0.069888, 0.936408, 0.079143, 1.003060, 0.524741, 1.363180, 1.023770, 1.069060, 0.954322,
+                          0.981171, 0.476741, 0.575316, 0.866827, 1.145010, -0.079294, 1.051660, 1.147100, 1.404620,
+                          8.0])
+
+
+def with_model(p, seed, hardening="swift", fbar=False, orient=None, barlat=None):
+    """Problem p with another hardening law, the F-bar element, an orientation
+    and/or the Barlat yield function (barlat: 19 coefficients, e.g.
+    BARLAT_AA6111): "voce" replaces slots 8-10 of the parameters by Voce values
     (per element draws if p is per element); orient is None, "uniform" (one
     random rotation) or "per_element" (one random in-plane angle per element)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -121,6 +131,7 @@ def with_model(p, seed, hardening="swift", fbar=False, orient=None):
         ori = np.asarray(orient, dtype=np.float64)
     import dataclasses
     return dataclasses.replace(p, prm=prm, hardening=hardening, fbar=fbar, orient=ori,
+                               barlat=None if barlat is None else np.asarray(barlat, dtype=np.float64),
                                name=f"{p.name}_{hardening}{'_fbar' if fbar else ''}{'_' + orient if isinstance(orient, str) else ''}")
 
 

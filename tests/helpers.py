@@ -28,8 +28,12 @@ def hist_rel(a, b):
 
 
 def oracle_model(p):
-    """Model flags and per-element orientation of a synth.Problem for the oracle."""
+    """Model flags and per-element orientation of a synth.Problem for the oracle
+    (the Barlat coefficients, if any, are installed in the oracle)."""
     flags = (oracle.MODEL_VOCE if p.hardening == "voce" else 0) | (oracle.MODEL_FBAR if p.fbar else 0)
+    if p.barlat is not None:
+        oracle.set_barlat(p.barlat)
+        flags |= oracle.MODEL_BARLAT
     return flags, p.orient
 
 
@@ -62,7 +66,8 @@ def gpu_problem(p, fem, device="cuda"):
     """Device copies of a synth.Problem for the binding."""
     import torch
     mesh = fem.Mesh(p.X, p.conn, device)
-    params = fem.Params(p.prm, p.n_elems, device, hardening=p.hardening, fbar=p.fbar, orient=p.orient)
+    params = fem.Params(p.prm, p.n_elems, device, hardening=p.hardening, fbar=p.fbar, orient=p.orient,
+                        barlat=p.barlat)
     d = torch.as_tensor(np.ascontiguousarray(p.d, dtype=np.float64)).to(device)
     h = torch.as_tensor(np.ascontiguousarray(p.hist_n, dtype=np.float64)).to(device)
     bc = torch.as_tensor(np.ascontiguousarray(p.bc_mask, dtype=np.uint8)).to(device) if p.bc_mask is not None else None
