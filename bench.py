@@ -254,11 +254,13 @@ def main():
         # ---- model variants on the same cube: Voce hardening, one orientation
         # per element (in-plane angles), the F-bar element, and all three
         variants = {}
-        for vname, hard, fbar, orient in (("voce", "voce", False, None), ("orient_per_elem", "swift", False, "per_element"),
-                                          ("fbar", "swift", True, None),
-                                          ("fbar_voce_orient", "voce", True, "per_element")):
-            pm = synth.with_model(p, 11, hard, fbar, orient)
-            vparams = fem.Params(pm.prm, pm.n_elems, hardening=hard, fbar=fbar, orient=pm.orient)
+        for vname, hard, fbar, orient, bar in (("voce", "voce", False, None, None),
+                                               ("orient_per_elem", "swift", False, "per_element", None),
+                                               ("fbar", "swift", True, None, None),
+                                               ("fbar_voce_orient", "voce", True, "per_element", None),
+                                               ("barlat_aa6111", "swift", False, None, synth.BARLAT_AA6111)):
+            pm = synth.with_model(p, 11, hard, fbar, orient, barlat=bar)
+            vparams = fem.Params(pm.prm, pm.n_elems, hardening=hard, fbar=fbar, orient=pm.orient, barlat=bar)
             ms_v, _, kt_v = time_passes(
                 lambda: fem.residual_tangent(mesh, csr, vparams, d, h, bc_mask=bc, prec=fem.FP32_MIXED, out=out_m),
                 max(args.steps // 2, 3), 2, torch, KS, fem)

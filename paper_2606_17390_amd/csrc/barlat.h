@@ -270,11 +270,11 @@ __device__ inline void chol6_solve(const double L[6][6], double x[6]) {
     }
 }
 
-// Result of the Barlat local update (material frame)
+// Result of the Barlat local update (material frame); the algorithmic
+// tangent goes to the caller's array cep[21] (upper triangle, row by row)
 struct LocalB {
     double T[6];
     double hist[7];
-    double Cep[6][6];
     double ftr, sy_n;
     int plastic, converged;
 };
@@ -312,7 +312,7 @@ __device__ inline double barlat_residual(const BarlatCoef& b, const Mat& m, cons
 }
 
 __device__ inline void local_update_barlat(const double eps[6], const double* hist_n, const Mat& m, const Modes& md,
-                                           const BarlatCoef& b, LocalB& o) {
+                                           const BarlatCoef& b, LocalB& o, double* __restrict__ cep) {
     double ee[6];
     ee[0] = eps[0] - hist_n[0];
     ee[1] = eps[1] - hist_n[1];
@@ -337,16 +337,35 @@ __device__ inline void local_update_barlat(const double eps[6], const double* hi
         for (int i = 0; i < 6; ++i) o.T[i] = t_tr[i];
 #pragma unroll
         for (int i = 0; i < 7; ++i) o.hist[i] = hist_n[i];
+        int c = 0;
 #pragma unroll
         for (int i = 0; i < 6; ++i)
 #pragma unroll
-            for (int j = 0; j < 6; ++j) o.Cep[i][j] = ((i < 3 && j < 3) ? md.lam : 0.0) + ((i == j) ? md.mu2 : 0.0);
+            for (int j = i; j < 6; ++j) cep[c++] = ((i < 3 && j < 3) ? md.lam : 0.0) + ((i == j) ? md.mu2 : 0.0);
         return;
     }
     o.plastic = 1;
-    double T[6], dg = 0.0, G[7], dsig;
+    // start on the current yield surface: phi is homogeneous of degree one, so
+    // T0 = t_tr sigma_y(alpha_n) / phi(t_tr), and dgamma0 from the flow rule
+    // projected on N(T0) (the root is unique, the start only saves iterations)
+    double T[6], dg, G[7], dsig;
+    {
+        const double r = o.sy_n / phi_tr;
+        double N0[6], c[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) T[i] = t_tr[i];
+        for (int i = 0; i < 6; ++i) T[i] = r * t_tr[i];
+        barlat_principal(b, T, st);
+        barlat_flow(b, st, N0);
+        elastic_compliance(md, t_tr, c);
+        double nc = 0.0, nn = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            nc += N0[i] * c[i];
+            nn += N0[i] * N0[i];
+        }
+        dg = (1.0 - r) * nc / nn;
+        if (!(dg > 0.0)) dg = 0.0;
+    }
     double psi = barlat_residual(b, m, md, t_tr, alpha_n, T, dg, o.sy_n, G, st, dsig);
     double prev = __builtin_inf();
     int conv = 0;
@@ -467,13 +486,14 @@ __device__ inline void local_update_barlat(const double eps[6], const double* hi
 #pragma unroll
     for (int k = 0; k < 6; ++k) NXN += N[k] * XN[k];
     const double den = 1.0 / (NXN + dsig);
+    // column j of Xi, entries i <= j of Cep (symmetric)
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         double x[6] = {0, 0, 0, 0, 0, 0};
         x[j] = 1.0;
         chol6_solve(A, x);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) o.Cep[i][j] = x[i] - XN[i] * XN[j] * den;
+        for (int i = 0; i <= j; ++i) cep[i * 6 - (i * (i - 1)) / 2 + (j - i)] = x[i] - XN[i] * XN[j] * den;
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) o.T[k] = T[k];

@@ -287,7 +287,7 @@ void fwd_kernel(const FwdArgs a) {
             BarlatCoef bco;
             load_barlat(a.barlat, bco);
             LocalB lb;
-            local_update_barlat(eps, hn, mat, md, bco, lb);
+            local_update_barlat(eps, hn, mat, md, bco, lb, &sCep[slot][gp][0]);
 #pragma unroll
             for (int k = 0; k < 6; ++k) loc.T[k] = lb.T[k];
 #pragma unroll
@@ -296,11 +296,6 @@ void fwd_kernel(const FwdArgs a) {
             loc.converged = lb.converged;
             loc.ftr = lb.ftr;
             loc.sy_n = lb.sy_n;
-            int c = 0;
-#pragma unroll
-            for (int i = 0; i < 6; ++i)
-#pragma unroll
-                for (int j = i; j < 6; ++j) sCep[slot][gp][c++] = lb.Cep[i][j];
         } else {
             local_update(eps, hn, mat, md, loc);
         }
