@@ -1,0 +1,91 @@
+"""Quasi-static load path on the GPU: load factor t from 0 to t_end in
+adaptive increments, each solved by the damped Newton iteration of newton.py
+(Sec. 2.2.4: R(d; h_n) = 0 with the history of the last converged increment),
+with the automatic stepping of Sec. 2.4:
+
+* prescribed values t u1 on the constrained dofs (a load proportional to t);
+* the Newton start of an increment is the linear extrapolation of the two
+  last converged solutions (the converged solution itself on the first);
+* a failed increment (no convergence, non-finite residual) is retried with
+  dt times `cutback`, down to dt_min; after `grow_after` converged increments
+  in a row dt grows by `grow`, up to dt_max;
+* convergence: ||R|| <= ftol f_ref, f_ref the largest norm of the reactions
+  (the unconstrained residual on the constrained dofs) met so far, or of the
+  first increment's starting residual before any reaction exists.
+
+The performance study of the paper uses dt0 1e-3, dt_min 1e-5, dt_max 5e-2.
+
+    res = loadpath.solve(mesh, csr, params, bc_mask, u1, hist0)
+"""
+import time
+
+import torch
+
+from . import fem, newton
+
+
+def reaction_norm(mesh, csr, params, d, hist, bc, prec=fem.FP64):
+    """Norm of the internal force on the constrained dofs (flat bool mask bc)."""
+    r = fem.residual_tangent(mesh, csr, params, d, hist, bc_mask=None, prec=prec, want_K=False, want_hist=False)
+    return float(r.R[bc].norm().cpu())
+
+
+def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
+          grow_after=1, cutback=0.5, ftol=1e-6, max_it=20, lin_rtol=1e-6, lin_max_iter=20000, t_end=1.0,
+          max_steps=10000, log=None):
+    """Returns a dict with the final displacement and history, the accepted
+    increments [(t, dt, Newton iterations, linear iterations)], the failed
+    increments, the total Newton and linear iterations and the wall time."""
+    dev = hist0.device
+    bc = bc_mask.bool().view(-1)
+    out = fem.Forward(mesh, csr, prec)
+    solver = fem.Solver(csr, dev)
+    d = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
+    d_prev, dt_prev = None, None
+    h = hist0.clone()
+    u1f = u1.reshape(-1)
+    t, dt = 0.0, dt0
+    f_ref = 0.0
+    steps, failed, newton_its, lin_its, streak = [], [], 0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while t < t_end * (1 - 1e-12) and len(steps) < max_steps:
+        dt = min(dt, t_end - t)
+        trial = d.clone()
+        if d_prev is not None:
+            trial.add_(d - d_prev, alpha=dt / dt_prev)
+        trial.view(-1)[bc] = (t + dt) * u1f[bc]
+        trace = []
+        try:
+            h_new, its, norms = newton.solve_step(mesh, csr, params, trial, h, bc_mask, prec=prec,
+                                                  tol=ftol if f_ref == 0.0 else 0.0, atol=ftol * f_ref,
+                                                  max_it=max_it, lin_rtol=lin_rtol, lin_max_iter=lin_max_iter,
+                                                  solver=solver, out=out, trace=trace)
+        except RuntimeError as err:
+            failed.append((t, dt, str(err)))
+            if log:
+                log(f"increment t={t:.5f} dt={dt:.2e} failed: {err}")
+            dt *= cutback
+            streak = 0
+            if dt < dt_min:
+                raise RuntimeError(f"load path: increment below {dt_min:g} at t = {t:.5f}") from err
+            continue
+        finally:
+            lin_its += sum(x[0] for x in trace)
+        d_prev, dt_prev = d, dt
+        d, h = trial, h_new
+        t += dt
+        newton_its += its
+        f_reac = reaction_norm(mesh, csr, params, d, h_new, bc)
+        f_ref = max(f_ref, f_reac)
+        steps.append((t, dt, its, sum(x[0] for x in trace)))
+        if log:
+            log(f"t={t:.5f} dt={dt:.2e} Newton {its} ||R|| {norms[0]:.2e} -> {norms[-1]:.2e} "
+                f"reaction {f_reac:.3e} linear {[x[0] for x in trace]} steps {[x[2] for x in trace]}")
+        streak += 1
+        if streak >= grow_after:
+            dt = min(dt * grow, dt_max)
+            streak = 0
+    torch.cuda.synchronize()
+    return dict(d=d, hist=h, steps=steps, failed=failed, newton_iterations=newton_its, linear_iterations=lin_its,
+                seconds=time.perf_counter() - t0)

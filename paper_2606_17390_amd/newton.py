@@ -19,15 +19,20 @@ residual below 1e-3 is used.
 Every step runs in the library (residual, tangent, assembly, linear solve);
 this module only sequences the calls and reads the residual norm back.
 """
+import math
+
 from . import fem
 
 
 def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, max_it=30, lin_rtol=1e-10,
-               lin_max_iter=5000, solver=None, out=None, stream=None, line_search=True, max_backtracks=8):
+               lin_max_iter=5000, solver=None, out=None, stream=None, line_search=True, max_backtracks=8, atol=0.0,
+               trace=None):
     """Newton iteration on d (device [n_nodes][3], updated in place) until
-    ||R|| <= tol ||R_0||.  Returns (hist_np1, iterations, list of ||R||).
-    Raises RuntimeError if the tolerance is not reached in max_it iterations
-    or a linear solve fails."""
+    ||R|| <= max(tol ||R_0||, atol).  Returns (hist_np1, iterations, list of
+    ||R||).  Raises RuntimeError if the tolerance is not reached in max_it
+    iterations, a linear solve fails or ||R|| is not finite.  A list passed
+    as trace receives one (linear iterations, linear relative residual, step
+    length) tuple per Newton iteration."""
     if out is None:
         out = fem.Forward(mesh, csr, prec)
     if solver is None:
@@ -42,11 +47,13 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
     rn = evaluate()
     for it in range(max_it + 1):
         norms.append(rn)
-        if rn == 0.0 or rn <= tol * norms[0]:
+        if not math.isfinite(rn):
+            raise RuntimeError(f"Newton: ||R|| is not finite at iteration {it}")
+        if rn == 0.0 or rn <= max(tol * norms[0], atol):
             return out.hist.clone(), it, norms
         if it == max_it:
             break
-        du, _, res = solver.solve(out.K, -out.R, rtol=lin_rtol, max_iter=lin_max_iter, stream=stream, check=False)
+        du, lin_its, res = solver.solve(out.K, -out.R, rtol=lin_rtol, max_iter=lin_max_iter, stream=stream, check=False)
         if not (res <= 1e-3):
             raise RuntimeError(f"Newton: linear solve reached only a relative residual of {res:.3e}")
         base = flat.clone()
@@ -58,5 +65,7 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
             if not line_search or rn_new < (1.0 - 1e-4 * t) * rn or k == max_backtracks:
                 break
             t *= 0.5
+        if trace is not None:
+            trace.append((lin_its, res, t))
         rn = rn_new
     raise RuntimeError(f"Newton: ||R|| = {norms[-1]:.3e} after {max_it} iterations (start {norms[0]:.3e})")

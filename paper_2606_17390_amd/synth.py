@@ -423,6 +423,43 @@ def batch64(n_spec=64, lo=2000, hi=60000, seed=4000):
     return [uneven_slab(seed + i, int(round(s))) for i, s in enumerate(sizes)]
 
 
+def hill_from_r(r11, r22, r33, r12, r13, r23):
+    """F, G, H, L, M, N of the phi^2 form from the yield-stress ratios of App. A
+    (G+H = 1/r11^2, F+H = 1/r22^2, F+G = 1/r33^2, N = 3/(2 r12^2),
+    M = 3/(2 r13^2), L = 3/(2 r23^2))."""
+    a, b, c = 1.0 / r11 ** 2, 1.0 / r22 ** 2, 1.0 / r33 ** 2
+    return dict(F=0.5 * (b + c - a), G=0.5 * (a + c - b), H=0.5 * (a + b - c),
+                L=1.5 / r23 ** 2, M=1.5 / r13 ** 2, N=1.5 / r12 ** 2)
+
+
+def unit_cube_forward(n=100, nu=NU_DEFAULT):
+    """The forward-simulation benchmark of the paper's performance study: the
+    unit cube [0, 1]^3 mm in n^3 hex8 elements, Hill-48 with the yield-stress
+    ratios r11..r23 = 1.5449, 1.0666, 1, 1.0307, 1, 1 and Voce hardening
+    sigma0 = 138, Q = 410 MPa, b = 3.8, E = 219 GPa (nu not given: 0.3);
+    the x = 0 face fixed, the x = 1 face moved by t (0.2, 0.1) mm in (x, y),
+    its z motion free.  Returns the Problem at t = 0 (hardening "voce") and
+    the prescribed values at load factor t via meta["bc_at"](t)."""
+    X, conn = hex_grid(n, n, n, 1.0, 1.0, 1.0)
+    hp = hill_from_r(1.5449, 1.0666, 1.0, 1.0307, 1.0, 1.0)
+    prm = voce_params(sig0=138.0, Q=410.0, b=3.8, E=219000.0, nu=nu, **hp)
+    left, right = np.isclose(X[:, 0], 0.0), np.isclose(X[:, 0], 1.0)
+    bc = np.zeros((X.shape[0], 3), dtype=np.uint8)
+    bc[left] = 1
+    bc[right, 0] = 1
+    bc[right, 1] = 1
+
+    def bc_at(t):
+        u = np.zeros((X.shape[0], 3))
+        u[right, 0] = 0.2 * t
+        u[right, 1] = 0.1 * t
+        return u
+
+    ne = conn.shape[0]
+    return Problem(f"unit_cube_{n}", X, conn, np.zeros_like(X), np.zeros((7, 8 * ne)), prm, bc.ravel(), None,
+                   dict(nx=n, ny=n, nz=n, bc_at=bc_at), hardening="voce")
+
+
 def small_slab(seed, nx, ny, nz, per_element=False, strain=0.05, jitter=0.05, alpha_max=0.1):
     """Small jittered slab for parity tests with ragged element counts."""
     rng = np.random.Generator(np.random.PCG64(seed))
