@@ -65,10 +65,16 @@ typedef enum {
 
 typedef enum {
     FEM_FP64 = 0,      /* everything in FP64 */
-    FEM_FP32_MIXED = 1 /* kinematics, log strain, stress pull-back, B^T C B and
+    FEM_FP32_MIXED = 1, /* kinematics, log strain, stress pull-back, B^T C B and
                           assembly in FP32; trial stress, yield function, local
                           return-mapping Newton and residual norm in FP64;
                           K_vals is float */
+    FEM_FP64_K32 = 2    /* fem_residual_tangent only: FP64 arithmetic as
+                          FEM_FP64 (R, history and norm identical), K_vals
+                          rounded to float once per entry of K^e and assembled
+                          in float: an exact residual for the global Newton
+                          iteration with the Krylov solve reading half the
+                          matrix bytes */
 } fem_precision;
 
 enum {
@@ -264,25 +270,35 @@ int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_par
  * fem_residual_tangent); x, y device [n_rows] doubles (not aliased).  Errors:
  * FEM_EINVAL, FEM_EHIP.
  *
- * fem_solve -- K x = b by BiCGSTAB preconditioned with the inverse diagonal
- * of K; vectors and scalars in FP64 whatever the type of K.
+ * fem_solve -- K x = b by BiCGSTAB (the linear solve of the global Newton
+ * iteration, Sec. 2.2.4 / Eq. (Stiffness_mat); the paper's default Krylov
+ * method of Sec. 2.4), right-preconditioned by M:
+ *   FEM_PC_JACOBI        M = inverse of the diagonal of K
+ *   FEM_PC_BLOCK_JACOBI  M = inverses of the 3x3 node blocks K[3I+a][3I+b]
+ *                        (a singular block falls back to its diagonal)
+ * The CSR must be a pattern of fem_csr_pattern (node blocks, nnz a multiple
+ * of 9).  Vectors and scalars are FP64 whatever the type of K.
  *   b        device [n_rows]
  *   x        device [n_rows], initial guess in, solution out
  *   max_iter iteration limit (>= 0); rtol: stop at ||b - K x|| <= rtol ||b||
+ *            (||b - K x|| if b = 0), with ||b - K x|| the recursive residual
  *   iters, rel_res  host outputs (iterations done, final relative residual),
  *            or NULL
- *   ws       device workspace of fem_solver_workspace_bytes(n_rows) bytes
- * The reductions are fixed-order (bitwise reproducible).  Synchronises the
- * stream once per iteration (the convergence test reads one double back).
+ *   ws       device workspace of fem_solver_workspace_bytes(n_rows, nnz) bytes
+ * The reductions are fixed-order (bitwise reproducible).  The iteration state
+ * stays on the device; the host reads the stop flag once per 32 iterations
+ * (one stream synchronisation each).  A breakdown (a zero inner product) or
+ * a non-finite residual ends the iteration.
  * Returns FEM_ENOCONV if rtol is not reached (x holds the last iterate).
  * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOCONV.
  */
-size_t fem_solver_workspace_bytes(int32_t n_rows);
+typedef enum { FEM_PC_JACOBI = 0, FEM_PC_BLOCK_JACOBI = 1 } fem_precond;
+size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz);
 int fem_csr_spmv(const fem_csr *csr, const void *K_vals, fem_precision prec, const double *x, double *y,
                  void *stream);
-int fem_solve(const fem_csr *csr, const void *K_vals, fem_precision prec, const double *b, double *x,
-              int32_t max_iter, double rtol, int32_t *iters, double *rel_res, void *ws, size_t ws_bytes,
-              void *stream);
+int fem_solve(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_precond pc, const double *b,
+              double *x, int32_t max_iter, double rtol, int32_t *iters, double *rel_res, void *ws,
+              size_t ws_bytes, void *stream);
 
 /*
  * fem_csr_transpose -- KT_vals = values of K^T on the same pattern (the

@@ -1088,7 +1088,7 @@ void carve_forward(C& c, int32_t n_nodes, int32_t n_elems, fem_precision prec, F
     auto re = c.template take<double>((size_t)n_elems * 24 + 1);
     auto ke = c.template take<char>((size_t)n_elems * kKeStride * kb + 16);
     auto pa = c.template take<double>((size_t)residual_blocks(n_nodes) + 1);
-    auto fl = c.template take<int32_t>(prec == FEM_FP64 ? 1 : (size_t)n_elems + 1);
+    auto fl = c.template take<int32_t>(prec == FEM_FP32_MIXED ? (size_t)n_elems + 1 : 1);
     auto fc = c.template take<int32_t>(4);
     if (w) *w = FwdWs{re, (void*)ke, pa, fl, fc};
 }
@@ -1132,7 +1132,7 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
     clear_error();
     if (!mesh || !params) return set_error(FEM_EINVAL, "fem_residual_tangent: mesh and params must not be NULL");
     if (mesh->n_nodes < 0 || mesh->n_elems < 0) return set_error(FEM_EINVAL, "fem_residual_tangent: negative sizes");
-    if (prec != FEM_FP64 && prec != FEM_FP32_MIXED)
+    if (prec != FEM_FP64 && prec != FEM_FP32_MIXED && prec != FEM_FP64_K32)
         return set_error(FEM_EINVAL, "fem_residual_tangent: unknown precision %d", (int)prec);
     const int64_t ne = mesh->n_elems, n_dof = 3 * (int64_t)mesh->n_nodes;
     if (rnorm2 && !R && n_dof > 0) return set_error(FEM_EINVAL, "fem_residual_tangent: rnorm2 requires R");
@@ -1168,7 +1168,7 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
     FEM_HIP_CHECK(zero_counters(diag, 4, (ne > 0 && prec == FEM_FP32_MIXED) ? w.fix_count : nullptr, 1, s));
 
     if (ne > 0) {
-        fem_launch cfg = launch_config(FEM_KERNEL_FORWARD, prec);
+        fem_launch cfg = launch_config(FEM_KERNEL_FORWARD, prec == FEM_FP32_MIXED ? FEM_FP32_MIXED : FEM_FP64);
         if (params->model || params->orient) cfg.block = 64;  // model variants: 64-thread workgroups
         FwdArgs a;
         a.n_nodes = mesh->n_nodes;
@@ -1198,8 +1198,9 @@ extern "C" int fem_residual_tangent(const fem_mesh* mesh, const fem_batch* batch
         a.fix_count = w.fix_count;
         const int grid = persistent_grid(cfg, a.n_tiles);
         void* tk = timing_begin(s);
-        hipError_t e = (prec == FEM_FP64) ? launch_fwd_main<double>(a, cfg.block, grid, s)
-                                          : launch_fwd_main<float>(a, cfg.block, grid, s);
+        hipError_t e = (prec == FEM_FP64)        ? launch_fwd_main<double>(a, cfg.block, grid, s)
+                       : (prec == FEM_FP64_K32) ? launch_fwd_variant<double, float, false>(a, cfg.block, grid, s)
+                                                : launch_fwd_main<float>(a, cfg.block, grid, s);
         timing_end(tk, FEM_KERNEL_FORWARD, s);
         if (e != hipSuccess) return set_error(FEM_EHIP, "forward kernel launch failed: %s", hipGetErrorString(e));
         if (prec == FEM_FP32_MIXED) {

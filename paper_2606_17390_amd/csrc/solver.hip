@@ -1,17 +1,24 @@
 // solver.hip -- the linear solve of the global Newton iteration (Sec. 2.2.4:
 // K du = -R with the Dirichlet rows of App. E replaced by identity rows, so
-// K is not symmetric): CSR matrix-vector product and BiCGSTAB with a Jacobi
-// preconditioner (the inverse of the diagonal of K).
+// K is not symmetric): CSR matrix-vector product and BiCGSTAB, preconditioned
+// by the inverse diagonal of K or by the inverses of its 3x3 node blocks.
 //
 // The matrix is the CSR pattern of fem_csr_pattern (rows 3I+a; the three
-// rows of a node are consecutive and share their sorted column list).
-// Vectors are FP64; the matrix values are FP64 or FP32 (the mixed form keeps
-// K in FP32 and solves in FP64).  Every reduction is a fixed two-stage tree,
-// so a solve is bitwise reproducible.  The iteration runs on the host: the
-// scalars stay in device memory and the residual norm is read back once per
-// iteration for the convergence test.
+// rows of a node are consecutive and share their sorted column list, which
+// runs over whole node blocks 3J, 3J+1, 3J+2).  Vectors are FP64; the matrix
+// values are FP64 or FP32 (the mixed form keeps K in FP32 and solves in FP64).
+//
+// Solve layout: a node-column list (one index J per 3x3 block, a ninth of
+// col_idx) is built once per solve, so the iteration's matrix products read
+// the values, one index per block and three consecutive x values per block.
+// The dot products are fused into the kernels that produce their operands
+// and reduced in two fixed stages (fixed grids), so a solve is bitwise
+// reproducible.  Scalars, the iteration count and a stop flag live in device
+// memory: every kernel of an iteration returns at once when the flag is set,
+// and the host reads the flag back once per chunk of iterations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "fem_internal.h"
@@ -20,8 +27,6 @@ namespace fem {
 namespace {
 
 constexpr int kSpmvLanes = 32;    // lanes per node (3 rows) of the matrix-vector product
-constexpr int kVecThreads = 256;  // vector kernels
-constexpr int kDotBlocks = 256;   // fixed grid of the first reduction stage
 
 // y = K x over the pattern of fem_csr_pattern, where the three rows of a node
 // are consecutive, equally long and share their column list: 32 lanes per
@@ -88,118 +93,326 @@ __global__ __launch_bounds__(256) void transpose_kernel(int32_t n_nodes, const i
         }
 }
 
-// dinv[i] = 1 / K_ii (1 where the diagonal entry is absent or zero)
-template <typename RV>
-__global__ void diag_inv_kernel(int32_t n_rows, const int32_t* __restrict__ row_ptr,
-                                const int32_t* __restrict__ col_idx, const RV* __restrict__ val,
-                                double* __restrict__ dinv) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_rows) return;
-    int32_t lo = row_ptr[i], hi = row_ptr[i + 1] - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (col_idx[mid] < i) lo = mid + 1;
-        else hi = mid;
-    }
-    const double dii = (lo <= hi && col_idx[lo] == i) ? (double)val[lo] : 0.0;
-    dinv[i] = (dii != 0.0) ? 1.0 / dii : 1.0;
+
+constexpr int kGrid = 1024;      // blocks of the fused vector kernels (fixed: reproducible reductions)
+constexpr int kSpmvGrid = 2048;  // blocks of the fused matrix-vector products
+constexpr int kParts = kSpmvGrid > kGrid ? kSpmvGrid : kGrid;
+constexpr int kChunk = 32;       // iterations enqueued between two reads of the stop flag
+
+// Scalars of the iteration (device memory) and integer flags.
+enum { S_RHO, S_RHO_NEW, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_RES, S_COUNT };
+enum { F_STOP, F_ITER, F_COUNT };
+
+// ncol[row_ptr[3I]/9 + k] = J, the node of the k-th 3x3 block of node I's rows
+// (each row of node I has 3 deg(I) entries, so row_ptr[3I] is a multiple of 9).
+__global__ __launch_bounds__(256) void node_cols_kernel(int32_t n_nodes, const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col_idx,
+                                                        int32_t* __restrict__ ncol) {
+    const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSpmvLanes;
+    const int l = (int)(threadIdx.x & (kSpmvLanes - 1));
+    if (I >= n_nodes) return;
+    const int32_t b = row_ptr[3 * I], deg = (row_ptr[3 * I + 1] - b) / 3;
+    for (int32_t k = l; k < deg; k += kSpmvLanes) ncol[b / 9 + k] = col_idx[b + 3 * k] / 3;
 }
 
-// ---- fixed-order reductions: kDotBlocks partials (grid-stride over the
-// vector), then one workgroup adds them in a fixed tree.
+// minv[9I + 3a + c] = preconditioner block of node I: the inverse of the 3x3
+// diagonal block K[3I+a][3I+c] (block = 1), or the inverse of its diagonal
+// (block = 0).  A zero diagonal entry gives 1; a singular block (or a block
+// whose determinant underflows against its diagonal) falls back to its
+// diagonal.
+template <typename RV>
+__global__ __launch_bounds__(256) void precond_kernel(int32_t n_nodes, const int32_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ ncol, const RV* __restrict__ val,
+                                                      int block, double* __restrict__ minv) {
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= n_nodes) return;
+    const int32_t b = row_ptr[3 * I], deg = (row_ptr[3 * I + 1] - b) / 3;
+    const int32_t* __restrict__ nc = ncol + b / 9;
+    int32_t lo = 0, hi = deg - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (nc[mid] < I) lo = mid + 1;
+        else hi = mid;
+    }
+    double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    if (deg > 0 && nc[lo] == I)
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) D[a][c] = (double)val[(int64_t)b + (int64_t)a * 3 * deg + 3 * lo + c];
+    double M[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool done = false;
+    if (block) {
+        const double c00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+        const double c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+        const double c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+        const double det = D[0][0] * c00 + D[0][1] * c01 + D[0][2] * c02;
+        const double scale = fabs(D[0][0] * D[1][1] * D[2][2]);
+        if (det != 0.0 && fabs(det) > 1e-12 * scale && isfinite(1.0 / det)) {
+            const double id = 1.0 / det;
+            M[0] = c00 * id;
+            M[1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
+            M[2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * id;
+            M[3] = c01 * id;
+            M[4] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * id;
+            M[5] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
+            M[6] = c02 * id;
+            M[7] = (D[0][1] * D[2][0] - D[0][0] * D[2][1]) * id;
+            M[8] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
+            done = true;
+        }
+    }
+    if (!done)
+        for (int a = 0; a < 3; ++a) M[4 * a] = D[a][a] != 0.0 ? 1.0 / D[a][a] : 1.0;
+    for (int k = 0; k < 9; ++k) minv[9 * I + k] = M[k];
+}
 
-__device__ inline void block_sum_to(double v, double* __restrict__ out) {
-    __shared__ double sh[kVecThreads];
+// Fixed-order block sum of one value per thread (256 threads); every thread
+// gets the result.
+__device__ inline double block_sum(double v) {
+    __shared__ double sh[256];
+    __syncthreads();
     sh[threadIdx.x] = v;
     __syncthreads();
-    for (int o = kVecThreads / 2; o > 0; o >>= 1) {
+    for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    return sh[0];
 }
 
-__global__ __launch_bounds__(kVecThreads) void dot_partial(int64_t n, const double* __restrict__ a,
-                                                           const double* __restrict__ b, double* __restrict__ part) {
+// Second stage: the sum of n partials in a fixed order (one 256-thread block).
+__device__ inline double sum_parts(const double* __restrict__ part, int n) {
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += (int64_t)kDotBlocks * kVecThreads)
-        s += a[i] * b[i];
-    block_sum_to(s, part + blockIdx.x);
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    return block_sum(s);
 }
 
-__global__ __launch_bounds__(kVecThreads) void dot_final(const double* __restrict__ part, double* __restrict__ out) {
-    block_sum_to(part[threadIdx.x], out);  // kDotBlocks == kVecThreads
+// y = K x on node blocks with the fused partial dot products
+//   ND >= 1: part0[block] = sum of w . y over the block's rows
+//   ND == 2: part1[block] = sum of y . y
+// 32 lanes per node, lane k takes the 3x3 blocks k, k + 32 of the node's rows;
+// fixed grid kSpmvGrid, 8 nodes per block and round.  Skipped when the stop
+// flag is set (if `fl` is given).
+template <typename RV, int ND>
+__global__ __launch_bounds__(256) void spmv_dot_kernel(int32_t n_nodes, const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ ncol,
+                                                       const RV* __restrict__ val, const double* __restrict__ x,
+                                                       double* __restrict__ y, const double* __restrict__ w,
+                                                       double* __restrict__ part0, double* __restrict__ part1,
+                                                       const int32_t* __restrict__ fl) {
+    if (fl && fl[F_STOP]) return;
+    const int l = (int)(threadIdx.x & (kSpmvLanes - 1));
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 8; base < n_nodes; base += (int64_t)kSpmvGrid * 8) {
+        const int64_t node = base + (threadIdx.x >> 5);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        if (node < n_nodes) {
+            const int32_t b = row_ptr[3 * node], len = row_ptr[3 * node + 1] - b, deg = len / 3;
+            const int32_t* __restrict__ nc = ncol + b / 9;
+            for (int32_t k = l; k < deg; k += kSpmvLanes) {
+                const int64_t J = nc[k];
+                const double x0 = x[3 * J], x1 = x[3 * J + 1], x2 = x[3 * J + 2];
+                const RV* __restrict__ v = val + b + 3 * k;
+                s0 += (double)v[0] * x0 + (double)v[1] * x1 + (double)v[2] * x2;
+                s1 += (double)v[len] * x0 + (double)v[len + 1] * x1 + (double)v[len + 2] * x2;
+                s2 += (double)v[2 * len] * x0 + (double)v[2 * len + 1] * x1 + (double)v[2 * len + 2] * x2;
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < kSpmvLanes; m <<= 1) {
+            s0 += __shfl_xor(s0, m, kSpmvLanes);
+            s1 += __shfl_xor(s1, m, kSpmvLanes);
+            s2 += __shfl_xor(s2, m, kSpmvLanes);
+        }
+        if (node < n_nodes && l < 3) {
+            const double yl = l == 0 ? s0 : (l == 1 ? s1 : s2);
+            y[3 * node + l] = yl;
+            if (ND >= 1) d0 += w[3 * node + l] * yl;
+            if (ND == 2) d1 += yl * yl;
+        }
+    }
+    if (ND >= 1) {
+        const double t0 = block_sum(d0);
+        if (threadIdx.x == 0) part0[blockIdx.x] = t0;
+    }
+    if (ND == 2) {
+        const double t1 = block_sum(d1);
+        if (threadIdx.x == 0) part1[blockIdx.x] = t1;
+    }
 }
 
-// Scalars of the iteration, in device memory.
-enum { S_RHO, S_RHO_NEW, S_ALPHA, S_OMEGA, S_RV, S_TS, S_TT, S_RR, S_BB, S_COUNT };
+__device__ inline void apply_minv(const double* __restrict__ minv, int64_t I, const double q[3], double* out) {
+    const double* m = minv + 9 * I;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[3 * I + a] = m[3 * a] * q[0] + m[3 * a + 1] * q[1] + m[3 * a + 2] * q[2];
+}
 
-// r = b - y, rh = r, p = v = 0; rho = alpha = omega = 1
-__global__ void init_kernel(int64_t n, const double* __restrict__ b, const double* __restrict__ y,
-                            double* __restrict__ r, double* __restrict__ rh, double* __restrict__ p,
-                            double* __restrict__ v, double* __restrict__ sc) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
+__global__ void reset_flags(int32_t* __restrict__ fl) {
+    fl[F_STOP] = 0;
+    fl[F_ITER] = 0;
+}
+
+// r = b - y, rh = r, p = v = 0; part0 = partials of r . r, part1 = of b . b
+__global__ __launch_bounds__(256) void init_kernel(int64_t n, const double* __restrict__ b,
+                                                   const double* __restrict__ y, double* __restrict__ r,
+                                                   double* __restrict__ rh, double* __restrict__ p,
+                                                   double* __restrict__ v, double* __restrict__ part0,
+                                                   double* __restrict__ part1) {
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kGrid * 256) {
+        const double bi = b[i], ri = bi - y[i];
+        r[i] = ri;
+        rh[i] = ri;
+        p[i] = 0.0;
+        v[i] = 0.0;
+        rr += ri * ri;
+        bb += bi * bi;
+    }
+    const double t0 = block_sum(rr);
+    const double t1 = block_sum(bb);
+    if (threadIdx.x == 0) {
+        part0[blockIdx.x] = t0;
+        part1[blockIdx.x] = t1;
+    }
+}
+
+__device__ inline double rel_of(double rr, double bb) {
+    const double bn = sqrt(bb);
+    return bn > 0.0 ? sqrt(rr) / bn : sqrt(rr);
+}
+
+__global__ __launch_bounds__(256) void fin_init(const double* __restrict__ part0, const double* __restrict__ part1,
+                                                double* __restrict__ sc, int32_t* __restrict__ fl, double rtol,
+                                                int32_t max_iter) {
+    const double rr = sum_parts(part0, kGrid);
+    const double bb = sum_parts(part1, kGrid);
+    if (threadIdx.x == 0) {
+        const double res = rel_of(rr, bb);
         sc[S_RHO] = 1.0;
         sc[S_ALPHA] = 1.0;
         sc[S_OMEGA] = 1.0;
+        sc[S_RHO_NEW] = rr;  // (rh, r) with rh = r
+        sc[S_BETA] = 0.0;    // p = v = 0: the first direction is r
+        sc[S_RR] = rr;
+        sc[S_BB] = bb;
+        sc[S_RES] = res;
+        fl[F_ITER] = 0;
+        fl[F_STOP] = (res <= rtol || !isfinite(res) || max_iter <= 0 || (bb == 0.0 && rr == 0.0)) ? 1 : 0;
     }
-    if (i >= n) return;
-    const double ri = b[i] - y[i];
-    r[i] = ri;
-    rh[i] = ri;
-    p[i] = 0.0;
-    v[i] = 0.0;
 }
 
-// p = r + beta (p - omega v), beta = (rho_new / rho)(alpha / omega); ph = dinv p
-__global__ void update_p(int64_t n, const double* __restrict__ r, const double* __restrict__ v,
-                         const double* __restrict__ dinv, double* __restrict__ p, double* __restrict__ ph,
-                         const double* __restrict__ sc) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double beta = (sc[S_RHO_NEW] / sc[S_RHO]) * (sc[S_ALPHA] / sc[S_OMEGA]);
-    const double pi = r[i] + beta * (p[i] - sc[S_OMEGA] * v[i]);
-    p[i] = pi;
-    ph[i] = dinv[i] * pi;
+// p = r + beta (p - omega v); ph = M p   (one thread per node)
+__global__ __launch_bounds__(256) void update_p(int32_t n_nodes, const double* __restrict__ r,
+                                                const double* __restrict__ v, const double* __restrict__ minv,
+                                                double* __restrict__ p, double* __restrict__ ph,
+                                                const double* __restrict__ sc, const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    const double beta = sc[S_BETA], omega = sc[S_OMEGA];
+    for (int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x; I < n_nodes; I += (int64_t)kGrid * 256) {
+        double q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q[a] = r[3 * I + a] + beta * (p[3 * I + a] - omega * v[3 * I + a]);
+            p[3 * I + a] = q[a];
+        }
+        apply_minv(minv, I, q, ph);
+    }
 }
 
-// alpha = rho_new / (rh, v); s = r - alpha v; sh = dinv s
-__global__ void update_s(int64_t n, const double* __restrict__ r, const double* __restrict__ v,
-                         const double* __restrict__ dinv, double* __restrict__ s, double* __restrict__ sh,
-                         double* __restrict__ sc) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double alpha = sc[S_RHO_NEW] / sc[S_RV];
-    if (i == 0) sc[S_ALPHA] = alpha;  // read by later kernels only
-    if (i >= n) return;
-    const double si = r[i] - alpha * v[i];
-    s[i] = si;
-    sh[i] = dinv[i] * si;
+// alpha = rho_new / (rh, v) (breakdown if (rh, v) = 0 or alpha is not finite)
+__global__ __launch_bounds__(256) void fin_alpha(const double* __restrict__ part0, double* __restrict__ sc,
+                                                 int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    const double rv = sum_parts(part0, kSpmvGrid);
+    if (threadIdx.x == 0) {
+        const double alpha = sc[S_RHO_NEW] / rv;
+        if (rv == 0.0 || !isfinite(alpha)) fl[F_STOP] = 1;
+        else sc[S_ALPHA] = alpha;
+    }
 }
 
-// omega = (t, s) / (t, t); x += alpha ph + omega sh; r = s - omega t
-__global__ void update_x(int64_t n, const double* __restrict__ ph, const double* __restrict__ sh,
-                         const double* __restrict__ s, const double* __restrict__ t, double* __restrict__ x,
-                         double* __restrict__ r, const double* __restrict__ sc) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double omega = sc[S_TT] > 0.0 ? sc[S_TS] / sc[S_TT] : 0.0;
-    x[i] += sc[S_ALPHA] * ph[i] + omega * sh[i];
-    r[i] = s[i] - omega * t[i];
+// s = r - alpha v; sh = M s
+__global__ __launch_bounds__(256) void update_s(int32_t n_nodes, const double* __restrict__ r,
+                                                const double* __restrict__ v, const double* __restrict__ minv,
+                                                double* __restrict__ s, double* __restrict__ sh,
+                                                const double* __restrict__ sc, const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    const double alpha = sc[S_ALPHA];
+    for (int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x; I < n_nodes; I += (int64_t)kGrid * 256) {
+        double q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q[a] = r[3 * I + a] - alpha * v[3 * I + a];
+            s[3 * I + a] = q[a];
+        }
+        apply_minv(minv, I, q, sh);
+    }
 }
 
-// the scalars that carry over to the next iteration
-__global__ void roll_scalars(double* __restrict__ sc) {
-    sc[S_OMEGA] = sc[S_TT] > 0.0 ? sc[S_TS] / sc[S_TT] : 0.0;
-    sc[S_RHO] = sc[S_RHO_NEW];
+// omega = (t, s) / (t, t) (0 if t = 0)
+__global__ __launch_bounds__(256) void fin_omega(const double* __restrict__ part0, const double* __restrict__ part1,
+                                                 double* __restrict__ sc, const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    const double ts = sum_parts(part0, kSpmvGrid);
+    const double tt = sum_parts(part1, kSpmvGrid);
+    if (threadIdx.x == 0) sc[S_OMEGA] = tt > 0.0 ? ts / tt : 0.0;
+}
+
+// x += alpha ph + omega sh; r = s - omega t; part0 = partials of (rh, r),
+// part1 = of (r, r)
+__global__ __launch_bounds__(256) void update_x(int64_t n, const double* __restrict__ ph,
+                                                const double* __restrict__ sh, const double* __restrict__ s,
+                                                const double* __restrict__ t, const double* __restrict__ rh,
+                                                double* __restrict__ x, double* __restrict__ r,
+                                                double* __restrict__ part0, double* __restrict__ part1,
+                                                const double* __restrict__ sc, const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    const double alpha = sc[S_ALPHA], omega = sc[S_OMEGA];
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kGrid * 256) {
+        x[i] += alpha * ph[i] + omega * sh[i];
+        const double ri = s[i] - omega * t[i];
+        r[i] = ri;
+        d0 += rh[i] * ri;
+        d1 += ri * ri;
+    }
+    const double t0 = block_sum(d0);
+    const double t1 = block_sum(d1);
+    if (threadIdx.x == 0) {
+        part0[blockIdx.x] = t0;
+        part1[blockIdx.x] = t1;
+    }
+}
+
+// end of an iteration: rho, rho_new, the residual, beta for the next
+// direction; stop on convergence, a non-finite residual, a breakdown
+// (rho_new = 0 or omega = 0) or the iteration limit
+__global__ __launch_bounds__(256) void fin_rho(const double* __restrict__ part0, const double* __restrict__ part1,
+                                               double* __restrict__ sc, int32_t* __restrict__ fl, double rtol,
+                                               int32_t max_iter) {
+    if (fl[F_STOP]) return;
+    const double rho_new = sum_parts(part0, kGrid);
+    const double rr = sum_parts(part1, kGrid);
+    if (threadIdx.x == 0) {
+        const double rho = sc[S_RHO_NEW], alpha = sc[S_ALPHA], omega = sc[S_OMEGA];
+        const double res = rel_of(rr, sc[S_BB]);
+        const int32_t it = fl[F_ITER] + 1;
+        sc[S_RHO] = rho;
+        sc[S_RHO_NEW] = rho_new;
+        sc[S_RR] = rr;
+        sc[S_RES] = res;
+        sc[S_BETA] = (rho_new / rho) * (alpha / omega);
+        fl[F_ITER] = it;
+        if (res <= rtol || !isfinite(res) || rho_new == 0.0 || omega == 0.0 || it >= max_iter) fl[F_STOP] = 1;
+    }
 }
 
 struct SolverWs {
-    double *r, *rh, *p, *ph, *v, *s, *sh, *t, *y, *dinv, *part, *sc;
+    double *r, *rh, *p, *ph, *v, *s, *sh, *t, *minv, *part0, *part1, *sc;
+    int32_t *ncol, *fl;
 };
 
 template <typename C>
-void carve_solver(C& c, int32_t n, SolverWs* w) {
+void carve_solver(C& c, int32_t n, int64_t nnz, SolverWs* w) {
     SolverWs o;
     o.r = c.template take<double>((size_t)n + 1);
     o.rh = c.template take<double>((size_t)n + 1);
@@ -209,10 +422,12 @@ void carve_solver(C& c, int32_t n, SolverWs* w) {
     o.s = c.template take<double>((size_t)n + 1);
     o.sh = c.template take<double>((size_t)n + 1);
     o.t = c.template take<double>((size_t)n + 1);
-    o.y = c.template take<double>((size_t)n + 1);
-    o.dinv = c.template take<double>((size_t)n + 1);
-    o.part = c.template take<double>(kDotBlocks);
+    o.minv = c.template take<double>(3 * (size_t)n + 1);
+    o.part0 = c.template take<double>(kParts);
+    o.part1 = c.template take<double>(kParts);
     o.sc = c.template take<double>(S_COUNT);
+    o.ncol = c.template take<int32_t>((size_t)(nnz / 9) + 1);
+    o.fl = c.template take<int32_t>(F_COUNT);
     if (w) *w = o;
 }
 
@@ -239,10 +454,16 @@ hipError_t spmv(const fem_csr* csr, const void* vals, fem_precision prec, const 
     return hipGetLastError();
 }
 
-hipError_t dot(int64_t n, const double* a, const double* b, double* part, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(dot_partial, dim3(kDotBlocks), dim3(kVecThreads), 0, s, n, a, b, part);
-    hipLaunchKernelGGL(dot_final, dim3(1), dim3(kVecThreads), 0, s, part, out);
-    return hipGetLastError();
+template <int ND>
+void spmv_dot(const fem_csr* csr, const int32_t* ncol, const void* vals, fem_precision prec, const double* x,
+              double* y, const double* w, double* part0, double* part1, const int32_t* fl, hipStream_t s) {
+    const int32_t nn = csr->n_rows / 3;
+    if (prec == FEM_FP64)
+        hipLaunchKernelGGL((spmv_dot_kernel<double, ND>), dim3(kSpmvGrid), dim3(256), 0, s, nn, csr->row_ptr, ncol,
+                           static_cast<const double*>(vals), x, y, w, part0, part1, fl);
+    else
+        hipLaunchKernelGGL((spmv_dot_kernel<float, ND>), dim3(kSpmvGrid), dim3(256), 0, s, nn, csr->row_ptr, ncol,
+                           static_cast<const float*>(vals), x, y, w, part0, part1, fl);
 }
 
 int check_csr(const fem_csr* csr, const void* vals, const char* who) {
@@ -258,10 +479,10 @@ int check_csr(const fem_csr* csr, const void* vals, const char* who) {
 
 using namespace fem;
 
-extern "C" size_t fem_solver_workspace_bytes(int32_t n_rows) {
-    if (n_rows < 0) return 0;
+extern "C" size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz) {
+    if (n_rows < 0 || nnz < 0) return 0;
     CountAdapterS c;
-    carve_solver(c, n_rows, (SolverWs*)nullptr);
+    carve_solver(c, n_rows, nnz, (SolverWs*)nullptr);
     return c.cnt.used + 256;
 }
 
@@ -297,72 +518,72 @@ extern "C" int fem_csr_transpose(const fem_csr* csr, const void* K_vals, fem_pre
     return FEM_OK;
 }
 
-extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision prec, const double* b, double* x,
-                         int32_t max_iter, double rtol, int32_t* iters, double* rel_res, void* ws, size_t ws_bytes,
-                         void* stream) {
+extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision prec, fem_precond pc,
+                         const double* b, double* x, int32_t max_iter, double rtol, int32_t* iters, double* rel_res,
+                         void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (int rc = check_csr(csr, K_vals, "fem_solve")) return rc;
     if (prec != FEM_FP64 && prec != FEM_FP32_MIXED) return set_error(FEM_EINVAL, "fem_solve: bad precision");
+    if (pc != FEM_PC_JACOBI && pc != FEM_PC_BLOCK_JACOBI) return set_error(FEM_EINVAL, "fem_solve: bad preconditioner");
     if (max_iter < 0 || !(rtol >= 0.0)) return set_error(FEM_EINVAL, "fem_solve: max_iter >= 0 and rtol >= 0");
-    const int32_t n = csr->n_rows;
+    const int32_t n = csr->n_rows, nn = n / 3;
     if (iters) *iters = 0;
     if (rel_res) *rel_res = 0.0;
     if (n == 0) return FEM_OK;
     if (!b || !x) return set_error(FEM_EINVAL, "fem_solve: b and x must not be NULL");
-    const size_t need = fem_solver_workspace_bytes(n);
+    if (csr->nnz < 0 || csr->nnz % 9) return set_error(FEM_EINVAL, "fem_solve: nnz must be a multiple of 9");
+    const size_t need = fem_solver_workspace_bytes(n, csr->nnz);
     if (!ws || ws_bytes < need)
         return set_error(FEM_ENOMEM, "fem_solve: workspace of %zu bytes required, %zu given", need, ws_bytes);
     hipStream_t s = (hipStream_t)stream;
     WsCarver c(ws, ws_bytes);
     SolverWs w;
-    carve_solver(c, n, &w);
-    const unsigned nb = (unsigned)(((int64_t)n + kVecThreads - 1) / kVecThreads);
+    carve_solver(c, n, csr->nnz, &w);
+    const unsigned nbl = (unsigned)(((int64_t)nn * kSpmvLanes + 255) / 256);
+    const unsigned nbn = (unsigned)(((int64_t)nn + 255) / 256);
+    const int block = pc == FEM_PC_BLOCK_JACOBI ? 1 : 0;
+    hipLaunchKernelGGL(node_cols_kernel, dim3(nbl), dim3(256), 0, s, nn, csr->row_ptr, csr->col_idx, w.ncol);
     if (prec == FEM_FP64)
-        hipLaunchKernelGGL(diag_inv_kernel<double>, dim3(nb), dim3(kVecThreads), 0, s, n, csr->row_ptr,
-                           csr->col_idx, static_cast<const double*>(K_vals), w.dinv);
+        hipLaunchKernelGGL(precond_kernel<double>, dim3(nbn), dim3(256), 0, s, nn, csr->row_ptr, w.ncol,
+                           static_cast<const double*>(K_vals), block, w.minv);
     else
-        hipLaunchKernelGGL(diag_inv_kernel<float>, dim3(nb), dim3(kVecThreads), 0, s, n, csr->row_ptr,
-                           csr->col_idx, static_cast<const float*>(K_vals), w.dinv);
-    FEM_HIP_CHECK(dot(n, b, b, w.part, w.sc + S_BB, s));
-    FEM_HIP_CHECK(spmv(csr, K_vals, prec, x, w.y, s));
-    hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(kVecThreads), 0, s, (int64_t)n, b, w.y, w.r, w.rh, w.p, w.v,
-                       w.sc);
-    FEM_HIP_CHECK(dot(n, w.r, w.r, w.part, w.sc + S_RR, s));
-    double hs[2];
-    FEM_HIP_CHECK(hipMemcpyAsync(hs, w.sc + S_RR, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    FEM_HIP_CHECK(hipStreamSynchronize(s));
-    const double bnorm = std::sqrt(hs[1]);
-    double res = (bnorm > 0.0) ? std::sqrt(hs[0]) / bnorm : std::sqrt(hs[0]);
-    if (rel_res) *rel_res = res;
-    if (bnorm == 0.0 && hs[0] == 0.0) return FEM_OK;  // x already solves K x = 0
-    int32_t it = 0;
-    while (res > rtol && it < max_iter) {
-        FEM_HIP_CHECK(dot(n, w.rh, w.r, w.part, w.sc + S_RHO_NEW, s));
-        hipLaunchKernelGGL(update_p, dim3(nb), dim3(kVecThreads), 0, s, (int64_t)n, w.r, w.v, w.dinv, w.p, w.ph,
-                           w.sc);
-        FEM_HIP_CHECK(spmv(csr, K_vals, prec, w.ph, w.v, s));
-        FEM_HIP_CHECK(dot(n, w.rh, w.v, w.part, w.sc + S_RV, s));
-        hipLaunchKernelGGL(update_s, dim3(nb), dim3(kVecThreads), 0, s, (int64_t)n, w.r, w.v, w.dinv, w.s, w.sh,
-                           w.sc);
-        FEM_HIP_CHECK(spmv(csr, K_vals, prec, w.sh, w.t, s));
-        FEM_HIP_CHECK(dot(n, w.t, w.s, w.part, w.sc + S_TS, s));
-        FEM_HIP_CHECK(dot(n, w.t, w.t, w.part, w.sc + S_TT, s));
-        hipLaunchKernelGGL(update_x, dim3(nb), dim3(kVecThreads), 0, s, (int64_t)n, w.ph, w.sh, w.s, w.t, x, w.r,
-                           w.sc);
-        hipLaunchKernelGGL(roll_scalars, dim3(1), dim3(1), 0, s, w.sc);
-        FEM_HIP_CHECK(dot(n, w.r, w.r, w.part, w.sc + S_RR, s));
-        double rr = 0.0, chk[2];
-        FEM_HIP_CHECK(hipMemcpyAsync(&rr, w.sc + S_RR, sizeof(double), hipMemcpyDeviceToHost, s));
-        FEM_HIP_CHECK(hipMemcpyAsync(chk, w.sc + S_RHO, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        FEM_HIP_CHECK(hipStreamSynchronize(s));
-        ++it;
-        res = (bnorm > 0.0) ? std::sqrt(rr) / bnorm : std::sqrt(rr);
-        if (!std::isfinite(res) || chk[0] == 0.0) break;  // breakdown (rho = 0) or non-finite values
+        hipLaunchKernelGGL(precond_kernel<float>, dim3(nbn), dim3(256), 0, s, nn, csr->row_ptr, w.ncol,
+                           static_cast<const float*>(K_vals), block, w.minv);
+    hipLaunchKernelGGL(reset_flags, dim3(1), dim3(1), 0, s, w.fl);
+    spmv_dot<0>(csr, w.ncol, K_vals, prec, x, w.t, nullptr, nullptr, nullptr, nullptr, s);
+    hipLaunchKernelGGL(init_kernel, dim3(kGrid), dim3(256), 0, s, (int64_t)n, b, w.t, w.r, w.rh, w.p, w.v, w.part0,
+                       w.part1);
+    hipLaunchKernelGGL(fin_init, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl, rtol, max_iter);
+    FEM_HIP_CHECK(hipGetLastError());
+    int32_t fl[F_COUNT];
+    double res = 0.0;
+    auto read_back = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(fl, w.fl, sizeof(fl), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&res, w.sc + S_RES, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e;
+    };
+    FEM_HIP_CHECK(read_back());
+    while (!fl[F_STOP] && fl[F_ITER] < max_iter) {
+        const int32_t chunk = std::min<int32_t>(kChunk, max_iter - fl[F_ITER]);
+        for (int32_t k = 0; k < chunk; ++k) {
+            hipLaunchKernelGGL(update_p, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, w.minv, w.p, w.ph, w.sc, w.fl);
+            spmv_dot<1>(csr, w.ncol, K_vals, prec, w.ph, w.v, w.rh, w.part0, nullptr, w.fl, s);
+            hipLaunchKernelGGL(fin_alpha, dim3(1), dim3(256), 0, s, w.part0, w.sc, w.fl);
+            hipLaunchKernelGGL(update_s, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, w.minv, w.s, w.sh, w.sc, w.fl);
+            spmv_dot<2>(csr, w.ncol, K_vals, prec, w.sh, w.t, w.s, w.part0, w.part1, w.fl, s);
+            hipLaunchKernelGGL(fin_omega, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl);
+            hipLaunchKernelGGL(update_x, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.ph, w.sh, w.s, w.t, w.rh, x, w.r,
+                               w.part0, w.part1, w.sc, w.fl);
+            hipLaunchKernelGGL(fin_rho, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl, rtol, max_iter);
+        }
+        FEM_HIP_CHECK(hipGetLastError());
+        FEM_HIP_CHECK(read_back());
     }
-    if (iters) *iters = it;
+    if (iters) *iters = fl[F_ITER];
     if (rel_res) *rel_res = res;
     if (!(res <= rtol))
-        return set_error(FEM_ENOCONV, "fem_solve: relative residual %.3e after %d iterations (rtol %.3e)", res, it,
-                         rtol);
+        return set_error(FEM_ENOCONV, "fem_solve: relative residual %.3e after %d iterations (rtol %.3e)", res,
+                         fl[F_ITER], rtol);
     return FEM_OK;
 }

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfem.so")
 
 FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOMEM, FEM_EOVERFLOW, FEM_EMESH, FEM_ENOCONV = 0, -1, -2, -3, -4, -5, -6
-FP64, FP32_MIXED = 0, 1
+FP64, FP32_MIXED, FP64_K32 = 0, 1, 2
 NPARAM, NGRAD = 11, 7
 MODEL_VOCE, MODEL_FBAR, MODEL_BARLAT = 1, 2, 4  # fem_params.model flags
 KERNEL_FORWARD, KERNEL_VJP, KERNEL_ASSEMBLE_K, KERNEL_ASSEMBLE_R = 0, 1, 2, 3
@@ -90,10 +90,11 @@ def lib():
     L.fem_graph_end.argtypes = [_c_p, ctypes.POINTER(_c_p)]
     L.fem_graph_launch.argtypes = [_c_p, _c_p]
     L.fem_graph_destroy.argtypes = [_c_p]
-    L.fem_solver_workspace_bytes.argtypes = [_c_i32]
+    L.fem_solver_workspace_bytes.argtypes = [_c_i32, ctypes.c_int64]
     L.fem_solver_workspace_bytes.restype = _c_sz
     L.fem_csr_spmv.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
-    L.fem_solve.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_i32, ctypes.c_double,
+    L.fem_solve.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, ctypes.c_int, _c_p, _c_p, _c_i32,
+                            ctypes.c_double,
                             ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double), _c_p, _c_sz, _c_p]
     L.fem_csr_transpose.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
     L.fem_history_adjoint_workspace_bytes.argtypes = [_c_i32, _c_i32]
@@ -123,6 +124,8 @@ def _prec(p):
         return FP64
     if p in (FP32_MIXED, "mixed", "fp32", "fp32_mixed", torch.float32):
         return FP32_MIXED
+    if p in (FP64_K32, "fp64_k32"):
+        return FP64_K32
     raise ValueError(f"unknown precision {p!r}")
 
 
@@ -536,21 +539,27 @@ def csr_spmv(csr, K, x, y=None, stream=None):
     return y
 
 
+PC_JACOBI, PC_BLOCK_JACOBI = 0, 1
+
+
 class Solver:
     """Workspace of fem_solve for a pattern (reused across solves)."""
 
-    def __init__(self, csr, device="cuda"):
+    def __init__(self, csr, device="cuda", precond=PC_BLOCK_JACOBI):
         self.csr = csr
-        self.ws_bytes = lib().fem_solver_workspace_bytes(csr.n_rows)
+        self.precond = int(precond)
+        self.ws_bytes = lib().fem_solver_workspace_bytes(csr.n_rows, csr.nnz)
         self.ws = _ws(self.ws_bytes, device)
 
-    def solve(self, K, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True):
-        """Solve K x = b (BiCGSTAB, Jacobi preconditioner); returns (x, iterations, relative residual)."""
+    def solve(self, K, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True, precond=None):
+        """Solve K x = b (BiCGSTAB; preconditioner PC_BLOCK_JACOBI, the 3x3
+        node blocks, unless given); returns (x, iterations, relative residual)."""
         if x is None:
             x = torch.zeros(self.csr.n_rows, dtype=torch.float64, device=b.device)
         it = _c_i32(0)
         res = ctypes.c_double(0.0)
-        rc = lib().fem_solve(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), _ptr(b), _ptr(x), int(max_iter),
+        pc = self.precond if precond is None else int(precond)
+        rc = lib().fem_solve(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), pc, _ptr(b), _ptr(x), int(max_iter),
                              float(rtol), ctypes.byref(it), ctypes.byref(res), _ptr(self.ws), self.ws_bytes,
                              _stream(stream))
         if check:

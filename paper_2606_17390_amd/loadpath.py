@@ -11,7 +11,11 @@ with the automatic stepping of Sec. 2.4:
   in a row dt grows by `grow`, up to dt_max;
 * convergence: ||R|| <= ftol f_ref, f_ref the largest norm of the reactions
   (the unconstrained residual on the constrained dofs) met so far, or of the
-  first increment's starting residual before any reaction exists.
+  first increment's starting residual before any reaction exists;
+* linear solves to the Eisenstat-Walker tolerance of newton.py (floor
+  lin_rtol) unless forcing is None (then lin_rtol throughout); without an
+  extrapolated start (the first increment) the first solve goes to
+  first_eta, since that direction carries the whole boundary increment.
 
 The performance study of the paper uses dt0 1e-3, dt_min 1e-5, dt_max 5e-2.
 
@@ -30,16 +34,16 @@ def reaction_norm(mesh, csr, params, d, hist, bc, prec=fem.FP64):
     return float(r.R[bc].norm().cpu())
 
 
-def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
+def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
           grow_after=1, cutback=0.5, ftol=1e-6, max_it=20, lin_rtol=1e-6, lin_max_iter=20000, t_end=1.0,
-          max_steps=10000, log=None):
+          max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew", first_eta=1e-4):
     """Returns a dict with the final displacement and history, the accepted
     increments [(t, dt, Newton iterations, linear iterations)], the failed
     increments, the total Newton and linear iterations and the wall time."""
     dev = hist0.device
     bc = bc_mask.bool().view(-1)
     out = fem.Forward(mesh, csr, prec)
-    solver = fem.Solver(csr, dev)
+    solver = fem.Solver(csr, dev, precond=precond)
     d = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
     d_prev, dt_prev = None, None
     h = hist0.clone()
@@ -60,7 +64,8 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64, dt0=1e-3, dt_min
             h_new, its, norms = newton.solve_step(mesh, csr, params, trial, h, bc_mask, prec=prec,
                                                   tol=ftol if f_ref == 0.0 else 0.0, atol=ftol * f_ref,
                                                   max_it=max_it, lin_rtol=lin_rtol, lin_max_iter=lin_max_iter,
-                                                  solver=solver, out=out, trace=trace)
+                                                  solver=solver, out=out, trace=trace, forcing=forcing,
+                                                  eta0=None if d_prev is not None else first_eta)
         except RuntimeError as err:
             failed.append((t, dt, str(err)))
             if log:

@@ -16,6 +16,13 @@ lin_rtol (stagnation of BiCGSTAB at its attainable accuracy): an inexact
 direction only slows Newton down, so any finite solve with a relative
 residual below 1e-3 is used.
 
+With forcing="ew" the linear tolerance follows the Eisenstat-Walker rule
+(their choice 2, gamma 0.9, exponent 2): eta_k = 0.9 (||R_k|| /
+||R_k-1||)^2, safeguarded by 0.9 eta_k-1^2 when that exceeds 0.1, capped at
+eta_max, and never tighter than lin_rtol or than half the distance to the
+Newton target: the early, far-from-converged iterations get loose solves.
+The first iteration uses eta0 (default eta_max).
+
 Every step runs in the library (residual, tangent, assembly, linear solve);
 this module only sequences the calls and reads the residual norm back.
 """
@@ -26,7 +33,7 @@ from . import fem
 
 def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, max_it=30, lin_rtol=1e-10,
                lin_max_iter=5000, solver=None, out=None, stream=None, line_search=True, max_backtracks=8, atol=0.0,
-               trace=None):
+               trace=None, forcing=None, eta_max=0.1, eta0=None):
     """Newton iteration on d (device [n_nodes][3], updated in place) until
     ||R|| <= max(tol ||R_0||, atol).  Returns (hist_np1, iterations, list of
     ||R||).  Raises RuntimeError if the tolerance is not reached in max_it
@@ -53,8 +60,20 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
             return out.hist.clone(), it, norms
         if it == max_it:
             break
-        du, lin_its, res = solver.solve(out.K, -out.R, rtol=lin_rtol, max_iter=lin_max_iter, stream=stream, check=False)
-        if not (res <= 1e-3):
+        rt = lin_rtol
+        if forcing == "ew":
+            if it == 0:
+                eta = eta_max if eta0 is None else eta0
+            else:
+                e = 0.9 * (rn / norms[-2]) ** 2
+                if 0.9 * eta * eta > 0.1:
+                    e = max(e, 0.9 * eta * eta)
+                eta = min(eta_max, e)
+            rt = max(lin_rtol, min(eta_max, max(eta, 0.5 * max(tol * norms[0], atol) / rn)))
+        elif forcing is not None:
+            raise ValueError(f"forcing must be None or 'ew', not {forcing!r}")
+        du, lin_its, res = solver.solve(out.K, -out.R, rtol=rt, max_iter=lin_max_iter, stream=stream, check=False)
+        if not (res <= max(1e-3, rt)):
             raise RuntimeError(f"Newton: linear solve reached only a relative residual of {res:.3e}")
         base = flat.clone()
         t = 1.0

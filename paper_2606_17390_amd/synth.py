@@ -432,15 +432,19 @@ def hill_from_r(r11, r22, r33, r12, r13, r23):
                 L=1.5 / r23 ** 2, M=1.5 / r13 ** 2, N=1.5 / r12 ** 2)
 
 
-def unit_cube_forward(n=100, nu=NU_DEFAULT):
+def unit_cube_forward(n=100, ny=None, nz=None, nu=NU_DEFAULT):
     """The forward-simulation benchmark of the paper's performance study: the
     unit cube [0, 1]^3 mm in n^3 hex8 elements, Hill-48 with the yield-stress
     ratios r11..r23 = 1.5449, 1.0666, 1, 1.0307, 1, 1 and Voce hardening
     sigma0 = 138, Q = 410 MPa, b = 3.8, E = 219 GPa (nu not given: 0.3);
     the x = 0 face fixed, the x = 1 face moved by t (0.2, 0.1) mm in (x, y),
-    its z motion free.  Returns the Problem at t = 0 (hardening "voce") and
-    the prescribed values at load factor t via meta["bc_at"](t)."""
-    X, conn = hex_grid(n, n, n, 1.0, 1.0, 1.0)
+    its z motion free.  n x ny x nz elements (ny, nz default to n; the
+    larger run of the study is 250 x 150 x 120).  Returns the Problem at
+    t = 0 (hardening "voce") and the prescribed values at load factor t via
+    meta["bc_at"](t)."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    X, conn = hex_grid(n, ny, nz, 1.0, 1.0, 1.0)
     hp = hill_from_r(1.5449, 1.0666, 1.0, 1.0307, 1.0, 1.0)
     prm = voce_params(sig0=138.0, Q=410.0, b=3.8, E=219000.0, nu=nu, **hp)
     left, right = np.isclose(X[:, 0], 0.0), np.isclose(X[:, 0], 1.0)
@@ -456,8 +460,8 @@ def unit_cube_forward(n=100, nu=NU_DEFAULT):
         return u
 
     ne = conn.shape[0]
-    return Problem(f"unit_cube_{n}", X, conn, np.zeros_like(X), np.zeros((7, 8 * ne)), prm, bc.ravel(), None,
-                   dict(nx=n, ny=n, nz=n, bc_at=bc_at), hardening="voce")
+    return Problem(f"unit_cube_{n}x{ny}x{nz}", X, conn, np.zeros_like(X), np.zeros((7, 8 * ne)), prm, bc.ravel(),
+                   None, dict(nx=n, ny=ny, nz=nz, bc_at=bc_at), hardening="voce")
 
 
 def small_slab(seed, nx, ny, nz, per_element=False, strain=0.05, jitter=0.05, alpha_max=0.1):

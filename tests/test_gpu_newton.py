@@ -80,21 +80,54 @@ def test_spmv_long_rows_matches_scipy(fem, prec_name):
     assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("pc", ["PC_JACOBI", "PC_BLOCK_JACOBI"])
 @pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
-def test_solve_matches_dense_solve(fem, prec_name):
+def test_solve_matches_dense_solve(fem, prec_name, pc):
     csr, out = system(fem, getattr(fem, prec_name))
     A = dense(csr, out.K).toarray()
     b = np.random.default_rng(4).standard_normal(csr.n_rows)
-    say(f"solve {prec_name}: n {csr.n_rows}")
-    s = fem.Solver(csr)
+    say(f"solve {prec_name} {pc}: n {csr.n_rows}")
+    s = fem.Solver(csr, precond=getattr(fem, pc))
     x, its, res = s.solve(out.K, torch.as_tensor(b).cuda(), rtol=1e-12)
     torch.cuda.synchronize()
     ref = np.linalg.solve(A, b)
     assert res <= 1e-12 and its > 0
     assert np.abs(x.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
+    # the recursive residual is the true one to rounding
+    assert np.linalg.norm(b - A @ x.cpu().numpy()) <= 1e-9 * np.linalg.norm(b)
     # the same solve again is bitwise the same (fixed-order reductions)
     x2, its2, _ = s.solve(out.K, torch.as_tensor(b).cuda(), rtol=1e-12)
     assert its2 == its and torch.equal(x, x2)
+
+
+def test_fp64_k32_pass_is_fp64_with_a_float_tangent(fem):
+    """FEM_FP64_K32: R, history and norm bitwise those of the FP64 pass; K the
+    FP64 tangent to float rounding."""
+    p = synth.small_slab(53, 5, 4, 3)
+    mesh, params, d, h, bc, _ = gpu_problem(p, fem)
+    csr = fem.csr_pattern(mesh)
+    a = fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP64)
+    b = fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP64_K32)
+    torch.cuda.synchronize()
+    say(f"fp64_k32: nnz {csr.nnz}")
+    assert b.K.dtype == torch.float32
+    assert torch.equal(a.R, b.R) and torch.equal(a.hist, b.hist) and torch.equal(a.rnorm2, b.rnorm2)
+    assert torch.equal(a.diag, b.diag)
+    err = float(((b.K.double() - a.K).abs().max() / a.K.abs().max()).cpu())
+    assert err <= 1e-6
+
+
+def test_solve_initial_guess_and_zero_rhs(fem):
+    """A converged initial guess takes no iteration; b = 0 with x = 0 is solved by x = 0."""
+    csr, out = system(fem, fem.FP64)
+    b = torch.as_tensor(np.random.default_rng(6).standard_normal(csr.n_rows)).cuda()
+    s = fem.Solver(csr)
+    x, its, _ = s.solve(out.K, b, rtol=1e-12)
+    x2, its2, res2 = s.solve(out.K, b, x=x.clone(), rtol=1e-8)
+    assert its > 0 and its2 == 0 and res2 <= 1e-8
+    z, its3, res3 = s.solve(out.K, torch.zeros_like(b), rtol=1e-12)
+    torch.cuda.synchronize()
+    assert its3 == 0 and res3 == 0.0 and not z.any()
 
 
 def test_solve_reports_no_convergence(fem):
@@ -109,6 +142,7 @@ def test_solve_reports_no_convergence(fem):
 
 @pytest.mark.parametrize("prec_name,tol,atol,variant", [("FP64", 1e-10, 1e-9, "plain"),
                                                         ("FP32_MIXED", 1e-6, 1e-5, "plain"),
+                                                        ("FP64_K32", 1e-10, 1e-9, "plain"),
                                                         ("FP64", 1e-10, 1e-9, "fbar_voce")])
 def test_uniaxial_tension_newton_matches_one_dimensional_solution(fem, prec_name, tol, atol, variant):
     """The homogeneous field makes F-bar reduce to the plain element (its
