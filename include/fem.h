@@ -270,9 +270,17 @@ int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_par
  * fem_residual_tangent); x, y device [n_rows] doubles (not aliased).  Errors:
  * FEM_EINVAL, FEM_EHIP.
  *
- * fem_solve -- K x = b by BiCGSTAB (the linear solve of the global Newton
- * iteration, Sec. 2.2.4 / Eq. (Stiffness_mat); the paper's default Krylov
- * method of Sec. 2.4), right-preconditioned by M:
+ * fem_solve -- K x = b (the linear solve of the global Newton iteration,
+ * Sec. 2.2.4 / Eq. (Stiffness_mat); Sec. 2.4 lists CG and BiCGSTAB) by
+ *   FEM_KRYLOV_BICGSTAB  BiCGSTAB, right-preconditioned by M (any K)
+ *   FEM_KRYLOV_CG        preconditioned conjugate gradients, for a K that is
+ *                        symmetric positive definite on the free dofs (the
+ *                        tangent without F-bar) with identity rows on the
+ *                        constrained ones, and x = b there on entry (the
+ *                        Newton correction: both zero); the iterates then
+ *                        stay on the free-free block.  Ends (FEM_ENOCONV) if
+ *                        a search direction has p.Kp <= 0.
+ * with the preconditioner M:
  *   FEM_PC_JACOBI        M = inverse of the diagonal of K
  *   FEM_PC_BLOCK_JACOBI  M = inverses of the 3x3 node blocks K[3I+a][3I+b]
  *                        (a singular block falls back to its diagonal)
@@ -288,17 +296,19 @@ int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_par
  * The reductions are fixed-order (bitwise reproducible).  The iteration state
  * stays on the device; the host reads the stop flag once per 32 iterations
  * (one stream synchronisation each).  A breakdown (a zero inner product) or
- * a non-finite residual ends the iteration.
+ * a non-finite residual ends the iteration.  ||b - K x|| is the recursive
+ * residual of the method.
  * Returns FEM_ENOCONV if rtol is not reached (x holds the last iterate).
  * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOCONV.
  */
 typedef enum { FEM_PC_JACOBI = 0, FEM_PC_BLOCK_JACOBI = 1 } fem_precond;
+typedef enum { FEM_KRYLOV_BICGSTAB = 0, FEM_KRYLOV_CG = 1 } fem_krylov;
 size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz);
 int fem_csr_spmv(const fem_csr *csr, const void *K_vals, fem_precision prec, const double *x, double *y,
                  void *stream);
-int fem_solve(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_precond pc, const double *b,
-              double *x, int32_t max_iter, double rtol, int32_t *iters, double *rel_res, void *ws,
-              size_t ws_bytes, void *stream);
+int fem_solve(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_krylov method, fem_precond pc,
+              const double *b, double *x, int32_t max_iter, double rtol, int32_t *iters, double *rel_res,
+              void *ws, size_t ws_bytes, void *stream);
 
 /*
  * fem_csr_transpose -- KT_vals = values of K^T on the same pattern (the

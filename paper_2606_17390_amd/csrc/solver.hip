@@ -1,7 +1,8 @@
 // solver.hip -- the linear solve of the global Newton iteration (Sec. 2.2.4:
 // K du = -R with the Dirichlet rows of App. E replaced by identity rows, so
-// K is not symmetric): CSR matrix-vector product and BiCGSTAB, preconditioned
-// by the inverse diagonal of K or by the inverses of its 3x3 node blocks.
+// K is not symmetric): CSR matrix-vector product, BiCGSTAB, and conjugate
+// gradients for a symmetric tangent, preconditioned by the inverse diagonal
+// of K or by the inverses of its 3x3 node blocks.
 //
 // The matrix is the CSR pattern of fem_csr_pattern (rows 3I+a; the three
 // rows of a node are consecutive and share their sorted column list, which
@@ -406,8 +407,138 @@ __global__ __launch_bounds__(256) void fin_rho(const double* __restrict__ part0,
     }
 }
 
+// ---- preconditioned conjugate gradients (symmetric K: the tangent without
+// F-bar; identity rows of constrained dofs with x = b = 0 there keep every
+// iterate zero on them, so the iteration runs on the free-free block)
+
+// r = b - y; z = M r; p = z; part0 = partials of (r, z), part1 = of (r, r),
+// part2 = of (b, b)   (one thread per node)
+__global__ __launch_bounds__(256) void cg_init(int32_t n_nodes, const double* __restrict__ b,
+                                               const double* __restrict__ y, const double* __restrict__ minv,
+                                               double* __restrict__ r, double* __restrict__ z,
+                                               double* __restrict__ p, double* __restrict__ part0,
+                                               double* __restrict__ part1, double* __restrict__ part2) {
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    for (int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x; I < n_nodes; I += (int64_t)kGrid * 256) {
+        double q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double bi = b[3 * I + a];
+            q[a] = bi - y[3 * I + a];
+            r[3 * I + a] = q[a];
+            rr += q[a] * q[a];
+            bb += bi * bi;
+        }
+        apply_minv(minv, I, q, z);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double zi = z[3 * I + a];
+            p[3 * I + a] = zi;
+            rz += q[a] * zi;
+        }
+    }
+    const double t0 = block_sum(rz), t1 = block_sum(rr), t2 = block_sum(bb);
+    if (threadIdx.x == 0) {
+        part0[blockIdx.x] = t0;
+        part1[blockIdx.x] = t1;
+        part2[blockIdx.x] = t2;
+    }
+}
+
+__global__ __launch_bounds__(256) void cg_fin_init(const double* __restrict__ part0, const double* __restrict__ part1,
+                                                   const double* __restrict__ part2, double* __restrict__ sc,
+                                                   int32_t* __restrict__ fl, double rtol, int32_t max_iter) {
+    const double rz = sum_parts(part0, kGrid);
+    const double rr = sum_parts(part1, kGrid);
+    const double bb = sum_parts(part2, kGrid);
+    if (threadIdx.x == 0) {
+        const double res = rel_of(rr, bb);
+        sc[S_RHO] = rz;
+        sc[S_RR] = rr;
+        sc[S_BB] = bb;
+        sc[S_RES] = res;
+        fl[F_ITER] = 0;
+        fl[F_STOP] = (res <= rtol || !isfinite(res) || max_iter <= 0 || rz == 0.0) ? 1 : 0;
+    }
+}
+
+// alpha = rho / (p, K p); stop if (p, K p) <= 0 (K not positive definite on
+// the search space) or alpha is not finite
+__global__ __launch_bounds__(256) void cg_fin_alpha(const double* __restrict__ part0, double* __restrict__ sc,
+                                                    int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    const double pq = sum_parts(part0, kSpmvGrid);
+    if (threadIdx.x == 0) {
+        const double alpha = sc[S_RHO] / pq;
+        if (!(pq > 0.0) || !isfinite(alpha)) fl[F_STOP] = 1;
+        else sc[S_ALPHA] = alpha;
+    }
+}
+
+// x += alpha p; r -= alpha q; z = M r; part0 = partials of (r, z), part1 =
+// of (r, r)   (one thread per node)
+__global__ __launch_bounds__(256) void cg_update(int32_t n_nodes, const double* __restrict__ p,
+                                                 const double* __restrict__ q, const double* __restrict__ minv,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 double* __restrict__ z, double* __restrict__ part0,
+                                                 double* __restrict__ part1, const double* __restrict__ sc,
+                                                 const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    const double alpha = sc[S_ALPHA];
+    double rz = 0.0, rr = 0.0;
+    for (int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x; I < n_nodes; I += (int64_t)kGrid * 256) {
+        double ri[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            x[3 * I + a] += alpha * p[3 * I + a];
+            ri[a] = r[3 * I + a] - alpha * q[3 * I + a];
+            r[3 * I + a] = ri[a];
+            rr += ri[a] * ri[a];
+        }
+        const double* m = minv + 9 * I;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double zi = m[3 * a] * ri[0] + m[3 * a + 1] * ri[1] + m[3 * a + 2] * ri[2];
+            z[3 * I + a] = zi;
+            rz += ri[a] * zi;
+        }
+    }
+    const double t0 = block_sum(rz), t1 = block_sum(rr);
+    if (threadIdx.x == 0) {
+        part0[blockIdx.x] = t0;
+        part1[blockIdx.x] = t1;
+    }
+}
+
+// end of a CG iteration: beta = rho_new / rho, the residual, stop tests
+__global__ __launch_bounds__(256) void cg_fin_beta(const double* __restrict__ part0, const double* __restrict__ part1,
+                                                   double* __restrict__ sc, int32_t* __restrict__ fl, double rtol,
+                                                   int32_t max_iter) {
+    if (fl[F_STOP]) return;
+    const double rz = sum_parts(part0, kGrid);
+    const double rr = sum_parts(part1, kGrid);
+    if (threadIdx.x == 0) {
+        const double res = rel_of(rr, sc[S_BB]);
+        const int32_t it = fl[F_ITER] + 1;
+        sc[S_BETA] = rz / sc[S_RHO];
+        sc[S_RHO] = rz;
+        sc[S_RR] = rr;
+        sc[S_RES] = res;
+        fl[F_ITER] = it;
+        if (res <= rtol || !isfinite(res) || rz == 0.0 || it >= max_iter) fl[F_STOP] = 1;
+    }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(256) void cg_update_p(int64_t n, const double* __restrict__ z, double* __restrict__ p,
+                                                   const double* __restrict__ sc, const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    const double beta = sc[S_BETA];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kGrid * 256) p[i] = z[i] + beta * p[i];
+}
+
 struct SolverWs {
-    double *r, *rh, *p, *ph, *v, *s, *sh, *t, *minv, *part0, *part1, *sc;
+    double *r, *rh, *p, *ph, *v, *s, *sh, *t, *minv, *part0, *part1, *part2, *sc;
     int32_t *ncol, *fl;
 };
 
@@ -425,6 +556,7 @@ void carve_solver(C& c, int32_t n, int64_t nnz, SolverWs* w) {
     o.minv = c.template take<double>(3 * (size_t)n + 1);
     o.part0 = c.template take<double>(kParts);
     o.part1 = c.template take<double>(kParts);
+    o.part2 = c.template take<double>(kParts);
     o.sc = c.template take<double>(S_COUNT);
     o.ncol = c.template take<int32_t>((size_t)(nnz / 9) + 1);
     o.fl = c.template take<int32_t>(F_COUNT);
@@ -518,13 +650,15 @@ extern "C" int fem_csr_transpose(const fem_csr* csr, const void* K_vals, fem_pre
     return FEM_OK;
 }
 
-extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision prec, fem_precond pc,
-                         const double* b, double* x, int32_t max_iter, double rtol, int32_t* iters, double* rel_res,
+extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision prec, fem_krylov method,
+                         fem_precond pc, const double* b, double* x, int32_t max_iter, double rtol, int32_t* iters, double* rel_res,
                          void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (int rc = check_csr(csr, K_vals, "fem_solve")) return rc;
     if (prec != FEM_FP64 && prec != FEM_FP32_MIXED) return set_error(FEM_EINVAL, "fem_solve: bad precision");
     if (pc != FEM_PC_JACOBI && pc != FEM_PC_BLOCK_JACOBI) return set_error(FEM_EINVAL, "fem_solve: bad preconditioner");
+    if (method != FEM_KRYLOV_BICGSTAB && method != FEM_KRYLOV_CG)
+        return set_error(FEM_EINVAL, "fem_solve: bad Krylov method");
     if (max_iter < 0 || !(rtol >= 0.0)) return set_error(FEM_EINVAL, "fem_solve: max_iter >= 0 and rtol >= 0");
     const int32_t n = csr->n_rows, nn = n / 3;
     if (iters) *iters = 0;
@@ -551,9 +685,17 @@ extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision p
                            static_cast<const float*>(K_vals), block, w.minv);
     hipLaunchKernelGGL(reset_flags, dim3(1), dim3(1), 0, s, w.fl);
     spmv_dot<0>(csr, w.ncol, K_vals, prec, x, w.t, nullptr, nullptr, nullptr, nullptr, s);
-    hipLaunchKernelGGL(init_kernel, dim3(kGrid), dim3(256), 0, s, (int64_t)n, b, w.t, w.r, w.rh, w.p, w.v, w.part0,
-                       w.part1);
-    hipLaunchKernelGGL(fin_init, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl, rtol, max_iter);
+    const bool cg = method == FEM_KRYLOV_CG;
+    if (cg) {
+        hipLaunchKernelGGL(cg_init, dim3(kGrid), dim3(256), 0, s, nn, b, w.t, w.minv, w.r, w.s, w.p, w.part0, w.part1,
+                           w.part2);
+        hipLaunchKernelGGL(cg_fin_init, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.part2, w.sc, w.fl, rtol,
+                           max_iter);
+    } else {
+        hipLaunchKernelGGL(init_kernel, dim3(kGrid), dim3(256), 0, s, (int64_t)n, b, w.t, w.r, w.rh, w.p, w.v,
+                           w.part0, w.part1);
+        hipLaunchKernelGGL(fin_init, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl, rtol, max_iter);
+    }
     FEM_HIP_CHECK(hipGetLastError());
     int32_t fl[F_COUNT];
     double res = 0.0;
@@ -566,7 +708,15 @@ extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision p
     FEM_HIP_CHECK(read_back());
     while (!fl[F_STOP] && fl[F_ITER] < max_iter) {
         const int32_t chunk = std::min<int32_t>(kChunk, max_iter - fl[F_ITER]);
-        for (int32_t k = 0; k < chunk; ++k) {
+        for (int32_t k = 0; cg && k < chunk; ++k) {
+            spmv_dot<1>(csr, w.ncol, K_vals, prec, w.p, w.v, w.p, w.part0, nullptr, w.fl, s);
+            hipLaunchKernelGGL(cg_fin_alpha, dim3(1), dim3(256), 0, s, w.part0, w.sc, w.fl);
+            hipLaunchKernelGGL(cg_update, dim3(kGrid), dim3(256), 0, s, nn, w.p, w.v, w.minv, x, w.r, w.s, w.part0,
+                               w.part1, w.sc, w.fl);
+            hipLaunchKernelGGL(cg_fin_beta, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl, rtol, max_iter);
+            hipLaunchKernelGGL(cg_update_p, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.s, w.p, w.sc, w.fl);
+        }
+        for (int32_t k = 0; !cg && k < chunk; ++k) {
             hipLaunchKernelGGL(update_p, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, w.minv, w.p, w.ph, w.sc, w.fl);
             spmv_dot<1>(csr, w.ncol, K_vals, prec, w.ph, w.v, w.rh, w.part0, nullptr, w.fl, s);
             hipLaunchKernelGGL(fin_alpha, dim3(1), dim3(256), 0, s, w.part0, w.sc, w.fl);

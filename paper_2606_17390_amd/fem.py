@@ -93,8 +93,8 @@ def lib():
     L.fem_solver_workspace_bytes.argtypes = [_c_i32, ctypes.c_int64]
     L.fem_solver_workspace_bytes.restype = _c_sz
     L.fem_csr_spmv.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
-    L.fem_solve.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, ctypes.c_int, _c_p, _c_p, _c_i32,
-                            ctypes.c_double,
+    L.fem_solve.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_p, _c_p,
+                            _c_i32, ctypes.c_double,
                             ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double), _c_p, _c_sz, _c_p]
     L.fem_csr_transpose.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
     L.fem_history_adjoint_workspace_bytes.argtypes = [_c_i32, _c_i32]
@@ -540,26 +540,30 @@ def csr_spmv(csr, K, x, y=None, stream=None):
 
 
 PC_JACOBI, PC_BLOCK_JACOBI = 0, 1
+KRYLOV = {"bicgstab": 0, "cg": 1}
 
 
 class Solver:
     """Workspace of fem_solve for a pattern (reused across solves)."""
 
-    def __init__(self, csr, device="cuda", precond=PC_BLOCK_JACOBI):
+    def __init__(self, csr, device="cuda", precond=PC_BLOCK_JACOBI, method="bicgstab"):
         self.csr = csr
         self.precond = int(precond)
+        self.method = KRYLOV[method]
         self.ws_bytes = lib().fem_solver_workspace_bytes(csr.n_rows, csr.nnz)
         self.ws = _ws(self.ws_bytes, device)
 
-    def solve(self, K, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True, precond=None):
-        """Solve K x = b (BiCGSTAB; preconditioner PC_BLOCK_JACOBI, the 3x3
-        node blocks, unless given); returns (x, iterations, relative residual)."""
+    def solve(self, K, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True, precond=None, method=None):
+        """Solve K x = b (method "bicgstab", or "cg" for a tangent symmetric
+        on the free dofs; preconditioner PC_BLOCK_JACOBI, the 3x3 node blocks,
+        unless given); returns (x, iterations, relative residual)."""
         if x is None:
             x = torch.zeros(self.csr.n_rows, dtype=torch.float64, device=b.device)
         it = _c_i32(0)
         res = ctypes.c_double(0.0)
         pc = self.precond if precond is None else int(precond)
-        rc = lib().fem_solve(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), pc, _ptr(b), _ptr(x), int(max_iter),
+        mt = self.method if method is None else KRYLOV[method]
+        rc = lib().fem_solve(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), mt, pc, _ptr(b), _ptr(x), int(max_iter),
                              float(rtol), ctypes.byref(it), ctypes.byref(res), _ptr(self.ws), self.ws_bytes,
                              _stream(stream))
         if check:

@@ -12,7 +12,9 @@ with the automatic stepping of Sec. 2.4:
 * convergence: ||R|| <= ftol f_ref, f_ref the largest norm of the reactions
   (the unconstrained residual on the constrained dofs) met so far, or of the
   first increment's starting residual before any reaction exists;
-* linear solves to the Eisenstat-Walker tolerance of newton.py (floor
+* linear solves by conjugate gradients where the tangent is symmetric (every
+  model but F-bar; BiCGSTAB for F-bar, and where CG meets a direction of
+  non-positive curvature), to the Eisenstat-Walker tolerance of newton.py (floor
   lin_rtol) unless forcing is None (then lin_rtol throughout); without an
   extrapolated start (the first increment) the first solve goes to
   first_eta, since that direction carries the whole boundary increment.
@@ -35,22 +37,26 @@ def reaction_norm(mesh, csr, params, d, hist, bc, prec=fem.FP64):
 
 
 def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
-          grow_after=1, cutback=0.5, ftol=1e-6, max_it=20, lin_rtol=1e-6, lin_max_iter=20000, t_end=1.0,
-          max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew", first_eta=1e-4):
+          grow_after=1, cutback=0.5, ftol=1e-6, max_it=15, lin_rtol=1e-6, lin_max_iter=20000, t_end=1.0,
+          max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew", first_eta=1e-4, krylov="auto",
+          line_search=True):
     """Returns a dict with the final displacement and history, the accepted
     increments [(t, dt, Newton iterations, linear iterations)], the failed
-    increments, the total Newton and linear iterations and the wall time."""
+    increments, the total Newton and linear iterations, the wall time and
+    the part of it spent in linear solves."""
     dev = hist0.device
     bc = bc_mask.bool().view(-1)
     out = fem.Forward(mesh, csr, prec)
-    solver = fem.Solver(csr, dev, precond=precond)
+    if krylov == "auto":
+        krylov = "bicgstab" if params.model & fem.MODEL_FBAR else "cg"
+    solver = fem.Solver(csr, dev, precond=precond, method=krylov)
     d = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
     d_prev, dt_prev = None, None
     h = hist0.clone()
     u1f = u1.reshape(-1)
     t, dt = 0.0, dt0
     f_ref = 0.0
-    steps, failed, newton_its, lin_its, streak = [], [], 0, 0, 0
+    steps, failed, newton_its, lin_its, streak, lin_s = [], [], 0, 0, 0, 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while t < t_end * (1 - 1e-12) and len(steps) < max_steps:
@@ -65,7 +71,8 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
                                                   tol=ftol if f_ref == 0.0 else 0.0, atol=ftol * f_ref,
                                                   max_it=max_it, lin_rtol=lin_rtol, lin_max_iter=lin_max_iter,
                                                   solver=solver, out=out, trace=trace, forcing=forcing,
-                                                  eta0=None if d_prev is not None else first_eta)
+                                                  eta0=None if d_prev is not None else first_eta,
+                                                  line_search=line_search)
         except RuntimeError as err:
             failed.append((t, dt, str(err)))
             if log:
@@ -77,6 +84,7 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
             continue
         finally:
             lin_its += sum(x[0] for x in trace)
+            lin_s += sum(x[3] for x in trace)
         d_prev, dt_prev = d, dt
         d, h = trial, h_new
         t += dt
@@ -85,12 +93,14 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
         f_ref = max(f_ref, f_reac)
         steps.append((t, dt, its, sum(x[0] for x in trace)))
         if log:
-            log(f"t={t:.5f} dt={dt:.2e} Newton {its} ||R|| {norms[0]:.2e} -> {norms[-1]:.2e} "
-                f"reaction {f_reac:.3e} linear {[x[0] for x in trace]} steps {[x[2] for x in trace]}")
+            log(f"t={t:.5f} dt={dt:.2e} Newton {its} reaction {f_reac:.3e} ||R|| "
+                + " ".join(f"{r:.1e}" for r in norms)
+                + " | linear " + " ".join(f"{x[0]}@{x[4]:.0e}" for x in trace)
+                + " | steps " + " ".join(f"{x[2]:g}" for x in trace))
         streak += 1
         if streak >= grow_after:
             dt = min(dt * grow, dt_max)
             streak = 0
     torch.cuda.synchronize()
     return dict(d=d, hist=h, steps=steps, failed=failed, newton_iterations=newton_its, linear_iterations=lin_its,
-                seconds=time.perf_counter() - t0)
+                linear_seconds=lin_s, seconds=time.perf_counter() - t0)

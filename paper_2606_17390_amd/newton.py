@@ -21,12 +21,15 @@ With forcing="ew" the linear tolerance follows the Eisenstat-Walker rule
 ||R_k-1||)^2, safeguarded by 0.9 eta_k-1^2 when that exceeds 0.1, capped at
 eta_max, and never tighter than lin_rtol or than half the distance to the
 Newton target: the early, far-from-converged iterations get loose solves.
-The first iteration uses eta0 (default eta_max).
+The first iteration uses eta0 (default eta_max).  forcing="const" keeps
+eta_max throughout (the same floors): Newton then contracts by about eta_max
+per iteration, for solves that stop at the cheap first decades.
 
 Every step runs in the library (residual, tangent, assembly, linear solve);
 this module only sequences the calls and reads the residual norm back.
 """
 import math
+import time
 
 from . import fem
 
@@ -39,7 +42,8 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
     ||R||).  Raises RuntimeError if the tolerance is not reached in max_it
     iterations, a linear solve fails or ||R|| is not finite.  A list passed
     as trace receives one (linear iterations, linear relative residual, step
-    length) tuple per Newton iteration."""
+    length, seconds in the linear solve, linear tolerance) tuple per Newton
+    iteration."""
     if out is None:
         out = fem.Forward(mesh, csr, prec)
     if solver is None:
@@ -61,9 +65,11 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
         if it == max_it:
             break
         rt = lin_rtol
-        if forcing == "ew":
+        if forcing in ("ew", "const"):
             if it == 0:
                 eta = eta_max if eta0 is None else eta0
+            elif forcing == "const":
+                eta = eta_max
             else:
                 e = 0.9 * (rn / norms[-2]) ** 2
                 if 0.9 * eta * eta > 0.1:
@@ -71,8 +77,15 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
                 eta = min(eta_max, e)
             rt = max(lin_rtol, min(eta_max, max(eta, 0.5 * max(tol * norms[0], atol) / rn)))
         elif forcing is not None:
-            raise ValueError(f"forcing must be None or 'ew', not {forcing!r}")
+            raise ValueError(f"forcing must be None, 'ew' or 'const', not {forcing!r}")
+        t_lin = time.perf_counter()
         du, lin_its, res = solver.solve(out.K, -out.R, rtol=rt, max_iter=lin_max_iter, stream=stream, check=False)
+        if not (res <= max(1e-3, rt)) and solver.method == fem.KRYLOV["cg"]:
+            # CG stops on a direction of non-positive curvature: BiCGSTAB instead
+            du, its2, res = solver.solve(out.K, -out.R, rtol=rt, max_iter=lin_max_iter, stream=stream, check=False,
+                                         method="bicgstab")
+            lin_its += its2
+        t_lin = time.perf_counter() - t_lin
         if not (res <= max(1e-3, rt)):
             raise RuntimeError(f"Newton: linear solve reached only a relative residual of {res:.3e}")
         base = flat.clone()
@@ -85,6 +98,6 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
                 break
             t *= 0.5
         if trace is not None:
-            trace.append((lin_its, res, t))
+            trace.append((lin_its, res, t, t_lin, rt))
         rn = rn_new
     raise RuntimeError(f"Newton: ||R|| = {norms[-1]:.3e} after {max_it} iterations (start {norms[0]:.3e})")
