@@ -141,7 +141,7 @@ PAPER_FORWARD_S = {(100, 100, 100): 2030.0}
 
 
 def forward_benchmark(spec, torch, fem, synth):
-    """The unit-cube forward simulation of the performance study (Hill-48
+    """The unit-cube forward simulation of the performance study, Sec. 3.1.3 (Hill-48
     from the r-values, Voce, x = 0 clamped, x = 1 moved by t (0.2, 0.1) mm)
     through the adaptive load path: FP64 residual and history, float tangent
     for the Krylov solve, BiCGSTAB with 3x3 node-block Jacobi and

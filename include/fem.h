@@ -271,7 +271,7 @@ int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_par
  * FEM_EINVAL, FEM_EHIP.
  *
  * fem_solve -- K x = b (the linear solve of the global Newton iteration,
- * Sec. 2.2.4 / Eq. (Stiffness_mat); Sec. 2.4 lists CG and BiCGSTAB) by
+ * Sec. 2.2.4 / Eq. (Stiffness_mat); Sec. 2.2.5 lists CG and BiCGSTAB) by
  *   FEM_KRYLOV_BICGSTAB  BiCGSTAB, right-preconditioned by M (any K)
  *   FEM_KRYLOV_CG        preconditioned conjugate gradients, for a K that is
  *                        symmetric positive definite on the free dofs (the

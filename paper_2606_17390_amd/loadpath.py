@@ -1,7 +1,7 @@
 """Quasi-static load path on the GPU: load factor t from 0 to t_end in
 adaptive increments, each solved by the damped Newton iteration of newton.py
 (Sec. 2.2.4: R(d; h_n) = 0 with the history of the last converged increment),
-with the automatic stepping of Sec. 2.4:
+with the automatic stepping of Sec. 2.2.5:
 
 * prescribed values t u1 on the constrained dofs (a load proportional to t);
 * the Newton start of an increment is the linear extrapolation of the two
@@ -19,7 +19,7 @@ with the automatic stepping of Sec. 2.4:
   extrapolated start (the first increment) the first solve goes to
   first_eta, since that direction carries the whole boundary increment.
 
-The performance study of the paper uses dt0 1e-3, dt_min 1e-5, dt_max 5e-2.
+The performance study of Sec. 3.1.3 uses dt0 1e-3, dt_min 1e-5, dt_max 5e-2.
 
     res = loadpath.solve(mesh, csr, params, bc_mask, u1, hist0)
 """

@@ -433,7 +433,7 @@ def hill_from_r(r11, r22, r33, r12, r13, r23):
 
 
 def unit_cube_forward(n=100, ny=None, nz=None, nu=NU_DEFAULT):
-    """The forward-simulation benchmark of the paper's performance study: the
+    """The forward-simulation benchmark of the performance study (Sec. 3.1.3): the
     unit cube [0, 1]^3 mm in n^3 hex8 elements, Hill-48 with the yield-stress
     ratios r11..r23 = 1.5449, 1.0666, 1, 1.0307, 1, 1 and Voce hardening
     sigma0 = 138, Q = 410 MPa, b = 3.8, E = 219 GPa (nu not given: 0.3);
