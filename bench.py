@@ -143,6 +143,38 @@ PAPER_FORWARD_S = {
 }
 
 
+def elastic_solve(csr, torch, fem, synth):
+    """The linear-elastic solve of App. F on the 100^3 unit cube (3,090,903
+    dofs): the elastic tangent of the undeformed unit-cube forward problem
+    (the same pattern as the benchmark cube) and the right-hand side of its
+    first load increment, by CG and BiCGSTAB with the node-block preconditioner to
+    relative residuals 1e-6 and 1e-8 (seconds, iterations)."""
+    p = synth.unit_cube_forward(100)
+    mesh = fem.Mesh(p.X, p.conn)
+    params = fem.Params(p.prm, p.n_elems, hardening="voce")
+    bc = torch.as_tensor(p.bc_mask).cuda()
+    d = torch.as_tensor(p.meta["bc_at"](1e-3)).cuda()
+    h0 = torch.zeros((7, 8 * p.n_elems), dtype=torch.float64, device="cuda")
+    # K of the undeformed cube (elastic everywhere); b = -R at the first increment's start
+    out = fem.residual_tangent(mesh, csr, params, torch.zeros_like(d), h0, bc_mask=bc, prec=fem.FP64_K32)
+    b = -fem.residual_tangent(mesh, csr, params, d, h0, bc_mask=bc, prec=fem.FP64, want_K=False).R
+    res = {"dofs": 3 * p.n_nodes, "context": "paper App. F, same mesh, linear elastic, one H100: AMGX BiCGSTAB "
+                                             "1.96 s, JAX BiCGSTAB 11.21 s (tolerance not stated)"}
+    for method in ("cg", "bicgstab"):
+        solver = fem.Solver(csr, method=method)
+        solver.solve(out.K, b, rtol=1e-2, check=False)  # warm-up
+        for rtol in (1e-6, 1e-8):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, its, rr = solver.solve(out.K, b, rtol=rtol, max_iter=50000, check=False)
+            torch.cuda.synchronize()
+            res[f"{method}_{rtol:.0e}"] = dict(seconds=time.perf_counter() - t0, iterations=its, rel_res=rr)
+        del solver
+    log("elastic solve: " + ", ".join(f"{k} {v['seconds']:.3f} s / {v['iterations']} it"
+                                      for k, v in res.items() if isinstance(v, dict)))
+    return res
+
+
 def forward_benchmark(spec, torch, fem, synth):
     """The unit-cube forward simulation of the performance study, Sec. 3.1.3 (Hill-48
     from the r-values, Voce, x = 0 clamped, x = 1 moved by t (0.2, 0.1) mm)
@@ -298,6 +330,7 @@ def main():
                                       bicgstab_ms_per_iteration=ms_it, bicgstab_rel_res_after_64=res)
         log(f"spmv {ms_spmv:.3f} ms ({spmv_bytes / (ms_spmv * 1e6):.0f} GB/s), bicgstab {ms_it:.3f} ms/iteration")
         del solver, xv, yv, rhs
+        extras["elastic_solve"] = elastic_solve(csr, torch, fem, synth)
         out_d = fem.Forward(mesh, csr, fem.FP64)
         ms_d, _, kt_d = time_passes(
             lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP64, out=out_d),
