@@ -30,6 +30,11 @@ import torch
 from . import fem, newton
 
 
+def _sync(dev):
+    if dev.type == "cuda":
+        torch.cuda.synchronize(dev)
+
+
 def reaction_norm(mesh, csr, params, d, hist, bc, prec=fem.FP64):
     """Norm of the internal force on the constrained dofs (flat bool mask bc)."""
     r = fem.residual_tangent(mesh, csr, params, d, hist, bc_mask=None, prec=prec, want_K=False, want_hist=False)
@@ -57,7 +62,7 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
     t, dt = 0.0, dt0
     f_ref = 0.0
     steps, failed, newton_its, lin_its, streak, lin_s = [], [], 0, 0, 0, 0.0
-    torch.cuda.synchronize()
+    _sync(dev)
     t0 = time.perf_counter()
     while t < t_end * (1 - 1e-12) and len(steps) < max_steps:
         dt = min(dt, t_end - t)
@@ -76,7 +81,9 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
         except RuntimeError as err:
             failed.append((t, dt, str(err)))
             if log:
-                log(f"increment t={t:.5f} dt={dt:.2e} failed: {err}")
+                log(f"increment t={t:.5f} dt={dt:.2e} failed: {err} | linear "
+                    + " ".join(f"{x[0]}@{x[4]:.0e}" for x in trace)
+                    + " | steps " + " ".join(f"{x[2]:g}" for x in trace))
             dt *= cutback
             streak = 0
             if dt < dt_min:
@@ -101,6 +108,6 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
         if streak >= grow_after:
             dt = min(dt * grow, dt_max)
             streak = 0
-    torch.cuda.synchronize()
+    _sync(dev)
     return dict(d=d, hist=h, steps=steps, failed=failed, newton_iterations=newton_its, linear_iterations=lin_its,
                 linear_seconds=lin_s, seconds=time.perf_counter() - t0)

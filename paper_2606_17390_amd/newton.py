@@ -100,4 +100,5 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
         if trace is not None:
             trace.append((lin_its, res, t, t_lin, rt))
         rn = rn_new
-    raise RuntimeError(f"Newton: ||R|| = {norms[-1]:.3e} after {max_it} iterations (start {norms[0]:.3e})")
+    raise RuntimeError(f"Newton: ||R|| = {norms[-1]:.3e} after {max_it} iterations (start {norms[0]:.3e}; "
+                       + " ".join(f"{r:.1e}" for r in norms) + ")")
