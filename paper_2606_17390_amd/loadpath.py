@@ -5,7 +5,9 @@ with the automatic stepping of Sec. 2.2.5:
 
 * prescribed values t u1 on the constrained dofs (a load proportional to t);
 * the Newton start of an increment is the linear extrapolation of the two
-  last converged solutions (the converged solution itself on the first);
+  last converged solutions; before two exist, the solution of the problem
+  linearised about the converged state with the boundary increment
+  (tangent_start; else the converged solution with the boundary increment);
 * a failed increment (no convergence, non-finite residual) is retried with
   dt times `cutback`, down to dt_min; after `grow_after` converged increments
   in a row dt grows by `grow`, up to dt_max;
@@ -15,9 +17,10 @@ with the automatic stepping of Sec. 2.2.5:
 * linear solves by conjugate gradients where the tangent is symmetric (every
   model but F-bar; BiCGSTAB for F-bar, and where CG meets a direction of
   non-positive curvature), to the Eisenstat-Walker tolerance of newton.py (floor
-  lin_rtol) unless forcing is None (then lin_rtol throughout); without an
-  extrapolated start (the first increment) the first solve goes to
-  first_eta, since that direction carries the whole boundary increment.
+  lin_rtol) unless forcing is None (then lin_rtol throughout); the linear
+  step of the tangent start, or without it the first solve of an increment
+  with no extrapolated start, goes to first_eta, since that direction
+  carries the whole boundary increment.
 
 The performance study of Sec. 3.1.3 uses dt0 1e-3, dt_min 1e-5, dt_max 5e-2.
 
@@ -44,7 +47,7 @@ def reaction_norm(mesh, csr, params, d, hist, bc, prec=fem.FP64):
 def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
           grow_after=1, cutback=0.5, ftol=1e-6, max_it=15, lin_rtol=1e-6, lin_max_iter=20000, t_end=1.0,
           max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew", first_eta=1e-4, krylov="auto",
-          line_search=True):
+          line_search=True, tangent_start=True):
     """Returns a dict with the final displacement and history, the accepted
     increments [(t, dt, Newton iterations, linear iterations)], the failed
     increments, the total Newton and linear iterations, the wall time and
@@ -71,12 +74,27 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
             trial.add_(d - d_prev, alpha=dt / dt_prev)
         trial.view(-1)[bc] = (t + dt) * u1f[bc]
         trace = []
+        if d_prev is None and tangent_start:
+            # no extrapolation yet: the linearisation about the last converged
+            # state, K_n du = -(R_n + K_n delta) on the free dofs with delta the
+            # boundary increment (evaluating the residual at the boundary-
+            # increment start instead would let the elements along the moved
+            # boundary take the whole increment and yield)
+            t_lin = time.perf_counter()
+            fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc_mask, prec=prec, out=out)
+            rhs = fem.csr_spmv(csr, out.K, (trial - d).view(-1))
+            rhs.add_(out.R).neg_()
+            rhs[bc] = 0.0
+            du, its0, _ = solver.solve(out.K, rhs, rtol=first_eta, max_iter=lin_max_iter, check=False)
+            trial.view(-1).add_(du)
+            lin_its += its0
+            lin_s += time.perf_counter() - t_lin
         try:
             h_new, its, norms = newton.solve_step(mesh, csr, params, trial, h, bc_mask, prec=prec,
                                                   tol=ftol if f_ref == 0.0 else 0.0, atol=ftol * f_ref,
                                                   max_it=max_it, lin_rtol=lin_rtol, lin_max_iter=lin_max_iter,
                                                   solver=solver, out=out, trace=trace, forcing=forcing,
-                                                  eta0=None if d_prev is not None else first_eta,
+                                                  eta0=None if d_prev is not None or tangent_start else first_eta,
                                                   line_search=line_search)
         except RuntimeError as err:
             failed.append((t, dt, str(err)))

@@ -25,8 +25,15 @@ class Env:
         self.bc[:3] = 1  # node 0 constrained
         self.u1 = torch.arange(1.0, 3 * n + 1, dtype=torch.float64).reshape(n, 3)
         self.t = 0.0
-        monkeypatch.setattr(fem, "Forward", lambda *a, **k: None)
-        monkeypatch.setattr(fem, "Solver", lambda *a, **k: None)
+        self.pred = []  # (d, hist) of the tangent-start evaluations
+        out = types.SimpleNamespace(K=None, R=torch.zeros(3 * n, dtype=torch.float64))
+        monkeypatch.setattr(fem, "Forward", lambda *a, **k: out)
+        monkeypatch.setattr(fem, "residual_tangent",
+                            lambda m, c, p, d, h, **k: self.pred.append((d.clone(), k)) or out)
+        solver = types.SimpleNamespace(solve=lambda K, b, **k: (torch.zeros_like(b), 3, 1e-5))
+        monkeypatch.setattr(fem, "Solver", lambda *a, **k: solver)
+        monkeypatch.setattr(fem, "csr_spmv", lambda csr, K, x: self.spmv.append(x.clone()) or torch.zeros_like(x))
+        self.spmv = []
         monkeypatch.setattr(loadpath, "reaction_norm", lambda *a, **k: reaction)
         monkeypatch.setattr(loadpath.newton, "solve_step", self.solve_step)
 
@@ -55,7 +62,8 @@ def test_growth_and_exact_end(monkeypatch):
     assert dts[:6] == pytest.approx([1e-3, 2e-3, 4e-3, 8e-3, 1.6e-2, 3.2e-2])
     assert all(x == pytest.approx(5e-2) for x in dts[6:-1]) and dts[-1] <= 5e-2
     assert res["steps"][-1][0] == pytest.approx(1.0, abs=1e-12) and sum(dts) == pytest.approx(1.0)
-    assert res["newton_iterations"] == 2 * len(dts) and res["linear_iterations"] == 10 * len(dts)
+    # 10 per Newton trace entry, 3 for the tangent start of the first increment
+    assert res["newton_iterations"] == 2 * len(dts) and res["linear_iterations"] == 10 * len(dts) + 3
     assert not res["failed"]
     assert float(res["hist"][0, 0]) == len(dts)  # every accepted increment commits its history
 
@@ -88,7 +96,10 @@ def test_extrapolated_start_and_prescribed_values(monkeypatch):
     c = env.calls
     # first increment: previous solution (zero) with the prescribed values
     assert torch.equal(c[0]["d"].view(-1)[~bc], torch.zeros(int((~bc).sum()), dtype=torch.float64))
-    assert c[0]["kw"]["eta0"] == 1e-4  # the first solve goes to first_eta without an extrapolated start
+    assert c[0]["kw"]["eta0"] is None  # the tangent start took the first_eta solve
+    # tangent start: K and R at the converged state (zero), K applied to the boundary increment
+    assert len(env.pred) == 1 and not env.pred[0][0].any() and len(env.spmv) == 1
+    assert torch.equal(env.spmv[0], c[0]["d"].view(-1))
     for k in range(2, len(c)):
         t0, t1 = c[k - 2]["t"] + c[k - 2]["dt"], c[k - 1]["t"] + c[k - 1]["dt"]
         f = lambda t: t + t * t  # noqa: E731  (the stand-in solution's profile)
@@ -97,6 +108,13 @@ def test_extrapolated_start_and_prescribed_values(monkeypatch):
         assert torch.allclose(d[~bc], pred * env.u1.view(-1)[~bc], rtol=1e-14)
         assert torch.allclose(d[bc], (c[k]["t"] + c[k]["dt"]) * env.u1.view(-1)[bc], rtol=1e-14)
         assert c[k]["kw"]["eta0"] is None
+
+
+def test_without_tangent_start_the_first_solve_is_tight(monkeypatch):
+    env = Env(monkeypatch)
+    res = env.run(dt0=1e-3, t_end=3e-3, tangent_start=False)
+    assert not env.pred and env.calls[0]["kw"]["eta0"] == 1e-4 and env.calls[1]["kw"]["eta0"] is None
+    assert res["linear_iterations"] == 10 * len(res["steps"])
 
 
 def test_convergence_target_follows_the_reaction(monkeypatch):
