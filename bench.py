@@ -175,12 +175,14 @@ def elastic_solve(csr, torch, fem, synth):
     return res
 
 
-def forward_benchmark(spec, torch, fem, synth):
+def forward_benchmark(spec, torch, fem, synth, fbar=True):
     """The unit-cube forward simulation of the performance study, Sec. 3.1.3 (Hill-48
     from the r-values, Voce, x = 0 clamped, x = 1 moved by t (0.2, 0.1) mm)
     through the adaptive load path: FP64 residual and history, float tangent
-    for the Krylov solve, BiCGSTAB with 3x3 node-block Jacobi and
-    Eisenstat-Walker tolerances, convergence at 1e-6 of the reaction norm."""
+    for the Krylov solve with 3x3 node-block Jacobi and Eisenstat-Walker
+    tolerances, convergence at 1e-6 of the reaction norm.  The element is the
+    F-bar hex8 of Sec. 2.2.4 (the paper's; unsymmetric tangent: BiCGSTAB) or
+    the plain hex8 (symmetric tangent: CG)."""
     from paper_2606_17390_amd import loadpath
     dims = tuple(int(v) for v in spec.lower().split("x"))
     if len(dims) == 1:
@@ -191,7 +193,7 @@ def forward_benchmark(spec, torch, fem, synth):
     t0 = time.perf_counter()
     mesh = fem.Mesh(p.X, p.conn)
     csr = fem.csr_pattern(mesh)
-    params = fem.Params(p.prm, p.n_elems, hardening="voce")
+    params = fem.Params(p.prm, p.n_elems, hardening="voce", fbar=fbar)
     bc = torch.as_tensor(p.bc_mask).cuda()
     u1 = torch.as_tensor(p.meta["bc_at"](1.0)).cuda()
     h0 = torch.zeros((7, 8 * p.n_elems), dtype=torch.float64, device="cuda")
@@ -214,10 +216,12 @@ def forward_benchmark(spec, torch, fem, synth):
         "vs_baseline": res["seconds"] / paper[0] if paper else None,
         "dtype": "f64 (tangent f32 in the solve)",
         "data": "synthetic",
-        "config": {"workload": f"unit cube {dims[0]}x{dims[1]}x{dims[2]} hex8, {3 * p.n_nodes} dofs, Hill-48 "
+        "config": {"workload": f"unit cube {dims[0]}x{dims[1]}x{dims[2]} {'F-bar ' if fbar else ''}hex8, "
+                               f"{3 * p.n_nodes} dofs, Hill-48 "
                                "r = (1.5449, 1.0666, 1, 1.0307, 1, 1), Voce sigma0 138 Q 410 b 3.8, E 219 GPa, "
                                "nu 0.3; dt0 1e-3, dt_min 1e-5, dt_max 5e-2",
-                   "nnz": csr.nnz},
+                   "nnz": csr.nnz, "element": "fbar" if fbar else "plain",
+                   "krylov": "bicgstab" if fbar else "cg"},
         "increments": len(res["steps"]),
         "failed_increments": len(res["failed"]),
         "newton_iterations": res["newton_iterations"],
@@ -243,6 +247,8 @@ def main():
     ap.add_argument("--forward-benchmark", nargs="?", const="100x100x100", default=None, metavar="NXxNYxNZ",
                     help="instead of the pass benchmark: the paper's unit-cube forward simulation (adaptive load "
                          "path, Newton + BiCGSTAB) on an NX x NY x NZ mesh, one JSON line with its wall time")
+    ap.add_argument("--element", choices=("fbar", "plain"), default="fbar",
+                    help="element of --forward-benchmark: the paper's F-bar hex8 (BiCGSTAB) or the plain hex8 (CG)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -266,7 +272,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": dst.numel() * 4}))
         return
     if args.forward_benchmark:
-        print(json.dumps(forward_benchmark(args.forward_benchmark, torch, fem, synth)), flush=True)
+        print(json.dumps(forward_benchmark(args.forward_benchmark, torch, fem, synth, args.element == "fbar")),
+              flush=True)
         return
     log("generating the 100^3 cube")
     p = synth.large_cube()
