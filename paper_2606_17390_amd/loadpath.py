@@ -8,7 +8,9 @@ with the automatic stepping of Sec. 2.2.5:
   last converged solutions; before two exist, the solution of the problem
   linearised about the converged state with the boundary increment
   (tangent_start; else the converged solution with the boundary increment);
-* a failed increment (no convergence, non-finite residual) is retried with
+* a failed increment (no convergence in max_it iterations, a residual that
+  has not halved over the last stall_window iterations, a non-finite
+  residual) is retried with
   dt times `cutback`, down to dt_min; after `grow_after` converged increments
   in a row dt grows by `grow`, up to dt_max;
 * convergence: ||R|| <= ftol f_ref, f_ref the largest norm of the reactions
@@ -45,7 +47,8 @@ def reaction_norm(mesh, csr, params, d, hist, bc, prec=fem.FP64):
 
 
 def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
-          grow_after=1, cutback=0.5, ftol=1e-6, max_it=15, lin_rtol=1e-6, lin_max_iter=20000, t_end=1.0,
+          grow_after=1, cutback=0.5, ftol=1e-6, max_it=30, stall_window=5, stall_ratio=0.5, lin_rtol=1e-6,
+          lin_max_iter=20000, t_end=1.0,
           max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew", first_eta=1e-4, krylov="auto",
           line_search=True, tangent_start=True):
     """Returns a dict with the final displacement and history, the accepted
@@ -95,7 +98,8 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
                                                   max_it=max_it, lin_rtol=lin_rtol, lin_max_iter=lin_max_iter,
                                                   solver=solver, out=out, trace=trace, forcing=forcing,
                                                   eta0=None if d_prev is not None or tangent_start else first_eta,
-                                                  line_search=line_search)
+                                                  line_search=line_search, stall_window=stall_window,
+                                                  stall_ratio=stall_ratio)
         except RuntimeError as err:
             failed.append((t, dt, str(err)))
             if log:

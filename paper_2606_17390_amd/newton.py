@@ -36,9 +36,11 @@ from . import fem
 
 def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, max_it=30, lin_rtol=1e-10,
                lin_max_iter=5000, solver=None, out=None, stream=None, line_search=True, max_backtracks=8, atol=0.0,
-               trace=None, forcing=None, eta_max=0.1, eta0=None):
+               trace=None, forcing=None, eta_max=0.1, eta0=None, stall_window=0, stall_ratio=0.5):
     """Newton iteration on d (device [n_nodes][3], updated in place) until
-    ||R|| <= max(tol ||R_0||, atol).  Returns (hist_np1, iterations, list of
+    ||R|| <= max(tol ||R_0||, atol); with stall_window > 0 it also gives up
+    once ||R|| has not fallen by the factor stall_ratio over that many
+    iterations.  Returns (hist_np1, iterations, list of
     ||R||).  Raises RuntimeError if the tolerance is not reached in max_it
     iterations, a linear solve fails or ||R|| is not finite.  A list passed
     as trace receives one (linear iterations, linear relative residual, step
@@ -64,6 +66,9 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
             return out.hist.clone(), it, norms
         if it == max_it:
             break
+        if stall_window and it >= stall_window and rn > stall_ratio * norms[-1 - stall_window]:
+            raise RuntimeError(f"Newton: stalled at ||R|| = {rn:.3e} after {it} iterations (start {norms[0]:.3e}; "
+                               + " ".join(f"{r:.1e}" for r in norms) + ")")
         rt = lin_rtol
         if forcing in ("ew", "const"):
             if it == 0:
