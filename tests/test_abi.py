@@ -89,3 +89,35 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "oracle." not in txt.replace("the oracle", ""), f
+
+
+def test_solver_arguments_are_rejected_on_the_host(lib):
+    """fem_solve validates its arguments before any device work: the pointers
+    below are never dereferenced."""
+    from paper_2606_17390_amd import fem
+    fake = ctypes.c_void_p(256)
+
+    def solve(n_rows=6, nnz=18, prec=fem.FP64, method=1, pc=1, max_iter=10, rtol=1e-8, ws_bytes=1 << 40,
+              b=fake, x=fake):
+        c = fem.FemCsr(n_rows, nnz, fake, fake, None, None, None)
+        it = ctypes.c_int32(-1)
+        res = ctypes.c_double(-1.0)
+        rc = lib.fem_solve(ctypes.byref(c), fake, prec, method, pc, b, x, max_iter, rtol, ctypes.byref(it),
+                           ctypes.byref(res), fake, ws_bytes, None)
+        return rc, it.value, res.value
+
+    assert solve(method=2)[0] == fem.FEM_EINVAL and b"Krylov" in lib.fem_last_error()
+    assert solve(pc=5)[0] == fem.FEM_EINVAL and b"preconditioner" in lib.fem_last_error()
+    assert solve(prec=7)[0] == fem.FEM_EINVAL
+    assert solve(n_rows=5)[0] == fem.FEM_EINVAL  # not 3 n_nodes
+    assert solve(nnz=17)[0] == fem.FEM_EINVAL  # not whole 3x3 blocks
+    assert solve(max_iter=-1)[0] == fem.FEM_EINVAL
+    assert solve(rtol=float("nan"))[0] == fem.FEM_EINVAL
+    assert solve(b=None)[0] == fem.FEM_EINVAL
+    assert solve(ws_bytes=16)[0] == fem.FEM_ENOMEM and b"workspace" in lib.fem_last_error()
+    # an empty system is solved without any device work
+    assert solve(n_rows=0, nnz=0) == (fem.FEM_OK, 0, 0.0)
+    # workspace: vectors, the block preconditioner and the node-column list
+    small, big = lib.fem_solver_workspace_bytes(3000, 9 * 27 * 1000), lib.fem_solver_workspace_bytes(3000, 10 ** 8)
+    assert small >= 8 * 3000 * 8 + 3 * 3000 * 8 + 27 * 1000 * 4 and big - small >= 4 * (10 ** 8 // 9 - 27 * 1000)
+    assert lib.fem_solver_workspace_bytes(-3, 0) == 0 and lib.fem_solver_workspace_bytes(3, -1) == 0
