@@ -50,7 +50,7 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
           grow_after=1, cutback=0.5, ftol=1e-6, max_it=30, stall_window=5, stall_ratio=0.5, lin_rtol=1e-6,
           lin_max_iter=20000, t_end=1.0,
           max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew", first_eta=1e-4, krylov="auto",
-          line_search=True, tangent_start=True):
+          line_search=True, tangent_start=True, eta_max=0.1):
     """Returns a dict with the final displacement and history, the accepted
     increments [(t, dt, Newton iterations, linear iterations)], the failed
     increments, the total Newton and linear iterations, the wall time and
@@ -99,7 +99,7 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
                                                   solver=solver, out=out, trace=trace, forcing=forcing,
                                                   eta0=None if d_prev is not None or tangent_start else first_eta,
                                                   line_search=line_search, stall_window=stall_window,
-                                                  stall_ratio=stall_ratio)
+                                                  stall_ratio=stall_ratio, eta_max=eta_max)
         except RuntimeError as err:
             failed.append((t, dt, str(err)))
             if log:
