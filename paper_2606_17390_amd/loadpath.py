@@ -10,9 +10,9 @@ with the automatic stepping of Sec. 2.2.5:
   (tangent_start; else the converged solution with the boundary increment);
 * a failed increment (no convergence in max_it iterations, a residual that
   has not halved over the last stall_window iterations, a non-finite
-  residual) is retried with
-  dt times `cutback`, down to dt_min; after `grow_after` converged increments
-  in a row dt grows by `grow`, up to dt_max;
+  residual) is retried with dt times `cutback`, down to dt_min; after
+  `grow_after` converged increments in a row dt grows by `grow`, up to
+  dt_max;
 * convergence: ||R|| <= ftol f_ref, f_ref the largest norm of the reactions
   (the unconstrained residual on the constrained dofs) met so far, or of the
   first increment's starting residual before any reaction exists;
@@ -48,9 +48,8 @@ def reaction_norm(mesh, csr, params, d, hist, bc, prec=fem.FP64):
 
 def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
           grow_after=1, cutback=0.5, ftol=1e-6, max_it=30, stall_window=5, stall_ratio=0.5, lin_rtol=1e-6,
-          lin_max_iter=20000, t_end=1.0,
-          max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew", first_eta=1e-4, krylov="auto",
-          line_search=True, tangent_start=True, eta_max=0.1):
+          lin_max_iter=20000, t_end=1.0, max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew",
+          first_eta=1e-4, eta_max=0.1, krylov="auto", line_search=True, tangent_start=True):
     """Returns a dict with the final displacement and history, the accepted
     increments [(t, dt, Newton iterations, linear iterations)], the failed
     increments, the total Newton and linear iterations, the wall time and
