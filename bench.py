@@ -175,6 +175,81 @@ def elastic_solve(csr, torch, fem, synth):
     return res
 
 
+def gradient_benchmark(torch, fem, synth):
+    """One iteration of the inverse problem of Sec. 3.2 on the tensile-specimen
+    stand-in (5,250 hex8, 45 degree orientation, ten unequal load steps):
+    the forward run at the current parameters (damped Newton per step, FP64)
+    with its checkpoints, the objective J = w sum ||u^n - u_gt^n||^2 against
+    a forward run at the reference parameters, and dJ/dtheta for the seven
+    differentiated parameters (F, G, H, N, sig0, Q, b) by the time-history
+    adjoint of Alg. 1.  `value` times forward + objective + adjoint."""
+    import numpy as np
+
+    from paper_2606_17390_amd import adjoint
+    p = synth.tensile_specimen()
+    mesh = fem.Mesh(p.X, p.conn)
+    csr = fem.csr_pattern(mesh)
+    bc = torch.as_tensor(p.bc_mask).cuda()
+    steps = [torch.as_tensor(p.meta["bc_at"](t)).cuda() for t in p.meta["steps"]]
+    h0 = torch.zeros((7, 8 * p.n_elems), dtype=torch.float64, device="cuda")
+    ref = fem.Params(p.prm, p.n_elems, hardening="voce", orient=p.orient)
+    prm0 = p.prm.copy()
+    prm0[2:5] *= 1.05  # F, G, H
+    prm0[7] *= 1.05    # N
+    prm0[8:11] *= (0.95, 1.1, 0.9)  # sig0, Q, b
+    cur = fem.Params(prm0, p.n_elems, hardening="voce", orient=p.orient)
+    solver = fem.Solver(csr, method="cg")  # symmetric tangent (no F-bar): CG for K and K^T
+    log("gradient benchmark: reference forward run")
+    gt = adjoint.forward(mesh, csr, ref, bc, steps, h0, solver=solver)
+    w = 1.0
+    adjoint.gradient(mesh, csr, cur, bc, gt, gt.d, w, solver=solver)  # warm-up of every kernel (zero cotangent)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ck = adjoint.forward(mesh, csr, cur, bc, steps, h0, solver=solver)
+    J = adjoint.objective(ck, gt.d, w)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grad, _, _ = adjoint.gradient(mesh, csr, cur, bc, ck, gt.d, w, solver=solver)
+    g = grad.cpu().numpy()
+    t2 = time.perf_counter()
+    # outside the timed region: central difference of J in Q (slot 9, gradient entry FEM_G_Q = 5)
+    hq = 1e-5 * prm0[9]
+    jq = []
+    for sgn in (1.0, -1.0):
+        pq = prm0.copy()
+        pq[9] += sgn * hq
+        prq = fem.Params(pq, p.n_elems, hardening="voce", orient=p.orient)
+        jq.append(adjoint.objective(adjoint.forward(mesh, csr, prq, bc, steps, h0, solver=solver), gt.d, w))
+    fd_q = (jq[0] - jq[1]) / (2.0 * hq)
+    return {
+        "metric": "inverse-iteration gradient wall time (forward + time-history adjoint)",
+        "value": t2 - t0,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": len(steps),
+        "warmup": 1,
+        "ms_per_step": (t2 - t0) * 1e3 / len(steps),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"tensile-specimen stand-in: {p.n_elems} hex8, {3 * p.n_nodes} dofs, 45 degree "
+                               "orientation, 10 unequal load steps to 0.5 mm, Hill-48 + Voce, 7 parameters"},
+        "forward_s": t1 - t0,
+        "adjoint_s": t2 - t1,
+        "newton_iterations": int(sum(ck.iterations)),
+        "objective": J,
+        "gradient": [float(v) for v in g],
+        "gradient_finite": bool(np.all(np.isfinite(g))),
+        "fd_check_Q": {"adjoint": float(g[5]), "central_difference": fd_q,
+                       "rel_diff": abs(float(g[5]) - fd_q) / abs(fd_q)},
+        "context": ("paper Sec. 3.2, its tensile specimen (5,250 hex8, 25,083 dofs, 10 steps, 6 parameters): "
+                    "234 s by the JAX adjoint, 2,166 s by central differences; GPU not stated; the specimen's "
+                    "shape differs from this stand-in"),
+    }
+
+
 def forward_benchmark(spec, torch, fem, synth, fbar=True):
     """The unit-cube forward simulation of the performance study, Sec. 3.1.3 (Hill-48
     from the r-values, Voce, x = 0 clamped, x = 1 moved by t (0.2, 0.1) mm)
@@ -247,6 +322,9 @@ def main():
     ap.add_argument("--forward-benchmark", nargs="?", const="100x100x100", default=None, metavar="NXxNYxNZ",
                     help="instead of the pass benchmark: the paper's unit-cube forward simulation (adaptive load "
                          "path, Newton + BiCGSTAB) on an NX x NY x NZ mesh, one JSON line with its wall time")
+    ap.add_argument("--gradient-benchmark", action="store_true",
+                    help="instead of the pass benchmark: one inverse-iteration gradient (forward + time-history "
+                         "adjoint) on the tensile-specimen stand-in, one JSON line with its wall time")
     ap.add_argument("--element", choices=("fbar", "plain"), default="fbar",
                     help="element of --forward-benchmark: the paper's F-bar hex8 (BiCGSTAB) or the plain hex8 (CG)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -270,6 +348,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": dst.numel() * 4}))
+        return
+    if args.gradient_benchmark:
+        print(json.dumps(gradient_benchmark(torch, fem, synth)), flush=True)
         return
     if args.forward_benchmark:
         print(json.dumps(forward_benchmark(args.forward_benchmark, torch, fem, synth, args.element == "fbar")),

@@ -31,7 +31,8 @@ class Checkpoints:
         self.iterations = []
 
 
-def forward(mesh, csr, params, bc_mask, bc_steps, hist0, prec=fem.FP64, tol=1e-11, max_it=40, solver=None):
+def forward(mesh, csr, params, bc_mask, bc_steps, hist0, prec=fem.FP64, tol=1e-11, max_it=40, solver=None,
+            lin_rtol=1e-10, lin_max_iter=20000):
     """Solve the load steps; bc_steps[n] (device [n_nodes, 3]) holds the prescribed
     values of the constrained dofs at step n."""
     ck = Checkpoints(hist0)
@@ -42,7 +43,7 @@ def forward(mesh, csr, params, bc_mask, bc_steps, hist0, prec=fem.FP64, tol=1e-1
     for ub in bc_steps:
         d.view(-1)[bc] = ub.reshape(-1)[bc]
         hist, its, _ = newton.solve_step(mesh, csr, params, d, ck.h[-1], bc_mask, prec=prec, tol=tol, max_it=max_it,
-                                         solver=solver, out=out)
+                                         solver=solver, out=out, lin_rtol=lin_rtol, lin_max_iter=lin_max_iter)
         ck.d.append(d.clone())
         ck.h.append(hist)
         ck.iterations.append(its)

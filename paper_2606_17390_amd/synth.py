@@ -464,6 +464,37 @@ def unit_cube_forward(n=100, ny=None, nz=None, nu=NU_DEFAULT):
                    None, dict(nx=n, ny=ny, nz=nz, bc_at=bc_at), hardening="voce")
 
 
+# Load factors of the ten unequal steps of the tensile-specimen study (Sec. 3.2).
+TENSILE_STEPS = (0.005, 0.006, 0.02, 0.045, 0.09, 0.15, 0.3, 0.5, 0.75, 1.0)
+
+
+def tensile_specimen(nx=35, ny=30, nz=5, angle_deg=45.0):
+    """Stand-in for the tensile specimen of the inverse study (Sec. 3.2: 5,250
+    hex8, orientation 45 degrees to the load, bottom fixed, top moved 0.5 mm
+    in y over TENSILE_STEPS, E = 200 GPa, nu = 0.3, r11 = r13 = r23 = 1): the
+    specimen's shape is not given, so a 35 x 30 x 3 mm slab of nx x ny x nz
+    elements (5,250 by default) with the y = 0 face fixed and the y = 30 face
+    gripped (x, z fixed, y prescribed).  Hill-48 from r = (1, 1.1, 0.9, 1.05,
+    1, 1), Voce (200, 150, 20) as the reference material.  Returns the
+    Problem (hardening "voce", orientation set) with meta["bc_at"](t)."""
+    X, conn = hex_grid(nx, ny, nz, 35.0, 30.0, 3.0)
+    prm = voce_params(E=200000.0, nu=0.3, **hill_from_r(1.0, 1.1, 0.9, 1.05, 1.0, 1.0))
+    bottom, top = np.isclose(X[:, 1], 0.0), np.isclose(X[:, 1], 30.0)
+    bc = np.zeros((X.shape[0], 3), dtype=np.uint8)
+    bc[bottom] = 1
+    bc[top] = 1
+
+    def bc_at(t):
+        u = np.zeros((X.shape[0], 3))
+        u[top, 1] = 0.5 * t
+        return u
+
+    ne = conn.shape[0]
+    return Problem(f"tensile_{nx}x{ny}x{nz}", X, conn, np.zeros_like(X), np.zeros((7, 8 * ne)), prm, bc.ravel(),
+                   None, dict(nx=nx, ny=ny, nz=nz, bc_at=bc_at, steps=TENSILE_STEPS), hardening="voce",
+                   orient=rotation_z(np.deg2rad(angle_deg)).reshape(9))
+
+
 def small_slab(seed, nx, ny, nz, per_element=False, strain=0.05, jitter=0.05, alpha_max=0.1):
     """Small jittered slab for parity tests with ragged element counts."""
     rng = np.random.Generator(np.random.PCG64(seed))
