@@ -45,3 +45,29 @@ def test_batch_sizes_are_log_uniform_and_uneven():
     assert sizes.min() >= 2000 and sizes.max() <= 60000
     spec = synth.uneven_slab(4001, 3000)
     assert abs(spec.n_elems - 3000) / 3000 < 0.5
+
+
+def test_forward_benchmark_workloads():
+    """The unit cube of the performance study and the tensile-specimen stand-in:
+    sizes, constrained dofs, prescribed values, Hill-48 from the r-values."""
+    import numpy as np
+
+    from paper_2606_17390_amd import synth
+    vm = synth.hill_from_r(1, 1, 1, 1, 1, 1)
+    assert np.allclose([vm[k] for k in "FGH"], 0.5) and np.allclose([vm[k] for k in "LMN"], 1.5)
+    h = synth.hill_from_r(1.5449, 1.0666, 1.0, 1.0307, 1.0, 1.0)
+    assert np.isclose(h["G"] + h["H"], 1 / 1.5449 ** 2) and np.isclose(h["F"] + h["H"], 1 / 1.0666 ** 2)
+    assert np.isclose(h["F"] + h["G"], 1.0) and np.isclose(h["N"], 1.5 / 1.0307 ** 2)
+    p = synth.unit_cube_forward(4, 3, 2)
+    assert p.n_elems == 24 and p.n_nodes == 5 * 4 * 3 and p.hardening == "voce"
+    bc = p.bc_mask.reshape(-1, 3).astype(bool)
+    left, right = np.isclose(p.X[:, 0], 0.0), np.isclose(p.X[:, 0], 1.0)
+    assert bc[left].all() and bc[right][:, :2].all() and not bc[right][:, 2].any() and not bc[~(left | right)].any()
+    u = p.meta["bc_at"](0.5)
+    assert np.allclose(u[right], [0.1, 0.05, 0.0]) and not u[~right].any()
+    assert np.allclose(p.prm[[0, 8, 9, 10]], [219000.0, 138.0, 410.0, 3.8])
+    t = synth.tensile_specimen()
+    assert t.n_elems == 5250 and 3 * t.n_nodes == 20088 and len(t.meta["steps"]) == 10
+    assert np.allclose(t.orient.reshape(3, 3) @ [1.0, 0.0, 0.0], [np.sqrt(0.5), np.sqrt(0.5), 0.0])
+    top = np.isclose(t.X[:, 1], 30.0)
+    assert np.allclose(t.meta["bc_at"](1.0)[top], [0.0, 0.5, 0.0]) and t.bc_mask.reshape(-1, 3)[top].all()
