@@ -19,7 +19,7 @@ library; this module sequences the calls.
 """
 import torch
 
-from . import fem, newton
+from . import fem, loadpath, newton
 
 
 class Checkpoints:
@@ -32,18 +32,31 @@ class Checkpoints:
 
 
 def forward(mesh, csr, params, bc_mask, bc_steps, hist0, prec=fem.FP64, tol=1e-11, max_it=40, solver=None,
-            lin_rtol=1e-10, lin_max_iter=20000):
+            lin_rtol=1e-10, lin_max_iter=20000, forcing=None, tangent_start=False):
     """Solve the load steps; bc_steps[n] (device [n_nodes, 3]) holds the prescribed
-    values of the constrained dofs at step n."""
+    values of the constrained dofs at step n.  forcing="ew": Eisenstat-Walker
+    linear tolerances (floor lin_rtol); tangent_start: each step starts from
+    the problem linearised about the previous converged state
+    (loadpath.linearised_start, solved to 1e-4) instead of the previous
+    solution with the new boundary values."""
     ck = Checkpoints(hist0)
     out = fem.Forward(mesh, csr, prec)
     solver = solver or fem.Solver(csr, hist0.device)
     d = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=hist0.device)
     bc = bc_mask.bool().view(-1)
     for ub in bc_steps:
+        d_prev = d.clone() if tangent_start else None
         d.view(-1)[bc] = ub.reshape(-1)[bc]
-        hist, its, _ = newton.solve_step(mesh, csr, params, d, ck.h[-1], bc_mask, prec=prec, tol=tol, max_it=max_it,
-                                         solver=solver, out=out, lin_rtol=lin_rtol, lin_max_iter=lin_max_iter)
+        rtol, atol = tol, 0.0
+        if tangent_start:
+            # the tolerance is taken relative to the increment's force scale,
+            # not to the (already small) residual of the linearised start
+            _, f_inc = loadpath.linearised_start(mesh, csr, params, d_prev, ck.h[-1], d, bc_mask, prec, out, solver,
+                                                 1e-4, lin_max_iter)
+            rtol, atol = 0.0, tol * f_inc
+        hist, its, _ = newton.solve_step(mesh, csr, params, d, ck.h[-1], bc_mask, prec=prec, tol=rtol, atol=atol,
+                                         max_it=max_it, solver=solver, out=out, lin_rtol=lin_rtol,
+                                         lin_max_iter=lin_max_iter, forcing=forcing)
         ck.d.append(d.clone())
         ck.h.append(hist)
         ck.iterations.append(its)

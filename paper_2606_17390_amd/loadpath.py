@@ -46,6 +46,25 @@ def reaction_norm(mesh, csr, params, d, hist, bc, prec=fem.FP64):
     return float(r.R[bc].norm().cpu())
 
 
+def linearised_start(mesh, csr, params, d, h, trial, bc_mask, prec, out, solver, rtol, max_iter):
+    """Moves `trial` (the converged solution d with the boundary increment on
+    the constrained dofs) to the solution of the problem linearised about the
+    converged state (d, h): K_n du = -(R_n + K_n delta) on the free dofs,
+    delta = trial - d, solved to rtol.  Starting Newton from the boundary
+    increment alone lets the elements along the moved boundary take the whole
+    increment and yield.  `out` (a Forward of this pattern) is overwritten.
+    Returns the linear iterations and the norm of the right-hand side (the
+    force scale of the increment)."""
+    bc = bc_mask.bool().view(-1)
+    fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc_mask, prec=prec, out=out)
+    rhs = fem.csr_spmv(csr, out.K, (trial - d).view(-1))
+    rhs.add_(out.R).neg_()
+    rhs[bc] = 0.0
+    du, its, _ = solver.solve(out.K, rhs, rtol=rtol, max_iter=max_iter, check=False)
+    trial.view(-1).add_(du)
+    return its, float(rhs.norm().cpu())
+
+
 def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
           grow_after=1, cutback=0.5, ftol=1e-6, max_it=30, stall_window=5, stall_ratio=0.5, lin_rtol=1e-6,
           lin_max_iter=20000, t_end=1.0, max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew",
@@ -77,19 +96,9 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
         trial.view(-1)[bc] = (t + dt) * u1f[bc]
         trace = []
         if d_prev is None and tangent_start:
-            # no extrapolation yet: the linearisation about the last converged
-            # state, K_n du = -(R_n + K_n delta) on the free dofs with delta the
-            # boundary increment (evaluating the residual at the boundary-
-            # increment start instead would let the elements along the moved
-            # boundary take the whole increment and yield)
             t_lin = time.perf_counter()
-            fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc_mask, prec=prec, out=out)
-            rhs = fem.csr_spmv(csr, out.K, (trial - d).view(-1))
-            rhs.add_(out.R).neg_()
-            rhs[bc] = 0.0
-            du, its0, _ = solver.solve(out.K, rhs, rtol=first_eta, max_iter=lin_max_iter, check=False)
-            trial.view(-1).add_(du)
-            lin_its += its0
+            lin_its += linearised_start(mesh, csr, params, d, h, trial, bc_mask, prec, out, solver, first_eta,
+                                        lin_max_iter)[0]
             lin_s += time.perf_counter() - t_lin
         try:
             h_new, its, norms = newton.solve_step(mesh, csr, params, trial, h, bc_mask, prec=prec,

@@ -31,6 +31,7 @@ class Env:
         monkeypatch.setattr(fem, "residual_tangent",
                             lambda m, c, p, d, h, **k: self.pred.append((d.clone(), k)) or out)
         solver = types.SimpleNamespace(solve=lambda K, b, **k: (torch.zeros_like(b), 3, 1e-5))
+        # (the stand-in product returns zeros, so the tangent start's right-hand side is -R_n = 0)
         monkeypatch.setattr(fem, "Solver", lambda *a, **k: solver)
         monkeypatch.setattr(fem, "csr_spmv", lambda csr, K, x: self.spmv.append(x.clone()) or torch.zeros_like(x))
         self.spmv = []
