@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline pass only")
+    ap.add_argument("--no-forward", action="store_true",
+                    help="skip the paper's forward simulation (about 40 s) among the extras")
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--forward-benchmark", nargs="?", const="100x100x100", default=None, metavar="NXxNYxNZ",
                     help="instead of the pass benchmark: the paper's unit-cube forward simulation (adaptive load "
@@ -568,6 +570,15 @@ def main():
                                     ms_64_separate_fp64_calls=ms_sep)
         log(f"batched graph {ms_b:.3f} ms vs separate fp64 {ms_sep:.3f} ms")
         del sep, sep_out
+        if not args.no_forward:
+            # the paper's forward simulation of Sec. 3.1.3 end to end (F-bar element), after the timed pass
+            try:
+                fw = forward_benchmark("100x100x100", torch, fem, synth, True)
+                extras["forward_simulation"] = {k: fw[k] for k in (
+                    "metric", "value", "unit", "config", "increments", "failed_increments", "newton_iterations",
+                    "linear_iterations", "linear_solve_s", "vs_baseline", "context")}
+            except RuntimeError as err:
+                extras["forward_simulation"] = {"error": str(err)}
 
     value = n_gp / (ms_m * 1e-3)
     bc_np = p.bc_mask.astype(bool)
