@@ -94,7 +94,6 @@ __global__ __launch_bounds__(256) void transpose_kernel(int32_t n_nodes, const i
         }
 }
 
-
 constexpr int kGrid = 1024;      // blocks of the fused vector kernels (fixed: reproducible reductions)
 constexpr int kSpmvGrid = 2048;  // blocks of the fused matrix-vector products
 constexpr int kParts = kSpmvGrid > kGrid ? kSpmvGrid : kGrid;
