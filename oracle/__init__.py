@@ -15,6 +15,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_ASAN_PATH = os.path.join(_HERE, "liboracle_asan.so")
+# ORACLE_LIB names another build of oracle.c to load (the sanitizer build)
 _lib = None
 
 NPARAM = 11
@@ -25,25 +27,32 @@ MODEL_FBAR = 2
 MODEL_BARLAT = 4
 
 
-def build(force=True):
-    """Compile liboracle.so with gcc (OpenMP, -O2)."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
+def build(force=True, sanitize=False):
+    """Compile liboracle.so with gcc (OpenMP, -O2).  sanitize=True builds
+    liboracle_asan.so instead, with AddressSanitizer and UndefinedBehavior
+    checks (host code; the test suite loads it in a child process with the
+    ASan runtime preloaded)."""
+    path = _ASAN_PATH if sanitize else _LIB_PATH
+    if not force and os.path.exists(path):
+        return path
     src = os.path.join(_HERE, "oracle.c")
-    tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", src, "-o", tmp, "-lm"]
+    tmp = path + ".tmp"
+    flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+    cmd = ["gcc", *flags, "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", src, "-o", tmp, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, path)
+    return path
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    path = os.environ.get("ORACLE_LIB", _LIB_PATH)
+    if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
         build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64 = ctypes.c_int32, ctypes.c_int64
     lib.oracle_eig_sym3.argtypes = [P, P, P]
@@ -65,6 +74,11 @@ def _load():
     lib.oracle_set_barlat.argtypes = [P]
     lib.oracle_effective_stress.argtypes = [P, P, ci, P, P]
     lib.oracle_effective_stress.restype = ctypes.c_double
+    lib.oracle_local_return.argtypes = [P] * 3 + [ci, P, ci, ci, ci, P, P, ci, P]
+    lib.oracle_local_return.restype = ctypes.c_int
+    lib.oracle_local_merit.argtypes = [P] * 3 + [ci, P, ci, P]
+    lib.oracle_local_merit.restype = ctypes.c_double
+    lib.oracle_local_return_batch.argtypes = [i32] + [P] * 3 + [ci, P, ci, ci, ci, P, ci]
     _lib = lib
     del i64
     return lib
@@ -274,3 +288,57 @@ def effective_stress(T, prm, model=0, Theta=None):
     N = np.zeros((3, 3))
     phi = _load().oracle_effective_stress(_p(T), _p(p), int(model), _p(_theta(Theta)), _p(N))
     return phi, N
+
+
+# layout of a line-search trace record (oracle.h, oracle_local_return)
+TRACE_JMAX2 = 22
+TRACE_REC = 22 + 2 * TRACE_JMAX2
+
+
+def local_return(eps_m, hist_n, prm, model=0, Theta=None, line_search=True, kmax=100, merit_scaled=False,
+                 trace_cap=200):
+    """Local return map (Alg. C2, App. B line search) from the Mandel log strain
+    eps_m [6] and stored history hist_n [7].  Returns (iterations (negative if
+    not converged), y [8] = [T Mandel, alpha, dgamma], trace): trace is a list
+    of dicts per Newton step with k, gnorm, psi0, psi1, zeta, y, dy and the
+    line-search candidates zetas / psis (zetas[0] from Eq. (alpha_init))."""
+    e = _f64(eps_m).reshape(6)
+    h = _f64(hist_n).reshape(7)
+    p = _f64(prm).reshape(NPARAM)
+    y = np.zeros(8)
+    tr = np.zeros((trace_cap, TRACE_REC))
+    nrec = ctypes.c_int(0)
+    it = _load().oracle_local_return(_p(e), _p(h), _p(p), int(model), _p(_theta(Theta)), int(bool(line_search)),
+                                     int(kmax), int(bool(merit_scaled)), _p(y), _p(tr), int(trace_cap),
+                                     ctypes.byref(nrec))
+    recs = []
+    for r in tr[:nrec.value]:
+        m = int(r[5])
+        recs.append(dict(k=int(r[0]), gnorm=r[1], psi0=r[2], psi1=r[3], zeta=r[4], y=r[6:14].copy(),
+                         dy=r[14:22].copy(), zetas=r[22:22 + m].copy(),
+                         psis=r[22 + TRACE_JMAX2:22 + TRACE_JMAX2 + m].copy()))
+    return it, y, recs
+
+
+def local_merit(eps_m, hist_n, prm, y, model=0, Theta=None, merit_scaled=False):
+    """The merit psi(y) of the local system at y [8]."""
+    e = _f64(eps_m).reshape(6)
+    h = _f64(hist_n).reshape(7)
+    p = _f64(prm).reshape(NPARAM)
+    yy = _f64(y).reshape(8)
+    return _load().oracle_local_merit(_p(e), _p(h), _p(p), int(model), _p(_theta(Theta)), int(bool(merit_scaled)),
+                                      _p(yy))
+
+
+def local_return_batch(eps_m, hist_n, prm, model=0, Theta=None, line_search=True, kmax=100, merit_scaled=False,
+                       n_threads=0):
+    """Iteration counts (negative: not converged) of local_return for many
+    strains eps_m [n, 6] sharing hist_n."""
+    e = _f64(eps_m).reshape(-1, 6)
+    h = _f64(hist_n).reshape(7)
+    p = _f64(prm).reshape(NPARAM)
+    it = np.zeros(e.shape[0], dtype=np.int32)
+    _load().oracle_local_return_batch(e.shape[0], _p(e), _p(h), _p(p), int(model), _p(_theta(Theta)),
+                                      int(bool(line_search)), int(kmax), int(bool(merit_scaled)), _p(it),
+                                      int(n_threads))
+    return it

@@ -52,8 +52,7 @@ static const double SQRT2 = 1.41421356237309504880168872420969808;
 /* local Newton constants (not given by the paper; see design notes) */
 static const double LS_BETA = 1e-4; /* App. B, Goldstein constant */
 static const double LS_ETA = 0.1;   /* App. B, step safeguard     */
-static const int KMAX = 100;
-static const int JMAX = 20;
+enum { KMAX = 100, JMAX = 20 };
 static const double LOCAL_TOL = 1e-14;
 
 /* Mandel index pairs: (11, 22, 33, 23, 13, 12) */
@@ -622,14 +621,43 @@ static double cpp_merit(const cpp_ctx *c, const double y[8], const double D[8]) 
     return 0.5 * s;
 }
 
+/* Options of the local Newton iteration: the line search of App. B on or off
+ * (off: every step is the full Newton step, the "standard Newton method" of
+ * App. B's comparison), the iteration limit k_max, the merit scaling (1: the
+ * scaled residual D G of the design notes; 0: psi = 1/2 G^T G exactly as in
+ * Eq. (merit)), and an optional per-iteration trace (ORACLE_TRACE_REC doubles
+ * per outer iteration, layout in oracle.h). */
+typedef struct {
+    int line_search, kmax, scaled;
+    double *trace;
+    int trace_cap, n_rec;
+} cpp_opts;
+
+static cpp_opts default_opts(void) {
+    cpp_opts o = {1, KMAX, 0, NULL, 0, 0};
+    return o;
+}
+
 /* Alg. C2: Newton with the line search of App. B.  Returns the iteration
- * count (negative if not converged). */
-static int cpp_solve(const cpp_ctx *c, double y[8]) {
+ * count (negative if not converged).  Line search (App. B): the full step is
+ * taken if psi(1) < (1 - 2 beta) psi(0) (Goldstein); otherwise the first
+ * candidate minimises the quadratic model through psi(0), psi'(0) = -2 psi(0)
+ * and psi(1), Eq. (alpha_init), and is taken if it passes the Goldstein test
+ * with its own step length; each further candidate minimises the model
+ * through psi(0) and the merit at the previous candidate, Eq.
+ * (alpha_update_ls), bounded below by eta times the previous candidate, Eq.
+ * (alpha_safeguard), and is taken once it passes the Goldstein test.  After
+ * j_max rejected updates the last candidate is taken.  The merit is
+ * psi = 1/2 G^T G of Eq. (merit) unless the options ask for the scaled
+ * residual. */
+static int cpp_solve(const cpp_ctx *c, double y[8], cpp_opts *o) {
     double mu = c->Em[35] / 2.0;
     double sy_n = hardening(c->prm, c->voce, c->alpha_n, NULL);
     double D[8] = {1 / mu, 1 / mu, 1 / mu, 1 / mu, 1 / mu, 1 / mu, 1.0, 1.0 / sy_n};
+    double Dm[8];
+    for (int i = 0; i < 8; ++i) Dm[i] = o->scaled ? D[i] : 1.0;
     double prev = INFINITY;
-    for (int k = 0; k <= KMAX; ++k) {
+    for (int k = 0; k <= o->kmax; ++k) {
         double G[8], J[64], dy[8];
         cpp_residual(c, y, G);
         double gn = 0.0;
@@ -638,36 +666,84 @@ static int cpp_solve(const cpp_ctx *c, double y[8]) {
         if (gn <= LOCAL_TOL) return k;
         /* rounding floor reached: no further decrease below 1e-12 */
         if (gn <= 1e-12 && gn >= 0.5 * prev) return k;
+        if (k == o->kmax) break;
         prev = gn;
         cpp_jacobian(c, y, J);
         for (int i = 0; i < 8; ++i) dy[i] = -G[i];
         if (solve_dense(8, J, dy)) return -(k + 1);
         double psi0 = 0.0;
-        for (int i = 0; i < 8; ++i) psi0 += (D[i] * G[i]) * (D[i] * G[i]);
+        for (int i = 0; i < 8; ++i) psi0 += (Dm[i] * G[i]) * (Dm[i] * G[i]);
         psi0 *= 0.5;
         double yt[8];
         for (int i = 0; i < 8; ++i) yt[i] = y[i] + dy[i];
-        double psi1 = cpp_merit(c, yt, D);
+        double psi1 = cpp_merit(c, yt, Dm);
         double zeta = 1.0;
-        if (!(psi1 < (1.0 - 2.0 * LS_BETA) * psi0)) {
-            double zj = psi0 / (psi0 + psi1); /* Eq. (alpha_init) */
-            if (!(zj == zj)) zj = LS_ETA;
-            zeta = zj;
-            for (int j = 0; j <= JMAX; ++j) {
-                for (int i = 0; i < 8; ++i) yt[i] = y[i] + zj * dy[i];
-                double psij = cpp_merit(c, yt, D);
-                double zn = psi0 / (psi0 + psij); /* Eq. (alpha_update_ls) */
-                zn = fmax(LS_ETA * zj, zn);       /* Eq. (alpha_safeguard) */
-                for (int i = 0; i < 8; ++i) yt[i] = y[i] + zn * dy[i];
-                double psin = cpp_merit(c, yt, D);
-                zeta = zn;
-                if (psin < (1.0 - 2.0 * LS_BETA * zn) * psi0) break; /* Goldstein */
-                zj = zn;
+        double zs[JMAX + 2], ps[JMAX + 2];
+        int m = 0; /* candidates evaluated */
+        if (o->line_search && !(psi1 < (1.0 - 2.0 * LS_BETA) * psi0)) {
+            zs[0] = psi0 / (psi0 + psi1); /* Eq. (alpha_init) */
+            if (!(zs[0] == zs[0])) zs[0] = LS_ETA;
+            for (int i = 0; i < 8; ++i) yt[i] = y[i] + zs[0] * dy[i];
+            ps[0] = cpp_merit(c, yt, Dm);
+            m = 1;
+            zeta = zs[0];
+            /* App. B: the initial trial step is kept if it passes the Goldstein
+             * test; only otherwise is the quadratic model updated */
+            if (!(ps[0] < (1.0 - 2.0 * LS_BETA * zs[0]) * psi0)) {
+                for (int jj = 0; jj <= JMAX; ++jj) {
+                    double zn = psi0 / (psi0 + ps[jj]); /* Eq. (alpha_update_ls) */
+                    zn = fmax(LS_ETA * zs[jj], zn);      /* Eq. (alpha_safeguard) */
+                    for (int i = 0; i < 8; ++i) yt[i] = y[i] + zn * dy[i];
+                    zs[jj + 1] = zn;
+                    ps[jj + 1] = cpp_merit(c, yt, Dm);
+                    m = jj + 2;
+                    zeta = zn;
+                    if (ps[jj + 1] < (1.0 - 2.0 * LS_BETA * zn) * psi0) break; /* Goldstein */
+                }
             }
+        }
+        if (o->trace && o->n_rec < o->trace_cap) {
+            double *r = o->trace + (size_t)o->n_rec * ORACLE_TRACE_REC;
+            memset(r, 0, ORACLE_TRACE_REC * sizeof(double));
+            r[0] = k;
+            r[1] = gn;
+            r[2] = psi0;
+            r[3] = psi1;
+            r[4] = zeta;
+            r[5] = m;
+            for (int i = 0; i < 8; ++i) r[6 + i] = y[i];
+            for (int i = 0; i < 8; ++i) r[14 + i] = dy[i];
+            for (int j = 0; j < m; ++j) {
+                r[22 + j] = zs[j];
+                r[22 + (JMAX + 2) + j] = ps[j];
+            }
+            ++o->n_rec;
         }
         for (int i = 0; i < 8; ++i) y[i] += zeta * dy[i];
     }
-    return -(KMAX + 1);
+    return -(o->kmax + 1);
+}
+
+/* Sets up the local system of a material point from the Mandel logarithmic
+ * strain eps_{n+1}, the Mandel plastic strain eps^p_n and alpha_n. */
+static void cpp_ctx_init(cpp_ctx *c, const double eps_m[6], const double epsp_n[6], double alpha_n,
+                         const double prm[11], int model, const double *Theta) {
+    elastic_mandel(prm, c->Em);
+    hill_mandel(prm, c->Hm);
+    rotate_hill(Theta, c->Hm);
+    c->prm = prm;
+    c->voce = (model & ORACLE_MODEL_VOCE) != 0;
+    c->Theta = Theta;
+    c->barlat = (model & ORACLE_MODEL_BARLAT) != 0;
+    if (c->barlat) {
+        barlat_transform(g_barlat, c->L1);
+        barlat_transform(g_barlat + 9, c->L2);
+        rotate_hill(Theta, c->L1); /* the same rotation of a fourth-order tensor */
+        rotate_hill(Theta, c->L2);
+        c->mexp = g_barlat[18];
+    }
+    c->alpha_n = alpha_n;
+    for (int i = 0; i < 6; ++i) c->ee_tr[i] = eps_m[i] - epsp_n[i];
 }
 
 /* ------------------------------------------------------------------ */
@@ -721,22 +797,7 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
     (void)epsp_t;
 
     cpp_ctx *c = &s->ctx;
-    elastic_mandel(prm, c->Em);
-    hill_mandel(prm, c->Hm);
-    rotate_hill(Theta, c->Hm);
-    c->prm = prm;
-    c->voce = (model & ORACLE_MODEL_VOCE) != 0;
-    c->Theta = Theta;
-    c->barlat = (model & ORACLE_MODEL_BARLAT) != 0;
-    if (c->barlat) {
-        barlat_transform(g_barlat, c->L1);
-        barlat_transform(g_barlat + 9, c->L2);
-        rotate_hill(Theta, c->L1); /* the same rotation of a fourth-order tensor */
-        rotate_hill(Theta, c->L2);
-        c->mexp = g_barlat[18];
-    }
-    c->alpha_n = hist_n[6];
-    for (int i = 0; i < 6; ++i) c->ee_tr[i] = eps_m[i] - epsp_n[i];
+    cpp_ctx_init(c, eps_m, epsp_n, hist_n[6], prm, model, Theta);
 
     /* elastic predictor, Eq. (Tr_stress) */
     double ttr[6];
@@ -769,7 +830,8 @@ static void mp_update(const double F[9], const double hist_n[7], const double pr
         for (int i = 0; i < 6; ++i) y[i] = ttr[i];
         y[6] = c->alpha_n;
         y[7] = 0.0;
-        int it = cpp_solve(c, y);
+        cpp_opts o = default_opts();
+        int it = cpp_solve(c, y, &o);
         s->converged = it >= 0;
         s->iters = it >= 0 ? it : -it;
         s->dgamma = y[7];
@@ -930,6 +992,68 @@ int oracle_material_point(const double F[9], const double hist_n[7], const doubl
         info[5] = s.sy_n;
     }
     return s.converged ? 0 : 1;
+}
+
+/* hist_n (stored: eps^p tensor components 11,22,33,23,13,12, alpha) to the
+ * Mandel plastic strain */
+static void hist_to_mandel(const double hist_n[7], double epsp_n[6]) {
+    double hp[9];
+    hp[0] = hist_n[0];
+    hp[4] = hist_n[1];
+    hp[8] = hist_n[2];
+    hp[5] = hp[7] = hist_n[3];
+    hp[2] = hp[6] = hist_n[4];
+    hp[1] = hp[3] = hist_n[5];
+    sym_to_mandel(hp, epsp_n);
+}
+
+typedef char trace_rec_size_check[(ORACLE_TRACE_JMAX2 == JMAX + 2) ? 1 : -1];
+
+int oracle_local_return(const double eps_m[6], const double hist_n[7], const double prm[11], int model,
+                        const double *Theta, int line_search, int kmax, int merit_scaled, double y[8],
+                        double *trace, int trace_cap, int *n_rec) {
+    cpp_ctx c;
+    double epsp_n[6];
+    hist_to_mandel(hist_n, epsp_n);
+    cpp_ctx_init(&c, eps_m, epsp_n, hist_n[6], prm, model, Theta);
+    for (int i = 0; i < 6; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < 6; ++j) acc += c.Em[6 * i + j] * c.ee_tr[j];
+        y[i] = acc; /* trial stress, Eq. (Tr_stress) */
+    }
+    y[6] = c.alpha_n;
+    y[7] = 0.0;
+    cpp_opts o = {line_search != 0, kmax, merit_scaled != 0, trace, trace_cap, 0};
+    int it = cpp_solve(&c, y, &o);
+    if (n_rec) *n_rec = o.n_rec;
+    return it;
+}
+
+double oracle_local_merit(const double eps_m[6], const double hist_n[7], const double prm[11], int model,
+                          const double *Theta, int merit_scaled, const double y[8]) {
+    cpp_ctx c;
+    double epsp_n[6];
+    hist_to_mandel(hist_n, epsp_n);
+    cpp_ctx_init(&c, eps_m, epsp_n, hist_n[6], prm, model, Theta);
+    double mu = c.Em[35] / 2.0, sy_n = hardening(prm, c.voce, c.alpha_n, NULL);
+    double D[8] = {1 / mu, 1 / mu, 1 / mu, 1 / mu, 1 / mu, 1 / mu, 1.0, 1.0 / sy_n};
+    if (!merit_scaled)
+        for (int i = 0; i < 8; ++i) D[i] = 1.0;
+    return cpp_merit(&c, y, D);
+}
+
+void oracle_local_return_batch(int32_t n, const double *eps_m, const double hist_n[7], const double prm[11],
+                               int model, const double *Theta, int line_search, int kmax, int merit_scaled,
+                               int32_t *iters, int n_threads) {
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int32_t q = 0; q < n; ++q) {
+        double y[8];
+        iters[q] = oracle_local_return(eps_m + 6 * (size_t)q, hist_n, prm, model, Theta, line_search, kmax,
+                                       merit_scaled, y, NULL, 0, NULL);
+    }
 }
 
 double oracle_effective_stress(const double T[9], const double prm[11], int model, const double *Theta,

@@ -78,6 +78,40 @@ int oracle_material_point(const double F[9], const double hist_n[7], const doubl
                           int model, const double *Theta, double *S, double *P, double *T, double *hist_np1, double *A,
                           double *Cep, double *Cep_implicit, double *Cmat, double *info);
 
+/* Local return map at one material point (App. C Alg. C2 with the line search
+ * of App. B) from the Mandel logarithmic strain eps_m[6] and the stored
+ * history hist_n[7], starting at y^0 = [T^tr, alpha_n, 0].  Options:
+ * line_search (0: full Newton steps, the standard Newton method of App. B's
+ * comparison), kmax (iteration limit; the default of the other calls is 100),
+ * merit_scaled (1: psi = 1/2 |D G|^2 on the scaled residual
+ * D = (1/mu, ..., 1/mu, 1, 1/sigma_y(alpha_n)) used by the other calls; 0:
+ * psi = 1/2 G^T G as printed in Eq. (merit)).  The convergence test always
+ * uses the scaled residual.  y[8] = [T Mandel, alpha, dgamma] on return.
+ * Returns the number of Newton iterations, or -(kmax + 1) (or -(k + 1) on a
+ * singular Jacobian / non-finite residual) if not converged.  If trace is
+ * non-NULL, one record of ORACLE_TRACE_REC doubles per Newton step (at most
+ * trace_cap), count in *n_rec:
+ *   [0] k   [1] scaled max-norm of G(y^k)   [2] psi(0)   [3] psi(1)
+ *   [4] step length zeta^k taken   [5] m = line-search candidates evaluated
+ *   [6..13] y^k   [14..21] delta y^k
+ *   [22 + j] candidate zeta^(j), j < m (zeta^(0) from Eq. (alpha_init))
+ *   [22 + ORACLE_TRACE_JMAX2 + j] psi(zeta^(j)) */
+#define ORACLE_TRACE_JMAX2 22
+#define ORACLE_TRACE_REC (22 + 2 * ORACLE_TRACE_JMAX2)
+int oracle_local_return(const double eps_m[6], const double hist_n[7], const double prm[11], int model,
+                        const double *Theta, int line_search, int kmax, int merit_scaled, double y[8],
+                        double *trace, int trace_cap, int *n_rec);
+
+/* The merit psi(y) of the same local system (scaled or as printed). */
+double oracle_local_merit(const double eps_m[6], const double hist_n[7], const double prm[11], int model,
+                          const double *Theta, int merit_scaled, const double y[8]);
+
+/* oracle_local_return for n strains eps_m[n][6] sharing hist_n: iters[q] as
+ * returned there (no trace). */
+void oracle_local_return_batch(int32_t n, const double *eps_m, const double hist_n[7], const double prm[11],
+                               int model, const double *Theta, int line_search, int kmax, int merit_scaled,
+                               int32_t *iters, int n_threads);
+
 /* Element residual R[24] (index 3*I+a) and tangent K[576] (row 3*I+a, col 3*J+b)
  * from node coordinates X[8][3], displacements d[8][3] and per-GP history
  * hist[8][7] (GP-major).  hist_np1[8][7] may be NULL.  diag[4] accumulates

@@ -9,3 +9,4 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built libfem.so")
     config.addinivalue_line("markers", "slow: larger CPU case (still runs in the default suite)")
+    config.addinivalue_line("markers", "asan: the oracle's pins under AddressSanitizer (CPU)")
