@@ -178,8 +178,9 @@ const char *fem_last_error(void);
 
 /* Set (cfg != NULL) or reset (cfg == NULL) the launch configuration of an
  * element kernel (FEM_KERNEL_FORWARD or FEM_KERNEL_VJP) for a precision;
- * process-wide.  Defaults: {64, 8, 1} for both.  Returns
- * FEM_EINVAL for bad values. */
+ * process-wide; FEM_FP64_K32 shares the FEM_FP64 setting (it runs the same
+ * element kernels).  Defaults: {64, 8, 1} for both.  Returns FEM_EINVAL for
+ * bad values. */
 int fem_set_launch(int kernel, fem_precision prec, const fem_launch *cfg);
 int fem_get_launch(int kernel, fem_precision prec, fem_launch *cfg);
 

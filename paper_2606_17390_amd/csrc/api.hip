@@ -158,6 +158,7 @@ int fem_version(void) { return 100; }
 const char* fem_last_error(void) { return g_err; }
 
 int fem_set_launch(int kernel, fem_precision prec, const fem_launch* cfg) {
+    if (prec == FEM_FP64_K32) prec = FEM_FP64;  // the same element kernels as FEM_FP64
     if (kernel < 0 || kernel > 1 || (int)prec < 0 || (int)prec > 1)
         return set_error(FEM_EINVAL, "fem_set_launch: bad kernel %d or precision %d", kernel, (int)prec);
     std::lock_guard<std::mutex> lk(g_cfg_mu);
@@ -174,6 +175,7 @@ int fem_set_launch(int kernel, fem_precision prec, const fem_launch* cfg) {
 }
 
 int fem_get_launch(int kernel, fem_precision prec, fem_launch* cfg) {
+    if (prec == FEM_FP64_K32) prec = FEM_FP64;
     if (!cfg || kernel < 0 || kernel > 1 || (int)prec < 0 || (int)prec > 1)
         return set_error(FEM_EINVAL, "fem_get_launch: bad arguments");
     *cfg = launch_config(kernel, prec);

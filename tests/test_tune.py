@@ -47,6 +47,35 @@ def test_apply_cached_sets_the_launch(tune_mod):
         fem.set_launch(fem.KERNEL_VJP, fem.FP64)
 
 
+def test_variant_shapes_and_fp64_k32_slot(tune_mod, monkeypatch):
+    """A model variant is tuned over 64-thread workgroups only (the only size
+    its kernels take), under its own cache key; FEM_FP64_K32 is tuned and set
+    in the FP64 launch slot."""
+    from paper_2606_17390_amd import fem
+    seen = {}
+
+    def fake_search(kernel, prec, fn, reps, blocks, waves, remaps):
+        seen.update(blocks=tuple(blocks), prec=prec)
+        return [(1.0, blocks[-1], waves[0], remaps[0])]
+
+    monkeypatch.setattr(tune_mod, "_search", fake_search)
+    k_plain = tune_mod._key(fem.KERNEL_FORWARD, fem.FP64, 5000)
+    k_fbar = tune_mod._key(fem.KERNEL_FORWARD, fem.FP64, 5000, "m2o0")
+    assert k_plain != k_fbar
+    assert tune_mod._key(fem.KERNEL_FORWARD, fem.FP64_K32, 5000) == k_plain
+    try:
+        res = tune_mod.tune(fem.KERNEL_FORWARD, fem.FP64_K32, 5000, None, variant="m2o0")
+        assert seen["blocks"] == (64,) and seen["prec"] == fem.FP64
+        c = fem.get_launch(fem.KERNEL_FORWARD, fem.FP64_K32)
+        assert (c.block, c.waves_per_cu, c.xcd_remap) == res[1:]
+        c64 = fem.get_launch(fem.KERNEL_FORWARD, fem.FP64)
+        assert (c64.block, c64.waves_per_cu, c64.xcd_remap) == res[1:]
+        tune_mod.tune(fem.KERNEL_FORWARD, fem.FP64, 5000, None, variant="m0o0", use_cache=False)
+        assert seen["blocks"] == tune_mod.BLOCKS
+    finally:
+        fem.set_launch(fem.KERNEL_FORWARD, fem.FP64)
+
+
 @pytest.mark.gpu
 def test_tune_forward_applies_a_shape_and_keeps_results(tune_mod):
     torch = pytest.importorskip("torch")
