@@ -261,6 +261,28 @@ int fem_residual_vjp(const fem_mesh *mesh, const fem_batch *batch, const fem_par
                      void *stream);
 
 /*
+ * fem_residual_vjp_noalloc -- fem_residual_vjp without a workspace argument,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * workspace is a file-scope device array of FEM_VJP_SCRATCH_MAX_BYTES bytes,
+ * one per device the library runs on, held until the process ends; the call
+ * itself allocates nothing.  Arguments, outputs and results are those of
+ * fem_residual_vjp (the same kernels run).
+ * Limit: fem_vjp_workspace_bytes(n_elems, n_spec) must not exceed
+ * FEM_VJP_SCRATCH_MAX_BYTES (about 1.1 million elements); larger meshes get
+ * FEM_ENOMEM and must use fem_residual_vjp.
+ * All calls on one device share its array: calls that overlap on one device
+ * (on different streams, or from different threads) race and give undefined
+ * results.  Errors: as fem_residual_vjp, plus FEM_ENOMEM (too large) and
+ * FEM_EHIP (the array's device address could not be taken).
+ */
+#define FEM_VJP_SCRATCH_MAX_BYTES (64u << 20)
+int fem_residual_vjp_noalloc(const fem_mesh *mesh, const fem_batch *batch, const fem_params *params,
+                             const double *d, const double *hist_n, const double *lam,
+                             fem_precision prec, double *g_uniform, double *g_elem, int32_t *diag,
+                             void *stream);
+
+/*
  * Linear solve of the global Newton iteration (Sec. 2.2.4: K du = -R, with
  * the Dirichlet rows of App. E as identity rows, so K is not symmetric).
  *

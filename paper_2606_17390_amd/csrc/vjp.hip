@@ -17,6 +17,7 @@
 // Elastic Gauss points contribute exactly zero.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "fem_device.h"
@@ -523,4 +524,68 @@ extern "C" int fem_residual_vjp(const fem_mesh* mesh, const fem_batch* batch, co
         }
     }
     return FEM_OK;
+}
+
+// ---- fem_residual_vjp_noalloc: the same call with its workspace in a
+// file-scope device array (no allocation by the library or the caller).
+namespace {
+
+constexpr size_t kVjpScratchBytes = (size_t)FEM_VJP_SCRATCH_MAX_BYTES;
+// One copy per device the library runs on, resident until the process ends.
+// Host code never passes this symbol itself: the device address of the
+// current device's copy is taken once per device with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kVjpScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// device address of the current device's scratch array (nullptr on failure,
+// with the error set)
+void* scratch_address(int* status) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *status = set_error(FEM_EHIP, "fem_residual_vjp_noalloc: hipGetDevice failed: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *status = set_error(FEM_EINVAL, "fem_residual_vjp_noalloc: device %d out of range", dev);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            *status = set_error(FEM_EHIP, "fem_residual_vjp_noalloc: hipGetSymbolAddress failed: %s",
+                                hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int fem_residual_vjp_noalloc(const fem_mesh* mesh, const fem_batch* batch, const fem_params* params,
+                                        const double* d, const double* hist_n, const double* lam,
+                                        fem_precision prec, double* g_uniform, double* g_elem, int32_t* diag,
+                                        void* stream) {
+    clear_error();
+    if (!mesh) return set_error(FEM_EINVAL, "fem_residual_vjp_noalloc: mesh must not be NULL");
+    if (mesh->n_elems < 0) return set_error(FEM_EINVAL, "fem_residual_vjp_noalloc: negative sizes");
+    const int n_spec = batch ? batch->n_spec : 1;
+    const size_t need = fem_vjp_workspace_bytes(mesh->n_elems, n_spec);
+    if (need > kVjpScratchBytes)
+        return set_error(FEM_ENOMEM,
+                         "fem_residual_vjp_noalloc: %d elements need %zu bytes of scratch, the maximum is %zu "
+                         "(use fem_residual_vjp with a workspace)",
+                         mesh->n_elems, need, kVjpScratchBytes);
+    int status = FEM_OK;
+    void* ptr = scratch_address(&status);
+    if (!ptr) return status;
+    return fem_residual_vjp(mesh, batch, params, d, hist_n, lam, prec, g_uniform, g_elem, diag, ptr,
+                            kVjpScratchBytes, stream);
 }

@@ -55,8 +55,8 @@ _lib = None
 
 EXPORTS = ("fem_version", "fem_last_error", "fem_set_launch", "fem_get_launch", "fem_csr_workspace_bytes",
            "fem_forward_workspace_bytes", "fem_vjp_workspace_bytes", "fem_csr_pattern", "fem_residual_tangent",
-           "fem_residual_vjp", "fem_timing_enable", "fem_timing_read", "fem_graph_begin", "fem_graph_end",
-           "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes", "fem_csr_spmv", "fem_solve",
+           "fem_residual_vjp", "fem_residual_vjp_noalloc", "fem_timing_enable", "fem_timing_read",
+           "fem_graph_begin", "fem_graph_end", "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes", "fem_csr_spmv", "fem_solve",
            "fem_csr_transpose", "fem_history_adjoint_workspace_bytes", "fem_history_adjoint")
 
 
@@ -84,6 +84,9 @@ def lib():
                                        _c_p, _c_p, _c_p, _c_sz, _c_p]
     L.fem_residual_vjp.argtypes = [ctypes.POINTER(FemMesh), ctypes.POINTER(FemBatch), ctypes.POINTER(FemParams),
                                    _c_p, _c_p, _c_p, ctypes.c_int, _c_p, _c_p, _c_p, _c_p, _c_sz, _c_p]
+    L.fem_residual_vjp_noalloc.argtypes = [ctypes.POINTER(FemMesh), ctypes.POINTER(FemBatch),
+                                           ctypes.POINTER(FemParams), _c_p, _c_p, _c_p, ctypes.c_int, _c_p, _c_p,
+                                           _c_p, _c_p]
     L.fem_timing_enable.argtypes = [ctypes.c_int]
     L.fem_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_c_i32)]
     L.fem_graph_begin.argtypes = [_c_p]
@@ -390,6 +393,23 @@ def residual_vjp(mesh, params, d, hist_n, lam, prec=FP64, out=None, batch=None, 
                             _ptr(out.diag), _ptr(out.ws), out.ws_bytes, _stream(stream))
     _check("fem_residual_vjp", rc)
     return out
+
+
+VJP_SCRATCH_MAX_BYTES = 64 << 20  # FEM_VJP_SCRATCH_MAX_BYTES
+
+
+def residual_vjp_noalloc(mesh, params, d, hist_n, lam, g_uniform, g_elem=None, diag=None, prec=FP64, batch=None,
+                         stream=None):
+    """fem_residual_vjp_noalloc: the VJP into caller-given outputs (g_uniform
+    [n_spec, 7], g_elem [7, n_elems] or None, diag [4] int32 or None) with the
+    library's static device scratch as workspace (nothing is allocated)."""
+    cm, cp = mesh.c(), params.c()
+    cb = batch.c() if batch is not None else None
+    rc = lib().fem_residual_vjp_noalloc(ctypes.byref(cm), ctypes.byref(cb) if cb is not None else None,
+                                        ctypes.byref(cp), _ptr(d), _ptr(hist_n), _ptr(lam), _prec(prec),
+                                        _ptr(g_uniform), _ptr(g_elem) if g_elem is not None and mesh.n_elems
+                                        else None, _ptr(diag), _stream(stream))
+    _check("fem_residual_vjp_noalloc", rc)
 
 
 # ---------------------------------------------------------------------------

@@ -121,3 +121,17 @@ def test_solver_arguments_are_rejected_on_the_host(lib):
     small, big = lib.fem_solver_workspace_bytes(3000, 9 * 27 * 1000), lib.fem_solver_workspace_bytes(3000, 10 ** 8)
     assert small >= 8 * 3000 * 8 + 3 * 3000 * 8 + 27 * 1000 * 4 and big - small >= 4 * (10 ** 8 // 9 - 27 * 1000)
     assert lib.fem_solver_workspace_bytes(-3, 0) == 0 and lib.fem_solver_workspace_bytes(3, -1) == 0
+
+
+def test_noalloc_vjp_rejects_meshes_beyond_its_scratch(lib):
+    """fem_residual_vjp_noalloc refuses, before any device work, a mesh whose
+    workspace exceeds its static scratch (64 MiB: about 1.1M elements)."""
+    from paper_2606_17390_amd import fem
+    n = 1_200_000
+    assert lib.fem_vjp_workspace_bytes(n, 1) > fem.VJP_SCRATCH_MAX_BYTES
+    m = fem.FemMesh(3 * n, n, None, None)
+    rc = lib.fem_residual_vjp_noalloc(ctypes.byref(m), None, None, None, None, None, 0, None, None, None, None)
+    assert rc == fem.FEM_ENOMEM
+    assert b"maximum" in lib.fem_last_error()
+    assert lib.fem_residual_vjp_noalloc(None, None, None, None, None, None, 0, None, None, None, None) == \
+        fem.FEM_EINVAL
