@@ -7,15 +7,18 @@ Workload (synthetic, seeded): the 100x100x100 hex8 cube (1,000,000 elements,
 1,030,301 nodes, 3,090,903 dofs, 8,000,000 Gauss points, nnz 245,438,109),
 per-element Hill-48 F,G,H from smooth random fields, 30% of the Gauss points
 yielding at the trial state, x = 0 face constrained.  A step is one
-fem_residual_tangent call in FP32-mixed precision (element kernel with return
-map / residual / element tangent, FP64 re-run of the guard-band elements,
-residual assembly with Dirichlet rows and the FP64 residual norm, tangent
-assembly into the CSR values), inputs resident in HBM.  Prints ONE JSON line.
+fem_residual_tangent call in FP64, the paper's precision (element kernel with
+return map / residual / element tangent, residual assembly with Dirichlet
+rows and the FP64 residual norm, tangent assembly into the CSR values),
+inputs resident in HBM.  Prints ONE JSON line.
 
-Also reported (same JSON line): the plain FP64 pass on the same cube, the
+Also reported (same JSON line, "extras"): the FP32-mixed pass on the same
+cube with its own roofline, the 4x4x4 and 40x40x4 configurations, the
 parameter VJP on the 200x200x2 voided specimen, the batched 64-specimen
-forward + VJP graph, per-kernel rooflines (live HIP-event timing of each
-kernel on its launch stream), and the CPU oracle on a bounded sample.
+forward + VJP (graph against separate calls, in each precision, with tuned
+launch shapes), per-kernel rooflines (live HIP-event timing of each kernel on
+its launch stream), model variants, the linear solve, and the CPU oracle on
+bounded samples (median of 5, all host threads and one thread).
 """
 import argparse
 import json
@@ -27,21 +30,45 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU peak of the element kernels: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA)
-# x 2.4 GHz = 78.6 TFLOP/s, the rate of FP64 and of non-packed FP32 alike
-# (the library is built without packed FP32 instructions).
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Published MI355X vector peaks: FP64 78.6 TFLOP/s (256 CUs x 4 SIMDs x 16
+# lanes x 2 flop x 2.4 GHz), FP32 157.3 TFLOP/s (packed FMA; the library is
+# built without packed FP32 instructions, so 78.6 is what its FP32 code can
+# reach).
+FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 2 * FP64_PEAK_TFLOPS
 
-# Counted VALU flops per Gauss point of the main element kernel on the 100^3
-# cube: rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP32/_FP64/_FP32_TRANS/_FP64_TRANS
-# (per wave instruction; x 64 lanes), summed over one launch, divided by the
-# 8e6 Gauss points (profiles/fwd_kernel_large_cube_valu.md).  None where not
-# counted for the kernel as it stands.
-FLOP_PER_GP = {"mixed": 7516.4, "fp64": None}
-# HBM bytes per launch: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a
-# plain 1 GiB copy), profiles/hbm_traffic_large_cube_mixed.md; None where not
-# taken for the kernel as it stands.
-TRAFFIC_BYTES = {"fwd_kernel": 3.764e9, "assemble_tangent": 3.475e9, "assemble_residual": 3.661e8}
+# Counter figures of the element and assembly kernels, taken with rocprofv3 on
+# the 100^3 cube (profiles/): counted VALU flops per Gauss point
+# (SQ_INSTS_VALU_FLOPS_FP32/_FP64/_FP32_TRANS/_FP64_TRANS x 64 lanes / 8e6)
+# and HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors of
+# a plain 1 GiB copy).  They hold for the kernel sources whose hash is "sha";
+# once the sources differ they are reported as null.
+PROFILED = {
+    "sha": "7eacf972b90ef482",
+    "fp64": {"flop_per_gp": 9155.2,
+             "traffic": {"fwd_kernel": 6.076e9, "assemble_tangent": 6.759e9, "assemble_residual": 3.660e8}},
+    "mixed": {"flop_per_gp": 7516.4,
+              "traffic": {"fwd_kernel": 3.764e9, "assemble_tangent": 3.475e9, "assemble_residual": 3.663e8}},
+}
+KERNEL_SOURCES = ("paper_2606_17390_amd/csrc/forward.hip", "paper_2606_17390_amd/csrc/fem_device.h",
+                  "paper_2606_17390_amd/csrc/barlat.h")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled(prec, what, kernel=None):
+    """A counter figure of PROFILED if it was taken on the current sources."""
+    if PROFILED["sha"] is None or PROFILED["sha"] != kernel_source_sha():
+        return None
+    v = PROFILED[prec][what]
+    return v.get(kernel) if kernel is not None else v
 
 
 def log(*a):
@@ -50,7 +77,10 @@ def log(*a):
 
 def algorithmic_bytes(p, nnz, prec_mixed, per_elem_cols):
     """Bytes an ideal residual + tangent + assembly pass moves through HBM,
-    each input and output array once (no element scratch)."""
+    each input and output array once: X, d, conn, h_n, per-element
+    parameters, elem_rank, row_ptr, R, K values and h_{n+1} (no element
+    scratch).  On the 100^3 cube: 382 B per Gauss point in FP64, 259 in
+    FP32-mixed (K values in FP32)."""
     ne, nn = p.n_elems, p.n_nodes
     ngp = 8 * ne
     kb = 4 if prec_mixed else 8
@@ -68,10 +98,10 @@ def algorithmic_bytes(p, nnz, prec_mixed, per_elem_cols):
     return b
 
 
-def kernel_bytes(p, nnz, prec_mixed, per_elem_cols, n_bc_rows, bc_row_nnz):
-    """Algorithmic bytes of each kernel of one pass (its inputs read once, its
-    outputs written once, element scratch included where a kernel reads or
-    writes it)."""
+def design_bytes(p, nnz, prec_mixed, per_elem_cols, bc_row_nnz):
+    """Bytes each kernel of this design's pass reads and writes once, element
+    scratch (R^e, K^e) included: the design's traffic floor, not the method's
+    algorithmic bytes."""
     ne, nn = p.n_elems, p.n_nodes
     ngp = 8 * ne
     kb = 4 if prec_mixed else 8
@@ -89,7 +119,7 @@ def time_passes(fn, steps, warmup, torch, kernels, fem):
     torch.cuda.synchronize()
     for k in kernels:
         fem.timing_read(k)  # drop launches of the warm-up
-    fem.timing_enable(True)
+    fem.timing_enable(bool(kernels))  # per-launch events only where kernel times are read
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -109,30 +139,87 @@ def time_passes(fn, steps, warmup, torch, kernels, fem):
     return e0.elapsed_time(e1) / steps, wall / steps * 1e3, avg
 
 
-def cpu_baseline(p, n_sample):
-    """CPU oracle (OpenMP, all host threads) on the first n_sample elements."""
-    import numpy as np
+def _cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
 
-    import oracle
-    conn = p.conn[:n_sample]
+
+def _median_time(fn, reps):
+    import statistics
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), ts
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _sub_mesh(p, n):
+    """The first n elements of a problem, its nodes renumbered."""
+    import numpy as np
+    conn = p.conn[:n]
     used = np.unique(conn)
     remap = -np.ones(p.n_nodes, dtype=np.int64)
     remap[used] = np.arange(used.size)
-    sc = remap[conn].astype(np.int32)
-    X, d = p.X[used], p.d[used]
-    prm = p.prm[:n_sample]
-    hist = np.ascontiguousarray(p.hist_n[:, :8 * n_sample])
-    rp, ci, _ = oracle.csr_pattern(sc, used.size, with_rank=False)
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count()
-    t0 = time.perf_counter()
-    oracle.residual_tangent(X, sc, rp, ci, prm, d, hist, n_threads=cores)
-    dt = time.perf_counter() - t0
-    return dict(value=8 * n_sample / dt, unit="GP/s", cores=cores, kind="oracle",
-                sample=f"first {n_sample} elements ({8 * n_sample} Gauss points) of the 100^3 cube, "
-                       f"FP64 residual+tangent+CSR, {dt:.2f} s wall")
+    prm = p.prm[:n] if p.prm.ndim == 2 else p.prm
+    return used, remap[conn].astype(np.int32), prm, np.ascontiguousarray(p.hist_n[:, :8 * n])
+
+
+def cpu_baseline(p, n_sample, n_sample_1t, reps=5):
+    """The CPU oracle (FP64 residual + tangent + CSR, OpenMP over elements) on
+    the first n_sample elements of the cube with every host thread, and on
+    the first n_sample_1t elements with one thread; median of `reps` runs
+    each.  The oracle is timed as it stands (it is the checker, not tuned)."""
+    import oracle
+    cores = _cores()
+    res = {}
+    for key, n, nt in (("all", n_sample, cores), ("one", n_sample_1t, 1)):
+        used, sc, prm, hist = _sub_mesh(p, n)
+        rp, ci, _ = oracle.csr_pattern(sc, used.size, with_rank=False)
+        X, d = p.X[used], p.d[used]
+        res[key] = _median_time(lambda: oracle.residual_tangent(X, sc, rp, ci, prm, d, hist, n_threads=nt), reps)
+    t_all, ts_all = res["all"]
+    t_one, ts_one = res["one"]
+    return dict(value=8 * n_sample / t_all, unit="GP/s", cores=cores, kind="oracle",
+                sample=f"first {n_sample} elements ({8 * n_sample} Gauss points) of the 100^3 cube, FP64 "
+                       f"residual+tangent+CSR, median of {reps} runs: {t_all:.3f} s wall",
+                runs_s=ts_all,
+                single_thread=dict(value=8 * n_sample_1t / t_one, unit="GP/s", cores=1,
+                                   sample=f"first {n_sample_1t} elements, median of {reps} runs: {t_one:.3f} s",
+                                   runs_s=ts_one),
+                cpu_model=_cpu_model())
+
+
+def cpu_baseline_vjp(pv, n_sample_1t, reps=5):
+    """The CPU oracle's parameter VJP (forward-mode App. D, OpenMP over
+    elements) on the whole voided specimen with every host thread, and on its
+    first n_sample_1t elements with one thread; median of `reps` runs each."""
+    import oracle
+    cores = _cores()
+    t_all, ts_all = _median_time(lambda: oracle.residual_vjp(pv.X, pv.conn, pv.prm, pv.d, pv.hist_n, pv.lam,
+                                                             n_threads=cores), reps)
+    used, sc, prm, h1 = _sub_mesh(pv, n_sample_1t)
+    X, d, lam = pv.X[used], pv.d[used], pv.lam[used]
+    t_one, ts_one = _median_time(lambda: oracle.residual_vjp(X, sc, prm, d, h1, lam, n_threads=1), reps)
+    return dict(vjp_per_s=1.0 / t_all, gp_vjp_per_s=8 * pv.n_elems / t_all, cores=cores, kind="oracle",
+                sample=f"200x200x2 voided specimen ({pv.n_elems} elements), median of {reps} runs: {t_all:.3f} s",
+                runs_s=ts_all,
+                single_thread=dict(gp_vjp_per_s=8 * n_sample_1t / t_one, cores=1,
+                                   sample=f"first {n_sample_1t} elements, median of {reps} runs: {t_one:.3f} s",
+                                   runs_s=ts_one))
 
 
 # The paper's forward benchmarks on these meshes, one H100, wall time in
@@ -319,10 +406,18 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="headline pass only")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the linear solve, model variants, adjoint step, batched and forward-simulation extras")
+    ap.add_argument("--only", choices=("fp64", "mixed"), default=None,
+                    help="time only this precision's pass on the cube and print its timing (for profiler runs)")
     ap.add_argument("--no-forward", action="store_true",
                     help="skip the paper's forward simulation (about 40 s) among the extras")
-    ap.add_argument("--cpu-sample", type=int, default=200000)
+    ap.add_argument("--cpu-sample", type=int, default=100000,
+                    help="elements of the cube in the all-threads CPU oracle sample")
+    ap.add_argument("--cpu-sample-1t", type=int, default=8000,
+                    help="elements of the cube in the one-thread CPU oracle sample")
+    ap.add_argument("--cpu-sample-vjp-1t", type=int, default=6000,
+                    help="elements of the voided specimen in the one-thread CPU oracle VJP sample")
     ap.add_argument("--forward-benchmark", nargs="?", const="100x100x100", default=None, metavar="NXxNYxNZ",
                     help="instead of the pass benchmark: the paper's unit-cube forward simulation (adaptive load "
                          "path, Newton + BiCGSTAB) on an NX x NY x NZ mesh, one JSON line with its wall time")
@@ -378,21 +473,106 @@ def main():
     per_elem_cols = bin(params.per_elem_mask).count("1")
     n_gp = 8 * p.n_elems
     log(f"nnz {csr.nnz}, per-element parameter columns {per_elem_cols}")
-
-    # ---- headline: FP32-mixed residual + tangent + CSR pass
+    bc_np = p.bc_mask.astype(bool)
+    rp = csr.row_ptr.cpu().numpy()
+    bc_rows = np.nonzero(bc_np)[0]
+    bc_row_nnz = int((rp[bc_rows + 1] - rp[bc_rows]).sum())
     KS = (fem.KERNEL_FORWARD, fem.KERNEL_ASSEMBLE_K, fem.KERNEL_ASSEMBLE_R)
+    KNAMES = {fem.KERNEL_FORWARD: "fwd_kernel", fem.KERNEL_ASSEMBLE_K: "assemble_tangent",
+              fem.KERNEL_ASSEMBLE_R: "assemble_residual"}
+    if args.only:
+        prec = fem.FP64 if args.only == "fp64" else fem.FP32_MIXED
+        oo = fem.Forward(mesh, csr, prec)
+        ms_o, _, kt_o = time_passes(
+            lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=prec, out=oo),
+            args.steps, args.warmup, torch, KS, fem)
+        print(json.dumps({"only": args.only, "ms_per_pass": ms_o, "steps": args.steps,
+                          "kernel_ms": {KNAMES[k]: kt_o[k] for k in KS}}), flush=True)
+        return
+
+    def pass_record(prec_name, ms, kt):
+        """Roofline record of one pass: the pass's algorithmic bytes (382 or 259
+        B per Gauss point) over the dominant kernel's launch time against HBM,
+        the counted VALU flops over the same time against the published peak
+        of the kernel's type, and per-kernel design bytes."""
+        mixed = prec_name == "mixed"
+        alg = algorithmic_bytes(p, csr.nnz, mixed, per_elem_cols)
+        kb = design_bytes(p, csr.nnz, mixed, per_elem_cols, bc_row_nnz)
+        kms = {KNAMES[k]: kt[k] for k in KS}
+        dom = max(kms, key=lambda k: kms[k])
+        fl = profiled(prec_name, "flop_per_gp")
+        peak_alu = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+        alu = None
+        if fl and dom == "fwd_kernel":
+            ach_f = fl * n_gp / (kms[dom] * 1e-3) / 1e12
+            alu = dict(achieved=ach_f, peak=peak_alu, unit="TFLOP/s", frac=ach_f / peak_alu, flop_per_gp=fl)
+        ach = alg / (kms[dom] * 1e6)
+        roof = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=ach / HBM_PEAK_GBS, traffic=profiled(prec_name, "traffic", dom),
+                    bytes_per_gp=alg / n_gp, n_gp=n_gp, kernel_ms=kms[dom],
+                    pass_ms=ms, pass_frac=alg / (ms * 1e6) / HBM_PEAK_GBS, alu=alu,
+                    binding=("alu" if alu and alu["frac"] > ach / HBM_PEAK_GBS else "hbm"))
+        kernels = {}
+        for name, ms_k in kms.items():
+            kernels[name] = dict(kernel_ms=ms_k, design_bytes=kb[name], design_GBps=kb[name] / (ms_k * 1e6),
+                                 traffic=profiled(prec_name, "traffic", name))
+        return roof, kernels
+
+    # ---- headline: FP64 residual + tangent + CSR pass
+    out_d = fem.Forward(mesh, csr, fem.FP64)
+    ms_d, _, kt_d = time_passes(
+        lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP64, out=out_d),
+        args.steps, args.warmup, torch, KS, fem)
+    plastic = float((out_d.hist[6] != h[6]).double().mean().cpu())
+    diag_d = out_d.diag.cpu().tolist()
+    log(f"fp64: {ms_d:.3f} ms/pass, element kernel {kt_d[fem.KERNEL_FORWARD]:.3f} ms, tangent assembly "
+        f"{kt_d[fem.KERNEL_ASSEMBLE_K]:.3f} ms, residual assembly {kt_d[fem.KERNEL_ASSEMBLE_R]:.3f} ms, "
+        f"plastic {plastic:.4f}, diag {diag_d}")
+    roof_d, kern_d = pass_record("fp64", ms_d, kt_d)
+    extras = {"csr_pattern_ms": ms_pattern, "kernels_fp64": kern_d, "kernel_source_sha": kernel_source_sha(),
+              "counters_source_sha": PROFILED["sha"]}
+
+    # ---- FP32-mixed pass on the same cube
     out_m = fem.Forward(mesh, csr, fem.FP32_MIXED)
-    ms_m, wall_m, kt_m = time_passes(
+    ms_m, _, kt_m = time_passes(
         lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP32_MIXED, out=out_m),
         args.steps, args.warmup, torch, KS, fem)
-    kms_m = kt_m[fem.KERNEL_FORWARD]
-    plastic = float((out_m.hist[6] != h[6]).double().mean().cpu())
-    diag_m = out_m.diag.cpu().tolist()
-    log(f"mixed: {ms_m:.3f} ms/pass, element kernel {kms_m:.3f} ms, tangent assembly "
-        f"{kt_m[fem.KERNEL_ASSEMBLE_K]:.3f} ms, residual assembly {kt_m[fem.KERNEL_ASSEMBLE_R]:.3f} ms, "
-        f"plastic {plastic:.4f}, diag {diag_m}")
-    result = {}
-    extras = {"csr_pattern_ms": ms_pattern}
+    roof_m, kern_m = pass_record("mixed", ms_m, kt_m)
+    torch.cuda.synchronize()
+    km = out_m.K.double()
+    err_k = float(((km - out_d.K).abs().max() / out_d.K.abs().max()).cpu())
+    err_r = float(((out_m.R - out_d.R).abs().max() / out_d.R.abs().max()).cpu())
+    del km
+    log(f"mixed: {ms_m:.3f} ms/pass, element kernel {kt_m[fem.KERNEL_FORWARD]:.3f} ms, tangent assembly "
+        f"{kt_m[fem.KERNEL_ASSEMBLE_K]:.3f} ms; mixed vs fp64 K {err_k:.2e} R {err_r:.2e}")
+    extras["mixed"] = dict(gp_updates_per_s=n_gp / (ms_m * 1e-3), ms_per_pass=ms_m, dtype="f32+f64",
+                           speedup_vs_fp64=ms_d / ms_m, roofline=roof_m, kernels=kern_m,
+                           diag=out_m.diag.cpu().tolist(), rel_err_vs_fp64=dict(K=err_k, R=err_r))
+    del out_d
+    torch.cuda.empty_cache()
+
+    # ---- the small configurations: 4x4x4 unit cube and the 40x40x4 sheet slab
+    small = {}
+    for cname, pc in (("tiny_cube_4x4x4", synth.tiny_cube()), ("sheet_slab_40x40x4", synth.sheet_slab())):
+        mc = fem.Mesh(pc.X, pc.conn)
+        cc = fem.csr_pattern(mc)
+        prc = fem.Params(pc.prm, pc.n_elems)
+        dc, hc = torch.as_tensor(pc.d).cuda(), torch.as_tensor(pc.hist_n).cuda()
+        bcc, lc = torch.as_tensor(pc.bc_mask).cuda(), torch.as_tensor(pc.lam).cuda()
+        row = dict(n_elems=pc.n_elems, dofs=3 * pc.n_nodes, nnz=cc.nnz)
+        for pn, pr in (("fp64", fem.FP64), ("mixed", fem.FP32_MIXED)):
+            oc = fem.Forward(mc, cc, pr)
+            ms_c, _, _ = time_passes(lambda: fem.residual_tangent(mc, cc, prc, dc, hc, bc_mask=bcc, prec=pr, out=oc),
+                                     max(args.steps, 20), 5, torch, (), fem)
+            vo = fem.Vjp(mc)
+            ms_v, _, _ = time_passes(lambda: fem.residual_vjp(mc, prc, dc, hc, lc, prec=pr, out=vo),
+                                     max(args.steps, 20), 5, torch, (), fem)
+            row[pn] = dict(ms_per_pass=ms_c, gp_updates_per_s=8 * pc.n_elems / (ms_c * 1e-3), ms_per_vjp=ms_v,
+                           vjp_per_s=1e3 / ms_v)
+        small[cname] = row
+        log(f"{cname}: fp64 {row['fp64']['ms_per_pass']:.3f} ms, mixed {row['mixed']['ms_per_pass']:.3f} ms per pass")
+    extras["small_configs"] = small
+
     if not args.no_extras:
         # ---- linear solve of a Newton iteration on the same system (FP32 K)
         solver = fem.Solver(csr)
@@ -423,32 +603,10 @@ def main():
         log(f"spmv {ms_spmv:.3f} ms ({spmv_bytes / (ms_spmv * 1e6):.0f} GB/s), bicgstab {ms_it:.3f} ms/iteration")
         del solver, xv, yv, rhs
         extras["elastic_solve"] = elastic_solve(csr, torch, fem, synth)
-        out_d = fem.Forward(mesh, csr, fem.FP64)
-        ms_d, _, kt_d = time_passes(
-            lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=fem.FP64, out=out_d),
-            max(args.steps // 2, 3), 2, torch, KS, fem)
-        kms_d = kt_d[fem.KERNEL_FORWARD]
-        # mixed vs FP64 on this very workload
-        torch.cuda.synchronize()
-        kd = out_d.K
-        km = out_m.K.double()
-        err_k = float(((km - kd).abs().max() / kd.abs().max()).cpu())
-        err_r = float(((out_m.R - out_d.R).abs().max() / out_d.R.abs().max()).cpu())
-        del km
-        log(f"fp64: {ms_d:.3f} ms/pass, kernel {kms_d:.3f} ms; mixed vs fp64 K {err_k:.2e} R {err_r:.2e}")
-        extras["fp64"] = dict(gp_updates_per_s=n_gp / (ms_d * 1e-3), ms_per_pass=ms_d,
-                              kernel_ms={"fwd_kernel": kms_d, "assemble_tangent": kt_d[fem.KERNEL_ASSEMBLE_K],
-                                         "assemble_residual": kt_d[fem.KERNEL_ASSEMBLE_R]},
-                              pass_hbm_algorithmic_GBps=algorithmic_bytes(p, csr.nnz, False, per_elem_cols)
-                              / (ms_d * 1e6))
-        if FLOP_PER_GP["fp64"]:
-            extras["fp64"]["fwd_kernel_TFLOPs"] = FLOP_PER_GP["fp64"] * n_gp / (kms_d * 1e-3) / 1e12
-        extras["mixed_vs_fp64_rel_err"] = dict(K=err_k, R=err_r)
-        del out_d, kd
-        torch.cuda.empty_cache()
 
-        # ---- model variants on the same cube: Voce hardening, one orientation
-        # per element (in-plane angles), the F-bar element, and all three
+        # ---- model variants on the same cube (FP32-mixed): Voce hardening, one
+        # orientation per element (in-plane angles), the F-bar element, all
+        # three, and the Barlat yield function (FP64 element kernel)
         variants = {}
         for vname, hard, fbar, orient, bar in (("voce", "voce", False, None, None),
                                                ("orient_per_elem", "swift", False, "per_element", None),
@@ -499,77 +657,27 @@ def main():
         del lam_c, mu_c, adj, KT
         torch.cuda.empty_cache()
 
-        # ---- VJP on the voided specimen
-        pv = synth.void_specimen()
-        mv = fem.Mesh(pv.X, pv.conn)
-        pv_params = fem.Params(pv.prm, pv.n_elems)
-        dv = torch.as_tensor(pv.d).cuda()
-        hv = torch.as_tensor(pv.hist_n).cuda()
-        lv = torch.as_tensor(pv.lam).cuda()
-        vj = {}
-        for name, prec in (("fp64", fem.FP64), ("mixed", fem.FP32_MIXED)):
-            vo = fem.Vjp(mv)
-            ms_v, _, kt_v = time_passes(
-                lambda: fem.residual_vjp(mv, pv_params, dv, hv, lv, prec=prec, out=vo),
-                args.steps, args.warmup, torch, (fem.KERNEL_VJP,), fem)
-            kms_v = kt_v[fem.KERNEL_VJP]
-            vj[name] = dict(vjp_per_s=1e3 / ms_v, gp_vjp_per_s=8 * pv.n_elems / (ms_v * 1e-3), ms_per_vjp=ms_v,
-                            kernel_ms=kms_v)
-            log(f"vjp {name}: {ms_v:.3f} ms")
-        extras["vjp_void_specimen"] = dict(n_elems=pv.n_elems, **vj)
+    # ---- VJP on the voided specimen
+    pv = synth.void_specimen()
+    mv = fem.Mesh(pv.X, pv.conn)
+    pv_params = fem.Params(pv.prm, pv.n_elems)
+    dv = torch.as_tensor(pv.d).cuda()
+    hv = torch.as_tensor(pv.hist_n).cuda()
+    lv = torch.as_tensor(pv.lam).cuda()
+    vj = {}
+    for name, prec in (("fp64", fem.FP64), ("mixed", fem.FP32_MIXED)):
+        vo = fem.Vjp(mv)
+        ms_v, _, kt_v = time_passes(
+            lambda: fem.residual_vjp(mv, pv_params, dv, hv, lv, prec=prec, out=vo),
+            args.steps, args.warmup, torch, (fem.KERNEL_VJP,), fem)
+        kms_v = kt_v[fem.KERNEL_VJP]
+        vj[name] = dict(vjp_per_s=1e3 / ms_v, gp_vjp_per_s=8 * pv.n_elems / (ms_v * 1e-3), ms_per_vjp=ms_v,
+                        kernel_ms=kms_v)
+        log(f"vjp {name}: {ms_v:.3f} ms")
+    extras["vjp_void_specimen"] = dict(n_elems=pv.n_elems, **vj)
 
-        # ---- batched: 64 uneven specimens, forward (mixed) + VJP (mixed) in one graph
-        specs = synth.batch64()
-        mb = synth.concat(specs)
-        bmesh = fem.Mesh(mb.X, mb.conn)
-        bcsr = fem.csr_pattern(bmesh)
-        bparams = fem.Params(mb.meta["spec_prm"], mb.n_elems, per_spec=True)
-        batch = fem.Batch(mb.meta["elem_off"])
-        bd = torch.as_tensor(mb.d).cuda()
-        bh = torch.as_tensor(mb.hist_n).cuda()
-        bl = torch.as_tensor(mb.lam).cuda()
-        bbc = torch.as_tensor(mb.bc_mask).cuda()
-        st = torch.cuda.Stream()
-        bo = fem.Forward(bmesh, bcsr, fem.FP32_MIXED)
-        bvo = fem.Vjp(bmesh, batch.n_spec)
-        g = fem.Graph()
-        torch.cuda.synchronize()
-        with torch.cuda.stream(st):
-            with g.capture(st):
-                fem.residual_tangent(bmesh, bcsr, bparams, bd, bh, bc_mask=bbc, prec=fem.FP32_MIXED, out=bo,
-                                     batch=batch, stream=st)
-                fem.residual_vjp(bmesh, bparams, bd, bh, bl, prec=fem.FP32_MIXED, out=bvo, batch=batch, stream=st)
-            for _ in range(3):
-                g.replay(st)
-            st.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(st)
-            for _ in range(args.steps):
-                g.replay(st)
-            e1.record(st)
-            st.synchronize()
-        ms_b = e0.elapsed_time(e1) / args.steps
-        # the same work as 64 separate plain FP64 calls
-        sep = []
-        for s in specs:
-            ms_ = fem.Mesh(s.X, s.conn)
-            sep.append((ms_, fem.csr_pattern(ms_), fem.Params(s.prm, s.n_elems), torch.as_tensor(s.d).cuda(),
-                        torch.as_tensor(s.hist_n).cuda(), torch.as_tensor(s.lam).cuda(),
-                        torch.as_tensor(s.bc_mask).cuda()))
-        sep_out = [(fem.Forward(a[0], a[1], fem.FP64), fem.Vjp(a[0])) for a in sep]
-
-        def run_sep():
-            for (ms_, cs, pr, dd, hh, ll, bb), (fo, vo) in zip(sep, sep_out):
-                fem.residual_tangent(ms_, cs, pr, dd, hh, bc_mask=bb, prec=fem.FP64, out=fo)
-                fem.residual_vjp(ms_, pr, dd, hh, ll, prec=fem.FP64, out=vo)
-        ms_sep, _, _ = time_passes(run_sep, max(args.steps // 4, 3), 2, torch, (fem.KERNEL_FORWARD,), fem)
-        extras["batched_64"] = dict(n_elems=mb.n_elems, ms_graph_fwd_vjp_mixed=ms_b,
-                                    specimen_fwd_vjp_per_s=64 / (ms_b * 1e-3),
-                                    gp_updates_per_s=8 * mb.n_elems / (ms_b * 1e-3),
-                                    ms_64_separate_fp64_calls=ms_sep)
-        log(f"batched graph {ms_b:.3f} ms vs separate fp64 {ms_sep:.3f} ms")
-        del sep, sep_out
+    if not args.no_extras:
+        extras["batched_64"] = batched_benchmark(args, torch, fem, synth)
         if not args.no_forward:
             # the paper's forward simulation of Sec. 3.1.3 end to end (F-bar element), after the timed pass
             try:
@@ -580,59 +688,103 @@ def main():
             except RuntimeError as err:
                 extras["forward_simulation"] = {"error": str(err)}
 
-    value = n_gp / (ms_m * 1e-3)
-    bc_np = p.bc_mask.astype(bool)
-    rp = csr.row_ptr.cpu().numpy()
-    bc_rows = np.nonzero(bc_np)[0]
-    bc_row_nnz = int((rp[bc_rows + 1] - rp[bc_rows]).sum())
-    kb = kernel_bytes(p, csr.nnz, True, per_elem_cols, bc_rows.size, bc_row_nnz)
-    kms = {"fwd_kernel": kms_m, "assemble_tangent": kt_m[fem.KERNEL_ASSEMBLE_K],
-           "assemble_residual": kt_m[fem.KERNEL_ASSEMBLE_R]}
-    roofs = {}
-    for name, ms_k in kms.items():
-        if name == "fwd_kernel":
-            # bound by VALU arithmetic: counted flops against the VALU peak
-            fl = FLOP_PER_GP["mixed"]
-            ach = fl * n_gp / (ms_k * 1e-3) / 1e12 if fl else None
-            roofs[name] = dict(bound="alu", achieved=ach, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                               frac=(ach / VALU_PEAK_TFLOPS) if ach else None, traffic=TRAFFIC_BYTES[name],
-                               flop_per_gp=fl, n_gp=n_gp, kernel_ms=ms_k,
-                               hbm_algorithmic_bytes=kb[name],
-                               hbm_GBps=kb[name] / (ms_k * 1e6))
-        else:
-            ach = kb[name] / (ms_k * 1e6)
-            roofs[name] = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                               traffic=TRAFFIC_BYTES[name], algorithmic_bytes=kb[name], kernel_ms=ms_k)
-    dom = max(kms, key=lambda k: kms[k])
-    roof = dict(kernel=dom, **roofs[dom])
-    extras["kernels"] = roofs
-    extras["pass_hbm_algorithmic_GBps"] = algorithmic_bytes(p, csr.nnz, True, per_elem_cols) / (ms_m * 1e6)
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        result_cpu = cpu_baseline(p, args.cpu_sample)
+        result_cpu = cpu_baseline(p, args.cpu_sample, args.cpu_sample_1t)
+        result_cpu["vjp"] = cpu_baseline_vjp(pv, args.cpu_sample_vjp_1t)
+        log(f"cpu baseline: {result_cpu['value']:.3e} GP/s on {result_cpu['cores']} threads, "
+            f"{result_cpu['single_thread']['value']:.3e} GP/s on one")
     else:
         result_cpu = None
-    result.update({
-        "metric": "Gauss-point updates/s (residual + tangent + CSR assembly), FP32-mixed",
-        "value": value,
+    result = {
+        "metric": "Gauss-point updates/s (residual + tangent + CSR assembly), FP64",
+        "value": n_gp / (ms_d * 1e-3),
         "unit": "GP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_m,
+        "ms_per_step": ms_d,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "large_cube 100x100x100 hex8, 1e6 elements, 3,090,903 dofs, 8e6 Gauss points, "
                                "per-element Hill-48 fields, 30% plastic at trial, x=0 face constrained",
-                   "n_elems": p.n_elems, "nnz": csr.nnz, "plastic_fraction": plastic, "diag": diag_m},
-        "roofline": roof,
+                   "n_elems": p.n_elems, "nnz": csr.nnz, "plastic_fraction": plastic, "diag": diag_d},
+        "roofline": roof_d,
         "cpu_baseline": result_cpu,
         "extras": extras,
-    })
+    }
     print(json.dumps(result), flush=True)
+
+
+def batched_benchmark(args, torch, fem, synth):
+    """64 uneven specimens, forward + VJP: one graph replay of the batched
+    calls against 64 separate eager calls per specimen, in FP64 and in
+    FP32-mixed (like for like), after the autotuner has picked the element
+    kernels' launch shapes for the batched workload in each precision."""
+    from paper_2606_17390_amd import tune
+    specs = synth.batch64()
+    mb = synth.concat(specs)
+    bmesh = fem.Mesh(mb.X, mb.conn)
+    bcsr = fem.csr_pattern(bmesh)
+    bparams = fem.Params(mb.meta["spec_prm"], mb.n_elems, per_spec=True)
+    batch = fem.Batch(mb.meta["elem_off"])
+    bd = torch.as_tensor(mb.d).cuda()
+    bh = torch.as_tensor(mb.hist_n).cuda()
+    bl = torch.as_tensor(mb.lam).cuda()
+    bbc = torch.as_tensor(mb.bc_mask).cuda()
+    sep = []
+    for s in specs:
+        ms_ = fem.Mesh(s.X, s.conn)
+        sep.append((ms_, fem.csr_pattern(ms_), fem.Params(s.prm, s.n_elems), torch.as_tensor(s.d).cuda(),
+                    torch.as_tensor(s.hist_n).cuda(), torch.as_tensor(s.lam).cuda(),
+                    torch.as_tensor(s.bc_mask).cuda()))
+    res = dict(n_spec=len(specs), n_elems=mb.n_elems)
+    st = torch.cuda.Stream()
+    for pname, prec in (("fp64", fem.FP64), ("mixed", fem.FP32_MIXED)):
+        tf = tune.tune_forward(bmesh, bcsr, bparams, bd, bh, prec=prec, bc_mask=bbc, batch=batch, use_cache=False)
+        tv = tune.tune_vjp(bmesh, bparams, bd, bh, bl, prec=prec, batch=batch, use_cache=False)
+        tuned = dict(forward=dict(block=tf[1], waves_per_cu=tf[2], xcd_remap=tf[3], kernel_ms=tf[0]),
+                     vjp=dict(block=tv[1], waves_per_cu=tv[2], xcd_remap=tv[3], kernel_ms=tv[0]))
+        bo = fem.Forward(bmesh, bcsr, prec)
+        bvo = fem.Vjp(bmesh, batch.n_spec)
+        g = fem.Graph()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            with g.capture(st):
+                fem.residual_tangent(bmesh, bcsr, bparams, bd, bh, bc_mask=bbc, prec=prec, out=bo, batch=batch,
+                                     stream=st)
+                fem.residual_vjp(bmesh, bparams, bd, bh, bl, prec=prec, out=bvo, batch=batch, stream=st)
+            for _ in range(3):
+                g.replay(st)
+            st.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(args.steps):
+                g.replay(st)
+            e1.record(st)
+            st.synchronize()
+        ms_g = e0.elapsed_time(e1) / args.steps
+        sep_out = [(fem.Forward(a[0], a[1], prec), fem.Vjp(a[0])) for a in sep]
+
+        def run_sep():
+            for (ms_, cs, pr, dd, hh, ll, bb), (fo, vo) in zip(sep, sep_out):
+                fem.residual_tangent(ms_, cs, pr, dd, hh, bc_mask=bb, prec=prec, out=fo)
+                fem.residual_vjp(ms_, pr, dd, hh, ll, prec=prec, out=vo)
+        ms_sep, _, _ = time_passes(run_sep, max(args.steps // 4, 3), 2, torch, (), fem)
+        res[pname] = dict(ms_graph_fwd_vjp=ms_g, ms_64_separate_calls=ms_sep, graph_speedup=ms_sep / ms_g,
+                          specimen_fwd_vjp_per_s=len(specs) / (ms_g * 1e-3),
+                          gp_updates_per_s=8 * mb.n_elems / (ms_g * 1e-3), tuned_launch=tuned)
+        log(f"batched {pname}: graph {ms_g:.3f} ms vs 64 separate calls {ms_sep:.3f} ms; tuned forward "
+            f"{tf[1:]} vjp {tv[1:]}")
+        del bo, bvo, g, sep_out
+        fem.set_launch(fem.KERNEL_FORWARD, prec)
+        fem.set_launch(fem.KERNEL_VJP, prec)
+    res["mixed_vs_fp64_graph_speedup"] = res["fp64"]["ms_graph_fwd_vjp"] / res["mixed"]["ms_graph_fwd_vjp"]
+    return res
 
 
 if __name__ == "__main__":
