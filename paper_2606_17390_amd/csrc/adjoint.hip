@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kAdjBlock) void hadj_kernel(const AdjArgs a) {
     constexpr bool FBAR = (VAR & kVarFbarA) != 0;
     constexpr int EPB = kAdjEpb;
     __shared__ double sN[EPB][8][9];   // X, d, lambda of the element's nodes
-    __shared__ double sG[EPB][8][24];  // g^ = Q^T grad N per Gauss point
+    __shared__ double sG[EPB][8][25];  // g^ = Q^T grad N per Gauss point (odd row length: no bank conflicts)
     __shared__ double red[24][kAdjBlock + 1];
     __shared__ double sQb[FBAR ? EPB : 1][24];
     const int tid = threadIdx.x, slot = tid >> 3, gp = tid & 7;

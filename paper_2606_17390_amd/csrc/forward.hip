@@ -111,7 +111,10 @@ constexpr int kVarBarlat = 8;  // FP64 kernel only (R = double)
 // 64 (3a + b) + 8 I + J of the element's 576.  Both triangles are stored, so
 // the assembly of node I's rows reads, for each block, 8 consecutive entries
 // of row I per incident element (and no entry twice); the element kernel
-// writes each block as 8 consecutive rows.
+// writes each block as 8 consecutive rows.  (Storing only the six blocks
+// a <= b of a symmetric K^e was measured: the assembly then reads three
+// blocks by columns, 8 sectors per row, and took 22 % longer in FP64 and
+// 14 % longer in FP32 than it saved in bytes.)
 constexpr int kKeStride = 576;
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * 3 - (a * (a - 1)) / 2 + (b - a); }
 __host__ __device__ constexpr int pair_a(int p) { return p < 3 ? 0 : (p < 5 ? 1 : 2); }
@@ -151,9 +154,9 @@ struct GP {
 
 // FBAR: the material sees Fbar = beta F (fbar_gradient); s.H becomes
 // Fbar - I and beta, cw, jm1 = J - 1 are returned for the tangent.
-template <typename R, bool FBAR>
-__device__ inline void kin_and_log(const double (*nd)[6], int gp, GP<R>& s, double eps[6], R& beta, R& cw, R& jm1) {
-    kinematics_lds<R, 6>(nd, gp, s.g, s.detJ, s.H);
+template <typename R, bool FBAR, int W>
+__device__ inline void kin_and_log(const double (*nd)[W], int gp, GP<R>& s, double eps[6], R& beta, R& cw, R& jm1) {
+    kinematics_lds<R, W>(nd, gp, s.g, s.detJ, s.H);
     if constexpr (FBAR) fbar_gradient<R>(s.detJ, s.H, beta, cw, jm1);
     R M[3][3];
     cauchy_green_minus_identity<R>(s.H, M);
@@ -172,7 +175,9 @@ __device__ inline void kin_and_log(const double (*nd)[6], int gp, GP<R>& s, doub
 // stored element tangent blocks; FIXUP: walk the element list of the guard
 // band instead of all elements (FP64 recomputation for the mixed path).
 // The FP32 model variants are held to two waves per SIMD (the plain kernel
-// fits there by itself).
+// fits there by itself).  The FP64 kernel runs one wave per SIMD: held to
+// two (at most 256 registers, 20 KB of LDS, only Q parked across the local
+// update) it spilled about 100 registers to scratch and took 10 % longer.
 template <typename R, typename RO, int BLOCK, bool FIXUP, int VAR>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value && !FIXUP && VAR != 0 ? 2 : 1)))
 void fwd_kernel(const FwdArgs a) {
@@ -186,21 +191,29 @@ void fwd_kernel(const FwdArgs a) {
     // gradients g^ of every Gauss point; and one buffer used in turn for H
     // and Q (F-bar: and beta, cw) across the local update, the residual
     // reduction and the tangent hand-off (the 3 blocks A^ of one phase per
-    // Gauss point; F-bar: first the element sums of the rank-one term)
-    constexpr int kHQ = FBAR ? 20 : 18;
+    // Gauss point; F-bar: first the element sums of the rank-one term).
+    // Every per-lane row has an odd length (in values), so that the 64 lanes
+    // of a wave, each at its own row, spread over the LDS banks (even
+    // strides cost up to 16-way bank conflicts); a row read by the 8 lanes
+    // of an element at once is a broadcast.  The Barlat kernel keeps even
+    // node and hand-off rows: its LDS (with the parked Cep) must stay within
+    // 40 KB for four workgroups per CU, worth more to it than the conflicts.
+    constexpr int kHQ = FBAR ? 21 : 19;
     constexpr int kRed = 24 * (BLOCK + 1);
-    constexpr int kHand = EPB * 8 * 28;
+    constexpr int kHandW = BARLAT ? 28 : 29;
+    constexpr int kXDW = BARLAT ? 6 : 7;
+    constexpr int kHand = EPB * 8 * kHandW;
     constexpr int kPark = EPB * 8 * kHQ;
     constexpr int kBuf = kRed > kHand ? (kRed > kPark ? kRed : kPark) : (kHand > kPark ? kHand : kPark);
-    __shared__ double sXD[EPB][8][6];
-    __shared__ __attribute__((aligned(16))) R sG[EPB][8][24];  // [slot][g][3 I + q]
+    __shared__ double sXD[EPB][8][kXDW];                       // [slot][node][X 3, d 3, pad]
+    __shared__ __attribute__((aligned(16))) R sG[EPB][8][25];  // [slot][g][3 I + q] (+1 pad)
     __shared__ __attribute__((aligned(16))) R sbuf[kBuf];
     __shared__ int sFlag[EPB];
     __shared__ R sQb[FBAR ? EPB : 1][24];                      // F-bar: qbar of the element
     __shared__ double sCep[BARLAT ? EPB : 1][8][BARLAT ? 21 : 1];  // Barlat: Cep (upper triangle, material frame)
     R (*sHQ)[8][kHQ] = reinterpret_cast<R (*)[8][kHQ]>(sbuf);   // [slot][g][H 9, Q 9 (, beta, cw)]
     R (*red)[BLOCK + 1] = reinterpret_cast<R (*)[BLOCK + 1]>(sbuf);
-    R (*sA)[8][28] = reinterpret_cast<R (*)[8][28]>(sbuf);      // [slot][g][9 k + 3 q + s]
+    R (*sA)[8][kHandW] = reinterpret_cast<R (*)[8][kHandW]>(sbuf);  // [slot][g][9 k + 3 q + s]
 
     const int tid = threadIdx.x;
     const int slot = tid >> 3, gp = tid & 7;
@@ -250,7 +263,7 @@ void fwd_kernel(const FwdArgs a) {
         GP<R> s;
         double eps[6];
         R fb_beta = R(1), fb_cw = R(0), fb_jm1 = R(0);
-        kin_and_log<R, FBAR>(sXD[slot], gp, s, eps, fb_beta, fb_cw, fb_jm1);
+        kin_and_log<R, FBAR, kXDW>(sXD[slot], gp, s, eps, fb_beta, fb_cw, fb_jm1);
         if constexpr (FBAR) {
             // det F <= 0 is counted on F (s.H now holds Fbar - I)
             if (valid && !FIXUP) cnt_jf += (fb_jm1 <= R(-1)) ? 1 : 0;
@@ -589,7 +602,7 @@ void fwd_kernel(const FwdArgs a) {
             }
             // element sums Ubar (row gp) and qbar through the hand-off area, in
             // Gauss point order
-            R (*sU)[8][24] = reinterpret_cast<R (*)[8][24]>(sbuf);
+            R (*sU)[8][25] = reinterpret_cast<R (*)[8][25]>(sbuf);
             {
                 const R w3 = wdet * R(1.0 / 3.0);
 #pragma unroll
@@ -797,12 +810,12 @@ void fwd_kernel(const FwdArgs a) {
                 __syncthreads();
             });
             // blocks (b, a), a < b: row I of (b, a) is column I of (a, b),
-            // handed over through the g^ area (free after the two phases)
-            R* tt = &sG[slot][0][0];  // [3][8 I][8 J]
+            // handed over through the hand-off area (free after the two phases)
+            R* tt = &sA[slot][0][0];  // [3][8 I][9] (216 <= 8 x 28 values)
 #pragma unroll
             for (int t = 0; t < 3; ++t)
 #pragma unroll
-                for (int J = 0; J < 8; ++J) tt[64 * t + 8 * gp + J] = keep[t][J];
+                for (int J = 0; J < 8; ++J) tt[72 * t + 9 * gp + J] = keep[t][J];
             __syncthreads();
             if (valid) {
                 RO* Kd = reinterpret_cast<RO*>(a.Ke) + e * kKeStride;
@@ -812,10 +825,10 @@ void fwd_kernel(const FwdArgs a) {
                     RO* row = Kd + ke_offset(gp, pair_b(p), pair_a(p), 0);
                     RO v4[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) v4[j] = (RO)tt[64 * t + 8 * j + gp];
+                    for (int j = 0; j < 4; ++j) v4[j] = (RO)tt[72 * t + 9 * j + gp];
                     store4<RO>(row, v4);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) v4[j] = (RO)tt[64 * t + 8 * (4 + j) + gp];
+                    for (int j = 0; j < 4; ++j) v4[j] = (RO)tt[72 * t + 9 * (4 + j) + gp];
                     store4<RO>(row + 4, v4);
                 });
             }

@@ -139,8 +139,8 @@ void vjp_kernel(const VjpArgs a) {
     __shared__ int sFlag[EPB];
     // per lane, across the local update (registers are the limit there): the
     // frame gradients g^ = Q^T grad N and H, Q
-    __shared__ R sG[EPB][8][24];
-    __shared__ R sHQ[EPB][8][18];
+    __shared__ R sG[EPB][8][25];   // odd row lengths: the lanes spread over the LDS banks
+    __shared__ R sHQ[EPB][8][19];
     const int tid = threadIdx.x;
     const int slot = tid >> 3, gp = tid & 7;
     int32_t cnt_fail = 0, cnt_j0 = 0;
