@@ -49,10 +49,13 @@ enum { P_E, P_NU, P_F, P_G, P_H, P_L, P_M, P_N, P_K, P_EPS0, P_NEXP };
 
 static const double SQRT2 = 1.41421356237309504880168872420969808;
 
-/* local Newton constants (not given by the paper; see design notes) */
+/* local Newton constants: App. B gives the two line-search constants; the
+ * paper fixes no tolerance and no iteration limit for the element runs.  The
+ * limit is generous: with the merit of Eq. (merit) an extreme increment
+ * (stretches 3 and 0.2 in one step) needs about 130 damped iterations. */
 static const double LS_BETA = 1e-4; /* App. B, Goldstein constant */
 static const double LS_ETA = 0.1;   /* App. B, step safeguard     */
-enum { KMAX = 100, JMAX = 20 };
+enum { KMAX = 500, JMAX = 20 };
 static const double LOCAL_TOL = 1e-14;
 
 /* Mandel index pairs: (11, 22, 33, 23, 13, 12) */
@@ -656,7 +659,7 @@ static int cpp_solve(const cpp_ctx *c, double y[8], cpp_opts *o) {
     double D[8] = {1 / mu, 1 / mu, 1 / mu, 1 / mu, 1 / mu, 1 / mu, 1.0, 1.0 / sy_n};
     double Dm[8];
     for (int i = 0; i < 8; ++i) Dm[i] = o->scaled ? D[i] : 1.0;
-    double prev = INFINITY;
+    double prev = INFINITY, best = INFINITY, ybest[8];
     for (int k = 0; k <= o->kmax; ++k) {
         double G[8], J[64], dy[8];
         cpp_residual(c, y, G);
@@ -664,8 +667,19 @@ static int cpp_solve(const cpp_ctx *c, double y[8], cpp_opts *o) {
         for (int i = 0; i < 8; ++i) gn = fmax(gn, fabs(D[i] * G[i]));
         if (!(gn == gn)) return -(k + 1);
         if (gn <= LOCAL_TOL) return k;
-        /* rounding floor reached: no further decrease below 1e-12 */
-        if (gn <= 1e-12 && gn >= 0.5 * prev) return k;
+        /* rounding floor reached: a step below 1e-9 that does not halve the
+         * residual; the best iterate is kept.  The floor grows with the size
+         * of the stress (about 1.5e-12 at a hydrostatic stress of -8.5e4 MPa),
+         * so it is detected by the stalled decrease, not by a fixed level. */
+        if (gn <= 1e-9 && gn >= 0.5 * prev) {
+            if (best < gn)
+                for (int i = 0; i < 8; ++i) y[i] = ybest[i];
+            return k;
+        }
+        if (gn < best) {
+            best = gn;
+            for (int i = 0; i < 8; ++i) ybest[i] = y[i];
+        }
         if (k == o->kmax) break;
         prev = gn;
         cpp_jacobian(c, y, J);

@@ -127,6 +127,40 @@ def test_hill_reduces_to_von_mises(seed):
     assert rel(r["Cep_implicit"], C) <= 1e-12
 
 
+@pytest.mark.parametrize("F0", [np.diag([3.0, 0.2, 1.0]),
+                                np.array([[3.0, 0.8, 0.0], [0.0, 0.2, 0.1], [0.3, 0.0, 1.0]])])
+def test_extreme_increment_converges_to_radial_return(F0):
+    """An extreme increment (stretch 3 and 0.2 in one step, alpha_n = 1.5,
+    hydrostatic stress near -8.5e4 MPa) from a plastic history: the local
+    Newton stops at its rounding floor (about 1e-12 in scaled units, detected
+    by a stalled decrease), reports convergence, and at F = G = H = 0.5 its
+    state equals the textbook J2 radial return; with a generic Hill-48 the
+    returned state is on the yield surface."""
+    prm = vm_params()
+    h = np.zeros(7)
+    h[6] = 1.5
+    r = oracle.material_point(F0, h, prm)
+    assert r["plastic"] and r["converged"]
+    eps = 0.5 * np.real(sl.logm(F0.T @ F0))
+    T, epsp1, a1, C, plastic = j2_radial_return(eps, np.zeros((3, 3)), 1.5, prm[8], prm[9], prm[10])
+    assert plastic
+    assert rel(r["T"], T) <= 1e-12
+    assert abs(r["hist"][6] - a1) <= 1e-12 * a1
+    assert rel(r["hist"][:6], hist_vec(epsp1, a1)[:6]) <= 1e-11
+    hill = prm.copy()
+    hill[2:5] = (0.745901362, 0.22548628, 0.78819568)
+    rh = oracle.material_point(F0, h, hill)
+    assert rh["plastic"] and rh["converged"]
+    Tm = rh["T"]
+    Fh, Gh, Hh = hill[2:5]
+    phi = np.sqrt(Fh * (Tm[1, 1] - Tm[2, 2]) ** 2 + Gh * (Tm[2, 2] - Tm[0, 0]) ** 2 + Hh * (Tm[0, 0] - Tm[1, 1]) ** 2
+                  + 2 * 1.5 * (Tm[1, 2] ** 2 + Tm[0, 2] ** 2 + Tm[0, 1] ** 2))
+    a = rh["hist"][6]
+    # T = E : (eps - eps^p): its deviator (about 600 MPa) is a difference of
+    # terms of the size of |T| (about 8.5e4 MPa), so it is exact to ~1e-12 |T|
+    assert abs(phi - hill[8] * (hill[9] + a) ** hill[10]) <= 1e-11 * np.abs(Tm).max()
+
+
 # ---------------------------------------------------------------- closed forms, generic Hill
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
