@@ -133,16 +133,20 @@ def _node_rows_from_oracle(p, nodes, prm):
 
 
 @pytest.mark.parametrize("prec_name,variant", [("fp64", "plain"), ("mixed", "plain"),
-                                               ("mixed", "fbar_voce_orient")])
+                                               ("mixed", "fbar_voce_orient"), ("fp64", "barlat"),
+                                               ("mixed", "barlat")])
 def test_large_cube_sampled_parity(fem, prec_name, variant):
     """Full 100^3 problem (1e6 elements, nnz 245,438,109) in the launch
     configuration the benchmark uses; residual and tangent rows of sampled
     nodes and the history of sampled Gauss points against the oracle.  The
-    model variant adds the F-bar element, Voce hardening (per-element draws)
-    and one orientation per element."""
+    model variants add the F-bar element, Voce hardening (per-element draws)
+    and one orientation per element, or replace Hill-48 by the Barlat
+    Yld2004-18p function with the published AA6111 coefficients (App. A)."""
     p = synth.large_cube()
-    if variant != "plain":
+    if variant == "fbar_voce_orient":
         p = synth.with_model(p, 11, "voce", True, "per_element")
+    elif variant == "barlat":
+        p = synth.with_model(p, 11, barlat=synth.BARLAT_AA6111)
     prec = fem.FP64 if prec_name == "fp64" else fem.FP32_MIXED
     say("large cube", prec_name, variant)
     mesh, params, d, h, bc, lam = gpu_problem(p, fem)
@@ -189,3 +193,77 @@ def test_large_cube_sampled_parity(fem, prec_name, variant):
         assert abs(plastic - 0.30) <= 0.005
     else:
         assert plastic > 0.05
+
+
+@pytest.fixture(scope="module")
+def batch64():
+    specs = synth.batch64()
+    return specs, synth.concat(specs)
+
+
+@pytest.fixture(scope="module")
+def batch64_vjp_oracle(batch64):
+    specs, _ = batch64
+    return [oracle.residual_vjp(s.X, s.conn, s.prm, s.d, s.hist_n, s.lam) for s in specs]
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "mixed"])
+def test_batch64_per_specimen_parity(fem, batch64, batch64_vjp_oracle, prec_name):
+    """The 64-specimen batch (1.25M elements, element counts log-uniform in
+    [2,000, 60,000], per-specimen parameters) in one batched call each of the
+    forward pass and the VJP, with the Dirichlet rows, as the benchmark
+    launches it.  Per specimen against the oracle: the residual and tangent
+    rows of two sampled free nodes, the history of four sampled Gauss points,
+    the specimen's uniform gradient and its per-element gradients."""
+    specs, m = batch64
+    prec = fem.FP64 if prec_name == "fp64" else fem.FP32_MIXED
+    tol = TOL_FP64 if prec == fem.FP64 else TOL_MIXED
+    say("batch64", prec_name, m.n_elems)
+    mesh = fem.Mesh(m.X, m.conn)
+    csr = fem.csr_pattern(mesh)
+    params = fem.Params(m.meta["spec_prm"], m.n_elems, per_spec=True)
+    batch = fem.Batch(m.meta["elem_off"])
+    d = torch.as_tensor(m.d).cuda()
+    h = torch.as_tensor(m.hist_n).cuda()
+    lam = torch.as_tensor(m.lam).cuda()
+    bc = torch.as_tensor(m.bc_mask).cuda()
+    out = fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=prec, batch=batch)
+    v = fem.residual_vjp(mesh, params, d, h, lam, prec=prec, batch=batch)
+    torch.cuda.synchronize()
+    assert list(out.diag.cpu().numpy()) == [0, 0, 0, 0]
+    R = out.R.cpu().numpy()
+    rp = csr.row_ptr.cpu().numpy()
+    hist = out.hist.cpu().numpy()
+    gu = v.g_uniform.cpu().numpy()
+    ge = v.g_elem.cpu().numpy()
+    no, eo = m.meta["node_off"], m.meta["elem_off"]
+    rng = np.random.default_rng(6)
+    for i, s in enumerate(specs):
+        free = np.nonzero(~s.bc_mask.reshape(-1, 3).astype(bool).any(axis=1))[0]
+        nodes = [int(n) for n in rng.choice(free, 2, replace=False)]
+        prm_e = np.broadcast_to(s.prm, (s.n_elems, 11))
+        ref = _node_rows_from_oracle(s, nodes, prm_e)
+        Kscale = max(np.abs(Kr).max() for _, (_, kr) in ref.items() for Kr in kr.values())
+        Rscale = max(np.abs(r).max() for _, (r, _) in ref.items())
+        for n, (Rn, Krow) in ref.items():
+            gn = int(no[i]) + n
+            assert np.abs(R[3 * gn:3 * gn + 3] - Rn).max() <= tol * Rscale, (i, n)
+            for a in range(3):
+                r = 3 * gn + a
+                cols = csr.col_idx[rp[r]:rp[r + 1]].cpu().numpy()
+                vals = out.K[rp[r]:rp[r + 1]].double().cpu().numpy()
+                expect = np.zeros_like(vals)
+                for nj, blk in Krow.items():
+                    for b in range(3):
+                        expect[np.searchsorted(cols, 3 * (int(no[i]) + nj) + b)] = blk[a, b]
+                assert np.abs(vals - expect).max() <= tol * Kscale, (i, n, a)
+        for qq in rng.choice(8 * s.n_elems, 4, replace=False):
+            e, g = divmod(int(qq), 8)
+            _, _, hnp, _ = oracle.element(s.X[s.conn[e]], s.d[s.conn[e]], s.hist_n[:, 8 * e:8 * e + 8].T, s.prm,
+                                          want_K=False)
+            hq = hist[:, 8 * int(eo[i]) + int(qq)]
+            assert np.abs(hq[6] - hnp[g][6]) <= tol * max(abs(hnp[g][6]), 1e-3), (i, qq)
+            assert np.abs(hq[:6] - hnp[g][:6]).max() <= tol * max(np.abs(hnp[g][:6]).max(), 1e-4), (i, qq)
+        og, oge, _ = batch64_vjp_oracle[i]
+        assert np.abs(gu[i] - og).max() <= tol * np.abs(og).max(), i
+        assert np.abs(ge[:, eo[i]:eo[i + 1]] - oge).max() <= tol * np.abs(oge).max(), i

@@ -118,3 +118,51 @@ def test_non_finite_displacement_is_counted_and_contained(fem, prec_name):
     assert np.all(np.isfinite(g["R"][rows]))
     tol = TOL_FP64 if prec_name == "FP64" else TOL_MIXED
     assert rel_inf(g["R"][rows], o["R"][rows]) <= tol
+
+
+EXTREME_F = {
+    "stretch": np.diag([3.0, 0.2, 1.0]),
+    "stretch_shear": np.array([[3.0, 0.8, 0.0], [0.0, 0.2, 0.1], [0.3, 0.0, 1.0]]),
+}
+
+
+def extreme_problem(kind, hardening):
+    """A 2x1x1 slab deformed homogeneously by an extreme increment (stretches 3
+    and 0.2 in one step, hydrostatic stress near -8.5e4 MPa) from a plastic
+    history alpha_n = 1.5 (with a small random plastic strain), so that the
+    local Newton (Alg. C2) runs far from its start at every Gauss point."""
+    p = synth.small_slab(83, 2, 1, 1)
+    if hardening != "swift":
+        p = synth.with_model(p, 84, hardening)
+    F0 = EXTREME_F[kind]
+    Xc = p.X.mean(axis=0)
+    d = (p.X - Xc) @ (F0 - np.eye(3)).T
+    rng = np.random.default_rng(85)
+    h = np.zeros((7, 8 * p.n_elems))
+    h[:3] = rng.uniform(-1e-3, 1e-3, (3, 8 * p.n_elems))
+    h[:3] -= h[:3].mean(axis=0)  # plastic strain is deviatoric
+    h[6] = 1.5
+    return dataclasses.replace(p, d=d, hist_n=h, bc_mask=None)
+
+
+@pytest.mark.parametrize("kind", list(EXTREME_F))
+@pytest.mark.parametrize("hardening", ["swift", "voce"])
+def test_extreme_increment_matches_oracle(fem, kind, hardening):
+    """R, K, history and the diagnostic counters of an extreme increment
+    against the oracle: both local solvers converge (diag zero) to the same
+    state, in FP64 within 1e-10 and in the mixed form within 1e-5."""
+    p = extreme_problem(kind, hardening)
+    say("extreme increment", kind, hardening)
+    o = oracle_forward(p, bc=False)
+    assert list(o["diag"]) == [0, 0, 0, 0]
+    assert (o["hist"][6] > 2.5).all()  # far into the plastic range
+    g = gpu_forward(p, fem, fem.FP64, bc=False)
+    assert list(g["diag"]) == list(o["diag"])
+    assert rel_inf(g["R"], o["R"]) <= TOL_FP64
+    assert rel_inf(g["K"], o["K"]) <= TOL_FP64
+    assert hist_rel(g["hist"], o["hist"]) <= TOL_FP64
+    m = gpu_forward(p, fem, fem.FP32_MIXED, bc=False)
+    assert list(m["diag"]) == list(o["diag"])
+    assert rel_inf(m["R"], o["R"]) <= TOL_MIXED
+    assert rel_inf(m["K"], o["K"]) <= TOL_MIXED
+    assert hist_rel(m["hist"], o["hist"]) <= TOL_MIXED
