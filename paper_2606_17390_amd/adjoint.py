@@ -5,14 +5,17 @@ keeps the checkpoints H[n] = (u^n, h^n) in device memory.  The backward pass
 runs from the last step with mu^{N_T} = 0:
 
     ubar   = mu^n^T dH^n/du^n                          (fem_history_adjoint)
-    K^n^T lambda^n = -(2 w (u^n - u_gt^n) + ubar)      (fem_csr_transpose + fem_solve)
+    K^n^T lambda^n = -(2 w (u^n - u_gt^n) + ubar)      (fem_solve; fem_csr_transpose for F-bar)
     g     += lambda^n^T dR^n/dtheta + mu^n^T dH^n/dtheta
     mu^{n-1} = lambda^n^T dR^n/dh^{n-1} + mu^n^T dH^n/dh^{n-1}
 
 for the objective J = w sum_n ||u^n - u_gt^n||^2 of Eq. (J).  Constrained
 dofs are prescribed: their rows of K^T are identity rows and their
-right-hand side is zero, so lambda vanishes there.  Every step runs in the
-library; this module sequences the calls.
+right-hand side is zero, so lambda vanishes there.  The system is then the
+free-free block K_ff^T lambda_f = b_f, and for a symmetric tangent (every
+element but F-bar) K_ff^T = K_ff: the assembled K itself is solved (its
+constrained rows are identity rows too) and no transpose is formed.  Every
+step runs in the library; this module sequences the calls.
 
     ck = adjoint.forward(mesh, csr, params, bc_mask, bc_steps, hist0)
     J, grad = adjoint.objective(ck, u_gt, w), adjoint.gradient(mesh, csr, params, bc_mask, ck, u_gt, w)[0]
@@ -79,6 +82,7 @@ def gradient(mesh, csr, params, bc_mask, ck, u_gt, w, lin_rtol=1e-12, lin_max_it
     grad = torch.zeros(fem.NGRAD, dtype=torch.float64, device=dev)
     g_elem = torch.zeros((fem.NGRAD, mesh.n_elems), dtype=torch.float64, device=dev)
     KT = None
+    symmetric = (params.model & fem.MODEL_FBAR) == 0
     lams = [None] * len(ck.d)
     for n in range(len(ck.d) - 1, -1, -1):
         d, h_prev = ck.d[n], ck.h[n]
@@ -86,7 +90,10 @@ def gradient(mesh, csr, params, bc_mask, ck, u_gt, w, lin_rtol=1e-12, lin_max_it
         rhs = -(2.0 * w * (d - u_gt[n]) + adj.ubar).reshape(-1)
         rhs[bc] = 0.0
         fem.residual_tangent(mesh, csr, params, d, h_prev, bc_mask=bc_mask, prec=fem.FP64, out=fwd)
-        KT = fem.csr_transpose(csr, fwd.K, bc_mask=bc_mask, out=KT)
+        if symmetric:
+            KT = fwd.K  # K_ff^T = K_ff
+        else:
+            KT = fem.csr_transpose(csr, fwd.K, bc_mask=bc_mask, out=KT)
         lam, _, res = solver.solve(KT, rhs, rtol=lin_rtol, max_iter=lin_max_iter, check=False)
         if not (res <= 1e-8):
             raise RuntimeError(f"adjoint solve of step {n + 1}: relative residual {res:.3e}")
