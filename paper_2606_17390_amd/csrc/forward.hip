@@ -141,79 +141,6 @@ __device__ inline void tile_range(int64_t n_tiles, int remap, int64_t& first, in
     }
 }
 
-// The Gauss-point sums of three tangent blocks K^e(a,b), p = 3 ph + k, of the
-// 8 elements of each wave on the matrix cores (FP32, v_mfma_f32_4x4x1_16b:
-// 16 independent 4x4 outer-product tiles per instruction; the lane that
-// holds operand row i of tile t is 4t + i, and register i of lane 4t + j
-// receives entry (i, j)).  Per element, Gauss point g and block k:
-//   W = A^(k) G^T   (3 x 8, rows q, columns J:  W_qJ = sum_s A_qs g^_Js)
-//   K(k) += G W      (8 x 8:  K_IJ += sum_q g^_Iq W_qJ)
-// Tile t of lane l = 4t + i is (element 4 eh + t / 4 of the wave, row tile
-// tM = (t / 2) % 2, column tile tN = t % 2), for element halves eh = 0, 1;
-// the W tile of column tile tN comes out of the first product in exactly the
-// lanes and registers the second takes as its B operand.  Inputs: g^ and the
-// phase's A^ blocks of every Gauss point in LDS (sG[slot][g][3 I + q],
-// sA[slot][g][9 k + 3 q + s]); the blocks (b, a), a < b, are stored from the
-// same registers as their transposes.
-typedef float fem_v4f __attribute__((ext_vector_type(4)));
-template <int PH, typename RO, int EPB, typename GT, typename AT>
-__device__ inline void contract_phase_mfma(GT sG, AT sA, int64_t tile, int64_t n_work, void* Ke) {
-    const int tid = threadIdx.x;
-    const int l = tid & 63;
-    const int wslot = (tid >> 6) << 3;  // first element slot of this wave
-    const int eq = l >> 4, tM = (l >> 3) & 1, tN = (l >> 2) & 1, ii = l & 3;
-    fem_v4f acc[3][2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) acc[k][h] = fem_v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int g = 0; g < 8; ++g) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int es = wslot + 4 * h + eq;
-            float gB[3], gA[3];
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                gB[t] = sG[es][g][3 * (4 * tN + ii) + t];
-                gA[t] = sG[es][g][3 * (4 * tM + ii) + t];
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                fem_v4f w = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    const float av = ii < 3 ? sA[es][g][9 * k + 3 * ii + t] : 0.f;
-                    w = __builtin_amdgcn_mfma_f32_4x4x1f32(av, gB[t], w, 0, 0, 0);
-                }
-#pragma unroll
-                for (int q = 0; q < 3; ++q) acc[k][h] = __builtin_amdgcn_mfma_f32_4x4x1f32(gA[q], w[q], acc[k][h], 0, 0, 0);
-            }
-        }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int64_t e = tile * EPB + wslot + 4 * h + eq;
-        if (e >= n_work) continue;
-        RO* Kd = reinterpret_cast<RO*>(Ke) + e * kKeStride;
-        static_for<0, 3>([&](auto KK) {
-            constexpr int k = decltype(KK)::value;
-            constexpr int p = 3 * PH + k;
-            constexpr int pa = pair_a(p), pb = pair_b(p);
-            // entries (4 tM + r, 4 tN + ii) of block (pa, pb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Kd[ke_offset(4 * tM + r, pa, pb, 4 * tN + ii)] = (RO)acc[k][h][r];
-            if constexpr (pa != pb) {
-                // the same entries are (4 tN + ii, 4 tM + r) of block (pb, pa)
-                RO v4[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v4[r] = (RO)acc[k][h][r];
-                store4<RO>(Kd + ke_offset(4 * tN + ii, pb, pa, 4 * tM), v4);
-            }
-        });
-    }
-}
-
 // Everything one lane needs after the constitutive update, in working type R.
 template <typename R>
 struct GP {
@@ -247,19 +174,18 @@ __device__ inline void kin_and_log(const double (*nd)[W], int gp, GP<R>& s, doub
 // R: working type of kinematics, pull-back and contraction; RO: type of the
 // stored element tangent blocks; FIXUP: walk the element list of the guard
 // band instead of all elements (FP64 recomputation for the mixed path).
-// The FP32 kernels are held to two waves per SIMD.  The FP64 kernel runs one wave per SIMD: held to
+// The FP32 model variants are held to two waves per SIMD (the plain kernel
+// fits there by itself).  The FP64 kernel runs one wave per SIMD: held to
 // two (at most 256 registers, 20 KB of LDS, only Q parked across the local
 // update) it spilled about 100 registers to scratch and took 10 % longer.
 template <typename R, typename RO, int BLOCK, bool FIXUP, int VAR>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value && !FIXUP ? 2 : 1)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value && !FIXUP && VAR != 0 ? 2 : 1)))
 void fwd_kernel(const FwdArgs a) {
     constexpr int EPB = BLOCK / 8;
     constexpr bool FLAG = std::is_same<R, float>::value && !FIXUP;
     constexpr bool ORIENT = (VAR & kVarOrient) != 0;
     constexpr bool FBAR = (VAR & kVarFbar) != 0;
     constexpr bool BARLAT = (VAR & kVarBarlat) != 0;
-    // the FP32 contraction of the plain element on the matrix cores
-    constexpr bool MFMA = std::is_same<R, float>::value && VAR == 0 && !FIXUP;
     static_assert(!BARLAT || std::is_same<R, double>::value, "the Barlat variant runs in FP64");
     // LDS: node coordinates and displacements of the tile; the frame
     // gradients g^ of every Gauss point; and one buffer used in turn for H
@@ -827,11 +753,6 @@ void fwd_kernel(const FwdArgs a) {
                     });
                 });
                 __syncthreads();
-                if constexpr (MFMA) {
-                    contract_phase_mfma<ph, RO, EPB>(sG, sA, tile, n_work, a.Ke);
-                    __syncthreads();
-                    return;  // next phase (static_for body)
-                }
                 // lane gp = row I
                 R acc[3][8];
 #pragma unroll
@@ -890,7 +811,6 @@ void fwd_kernel(const FwdArgs a) {
             });
             // blocks (b, a), a < b: row I of (b, a) is column I of (a, b),
             // handed over through the hand-off area (free after the two phases)
-            if constexpr (!MFMA) {
             R* tt = &sA[slot][0][0];  // [3][8 I][9] (216 <= 8 x 28 values)
 #pragma unroll
             for (int t = 0; t < 3; ++t)
@@ -912,7 +832,6 @@ void fwd_kernel(const FwdArgs a) {
                     store4<RO>(row + 4, v4);
                 });
             }
-            }  // VALU transposes
             }  // F-bar / symmetric tangent
         }
         if (valid && !finite_gp && !FIXUP) ++cnt_nan;
