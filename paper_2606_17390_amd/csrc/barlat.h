@@ -288,10 +288,19 @@ __device__ inline void elastic_compliance(const Modes& h, const double x[6], dou
     for (int k = 0; k < 3; ++k) y[k] += hm / h.k3;  // (3 kappa)^-1 on the spherical part
 }
 
-// Scaled residual of the reduced closest-point equations at (T, dg):
-//   G1 = E^-1 (T - t_tr) + dg N(T)  (strain),  G3 = phi(T) - sigma_y(alpha_n + dg)
+// E : x for isotropic elasticity (Mandel)
+__device__ inline void elastic_stiffness(const Modes& h, const double x[6], double y[6]) {
+    const double tr = x[0] + x[1] + x[2];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] = h.mu2 * x[k] + (k < 3 ? h.lam * tr : 0.0);
+}
+
+// Residual of the reduced closest-point equations at (T, dg), alpha = alpha_n + dg:
+//   G1 = E^-1 (T - t_tr) + dg N(T)  (strain),  G3 = phi(T) - sigma_y(alpha_n + dg),
+// and the merit of Eq. (merit), psi = 1/2 G^T G with the stress rows
+// T - t_tr + dg E : N = E : G1 and the yield row G3 (both in stress units).
 __device__ inline double barlat_residual(const BarlatCoef& b, const Mat& m, const Modes& md, const double t_tr[6],
-                                         double alpha_n, const double T[6], double dg, double sy_scale, double G[7],
+                                         double alpha_n, const double T[6], double dg, double G[7],
                                          BarlatState& st, double& dsig) {
     barlat_principal(b, T, st);
     double N[6], dT[6], c[6];
@@ -299,15 +308,16 @@ __device__ inline double barlat_residual(const BarlatCoef& b, const Mat& m, cons
 #pragma unroll
     for (int k = 0; k < 6; ++k) dT[k] = T[k] - t_tr[k];
     elastic_compliance(md, dT, c);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) G[k] = c[k] + dg * N[k];
+    double Eg[6];
+    elastic_stiffness(md, G, Eg);
     double psi = 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        G[k] = c[k] + dg * N[k];
-        psi += (md.mu2 * G[k]) * (md.mu2 * G[k]);
-    }
+    for (int k = 0; k < 6; ++k) psi += Eg[k] * Eg[k];
     const double sy = hardening(m, alpha_n + dg, dsig);
     G[6] = st.phi - sy;
-    psi += (G[6] / sy_scale) * (G[6] / sy_scale);
+    psi += G[6] * G[6];
     return 0.5 * psi;
 }
 
@@ -366,16 +376,24 @@ __device__ inline void local_update_barlat(const double eps[6], const double* hi
         dg = (1.0 - r) * nc / nn;
         if (!(dg > 0.0)) dg = 0.0;
     }
-    double psi = barlat_residual(b, m, md, t_tr, alpha_n, T, dg, o.sy_n, G, st, dsig);
+    double psi = barlat_residual(b, m, md, t_tr, alpha_n, T, dg, G, st, dsig);
     double prev = __builtin_inf();
     int conv = 0;
     for (int it = 0; it < 60; ++it) {
+        // scaled residual: stress rows E : G1 over mu, the yield row over
+        // sigma_y(alpha_n); converged at 1e-14, or at the rounding floor (a
+        // step below 1e-9 that does not halve it; the floor grows with the
+        // stress, so no fixed level detects it)
         double gn = 0.0;
+        {
+            double Eg[6];
+            elastic_stiffness(md, G, Eg);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) gn = fmax(gn, fabs(md.mu2 * G[k]) / md.mu2 * 2.0);
+            for (int k = 0; k < 6; ++k) gn = fmax(gn, fabs(Eg[k]) * (2.0 / md.mu2));
+        }
         gn = fmax(gn, fabs(G[6]) / o.sy_n);
         if (!(gn == gn)) break;
-        if (gn <= 1e-14 || (gn <= 1e-12 && gn >= 0.5 * prev)) {
+        if (gn <= 1e-14 || (gn <= 1e-9 && gn >= 0.5 * prev)) {
             conv = 1;
             break;
         }
@@ -424,12 +442,12 @@ __device__ inline void local_update_barlat(const double eps[6], const double* hi
         double dT[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) dT[k] = -u[k] - w[k] * ddg;
-        // line search of App. B on psi
+        // line search of App. B on the merit of Eq. (merit)
         double Tt[6], Gt[7], dsg_t;
         BarlatState stt;
 #pragma unroll
         for (int k = 0; k < 6; ++k) Tt[k] = T[k] + dT[k];
-        double psi1 = barlat_residual(b, m, md, t_tr, alpha_n, Tt, dg + ddg, o.sy_n, Gt, stt, dsg_t);
+        double psi1 = barlat_residual(b, m, md, t_tr, alpha_n, Tt, dg + ddg, Gt, stt, dsg_t);
         double zeta = 1.0;
         if (!(psi1 < (1.0 - 2.0 * 1e-4) * psi)) {
             double zj = psi / (psi + psi1);
@@ -437,11 +455,11 @@ __device__ inline void local_update_barlat(const double eps[6], const double* hi
             for (int j = 0; j <= 20; ++j) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) Tt[k] = T[k] + zj * dT[k];
-                const double psij = barlat_residual(b, m, md, t_tr, alpha_n, Tt, dg + zj * ddg, o.sy_n, Gt, stt, dsg_t);
+                const double psij = barlat_residual(b, m, md, t_tr, alpha_n, Tt, dg + zj * ddg, Gt, stt, dsg_t);
                 double zn = fmax(0.1 * zj, psi / (psi + psij));
 #pragma unroll
                 for (int k = 0; k < 6; ++k) Tt[k] = T[k] + zn * dT[k];
-                psi1 = barlat_residual(b, m, md, t_tr, alpha_n, Tt, dg + zn * ddg, o.sy_n, Gt, stt, dsg_t);
+                psi1 = barlat_residual(b, m, md, t_tr, alpha_n, Tt, dg + zn * ddg, Gt, stt, dsg_t);
                 zeta = zn;
                 if (psi1 < (1.0 - 2.0 * 1e-4 * zn) * psi) break;
                 zj = zn;
@@ -450,7 +468,7 @@ __device__ inline void local_update_barlat(const double eps[6], const double* hi
 #pragma unroll
         for (int k = 0; k < 6; ++k) T[k] += zeta * dT[k];
         dg += zeta * ddg;
-        psi = barlat_residual(b, m, md, t_tr, alpha_n, T, dg, o.sy_n, G, st, dsig);
+        psi = barlat_residual(b, m, md, t_tr, alpha_n, T, dg, G, st, dsig);
     }
     o.converged = conv;
     // recovery and algorithmic tangent at the converged state

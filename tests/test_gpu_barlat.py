@@ -75,3 +75,50 @@ def test_vjp_rejects_barlat(fem):
     with pytest.raises(fem.FemError) as ei:
         fem.residual_vjp(mesh, params, d, h, lam, prec=fem.FP64)
     assert ei.value.code == fem.FEM_EINVAL
+
+
+def robustness_problem(n_theta=40, n_r=50):
+    """Trial states of App. B's robustness study (Barlat Yld2004-18p with the
+    verification table's fit, E = 1000, nu = 0.3, sigma0 = 1, perfect
+    plasticity, trial stresses in the deviatoric principal-stress plane between
+    the yield surface and 30 times it), one state per element: disjoint unit
+    cubes, each deformed homogeneously with principal stretches exp(eps_i)
+    along the material axes, so that the log strain of every Gauss point is
+    the state's trial strain."""
+    from test_oracle_linesearch import BARLAT, example_params, golden, pi_plane_states
+    import oracle
+    ls, coef = golden()
+    oracle.set_barlat(coef)
+    prm = example_params(ls)
+    eps = pi_plane_states(prm, n_theta=n_theta, n_r=n_r, r_max=ls["robustness_study"]["outer_surface_scale"])
+    n = eps.shape[0]
+    Xc, cc = synth.hex_grid(1, 1, 1, 1.0, 1.0, 1.0)
+    X = np.concatenate([Xc + np.array([2.0 * i, 0.0, 0.0]) for i in range(n)])
+    conn = np.concatenate([cc + 8 * i for i in range(n)]).astype(np.int32)
+    d = np.zeros_like(X)
+    for i in range(n):
+        Fd = np.exp(eps[i, :3]) - 1.0
+        xi = X[8 * i:8 * i + 8]
+        d[8 * i:8 * i + 8] = (xi - xi.mean(axis=0)) * Fd
+    p = synth.Problem("barlat_robustness", X, conn, d, np.zeros((7, 8 * n)), prm, None, None,
+                      barlat=np.asarray(coef, dtype=np.float64))
+    assert BARLAT == oracle.MODEL_BARLAT
+    return p
+
+
+def test_barlat_return_map_over_the_robustness_states(fem):
+    """The GPU closest-point iteration (radial start on the current yield
+    surface, Newton on (T, dgamma), line search of App. B on the merit of
+    Eq. (merit)) over 2,000 of the robustness study's trial states, up to 30
+    times the yield surface: every Gauss point converges (diag zero) to the
+    oracle's state (Alg. C2 from the trial state), residual and history
+    within 1e-10."""
+    p = robustness_problem()
+    say("barlat robustness states", p.n_elems)
+    o = oracle_forward(p, bc=False, want_K=False)
+    assert list(o["diag"]) == [0, 0, 0, 0]
+    assert (o["hist"][6] > 0).all()  # every state is plastic
+    g = gpu_forward(p, fem, fem.FP64, bc=False, want_K=False)
+    assert list(g["diag"]) == [0, 0, 0, 0]
+    assert hist_rel(g["hist"], o["hist"]) <= TOL_FP64
+    assert rel_inf(g["R"], o["R"]) <= TOL_FP64
