@@ -408,8 +408,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the linear solve, model variants, adjoint step, batched and forward-simulation extras")
-    ap.add_argument("--only", choices=("fp64", "mixed"), default=None,
-                    help="time only this precision's pass on the cube and print its timing (for profiler runs)")
+    ap.add_argument("--only", choices=("fp64", "mixed", "barlat"), default=None,
+                    help="time only this pass on the cube and print its timing (for profiler runs); barlat: "
+                         "the FP64 pass with the Barlat Yld2004-18p function (published AA6111 fit)")
     ap.add_argument("--no-forward", action="store_true",
                     help="skip the paper's forward simulation (about 40 s) among the extras")
     ap.add_argument("--cpu-sample", type=int, default=100000,
@@ -481,10 +482,14 @@ def main():
     KNAMES = {fem.KERNEL_FORWARD: "fwd_kernel", fem.KERNEL_ASSEMBLE_K: "assemble_tangent",
               fem.KERNEL_ASSEMBLE_R: "assemble_residual"}
     if args.only:
-        prec = fem.FP64 if args.only == "fp64" else fem.FP32_MIXED
+        prec = fem.FP32_MIXED if args.only == "mixed" else fem.FP64
+        prm_o = params
+        if args.only == "barlat":
+            pb = synth.with_model(p, 11, barlat=synth.BARLAT_AA6111)
+            prm_o = fem.Params(pb.prm, pb.n_elems, barlat=synth.BARLAT_AA6111)
         oo = fem.Forward(mesh, csr, prec)
         ms_o, _, kt_o = time_passes(
-            lambda: fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=prec, out=oo),
+            lambda: fem.residual_tangent(mesh, csr, prm_o, d, h, bc_mask=bc, prec=prec, out=oo),
             args.steps, args.warmup, torch, KS, fem)
         print(json.dumps({"only": args.only, "ms_per_pass": ms_o, "steps": args.steps,
                           "kernel_ms": {KNAMES[k]: kt_o[k] for k in KS}}), flush=True)

@@ -18,10 +18,12 @@
 namespace fem {
 
 // 18 coefficients c'12 c'13 c'21 c'23 c'31 c'32 c'44 c'55 c'66, the same nine
-// for c'', and the exponent m
+// for c'', and the exponent m; mi = m - 2 when m is an integer in [2, 64]
+// (the published fits use m = 8), else -1
 struct BarlatCoef {
     double c[2][9];
     double m;
+    int mi;
 };
 
 __device__ inline void load_barlat(const double* __restrict__ p, BarlatCoef& b) {
@@ -31,6 +33,21 @@ __device__ inline void load_barlat(const double* __restrict__ p, BarlatCoef& b) 
         b.c[1][k] = p[9 + k];
     }
     b.m = p[18];
+    b.mi = (b.m >= 2.0 && b.m <= 64.0 && b.m == floor(b.m)) ? (int)b.m - 2 : -1;
+}
+
+// |d|^(m-2): by repeated squaring for an integer exponent (the same for every
+// lane, so the branch is uniform), else pow; 1 at d = 0 for m = 2
+__device__ inline double abs_pow_m2(double ad, const BarlatCoef& b) {
+    if (b.mi >= 0) {
+        double r = 1.0, x = ad;
+        for (int k = b.mi; k; k >>= 1) {
+            if (k & 1) r *= x;
+            x *= x;
+        }
+        return r;
+    }
+    return pow(ad, b.m - 2.0);
 }
 
 // s = C : P : t as a symmetric 3x3 (t Mandel)
@@ -69,12 +86,46 @@ struct BarlatState {
     double phi;
 };
 
-__device__ inline double barlat_principal(const BarlatCoef& b, const double t[6], BarlatState& st) {
+// Symmetric 3x3 eigen-decomposition started from an orthonormal basis Q
+// (columns) close to the eigenvectors: cyclic Jacobi on Q^T S Q, which is
+// nearly diagonal, then Q <- Q Q'.  Between Newton iterates and line-search
+// trials the transformed deviators turn little, so one or two sweeps replace
+// the four to six of a start from the identity.
+__device__ inline void eig_sym3_from(const double S[3][3], double mu[3], double Q[3][3]) {
+    double W[3][3], B[3][3], Qs[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) W[i][q] = S[i][0] * Q[0][q] + S[i][1] * Q[1][q] + S[i][2] * Q[2][q];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = p; q < 3; ++q) {
+            const double v = Q[0][p] * W[0][q] + Q[1][p] * W[1][q] + Q[2][p] * W[2][q];
+            B[p][q] = v;
+            B[q][p] = v;
+        }
+    eig_sym3<double>(B, mu, Qs);
+    double Qn[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Qn[i][j] = Q[i][0] * Qs[0][j] + Q[i][1] * Qs[1][j] + Q[i][2] * Qs[2][j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Q[i][j] = Qn[i][j];
+}
+
+// warm: st.P holds eigenvectors of nearby deviators to start from
+__device__ inline double barlat_principal(const BarlatCoef& b, const double t[6], BarlatState& st,
+                                          bool warm = false) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         double S[3][3], mu[3];
         barlat_apply(b.c[a], t, S);
-        eig_sym3<double>(S, mu, st.P[a]);
+        if (warm) eig_sym3_from(S, mu, st.P[a]);
+        else eig_sym3<double>(S, mu, st.P[a]);
         st.lam[3 * a] = mu[0];
         st.lam[3 * a + 1] = mu[1];
         st.lam[3 * a + 2] = mu[2];
@@ -86,7 +137,7 @@ __device__ inline double barlat_principal(const BarlatCoef& b, const double t[6]
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const double d = st.lam[i] - st.lam[3 + j], ad = fabs(d);
-            const double p2 = pow(ad, m - 2.0);  // |d|^(m-2) (1 at d = 0 for m = 2)
+            const double p2 = abs_pow_m2(ad, b);  // |d|^(m-2)
             Phi += 0.25 * p2 * ad * ad;
             const double t1 = 0.25 * m * d * p2;
             dPhi[i] += t1;
@@ -112,7 +163,7 @@ __device__ inline void barlat_hessian(const BarlatCoef& b, const BarlatState& st
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const double d = st.lam[i] - st.lam[3 + j], ad = fabs(d);
-            const double p2 = pow(ad, m - 2.0);
+            const double p2 = abs_pow_m2(ad, b);
             Phi += 0.25 * p2 * ad * ad;
             const double t1 = 0.25 * m * d * p2, t2 = 0.25 * m * (m - 1.0) * p2;
             dPhi[i] += t1;
@@ -302,7 +353,7 @@ __device__ inline void elastic_stiffness(const Modes& h, const double x[6], doub
 __device__ inline double barlat_residual(const BarlatCoef& b, const Mat& m, const Modes& md, const double t_tr[6],
                                          double alpha_n, const double T[6], double dg, double G[7],
                                          BarlatState& st, double& dsig) {
-    barlat_principal(b, T, st);
+    barlat_principal(b, T, st, true);  // st.P: eigenvectors at a nearby stress
     double N[6], dT[6], c[6];
     barlat_flow(b, st, N);
 #pragma unroll
@@ -364,7 +415,7 @@ __device__ inline void local_update_barlat(const double eps[6], const double* hi
         double N0[6], c[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) T[i] = r * t_tr[i];
-        barlat_principal(b, T, st);
+        barlat_principal(b, T, st, true);  // T0 is a multiple of t_tr: the same eigenvectors
         barlat_flow(b, st, N0);
         elastic_compliance(md, t_tr, c);
         double nc = 0.0, nn = 0.0;
@@ -444,7 +495,7 @@ __device__ inline void local_update_barlat(const double eps[6], const double* hi
         for (int k = 0; k < 6; ++k) dT[k] = -u[k] - w[k] * ddg;
         // line search of App. B on the merit of Eq. (merit)
         double Tt[6], Gt[7], dsg_t;
-        BarlatState stt;
+        BarlatState stt = st;  // trial states start their eigen-solves from the current one
 #pragma unroll
         for (int k = 0; k < 6; ++k) Tt[k] = T[k] + dT[k];
         double psi1 = barlat_residual(b, m, md, t_tr, alpha_n, Tt, dg + ddg, Gt, stt, dsg_t);
