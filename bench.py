@@ -234,8 +234,10 @@ def elastic_solve(csr, torch, fem, synth):
     """The linear-elastic solve of App. F on the 100^3 unit cube (3,090,903
     dofs): the elastic tangent of the undeformed unit-cube forward problem
     (the same pattern as the benchmark cube) and the right-hand side of its
-    first load increment, by CG and BiCGSTAB with the node-block preconditioner to
-    relative residuals 1e-6 and 1e-8 (seconds, iterations)."""
+    first load increment, by CG and BiCGSTAB with the node-block preconditioner
+    and with the aggregation multigrid (numeric set-up inside each timed solve,
+    the hierarchy built in the warm-up) to relative residuals 1e-6 and 1e-8
+    (seconds, iterations)."""
     p = synth.unit_cube_forward(100)
     mesh = fem.Mesh(p.X, p.conn)
     params = fem.Params(p.prm, p.n_elems, hardening="voce")
@@ -247,16 +249,22 @@ def elastic_solve(csr, torch, fem, synth):
     b = -fem.residual_tangent(mesh, csr, params, d, h0, bc_mask=bc, prec=fem.FP64, want_K=False).R
     res = {"dofs": 3 * p.n_nodes, "context": "paper App. F, same mesh, linear elastic, one H100: AMGX BiCGSTAB "
                                              "1.96 s, JAX BiCGSTAB 11.21 s (tolerance not stated)"}
-    for method in ("cg", "bicgstab"):
-        solver = fem.Solver(csr, method=method)
-        solver.solve(out.K, b, rtol=1e-2, check=False)  # warm-up
-        for rtol in (1e-6, 1e-8):
+    for pc, tag in ((fem.PC_BLOCK_JACOBI, ""), (fem.PC_AMG, "_amg")):
+        for method in ("cg", "bicgstab"):
+            solver = fem.Solver(csr, method=method, precond=pc, bc_mask=bc)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, its, rr = solver.solve(out.K, b, rtol=rtol, max_iter=50000, check=False)
+            solver.solve(out.K, b, rtol=1e-2, check=False)  # warm-up (and the multigrid hierarchy)
             torch.cuda.synchronize()
-            res[f"{method}_{rtol:.0e}"] = dict(seconds=time.perf_counter() - t0, iterations=its, rel_res=rr)
-        del solver
+            if pc == fem.PC_AMG:
+                res[f"{method}{tag}_setup_s"] = time.perf_counter() - t0
+            for rtol in (1e-6, 1e-8):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, its, rr = solver.solve(out.K, b, rtol=rtol, max_iter=50000, check=False)
+                torch.cuda.synchronize()
+                res[f"{method}{tag}_{rtol:.0e}"] = dict(seconds=time.perf_counter() - t0, iterations=its, rel_res=rr)
+            del solver
     log("elastic solve: " + ", ".join(f"{k} {v['seconds']:.3f} s / {v['iterations']} it"
                                       for k, v in res.items() if isinstance(v, dict)))
     return res
@@ -339,7 +347,7 @@ def gradient_benchmark(torch, fem, synth):
     }
 
 
-def forward_benchmark(spec, torch, fem, synth, fbar=True):
+def forward_benchmark(spec, torch, fem, synth, fbar=True, precond="bj"):
     """The unit-cube forward simulation of the performance study, Sec. 3.1.3 (Hill-48
     from the r-values, Voce, x = 0 clamped, x = 1 moved by t (0.2, 0.1) mm)
     through the adaptive load path: FP64 residual and history, float tangent
@@ -363,7 +371,8 @@ def forward_benchmark(spec, torch, fem, synth, fbar=True):
     h0 = torch.zeros((7, 8 * p.n_elems), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    res = loadpath.solve(mesh, csr, params, bc, u1, h0, log=lambda m: log(m))
+    pc = fem.PC_AMG if precond == "amg" else fem.PC_BLOCK_JACOBI
+    res = loadpath.solve(mesh, csr, params, bc, u1, h0, log=lambda m: log(m), precond=pc)
     n_it = max(res["newton_iterations"], 1)
     alpha = res["hist"][6]
     paper = PAPER_FORWARD_S.get(dims)
@@ -385,7 +394,8 @@ def forward_benchmark(spec, torch, fem, synth, fbar=True):
                                "r = (1.5449, 1.0666, 1, 1.0307, 1, 1), Voce sigma0 138 Q 410 b 3.8, E 219 GPa, "
                                "nu 0.3; dt0 1e-3, dt_min 1e-5, dt_max 5e-2",
                    "nnz": csr.nnz, "element": "fbar" if fbar else "plain",
-                   "krylov": "bicgstab" if fbar else "cg"},
+                   "krylov": "bicgstab" if fbar else "cg",
+                   "preconditioner": "aggregation multigrid V(1,1)" if precond == "amg" else "3x3 node-block Jacobi"},
         "increments": len(res["steps"]),
         "failed_increments": len(res["failed"]),
         "newton_iterations": res["newton_iterations"],
@@ -427,6 +437,8 @@ def main():
                          "adjoint) on the tensile-specimen stand-in, one JSON line with its wall time")
     ap.add_argument("--element", choices=("fbar", "plain"), default="fbar",
                     help="element of --forward-benchmark: the paper's F-bar hex8 (BiCGSTAB) or the plain hex8 (CG)")
+    ap.add_argument("--precond", choices=("amg", "bj"), default="bj",
+                    help="preconditioner of --forward-benchmark: aggregation multigrid or 3x3 node-block Jacobi")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -453,8 +465,8 @@ def main():
         print(json.dumps(gradient_benchmark(torch, fem, synth)), flush=True)
         return
     if args.forward_benchmark:
-        print(json.dumps(forward_benchmark(args.forward_benchmark, torch, fem, synth, args.element == "fbar")),
-              flush=True)
+        print(json.dumps(forward_benchmark(args.forward_benchmark, torch, fem, synth, args.element == "fbar",
+                                           args.precond)), flush=True)
         return
     log("generating the 100^3 cube")
     p = synth.large_cube()

@@ -18,7 +18,9 @@
  * Alg. E1) and the VJP term (dR/dtheta)^T lambda of Alg. 1 / Eq. (main_grad).
  *
  * Memory: every pointer marked "device" is HIP device memory owned by the
- * caller; the library never frees or retains it.  Host pointers are marked
+ * caller; the library never frees or retains it (except the multigrid
+ * handle of fem_amg_create, which keeps the pattern and matrix pointers it
+ * is given and owns the device memory of its hierarchy).  Host pointers are marked
  * "host".  All work is enqueued on `stream` (a hipStream_t; NULL = the null
  * stream) and is asynchronous unless stated otherwise; output arrays are
  * overwritten, never accumulated into.  Scratch space comes from the caller
@@ -324,7 +326,7 @@ int fem_residual_vjp_noalloc(const fem_mesh *mesh, const fem_batch *batch, const
  * Returns FEM_ENOCONV if rtol is not reached (x holds the last iterate).
  * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOCONV.
  */
-typedef enum { FEM_PC_JACOBI = 0, FEM_PC_BLOCK_JACOBI = 1 } fem_precond;
+typedef enum { FEM_PC_JACOBI = 0, FEM_PC_BLOCK_JACOBI = 1, FEM_PC_AMG = 2 /* fem_solve_amg only */ } fem_precond;
 typedef enum { FEM_KRYLOV_BICGSTAB = 0, FEM_KRYLOV_CG = 1 } fem_krylov;
 size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz);
 int fem_csr_spmv(const fem_csr *csr, const void *K_vals, fem_precision prec, const double *x, double *y,
@@ -345,6 +347,72 @@ int fem_solve(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_kr
  */
 int fem_csr_transpose(const fem_csr *csr, const void *K_vals, fem_precision prec, const uint8_t *bc_mask,
                       void *KT_vals, void *stream);
+
+/*
+ * Aggregation multigrid preconditioner of the Newton solve (Sec. 2.2.5 and
+ * App. F solve the linear systems with an algebraic-multigrid-preconditioned
+ * Krylov method).  The hierarchy works on 3x3 node blocks:
+ *   - aggregation: each level pairs nodes three times by greedy matching
+ *     along the strongest connection (Frobenius norm of the block of K over
+ *     the geometric mean of the two diagonal-block norms; nodes visited in
+ *     index order), so an aggregate holds up to eight nodes; levels are added
+ *     until at most FEM_AMG_DENSE_NODES nodes remain or a level keeps more
+ *     than 85 % of the nodes of the one above (or FEM_AMG_MAX_LEVELS);
+ *   - prolongation P: piecewise-constant per displacement component (the
+ *     three translations of each aggregate), zero on constrained dofs;
+ *   - coarse operators A_{l+1} = P^T A_l P, sums of masked 3x3 blocks in
+ *     FP32 (fixed order); a coarse dof without a free fine dof gets an
+ *     identity row;
+ *   - smoother: one l1 block-Jacobi sweep before and after the coarse
+ *     correction, M_l = (D_I + diag of the absolute off-block row sums)^-1
+ *     per node (3x3 inverse; a singular block falls back to its diagonal);
+ *   - coarsest level: its explicit inverse (Gauss-Jordan with partial
+ *     pivoting in FP64; a pivot below 1e-13 of the largest diagonal entry
+ *     drops that dof) when it has at most FEM_AMG_DENSE_NODES nodes, else
+ *     one smoothing sweep pair.
+ * One application z = M r is one V(1,1)-cycle; for a symmetric K it is a
+ * symmetric operator (usable with CG).
+ *
+ * fem_amg_create -- aggregation and coarse patterns, built on the host from
+ *   the pattern of csr (fem_csr_pattern) and the block norms of K_vals
+ *   (device [nnz], double for FEM_FP64, float for FEM_FP32_MIXED), then
+ *   uploaded.  bc_mask: device [n_rows] uint8, nonzero on constrained dofs
+ *   (their rows of K are identity rows, as fem_residual_tangent writes
+ *   them), or NULL (no constrained dofs).  The handle keeps csr's device
+ *   pointers (they must stay valid) and owns device memory allocated here
+ *   (freed by fem_amg_destroy); the coarse values are not computed yet
+ *   (fem_amg_update).  Synchronises `stream`.
+ *   Errors: FEM_EINVAL (bad arguments, a node with more than 21845
+ *   neighbours), FEM_ENOMEM (host or device allocation), FEM_EHIP.
+ * fem_amg_update -- numeric set-up for values K_vals on the same pattern
+ *   (any precision above): Galerkin operators, smoother inverses and the
+ *   coarsest inverse.  The handle keeps K_vals (it must stay valid while
+ *   fem_amg_apply / fem_solve_amg use it).  Asynchronous on `stream`.
+ * fem_amg_apply -- z = M r, device [n_rows] each (FP64; must not alias).
+ *   Asynchronous on `stream`; calls on one handle must not overlap.
+ * fem_amg_info -- number of levels and, per level (up to
+ *   FEM_AMG_MAX_LEVELS entries each, either may be NULL), nodes and 3x3
+ *   blocks; dense = 1 if the coarsest level is inverted exactly.
+ * fem_amg_aggregates -- agg (host [nodes of level - 1]) = the aggregate, a
+ *   node of `level` (1 <= level < n_levels), of each node of the level above.
+ *   Synchronous.
+ * fem_solve_amg -- fem_solve (same arguments, workspace and stop rules)
+ *   with M = one V-cycle of amg, after fem_amg_update(amg, K_vals, prec).
+ *   csr must be the pattern amg was created on.
+ */
+#define FEM_AMG_MAX_LEVELS 12
+#define FEM_AMG_DENSE_NODES 32
+typedef struct fem_amg fem_amg;
+int fem_amg_create(const fem_csr *csr, const void *K_vals, fem_precision prec, const uint8_t *bc_mask,
+                   fem_amg **out, void *stream);
+int fem_amg_update(fem_amg *amg, const void *K_vals, fem_precision prec, void *stream);
+int fem_amg_apply(fem_amg *amg, const double *r, double *z, void *stream);
+int fem_amg_info(const fem_amg *amg, int32_t *n_levels, int32_t *nodes, int64_t *blocks, int32_t *dense);
+int fem_amg_aggregates(const fem_amg *amg, int32_t level, int32_t *agg);
+int fem_amg_destroy(fem_amg *amg);
+int fem_solve_amg(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_krylov method, fem_amg *amg,
+                  const double *b, double *x, int32_t max_iter, double rtol, int32_t *iters, double *rel_res,
+                  void *ws, size_t ws_bytes, void *stream);
 
 /*
  * fem_history_adjoint -- one load step of the time-history adjoint (Sec. 2.3,

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfem.so")
-SOURCES = ["api.hip", "pattern.hip", "forward.hip", "vjp.hip", "solver.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "pattern.hip", "forward.hip", "vjp.hip", "solver.hip", "amg.hip", "adjoint.hip"]
 ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -536,6 +536,35 @@ __global__ __launch_bounds__(256) void cg_update_p(int64_t n, const double* __re
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kGrid * 256) p[i] = z[i] + beta * p[i];
 }
 
+// ---- kernels of the multigrid-preconditioned iterations (z = V-cycle of r
+// computed between them)
+
+// p = z; part0 = partials of (r, z)
+__global__ __launch_bounds__(256) void cg_amg_start(int64_t n, const double* __restrict__ z,
+                                                    const double* __restrict__ r, double* __restrict__ p,
+                                                    double* __restrict__ part0, const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    double d = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kGrid * 256) {
+        const double zi = z[i];
+        p[i] = zi;
+        d += r[i] * zi;
+    }
+    const double t0 = block_sum(d);
+    if (threadIdx.x == 0) part0[blockIdx.x] = t0;
+}
+
+// part0 = partials of (a, b)
+__global__ __launch_bounds__(256) void dot_kernel(int64_t n, const double* __restrict__ a,
+                                                  const double* __restrict__ b, double* __restrict__ part0,
+                                                  const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    double d = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kGrid * 256) d += a[i] * b[i];
+    const double t0 = block_sum(d);
+    if (threadIdx.x == 0) part0[blockIdx.x] = t0;
+}
+
 struct SolverWs {
     double *r, *rh, *p, *ph, *v, *s, *sh, *t, *minv, *part0, *part1, *part2, *sc;
     int32_t *ncol, *fl;
@@ -649,25 +678,31 @@ extern "C" int fem_csr_transpose(const fem_csr* csr, const void* K_vals, fem_pre
     return FEM_OK;
 }
 
-extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision prec, fem_krylov method,
-                         fem_precond pc, const double* b, double* x, int32_t max_iter, double rtol, int32_t* iters, double* rel_res,
-                         void* ws, size_t ws_bytes, void* stream) {
-    clear_error();
-    if (int rc = check_csr(csr, K_vals, "fem_solve")) return rc;
-    if (prec != FEM_FP64 && prec != FEM_FP32_MIXED) return set_error(FEM_EINVAL, "fem_solve: bad precision");
-    if (pc != FEM_PC_JACOBI && pc != FEM_PC_BLOCK_JACOBI) return set_error(FEM_EINVAL, "fem_solve: bad preconditioner");
+namespace {
+
+// The Krylov iterations of fem_solve (amg NULL: Jacobi or block Jacobi by pc)
+// and fem_solve_amg (M = one V-cycle of amg).
+int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_precision prec, fem_krylov method,
+                 fem_precond pc, fem_amg* amg, const double* b, double* x, int32_t max_iter, double rtol,
+                 int32_t* iters, double* rel_res, void* ws, size_t ws_bytes, void* stream) {
+    if (int rc = check_csr(csr, K_vals, who)) return rc;
+    if (prec != FEM_FP64 && prec != FEM_FP32_MIXED) return set_error(FEM_EINVAL, "%s: bad precision", who);
+    if (!amg && pc != FEM_PC_JACOBI && pc != FEM_PC_BLOCK_JACOBI)
+        return set_error(FEM_EINVAL, "%s: bad preconditioner", who);
     if (method != FEM_KRYLOV_BICGSTAB && method != FEM_KRYLOV_CG)
-        return set_error(FEM_EINVAL, "fem_solve: bad Krylov method");
-    if (max_iter < 0 || !(rtol >= 0.0)) return set_error(FEM_EINVAL, "fem_solve: max_iter >= 0 and rtol >= 0");
+        return set_error(FEM_EINVAL, "%s: bad Krylov method", who);
+    if (max_iter < 0 || !(rtol >= 0.0)) return set_error(FEM_EINVAL, "%s: max_iter >= 0 and rtol >= 0", who);
     const int32_t n = csr->n_rows, nn = n / 3;
     if (iters) *iters = 0;
     if (rel_res) *rel_res = 0.0;
     if (n == 0) return FEM_OK;
-    if (!b || !x) return set_error(FEM_EINVAL, "fem_solve: b and x must not be NULL");
-    if (csr->nnz < 0 || csr->nnz % 9) return set_error(FEM_EINVAL, "fem_solve: nnz must be a multiple of 9");
+    if (!b || !x) return set_error(FEM_EINVAL, "%s: b and x must not be NULL", who);
+    if (csr->nnz < 0 || csr->nnz % 9) return set_error(FEM_EINVAL, "%s: nnz must be a multiple of 9", who);
+    if (amg && !amg_matches(amg, csr))
+        return set_error(FEM_EINVAL, "%s: the multigrid handle was built on another pattern", who);
     const size_t need = fem_solver_workspace_bytes(n, csr->nnz);
     if (!ws || ws_bytes < need)
-        return set_error(FEM_ENOMEM, "fem_solve: workspace of %zu bytes required, %zu given", need, ws_bytes);
+        return set_error(FEM_ENOMEM, "%s: workspace of %zu bytes required, %zu given", who, need, ws_bytes);
     hipStream_t s = (hipStream_t)stream;
     WsCarver c(ws, ws_bytes);
     SolverWs w;
@@ -676,16 +711,33 @@ extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision p
     const unsigned nbn = (unsigned)(((int64_t)nn + 255) / 256);
     const int block = pc == FEM_PC_BLOCK_JACOBI ? 1 : 0;
     hipLaunchKernelGGL(node_cols_kernel, dim3(nbl), dim3(256), 0, s, nn, csr->row_ptr, csr->col_idx, w.ncol);
-    if (prec == FEM_FP64)
+    // with multigrid the fused update kernels write the first smoothing sweep
+    // M_0 q into the cycle's finest iterate (mx) and the cycle writes M q
+    const double* minv = w.minv;
+    double* mx = nullptr;
+    if (amg) {
+        if (int rc = amg_update(amg, K_vals, prec, s)) return rc;
+        minv = amg_smoother0(amg);
+        mx = amg_level0_x(amg);
+    } else if (prec == FEM_FP64) {
         hipLaunchKernelGGL(precond_kernel<double>, dim3(nbn), dim3(256), 0, s, nn, csr->row_ptr, w.ncol,
                            static_cast<const double*>(K_vals), block, w.minv);
-    else
+    } else {
         hipLaunchKernelGGL(precond_kernel<float>, dim3(nbn), dim3(256), 0, s, nn, csr->row_ptr, w.ncol,
                            static_cast<const float*>(K_vals), block, w.minv);
+    }
     hipLaunchKernelGGL(reset_flags, dim3(1), dim3(1), 0, s, w.fl);
     spmv_dot<0>(csr, w.ncol, K_vals, prec, x, w.t, nullptr, nullptr, nullptr, nullptr, s);
     const bool cg = method == FEM_KRYLOV_CG;
-    if (cg) {
+    if (cg && amg) {
+        // r = b - K x, mx = M_0 r; z (in s) = M r; p = z; (r, z)
+        hipLaunchKernelGGL(cg_init, dim3(kGrid), dim3(256), 0, s, nn, b, w.t, minv, w.r, mx, w.p, w.part0, w.part1,
+                           w.part2);
+        FEM_HIP_CHECK(amg_vcycle(amg, w.r, w.s, true, w.fl, s));
+        hipLaunchKernelGGL(cg_amg_start, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.s, w.r, w.p, w.part0, w.fl);
+        hipLaunchKernelGGL(cg_fin_init, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.part2, w.sc, w.fl, rtol,
+                           max_iter);
+    } else if (cg) {
         hipLaunchKernelGGL(cg_init, dim3(kGrid), dim3(256), 0, s, nn, b, w.t, w.minv, w.r, w.s, w.p, w.part0, w.part1,
                            w.part2);
         hipLaunchKernelGGL(cg_fin_init, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.part2, w.sc, w.fl, rtol,
@@ -710,16 +762,24 @@ extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision p
         for (int32_t k = 0; cg && k < chunk; ++k) {
             spmv_dot<1>(csr, w.ncol, K_vals, prec, w.p, w.v, w.p, w.part0, nullptr, w.fl, s);
             hipLaunchKernelGGL(cg_fin_alpha, dim3(1), dim3(256), 0, s, w.part0, w.sc, w.fl);
-            hipLaunchKernelGGL(cg_update, dim3(kGrid), dim3(256), 0, s, nn, w.p, w.v, w.minv, x, w.r, w.s, w.part0,
-                               w.part1, w.sc, w.fl);
+            hipLaunchKernelGGL(cg_update, dim3(kGrid), dim3(256), 0, s, nn, w.p, w.v, minv, x, w.r, amg ? mx : w.s,
+                               w.part0, w.part1, w.sc, w.fl);
+            if (amg) {
+                FEM_HIP_CHECK(amg_vcycle(amg, w.r, w.s, true, w.fl, s));
+                hipLaunchKernelGGL(dot_kernel, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.r, w.s, w.part0, w.fl);
+            }
             hipLaunchKernelGGL(cg_fin_beta, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl, rtol, max_iter);
             hipLaunchKernelGGL(cg_update_p, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.s, w.p, w.sc, w.fl);
         }
         for (int32_t k = 0; !cg && k < chunk; ++k) {
-            hipLaunchKernelGGL(update_p, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, w.minv, w.p, w.ph, w.sc, w.fl);
+            hipLaunchKernelGGL(update_p, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, minv, w.p, amg ? mx : w.ph, w.sc,
+                               w.fl);
+            if (amg) FEM_HIP_CHECK(amg_vcycle(amg, w.p, w.ph, true, w.fl, s));
             spmv_dot<1>(csr, w.ncol, K_vals, prec, w.ph, w.v, w.rh, w.part0, nullptr, w.fl, s);
             hipLaunchKernelGGL(fin_alpha, dim3(1), dim3(256), 0, s, w.part0, w.sc, w.fl);
-            hipLaunchKernelGGL(update_s, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, w.minv, w.s, w.sh, w.sc, w.fl);
+            hipLaunchKernelGGL(update_s, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, minv, w.s, amg ? mx : w.sh, w.sc,
+                               w.fl);
+            if (amg) FEM_HIP_CHECK(amg_vcycle(amg, w.s, w.sh, true, w.fl, s));
             spmv_dot<2>(csr, w.ncol, K_vals, prec, w.sh, w.t, w.s, w.part0, w.part1, w.fl, s);
             hipLaunchKernelGGL(fin_omega, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl);
             hipLaunchKernelGGL(update_x, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.ph, w.sh, w.s, w.t, w.rh, x, w.r,
@@ -732,7 +792,26 @@ extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision p
     if (iters) *iters = fl[F_ITER];
     if (rel_res) *rel_res = res;
     if (!(res <= rtol))
-        return set_error(FEM_ENOCONV, "fem_solve: relative residual %.3e after %d iterations (rtol %.3e)", res,
+        return set_error(FEM_ENOCONV, "%s: relative residual %.3e after %d iterations (rtol %.3e)", who, res,
                          fl[F_ITER], rtol);
     return FEM_OK;
+}
+
+}  // namespace
+
+extern "C" int fem_solve(const fem_csr* csr, const void* K_vals, fem_precision prec, fem_krylov method,
+                         fem_precond pc, const double* b, double* x, int32_t max_iter, double rtol, int32_t* iters,
+                         double* rel_res, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    return krylov_solve("fem_solve", csr, K_vals, prec, method, pc, nullptr, b, x, max_iter, rtol, iters, rel_res, ws,
+                        ws_bytes, stream);
+}
+
+extern "C" int fem_solve_amg(const fem_csr* csr, const void* K_vals, fem_precision prec, fem_krylov method,
+                             fem_amg* amg, const double* b, double* x, int32_t max_iter, double rtol, int32_t* iters,
+                             double* rel_res, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!amg) return set_error(FEM_EINVAL, "fem_solve_amg: the multigrid handle must not be NULL");
+    return krylov_solve("fem_solve_amg", csr, K_vals, prec, method, FEM_PC_AMG, amg, b, x, max_iter, rtol, iters,
+                        rel_res, ws, ws_bytes, stream);
 }

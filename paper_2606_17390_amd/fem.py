@@ -57,7 +57,9 @@ EXPORTS = ("fem_version", "fem_last_error", "fem_set_launch", "fem_get_launch", 
            "fem_forward_workspace_bytes", "fem_vjp_workspace_bytes", "fem_csr_pattern", "fem_residual_tangent",
            "fem_residual_vjp", "fem_residual_vjp_noalloc", "fem_timing_enable", "fem_timing_read",
            "fem_graph_begin", "fem_graph_end", "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes", "fem_csr_spmv", "fem_solve",
-           "fem_csr_transpose", "fem_history_adjoint_workspace_bytes", "fem_history_adjoint")
+           "fem_csr_transpose", "fem_history_adjoint_workspace_bytes", "fem_history_adjoint", "fem_amg_create",
+           "fem_amg_update", "fem_amg_apply", "fem_amg_info", "fem_amg_aggregates", "fem_amg_destroy",
+           "fem_solve_amg")
 
 
 def lib():
@@ -100,6 +102,16 @@ def lib():
                             _c_i32, ctypes.c_double,
                             ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double), _c_p, _c_sz, _c_p]
     L.fem_csr_transpose.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
+    L.fem_amg_create.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, ctypes.POINTER(_c_p), _c_p]
+    L.fem_amg_update.argtypes = [_c_p, _c_p, ctypes.c_int, _c_p]
+    L.fem_amg_apply.argtypes = [_c_p, _c_p, _c_p, _c_p]
+    L.fem_amg_info.argtypes = [_c_p, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(_c_i32)]
+    L.fem_amg_aggregates.argtypes = [_c_p, _c_i32, _c_p]
+    L.fem_amg_destroy.argtypes = [_c_p]
+    L.fem_solve_amg.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, ctypes.c_int, _c_p, _c_p, _c_p,
+                                _c_i32, ctypes.c_double,
+                                ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double), _c_p, _c_sz, _c_p]
     L.fem_history_adjoint_workspace_bytes.argtypes = [_c_i32, _c_i32]
     L.fem_history_adjoint_workspace_bytes.restype = _c_sz
     L.fem_history_adjoint.argtypes = [ctypes.POINTER(FemMesh), ctypes.POINTER(FemCsr), ctypes.POINTER(FemParams)] + \
@@ -559,19 +571,76 @@ def csr_spmv(csr, K, x, y=None, stream=None):
     return y
 
 
-PC_JACOBI, PC_BLOCK_JACOBI = 0, 1
+PC_JACOBI, PC_BLOCK_JACOBI, PC_AMG = 0, 1, 2
 KRYLOV = {"bicgstab": 0, "cg": 1}
+AMG_MAX_LEVELS = 12
+
+
+class AMG:
+    """Aggregation multigrid hierarchy of fem_amg_create for pattern csr,
+    aggregated from the block norms of K; bc_mask (device [n_rows] uint8 or
+    bool, nonzero on constrained dofs) or None.  update(K) sets the numeric
+    operators, apply(r) is one V-cycle."""
+
+    def __init__(self, csr, K, bc_mask=None, stream=None):
+        self.csr = csr
+        self.h = _c_p()
+        bc = None if bc_mask is None else bc_mask.reshape(-1).to(torch.uint8).contiguous()
+        _check("fem_amg_create", lib().fem_amg_create(ctypes.byref(csr.c()), _ptr(K), _kprec(K), _ptr(bc),
+                                                      ctypes.byref(self.h), _stream(stream)))
+
+    def update(self, K, stream=None):
+        self.K = K
+        _check("fem_amg_update", lib().fem_amg_update(self.h, _ptr(K), _kprec(K), _stream(stream)))
+
+    def apply(self, r, z=None, stream=None):
+        if z is None:
+            z = torch.empty_like(r)
+        _check("fem_amg_apply", lib().fem_amg_apply(self.h, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def info(self):
+        """(levels as [(nodes, 3x3 blocks)], coarsest inverted exactly)"""
+        nl, dense = _c_i32(0), _c_i32(0)
+        nodes = (_c_i32 * AMG_MAX_LEVELS)()
+        blocks = (ctypes.c_int64 * AMG_MAX_LEVELS)()
+        _check("fem_amg_info", lib().fem_amg_info(self.h, ctypes.byref(nl), nodes, blocks, ctypes.byref(dense)))
+        return [(int(nodes[i]), int(blocks[i])) for i in range(nl.value)], bool(dense.value)
+
+    def aggregates(self, level):
+        """numpy int32 [nodes of level - 1]: aggregate of each node of the level above"""
+        levels, _ = self.info()
+        out = np.empty(levels[level - 1][0], dtype=np.int32)
+        _check("fem_amg_aggregates", lib().fem_amg_aggregates(self.h, int(level),
+                                                              out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            lib().fem_amg_destroy(self.h)
+            self.h = _c_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Solver:
-    """Workspace of fem_solve for a pattern (reused across solves)."""
+    """Workspace of fem_solve for a pattern (reused across solves).  With
+    precond=PC_AMG the multigrid hierarchy is built at the first solve from
+    that K (bc_mask: the constrained dofs, as for fem_residual_tangent) and
+    its numeric operators are rebuilt for each K."""
 
-    def __init__(self, csr, device="cuda", precond=PC_BLOCK_JACOBI, method="bicgstab"):
+    def __init__(self, csr, device="cuda", precond=PC_BLOCK_JACOBI, method="bicgstab", bc_mask=None):
         self.csr = csr
         self.precond = int(precond)
         self.method = KRYLOV[method]
         self.ws_bytes = lib().fem_solver_workspace_bytes(csr.n_rows, csr.nnz)
         self.ws = _ws(self.ws_bytes, device)
+        self.bc_mask = bc_mask
+        self.amg = None
 
     def solve(self, K, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True, precond=None, method=None):
         """Solve K x = b (method "bicgstab", or "cg" for a tangent symmetric
@@ -583,9 +652,18 @@ class Solver:
         res = ctypes.c_double(0.0)
         pc = self.precond if precond is None else int(precond)
         mt = self.method if method is None else KRYLOV[method]
-        rc = lib().fem_solve(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), mt, pc, _ptr(b), _ptr(x), int(max_iter),
-                             float(rtol), ctypes.byref(it), ctypes.byref(res), _ptr(self.ws), self.ws_bytes,
-                             _stream(stream))
+        if pc == PC_AMG:
+            if self.amg is None:
+                self.amg = AMG(self.csr, K, self.bc_mask, stream)
+            fn = "fem_solve_amg"
+            rc = lib().fem_solve_amg(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), mt, self.amg.h, _ptr(b), _ptr(x),
+                                     int(max_iter), float(rtol), ctypes.byref(it), ctypes.byref(res), _ptr(self.ws),
+                                     self.ws_bytes, _stream(stream))
+        else:
+            fn = "fem_solve"
+            rc = lib().fem_solve(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), mt, pc, _ptr(b), _ptr(x),
+                                 int(max_iter), float(rtol), ctypes.byref(it), ctypes.byref(res), _ptr(self.ws),
+                                 self.ws_bytes, _stream(stream))
         if check:
-            _check("fem_solve", rc)
+            _check(fn, rc)
         return x, int(it.value), float(res.value)

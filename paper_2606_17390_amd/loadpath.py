@@ -78,7 +78,7 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
     out = fem.Forward(mesh, csr, prec)
     if krylov == "auto":
         krylov = "bicgstab" if params.model & fem.MODEL_FBAR else "cg"
-    solver = fem.Solver(csr, dev, precond=precond, method=krylov)
+    solver = fem.Solver(csr, dev, precond=precond, method=krylov, bc_mask=bc_mask)
     d = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
     d_prev, dt_prev = None, None
     h = hist0.clone()

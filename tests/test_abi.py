@@ -123,6 +123,38 @@ def test_solver_arguments_are_rejected_on_the_host(lib):
     assert lib.fem_solver_workspace_bytes(-3, 0) == 0 and lib.fem_solver_workspace_bytes(3, -1) == 0
 
 
+def test_multigrid_arguments_are_rejected_on_the_host(lib):
+    """The multigrid entry points validate their arguments before any device
+    work (the fake pointers below are never dereferenced)."""
+    from paper_2606_17390_amd import fem
+    fake = ctypes.c_void_p(256)
+    h = ctypes.c_void_p()
+
+    def create(n_rows=6, nnz=18, prec=fem.FP64, K=fake, out=True):
+        c = fem.FemCsr(n_rows, nnz, fake, fake, None, None, None)
+        return lib.fem_amg_create(ctypes.byref(c), K, prec, None, ctypes.byref(h) if out else None, None)
+
+    assert create(out=False) == fem.FEM_EINVAL
+    assert create(K=None) == fem.FEM_EINVAL and h.value is None
+    assert create(prec=fem.FP64_K32) == fem.FEM_EINVAL  # K is FP64 or FP32
+    assert create(n_rows=0, nnz=0) == fem.FEM_EINVAL and b"non-empty" in lib.fem_last_error()
+    assert create(n_rows=5) == fem.FEM_EINVAL
+    assert create(nnz=17) == fem.FEM_EINVAL and b"multiple of 9" in lib.fem_last_error()
+    assert lib.fem_amg_update(None, fake, fem.FP64, None) == fem.FEM_EINVAL
+    assert lib.fem_amg_apply(None, fake, fake, None) == fem.FEM_EINVAL
+    assert lib.fem_amg_info(None, None, None, None, None) == fem.FEM_EINVAL
+    assert lib.fem_amg_aggregates(None, 1, fake) == fem.FEM_EINVAL
+    assert lib.fem_amg_destroy(None) == fem.FEM_OK
+    c = fem.FemCsr(6, 18, fake, fake, None, None, None)
+    it, res = ctypes.c_int32(-1), ctypes.c_double(-1.0)
+    assert lib.fem_solve_amg(ctypes.byref(c), fake, fem.FP64, 1, None, fake, fake, 10, 1e-8, ctypes.byref(it),
+                             ctypes.byref(res), fake, 1 << 40, None) == fem.FEM_EINVAL
+    assert b"multigrid" in lib.fem_last_error()
+    # fem_solve itself does not take the multigrid preconditioner
+    assert lib.fem_solve(ctypes.byref(c), fake, fem.FP64, 1, fem.PC_AMG, fake, fake, 10, 1e-8, ctypes.byref(it),
+                         ctypes.byref(res), fake, 1 << 40, None) == fem.FEM_EINVAL
+
+
 def test_noalloc_vjp_rejects_meshes_beyond_its_scratch(lib):
     """fem_residual_vjp_noalloc refuses, before any device work, a mesh whose
     workspace exceeds its static scratch (64 MiB: about 1.1M elements)."""

@@ -1,0 +1,233 @@
+"""Aggregation multigrid preconditioner on the GPU (through the C ABI):
+  - a hierarchy of one dense level is the exact inverse;
+  - the aggregates partition each level into connected groups of at most
+    eight nodes, and the level sizes agree with them;
+  - one V-cycle equals a numpy V-cycle built from the documented definitions
+    (masked piecewise-constant prolongation, FP32 Galerkin operators, l1
+    block-Jacobi sweeps, dense coarsest inverse) on the same aggregates;
+  - the preconditioned CG (plain tangent) and BiCGSTAB (F-bar tangent) solves
+    match a dense solve, and repeat bitwise;
+  - fewer iterations than node-block Jacobi on a 16^3 plastic state, and a
+    symmetric operator for a symmetric tangent.
+The matrices are tangents of the unit-cube forward problem of Sec. 3.1.3 at
+a trial state (x = 1 face moved by t (0.2, 0.1), t = 0.05, zero history):
+every Gauss point plastic, the tangent positive definite on the free dofs."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import gpu_problem
+from paper_2606_17390_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fem():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2606_17390_amd import fem as F
+    F.lib()
+    return F
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cube_state(n, t=0.05, fbar=False, ny=None, nz=None):
+    p = synth.unit_cube_forward(n, ny, nz)
+    d = np.zeros_like(p.X)
+    d[:, 0] = 0.2 * t * p.X[:, 0]
+    d[:, 1] = 0.1 * t * p.X[:, 0]
+    return dataclasses.replace(p, d=d, fbar=fbar)
+
+
+def tangent(fem, p, prec):
+    mesh, params, d, h, bc, _ = gpu_problem(p, fem)
+    csr = fem.csr_pattern(mesh)
+    out = fem.residual_tangent(mesh, csr, params, d, h, bc_mask=bc, prec=prec)
+    torch.cuda.synchronize()
+    return csr, out.K, bc
+
+
+def host_csr(csr, K):
+    import scipy.sparse as sp
+    n = csr.n_rows
+    return sp.csr_matrix((K.double().cpu().numpy(), csr.col_idx.cpu().numpy(), csr.row_ptr.cpu().numpy()),
+                         shape=(n, n))
+
+
+def ref_vcycle(A0, free0, aggs, r, fine_is_float):
+    """V(1,1)-cycle from the definitions (host, FP64 vectors): A0 the finest
+    operator (scipy CSR), free0 its free-dof mask, aggs the aggregate map of
+    each level transition."""
+    import scipy.sparse as sp
+
+    def l1_blocks(A):
+        n = A.shape[0] // 3
+        coo = A.tocoo()
+        inb = (coo.row // 3) == (coo.col // 3)
+        D = np.zeros((n, 3, 3))
+        np.add.at(D, (coo.row[inb] // 3, coo.row[inb] % 3, coo.col[inb] % 3), coo.data[inb])
+        l1 = np.zeros(A.shape[0])
+        np.add.at(l1, coo.row[~inb], np.abs(coo.data[~inb]))
+        D[:, [0, 1, 2], [0, 1, 2]] += l1.reshape(n, 3)
+        Minv = np.linalg.inv(D)
+        rows = np.repeat(np.arange(3 * n), 3)
+        cols = (3 * (np.arange(3 * n) // 3))[:, None] + np.arange(3)[None, :]
+        return sp.csr_matrix((Minv.reshape(-1), (rows, cols.reshape(-1))), shape=A.shape)
+
+    As, Ms, Ps, masks = [A0], [], [], [free0]
+    for agg in aggs:
+        nf, nc = agg.size, int(agg.max()) + 1
+        m = masks[-1].astype(float)
+        P = sp.csr_matrix((m, (np.arange(3 * nf), 3 * np.repeat(agg, 3) + np.tile(np.arange(3), nf))),
+                          shape=(3 * nf, 3 * nc))
+        Ac = (P.T @ As[-1] @ P).tocsr()
+        mc = np.zeros(3 * nc, dtype=bool)
+        np.logical_or.at(mc, 3 * np.repeat(agg, 3) + np.tile(np.arange(3), nf), masks[-1])
+        Ac = Ac + sp.diags((~mc).astype(float))
+        Ac.data = Ac.data.astype(np.float32).astype(np.float64)
+        Ps.append(P)
+        As.append(Ac.tocsr())
+        masks.append(mc)
+    for A in As:
+        Ms.append(l1_blocks(A))
+    Cinv = np.linalg.inv(As[-1].toarray())
+
+    def cycle(l, b):
+        if l == len(As) - 1:
+            return Cinv @ b
+        x = Ms[l] @ b
+        rc = Ps[l].T @ (b - As[l] @ x)
+        x = x + Ps[l] @ cycle(l + 1, rc)
+        return x + Ms[l] @ (b - As[l] @ x)
+
+    return cycle(0, r)
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
+def test_single_dense_level_is_the_inverse(fem, prec_name):
+    p = synth.small_slab(61, 3, 2, 1)
+    assert p.n_nodes <= 32
+    csr, K, bc = tangent(fem, p, getattr(fem, prec_name))
+    amg = fem.AMG(csr, K, bc)
+    amg.update(K)
+    levels, dense = amg.info()
+    say(f"dense level {prec_name}: {levels}")
+    assert len(levels) == 1 and dense and levels[0][0] == p.n_nodes
+    A = host_csr(csr, K).toarray()
+    r = np.random.default_rng(7).standard_normal(csr.n_rows)
+    z = amg.apply(torch.as_tensor(r).cuda())
+    torch.cuda.synchronize()
+    ref = np.linalg.solve(A, r)
+    assert np.abs(z.cpu().numpy() - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def check_aggregates(G, agg):
+    """agg partitions the nodes of the node graph G (scipy CSR pattern) into
+    connected groups of at most eight nodes; returns their number."""
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as cg
+    n = G.shape[0]
+    assert agg.shape == (n,) and agg.min() == 0
+    nc = int(agg.max()) + 1
+    sizes = np.bincount(agg, minlength=nc)
+    assert sizes.min() >= 1 and sizes.max() <= 8
+    coo = G.tocoo()
+    same = agg[coo.row] == agg[coo.col]
+    Gin = sp.csr_matrix((np.ones(same.sum()), (coo.row[same], coo.col[same])), shape=(n, n))
+    ncomp, _ = cg.connected_components(Gin, directed=False)
+    assert ncomp == nc  # one component per aggregate
+    return nc
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
+def test_hierarchy_and_vcycle_match_the_definitions(fem, prec_name):
+    import scipy.sparse as sp
+    p = cube_state(10, ny=9, nz=7)
+    csr, K, bc = tangent(fem, p, getattr(fem, prec_name))
+    amg = fem.AMG(csr, K, bc)
+    amg.update(K)
+    levels, dense = amg.info()
+    say(f"hierarchy {prec_name}: {levels} dense {dense}")
+    assert len(levels) >= 3 and dense and levels[0] == (p.n_nodes, csr.nnz // 9)
+    assert levels[-1][0] <= 32
+    A0 = host_csr(csr, K)
+    free0 = p.bc_mask == 0
+    coo = A0.tocoo()
+    G = sp.csr_matrix((np.ones(coo.nnz), (coo.row // 3, coo.col // 3)), shape=(p.n_nodes, p.n_nodes))
+    aggs = []
+    for l in range(1, len(levels)):
+        agg = amg.aggregates(l)
+        nc = check_aggregates(G, agg)
+        assert nc == levels[l][0]
+        # the coarse pattern: one block per pair of aggregates joined by a fine block
+        Pn = sp.csr_matrix((np.ones(agg.size), (np.arange(agg.size), agg)), shape=(agg.size, nc))
+        G = (Pn.T @ G @ Pn).tocsr()
+        assert G.nnz == levels[l][1]
+        aggs.append(agg)
+    rng = np.random.default_rng(11)
+    for trial in range(2):
+        r = rng.standard_normal(csr.n_rows) * free0
+        z = amg.apply(torch.as_tensor(r).cuda())
+        torch.cuda.synchronize()
+        ref = ref_vcycle(A0, free0, aggs, r, prec_name != "FP64")
+        err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+        say(f"  V-cycle {trial}: rel err {err:.2e}")
+        assert err <= 2e-6
+        assert np.all(z.cpu().numpy()[~free0] == 0.0)
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
+@pytest.mark.parametrize("fbar", [False, True])
+def test_preconditioned_solve_matches_dense_solve(fem, prec_name, fbar):
+    """CG on the plain (symmetric) tangent, BiCGSTAB on the F-bar one; the
+    right-hand side is zero on the constrained dofs (a Newton correction)."""
+    p = cube_state(7, fbar=fbar, ny=6, nz=5)
+    csr, K, bc = tangent(fem, p, getattr(fem, prec_name))
+    method = "bicgstab" if fbar else "cg"
+    A = host_csr(csr, K).toarray()
+    b = np.random.default_rng(5).standard_normal(csr.n_rows)
+    b[p.bc_mask.astype(bool)] = 0.0
+    s = fem.Solver(csr, precond=fem.PC_AMG, method=method, bc_mask=bc)
+    x, its, res = s.solve(K, torch.as_tensor(b).cuda(), rtol=1e-12)
+    torch.cuda.synchronize()
+    say(f"AMG {method} {prec_name}: {its} iterations, res {res:.2e}, levels {s.amg.info()}")
+    ref = np.linalg.solve(A, b)
+    assert res <= 1e-12 and its > 0
+    assert np.abs(x.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
+    assert np.linalg.norm(b - A @ x.cpu().numpy()) <= 1e-9 * np.linalg.norm(b)
+    x2, its2, _ = s.solve(K, torch.as_tensor(b).cuda(), rtol=1e-12)
+    assert its2 == its and torch.equal(x, x2)
+
+
+def test_fewer_iterations_than_block_jacobi_and_symmetric(fem):
+    p = cube_state(16)
+    csr, K, bc = tangent(fem, p, fem.FP64_K32)
+    b = np.random.default_rng(9).standard_normal(csr.n_rows)
+    b[p.bc_mask.astype(bool)] = 0.0
+    bt = torch.as_tensor(b).cuda()
+    s = fem.Solver(csr, precond=fem.PC_AMG, method="cg", bc_mask=bc)
+    x, its_amg, res = s.solve(K, bt, rtol=1e-8, max_iter=20000)
+    _, its_bj, res_bj = s.solve(K, bt, rtol=1e-8, max_iter=20000, precond=fem.PC_BLOCK_JACOBI)
+    torch.cuda.synchronize()
+    say(f"16^3 CG to 1e-8: AMG {its_amg} ({res:.1e}), block Jacobi {its_bj} ({res_bj:.1e}), levels {s.amg.info()}")
+    assert res <= 1e-8 and res_bj <= 1e-8
+    assert its_amg * 3 < its_bj
+    # M symmetric for the symmetric free-free block
+    free = torch.as_tensor(p.bc_mask == 0).cuda()
+    rng = np.random.default_rng(10)
+    u = torch.as_tensor(rng.standard_normal(csr.n_rows)).cuda() * free
+    v = torch.as_tensor(rng.standard_normal(csr.n_rows)).cuda() * free
+    Mu, Mv = s.amg.apply(u), s.amg.apply(v)
+    a, c = float(torch.dot(v, Mu)), float(torch.dot(u, Mv))
+    say(f"  v.Mu {a:.12e} u.Mv {c:.12e}")
+    assert abs(a - c) <= 1e-6 * max(abs(a), abs(c))
+    assert float(torch.dot(u, Mu)) > 0.0
