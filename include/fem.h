@@ -363,9 +363,13 @@ int fem_csr_transpose(const fem_csr *csr, const void *K_vals, fem_precision prec
  *   - coarse operators A_{l+1} = P^T A_l P, sums of masked 3x3 blocks in
  *     FP32 (fixed order); a coarse dof without a free fine dof gets an
  *     identity row;
- *   - smoother: one l1 block-Jacobi sweep before and after the coarse
- *     correction, M_l = (D_I + diag of the absolute off-block row sums)^-1
- *     per node (3x3 inverse; a singular block falls back to its diagonal);
+ *   - smoother: one damped block-Jacobi sweep before and after the coarse
+ *     correction, M_l = omega_l D_I^-1 per node (3x3 inverse of the
+ *     diagonal block; a singular block falls back to its diagonal), with
+ *     omega_l = (4/3) / rho_l and rho_l the spectral radius of D_l^-1 A_l
+ *     estimated by 10 power steps from a fixed pseudo-random start vector
+ *     (zero on constrained dofs; the set-up is deterministic); omega_l = 0.5
+ *     if the estimate is not positive and finite;
  *   - coarsest level: its explicit inverse (Gauss-Jordan with partial
  *     pivoting in FP64; a pivot below 1e-13 of the largest diagonal entry
  *     drops that dof) when it has at most FEM_AMG_DENSE_NODES nodes, else
@@ -385,14 +389,16 @@ int fem_csr_transpose(const fem_csr *csr, const void *K_vals, fem_precision prec
  *   Errors: FEM_EINVAL (bad arguments, a node with more than 21845
  *   neighbours), FEM_ENOMEM (host or device allocation), FEM_EHIP.
  * fem_amg_update -- numeric set-up for values K_vals on the same pattern
- *   (any precision above): Galerkin operators, smoother inverses and the
- *   coarsest inverse.  The handle keeps K_vals (it must stay valid while
+ *   (any precision above): Galerkin operators, smoother blocks and their
+ *   damping (power iteration), and the coarsest inverse.  The handle keeps K_vals (it must stay valid while
  *   fem_amg_apply / fem_solve_amg use it).  Asynchronous on `stream`.
  * fem_amg_apply -- z = M r, device [n_rows] each (FP64; must not alias).
  *   Asynchronous on `stream`; calls on one handle must not overlap.
  * fem_amg_info -- number of levels and, per level (up to
- *   FEM_AMG_MAX_LEVELS entries each, either may be NULL), nodes and 3x3
- *   blocks; dense = 1 if the coarsest level is inverted exactly.
+ *   FEM_AMG_MAX_LEVELS entries each, any may be NULL), nodes, 3x3 blocks and
+ *   the smoother damping omega_l of the last fem_amg_update (1 before it and
+ *   on a level inverted exactly; host copy, synchronous); dense = 1 if the
+ *   coarsest level is inverted exactly.
  * fem_amg_aggregates -- agg (host [nodes of level - 1]) = the aggregate, a
  *   node of `level` (1 <= level < n_levels), of each node of the level above.
  *   Synchronous.
@@ -407,7 +413,8 @@ int fem_amg_create(const fem_csr *csr, const void *K_vals, fem_precision prec, c
                    fem_amg **out, void *stream);
 int fem_amg_update(fem_amg *amg, const void *K_vals, fem_precision prec, void *stream);
 int fem_amg_apply(fem_amg *amg, const double *r, double *z, void *stream);
-int fem_amg_info(const fem_amg *amg, int32_t *n_levels, int32_t *nodes, int64_t *blocks, int32_t *dense);
+int fem_amg_info(const fem_amg *amg, int32_t *n_levels, int32_t *nodes, int64_t *blocks, int32_t *dense,
+                 double *omega);
 int fem_amg_aggregates(const fem_amg *amg, int32_t level, int32_t *agg);
 int fem_amg_destroy(fem_amg *amg);
 int fem_solve_amg(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_krylov method, fem_amg *amg,

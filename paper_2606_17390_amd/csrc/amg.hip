@@ -65,6 +65,10 @@ struct fem_amg {
     bool dense = false;
     int nd = 0;                // dofs of the dense coarsest level
     double* cinv = nullptr;    // device [nd][nd]
+    double* om = nullptr;      // device [FEM_AMG_MAX_LEVELS] smoother damping per level
+    double* sc = nullptr;      // device [2 FEM_AMG_MAX_LEVELS] power-iteration norms
+    double* part = nullptr;    // device partial sums of the power iteration
+    int npart = 0;
     Level L[FEM_AMG_MAX_LEVELS];
     void* mem = nullptr;       // one device allocation for everything above
     const void* K = nullptr;   // values of the last fem_amg_update
@@ -105,11 +109,11 @@ __global__ __launch_bounds__(256) void cols_norms_kernel(int32_t n, const int32_
     }
 }
 
-// minv[9I..] = inverse of D_I + diag(l1_I): D_I the diagonal 3x3 block of
-// node I, l1_I[a] = sum of |A(3I+a, j)| over the columns j outside node I.
-// A singular block falls back to the inverse of its diagonal (zero -> 1).
+// minv[9I..] = inverse of D_I, the diagonal 3x3 block of node I (32 lanes
+// per node find it; a singular block falls back to the inverse of its
+// diagonal, zero -> 1).  The damping factor is applied afterwards.
 template <typename RV>
-__global__ __launch_bounds__(256) void l1_minv_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
+__global__ __launch_bounds__(256) void bj_minv_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ ncol, const RV* __restrict__ val,
                                                       double* __restrict__ minv) {
     const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
@@ -117,31 +121,16 @@ __global__ __launch_bounds__(256) void l1_minv_kernel(int32_t n, const int32_t* 
     if (I >= n) return;  // whole 32-lane groups leave together
     const int32_t b = row_ptr[3 * I], len = row_ptr[3 * I + 1] - b, deg = len / 3;
     const int32_t* __restrict__ nc = ncol + b / 9;
-    double l1[3] = {0.0, 0.0, 0.0};
     int32_t kd = -1;
-    for (int32_t k = l; k < deg; k += kLanes) {
-        if (nc[k] == I) {
-            kd = k;
-            continue;
-        }
+    for (int32_t k = l; k < deg; k += kLanes)
+        if (nc[k] == I) kd = k;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) l1[a] += fabs((double)val[(int64_t)b + (int64_t)a * len + 3 * k + c]);
-    }
-#pragma unroll
-    for (int m = 1; m < kLanes; m <<= 1) {
-        l1[0] += __shfl_xor(l1[0], m, kLanes);
-        l1[1] += __shfl_xor(l1[1], m, kLanes);
-        l1[2] += __shfl_xor(l1[2], m, kLanes);
-        kd = max(kd, __shfl_xor(kd, m, kLanes));
-    }
+    for (int m = 1; m < kLanes; m <<= 1) kd = max(kd, __shfl_xor(kd, m, kLanes));
     if (l != 0) return;
     double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     if (kd >= 0)
         for (int a = 0; a < 3; ++a)
             for (int c = 0; c < 3; ++c) D[a][c] = (double)val[(int64_t)b + (int64_t)a * len + 3 * kd + c];
-    for (int a = 0; a < 3; ++a) D[a][a] += l1[a];
     const double c00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
     const double c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
     const double c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
@@ -344,28 +333,181 @@ __global__ __launch_bounds__(256) void residual_kernel(int32_t n, const int32_t*
     }
 }
 
-// coarse b = P^T r (masked sums over the aggregate's nodes), then x = M b
-__global__ __launch_bounds__(256) void restrict_kernel(int32_t n, const int32_t* __restrict__ mptr,
-                                                       const int32_t* __restrict__ mem,
-                                                       const uint8_t* __restrict__ fmask,
-                                                       const double* __restrict__ r, const double* __restrict__ minv,
-                                                       double* __restrict__ b, double* __restrict__ x,
-                                                       const int32_t* __restrict__ fl) {
+// Residual and restriction in one pass: workgroup C takes the (at most
+// eight) nodes of aggregate C, 32 lanes per node compute r = b - A x on its
+// rows, and the masked sums over the aggregate give the coarse right-hand
+// side cb = P^T r; then the first coarse sweep cx = M_c cb.  The fine
+// residual itself is never stored.
+template <typename RV>
+__global__ __launch_bounds__(256) void resid_restrict_kernel(const int32_t* __restrict__ mptr,
+                                                             const int32_t* __restrict__ mem,
+                                                             const uint8_t* __restrict__ fmask,
+                                                             const int32_t* __restrict__ row_ptr,
+                                                             const int32_t* __restrict__ ncol,
+                                                             const RV* __restrict__ val, const double* __restrict__ x,
+                                                             const double* __restrict__ b,
+                                                             const double* __restrict__ cminv, double* __restrict__ cb,
+                                                             double* __restrict__ cx, const int32_t* __restrict__ fl) {
     if (stopped(fl)) return;
-    const int64_t C = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (C >= n) return;
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int32_t k = mptr[C]; k < mptr[C + 1]; ++k) {
-        const int64_t i = mem[k];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            if (fmask[3 * i + a]) s[a] += r[3 * i + a];
+    __shared__ double part[8][3];
+    const int64_t C = blockIdx.x;
+    const int g = (int)(threadIdx.x >> 5), l = (int)(threadIdx.x & (kLanes - 1));
+    const int32_t m0 = mptr[C], cnt = mptr[C + 1] - m0;
+    int64_t I = -1;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (g < cnt) {
+        I = mem[m0 + g];
+        const int32_t bs = row_ptr[3 * I], len = row_ptr[3 * I + 1] - bs, deg = len / 3;
+        const int32_t* __restrict__ nc = ncol + bs / 9;
+        for (int32_t k = l; k < deg; k += kLanes) {
+            const int64_t J = nc[k];
+            const double x0 = x[3 * J], x1 = x[3 * J + 1], x2 = x[3 * J + 2];
+            const RV* __restrict__ v = val + bs + 3 * k;
+            s0 += (double)v[0] * x0 + (double)v[1] * x1 + (double)v[2] * x2;
+            s1 += (double)v[len] * x0 + (double)v[len + 1] * x1 + (double)v[len + 2] * x2;
+            s2 += (double)v[2 * len] * x0 + (double)v[2 * len + 1] * x1 + (double)v[2 * len + 2] * x2;
+        }
     }
-    const double* m = minv + 9 * C;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        b[3 * C + a] = s[a];
-        x[3 * C + a] = m[3 * a] * s[0] + m[3 * a + 1] * s[1] + m[3 * a + 2] * s[2];
+    for (int m = 1; m < kLanes; m <<= 1) {
+        s0 += __shfl_xor(s0, m, kLanes);
+        s1 += __shfl_xor(s1, m, kLanes);
+        s2 += __shfl_xor(s2, m, kLanes);
+    }
+    if (g < cnt && l < 3) {
+        const double ra = b[3 * I + l] - (l == 0 ? s0 : (l == 1 ? s1 : s2));
+        part[g][l] = fmask[3 * I + l] ? ra : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < cnt; ++k)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) r[a] += part[k][a];
+        const double* m = cminv + 9 * C;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cb[3 * C + a] = r[a];
+            cx[3 * C + a] = m[3 * a] * r[0] + m[3 * a + 1] * r[1] + m[3 * a + 2] * r[2];
+        }
+    }
+}
+
+// The levels t, ..., nl - 1 of at most kTailNodes nodes each in one
+// workgroup of 1024 threads (that part of the cycle is bound by launch
+// latency, not by work): on entry level t holds its right-hand side b and
+// first sweep x = M b; on exit its post-smoothed iterate y (or, when level t
+// is the dense coarsest level, x = Cinv b).  Phases are separated by
+// workgroup barriers; the products take 32 lanes per node as on the large
+// levels.
+constexpr int kTailNodes = 512;
+
+struct TailLevel {
+    int32_t n;
+    const int32_t* row_ptr;
+    const int32_t* ncol;
+    const float* vals;
+    const double* minv;
+    const uint8_t* mask;
+    double *b, *x, *r, *y;
+    const int32_t *agg, *mptr, *mem;  // transfer from the level above (unused at level t)
+};
+
+struct TailArgs {
+    int nlv;    // levels in the tail
+    int dense;  // last one inverted exactly
+    int nd;
+    const double* cinv;
+    TailLevel L[FEM_AMG_MAX_LEVELS];
+};
+
+// POST = 0: r = b - A x;  POST = 1: y = x + M (b - A x); 32 lanes per node.
+template <int POST>
+__device__ inline void tail_sweep(const TailLevel& F, int tid) {
+    const int g = tid >> 5, l = tid & (kLanes - 1);
+    for (int64_t base = 0; base < F.n; base += 1024 / kLanes) {
+        const int64_t I = base + g;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        if (I < F.n) {
+            const int32_t bs = F.row_ptr[3 * I], len = F.row_ptr[3 * I + 1] - bs, deg = len / 3;
+            for (int32_t k = l; k < deg; k += kLanes) {
+                const int64_t J = F.ncol[bs / 9 + k];
+                const double x0 = F.x[3 * J], x1 = F.x[3 * J + 1], x2 = F.x[3 * J + 2];
+                const float* v = F.vals + bs + 3 * k;
+                s0 += (double)v[0] * x0 + (double)v[1] * x1 + (double)v[2] * x2;
+                s1 += (double)v[len] * x0 + (double)v[len + 1] * x1 + (double)v[len + 2] * x2;
+                s2 += (double)v[2 * len] * x0 + (double)v[2 * len + 1] * x1 + (double)v[2 * len + 2] * x2;
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < kLanes; m <<= 1) {
+            s0 += __shfl_xor(s0, m, kLanes);
+            s1 += __shfl_xor(s1, m, kLanes);
+            s2 += __shfl_xor(s2, m, kLanes);
+        }
+        if (I < F.n && l < 3) {
+            const double r0 = F.b[3 * I] - s0, r1 = F.b[3 * I + 1] - s1, r2 = F.b[3 * I + 2] - s2;
+            if (POST) {
+                const double* m = F.minv + 9 * I;
+                F.y[3 * I + l] = F.x[3 * I + l] + m[3 * l] * r0 + m[3 * l + 1] * r1 + m[3 * l + 2] * r2;
+            } else {
+                F.r[3 * I + l] = l == 0 ? r0 : (l == 1 ? r1 : r2);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void tail_kernel(TailArgs A, const int32_t* fl) {
+    if (stopped(fl)) return;
+    const int tid = threadIdx.x;
+    const int nlv = A.nlv;
+    for (int l = 0; l + 1 < nlv; ++l) {
+        const TailLevel& F = A.L[l];
+        const TailLevel& C = A.L[l + 1];
+        tail_sweep<0>(F, tid);
+        __syncthreads();
+        for (int64_t c = tid; c < C.n; c += 1024) {
+            double s[3] = {0.0, 0.0, 0.0};
+            for (int32_t k = C.mptr[c]; k < C.mptr[c + 1]; ++k) {
+                const int64_t i = C.mem[k];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (F.mask[3 * i + a]) s[a] += F.r[3 * i + a];
+            }
+            const double* m = C.minv + 9 * c;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                C.b[3 * c + a] = s[a];
+                C.x[3 * c + a] = m[3 * a] * s[0] + m[3 * a + 1] * s[1] + m[3 * a + 2] * s[2];
+            }
+        }
+        __syncthreads();
+    }
+    const TailLevel& K = A.L[nlv - 1];
+    if (A.dense) {
+        for (int i = tid; i < A.nd; i += 1024) {
+            double s = 0.0;
+            for (int j = 0; j < A.nd; ++j) s += A.cinv[(int64_t)i * A.nd + j] * K.b[j];
+            K.x[i] = s;
+        }
+    } else {
+        tail_sweep<1>(K, tid);
+    }
+    __syncthreads();
+    const double* yc = A.dense ? K.x : K.y;
+    for (int l = nlv - 2; l >= 0; --l) {
+        const TailLevel& F = A.L[l];
+        const TailLevel& C = A.L[l + 1];
+        for (int64_t i = tid; i < F.n; i += 1024) {
+            const int64_t c = C.agg[i];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (F.mask[3 * i + a]) F.x[3 * i + a] += yc[3 * c + a];
+        }
+        __syncthreads();
+        tail_sweep<1>(F, tid);
+        __syncthreads();
+        yc = F.y;
     }
 }
 
@@ -412,6 +554,110 @@ __global__ __launch_bounds__(256) void prolong_kernel(int32_t n, const int32_t* 
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         if (fmask[3 * i + a]) x[3 * i + a] += y[3 * C + a];
+}
+
+// ---- damping of the smoother: omega_l = kOmegaNum / rho_l with rho_l the
+// spectral radius of D_l^-1 A_l estimated by kPowerSteps power steps from a
+// fixed pseudo-random start vector (zero on constrained dofs), so that the
+// set-up is deterministic.
+constexpr int kPowerSteps = 10;
+constexpr double kOmegaNum = 4.0 / 3.0;
+constexpr double kOmegaFallback = 0.5;  // for a non-positive or non-finite estimate
+
+// Fixed-order sum of one value per thread of a 256-thread block.
+__device__ inline double block_sum256(double v) {
+    __shared__ double sh[256];
+    __syncthreads();
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// v[i] = value in [-1, 1) from an integer hash of i (a SplitMix64-style
+// finaliser) on free dofs, 0 on constrained ones; part = block sums of v.v
+__global__ __launch_bounds__(256) void power_init(int64_t n3, const uint8_t* __restrict__ mask,
+                                                  double* __restrict__ v, double* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double x = 0.0;
+    if (i < n3) {
+        uint64_t h = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        h ^= h >> 31;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 29;
+        h *= 0x94D049BB133111EBull;
+        h ^= h >> 32;
+        x = mask[i] ? 2.0 * ((double)(h >> 11) * 0x1.0p-53) - 1.0 : 0.0;
+        v[i] = x;
+    }
+    const double t = block_sum256(x * x);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// w = D^-1 A (sc[1] v) (32 lanes per node); part = block sums of w.w
+template <typename RV>
+__global__ __launch_bounds__(256) void power_apply(int32_t n, const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ ncol, const RV* __restrict__ val,
+                                                   const double* __restrict__ minv, const double* __restrict__ v,
+                                                   const double* __restrict__ sc, double* __restrict__ w,
+                                                   double* __restrict__ part) {
+    const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
+    const int l = (int)(threadIdx.x & (kLanes - 1));
+    const double scale = sc[1];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (I < n) {
+        const int32_t bs = row_ptr[3 * I], len = row_ptr[3 * I + 1] - bs, deg = len / 3;
+        const int32_t* __restrict__ nc = ncol + bs / 9;
+        for (int32_t k = l; k < deg; k += kLanes) {
+            const int64_t J = nc[k];
+            const double x0 = v[3 * J], x1 = v[3 * J + 1], x2 = v[3 * J + 2];
+            const RV* __restrict__ q = val + bs + 3 * k;
+            s0 += (double)q[0] * x0 + (double)q[1] * x1 + (double)q[2] * x2;
+            s1 += (double)q[len] * x0 + (double)q[len + 1] * x1 + (double)q[len + 2] * x2;
+            s2 += (double)q[2 * len] * x0 + (double)q[2 * len + 1] * x1 + (double)q[2 * len + 2] * x2;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < kLanes; m <<= 1) {
+        s0 += __shfl_xor(s0, m, kLanes);
+        s1 += __shfl_xor(s1, m, kLanes);
+        s2 += __shfl_xor(s2, m, kLanes);
+    }
+    double ww = 0.0;
+    if (I < n && l < 3) {
+        const double* m = minv + 9 * I;
+        const double wl = scale * (m[3 * l] * s0 + m[3 * l + 1] * s1 + m[3 * l + 2] * s2);
+        w[3 * I + l] = wl;
+        ww = wl * wl;
+    }
+    const double t = block_sum256(ww);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// sc[0] = sqrt(sum of part), sc[1] = 1 / sc[0] (0 for a zero norm)
+__global__ __launch_bounds__(256) void power_norm(const double* __restrict__ part, int np, double* __restrict__ sc) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+    const double t = block_sum256(s);
+    if (threadIdx.x == 0) {
+        const double nr = sqrt(t);
+        sc[0] = nr;
+        sc[1] = nr > 0.0 ? 1.0 / nr : 0.0;
+    }
+}
+
+// minv *= omega = kOmegaNum / rho, rho = sc[0] (the norm of D^-1 A v for a
+// unit v after the last step); om = omega
+__global__ __launch_bounds__(256) void power_finish(int32_t n, const double* __restrict__ sc,
+                                                    double* __restrict__ minv, double* __restrict__ om) {
+    const double rho = sc[0];
+    const double omega = (rho > 0.0 && isfinite(kOmegaNum / rho)) ? kOmegaNum / rho : kOmegaFallback;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < 9 * (int64_t)n) minv[i] *= omega;
+    if (i == 0) om[0] = omega;
 }
 
 inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + 255) / 256); }
@@ -538,7 +784,10 @@ bool build_coarse(const HostLevel& f, std::vector<int32_t>&& agg, int32_t nc, Ho
     c.mptr.assign(nc + 1, 0);
     c.mem.resize(f.n);
     for (int32_t i = 0; i < f.n; ++i) ++c.mptr[c.agg[i] + 1];
-    for (int32_t k = 0; k < nc; ++k) c.mptr[k + 1] += c.mptr[k];
+    for (int32_t k = 0; k < nc; ++k) {
+        if (c.mptr[k + 1] > 8) return false;  // three pairings: at most eight nodes (one workgroup row each)
+        c.mptr[k + 1] += c.mptr[k];
+    }
     {
         std::vector<int32_t> fill(c.mptr.begin(), c.mptr.end() - 1);
         for (int32_t i = 0; i < f.n; ++i) c.mem[fill[c.agg[i]]++] = i;
@@ -626,11 +875,32 @@ bool build_hierarchy(std::vector<HostLevel>& H) {
     return true;
 }
 
+// Damped block-Jacobi blocks of level l (values V): the inverses of the
+// diagonal blocks, then omega_l from the power iteration (levels that are
+// inverted exactly keep omega = 1: their smoother is not used).
+template <typename V>
+void smoother_setup(fem_amg* h, int l, const V* vals, hipStream_t s) {
+    Level& L = h->L[l];
+    const unsigned nbl = blocks_for((int64_t)L.n * kLanes);
+    hipLaunchKernelGGL(bj_minv_kernel<V>, dim3(nbl), dim3(256), 0, s, L.n, L.row_ptr, L.ncol, vals, L.minv);
+    if (h->dense && l == h->nl - 1) return;
+    double* sc = h->sc + 2 * l;
+    const unsigned nbi = blocks_for(3 * (int64_t)L.n);
+    hipLaunchKernelGGL(power_init, dim3(nbi), dim3(256), 0, s, 3 * (int64_t)L.n, L.mask, L.r, h->part);
+    hipLaunchKernelGGL(power_norm, dim3(1), dim3(256), 0, s, h->part, (int)nbi, sc);
+    for (int k = 0; k < kPowerSteps; ++k) {
+        const double* v = (k & 1) ? L.y : L.r;
+        double* w = (k & 1) ? L.r : L.y;
+        hipLaunchKernelGGL(power_apply<V>, dim3(nbl), dim3(256), 0, s, L.n, L.row_ptr, L.ncol, vals, L.minv, v, sc, w,
+                           h->part);
+        hipLaunchKernelGGL(power_norm, dim3(1), dim3(256), 0, s, h->part, (int)nbl, sc);
+    }
+    hipLaunchKernelGGL(power_finish, dim3(blocks_for(9 * (int64_t)L.n)), dim3(256), 0, s, L.n, sc, L.minv, h->om + l);
+}
+
 template <typename RV>
 hipError_t update_typed(fem_amg* h, const RV* K, hipStream_t s) {
-    Level& L0 = h->L[0];
-    hipLaunchKernelGGL(l1_minv_kernel<RV>, dim3(blocks_for((int64_t)L0.n * kLanes)), dim3(256), 0, s, L0.n,
-                       L0.row_ptr, L0.ncol, K, L0.minv);
+    smoother_setup(h, 0, K, s);
     for (int l = 1; l < h->nl; ++l) {
         Level& c = h->L[l];
         const Level& f = h->L[l - 1];
@@ -640,8 +910,7 @@ hipError_t update_typed(fem_amg* h, const RV* K, hipStream_t s) {
         else
             hipLaunchKernelGGL(galerkin_kernel<float>, dim3(blocks_for(c.nb)), dim3(256), 0, s, c.nb, c.gptr, c.goff,
                                c.glen, c.gmask, c.gdst, c.gdlen, c.gfix, (const float*)f.vals, c.vals);
-        hipLaunchKernelGGL(l1_minv_kernel<float>, dim3(blocks_for((int64_t)c.n * kLanes)), dim3(256), 0, s, c.n,
-                           c.row_ptr, c.ncol, (const float*)c.vals, c.minv);
+        smoother_setup(h, l, (const float*)c.vals, s);
     }
     if (h->dense) {
         const Level& c = h->L[h->nl - 1];
@@ -706,26 +975,65 @@ hipError_t amg_vcycle(fem_amg* h, const double* b, double* z, bool presmoothed, 
     if (!presmoothed)
         hipLaunchKernelGGL(smooth0_kernel, dim3(blocks_for(L[0].n)), dim3(256), 0, s, L[0].n, L[0].minv, b, L[0].x,
                            fl);
+    if (nl == 1) {  // one level, not inverted: the two sweeps
+        level_residual<1>(h, 0, L[0].x, b, z, fl, s);
+        return hipGetLastError();
+    }
+    // levels [t, nl) run in the tail kernel; t = nl if no level is small enough
+    int t = nl;
+    for (int l = 1; l < nl; ++l)
+        if (L[l].n <= kTailNodes) {
+            t = l;
+            break;
+        }
+    const int down = std::min(t, nl - 1);  // fused residual-restriction steps 0 -> 1, ..., down - 1 -> down
     const double* bl = b;
-    for (int l = 0; l + 1 < nl; ++l) {
-        level_residual<0>(h, l, L[l].x, bl, L[l].r, fl, s);
+    for (int l = 0; l < down; ++l) {
         Level& c = L[l + 1];
-        if (l + 2 == nl && h->dense)
-            hipLaunchKernelGGL(dense_apply_kernel, dim3(1), dim3(256), 0, s, c.n, c.mptr, c.mem, L[l].mask, L[l].r,
-                               h->cinv, c.x, fl);
+        if (l > 0)
+            hipLaunchKernelGGL(resid_restrict_kernel<float>, dim3(c.n), dim3(256), 0, s, c.mptr, c.mem, L[l].mask,
+                               L[l].row_ptr, L[l].ncol, (const float*)L[l].vals, L[l].x, bl, c.minv, c.b, c.x, fl);
+        else if (h->prec == FEM_FP64)
+            hipLaunchKernelGGL(resid_restrict_kernel<double>, dim3(c.n), dim3(256), 0, s, c.mptr, c.mem, L[0].mask,
+                               L[0].row_ptr, L[0].ncol, static_cast<const double*>(h->K), L[0].x, bl, c.minv, c.b,
+                               c.x, fl);
         else
-            hipLaunchKernelGGL(restrict_kernel, dim3(blocks_for(c.n)), dim3(256), 0, s, c.n, c.mptr, c.mem,
-                               L[l].mask, L[l].r, c.minv, c.b, c.x, fl);
+            hipLaunchKernelGGL(resid_restrict_kernel<float>, dim3(c.n), dim3(256), 0, s, c.mptr, c.mem, L[0].mask,
+                               L[0].row_ptr, L[0].ncol, static_cast<const float*>(h->K), L[0].x, bl, c.minv, c.b,
+                               c.x, fl);
         bl = c.b;
     }
-    // coarsest: exact (dense) or one more sweep
-    const double* yc = L[nl - 1].x;
-    if (!h->dense) {
-        double* out = nl == 1 ? z : L[nl - 1].y;
-        level_residual<1>(h, nl - 1, L[nl - 1].x, nl == 1 ? b : L[nl - 1].b, out, fl, s);
-        yc = out;
+    const double* yc;
+    if (t < nl) {
+        TailArgs A;
+        A.nlv = nl - t;
+        A.dense = h->dense ? 1 : 0;
+        A.nd = h->nd;
+        A.cinv = h->cinv;
+        for (int l = t; l < nl; ++l) {
+            const Level& S = L[l];
+            TailLevel& T = A.L[l - t];
+            T.n = S.n;
+            T.row_ptr = S.row_ptr;
+            T.ncol = S.ncol;
+            T.vals = S.vals;
+            T.minv = S.minv;
+            T.mask = S.mask;
+            T.b = S.b;
+            T.x = S.x;
+            T.r = S.r;
+            T.y = S.y;
+            T.agg = S.agg;
+            T.mptr = S.mptr;
+            T.mem = S.mem;
+        }
+        hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, A, fl);
+        yc = (t == nl - 1 && h->dense) ? L[t].x : L[t].y;
+    } else {  // coarsest level not inverted and too large for the tail: the second sweep
+        level_residual<1>(h, nl - 1, L[nl - 1].x, L[nl - 1].b, L[nl - 1].y, fl, s);
+        yc = L[nl - 1].y;
     }
-    for (int l = nl - 2; l >= 0; --l) {
+    for (int l = down - 1; l >= 0; --l) {
         hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(L[l].n)), dim3(256), 0, s, L[l].n, L[l + 1].agg, L[l].mask,
                            yc, L[l].x, fl);
         double* out = l == 0 ? z : L[l].y;
@@ -806,7 +1114,8 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
     nrm.shrink_to_fit();
 
     if (!build_hierarchy(H))
-        return set_error(FEM_EINVAL, "fem_amg_create: a coarse node has more than 21845 neighbours");
+        return set_error(FEM_EINVAL, "fem_amg_create: a coarse node has more than 21845 neighbours (or an "
+                                     "aggregate more than eight nodes)");
     const int nl = (int)H.size();
     const bool dense = H.back().n <= FEM_AMG_DENSE_NODES;
 
@@ -839,6 +1148,9 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
             }
         }
         if (dense) c.take<double>((size_t)9 * H.back().n * H.back().n);
+        c.take<double>(FEM_AMG_MAX_LEVELS);
+        c.take<double>(2 * FEM_AMG_MAX_LEVELS);
+        c.take<double>(blocks_for((int64_t)H[0].n * kLanes) + 1);
     };
     WsCounter cnt;
     sizes(cnt);
@@ -857,6 +1169,8 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
     h->dense = dense;
     h->nd = 3 * H.back().n;
     WsCarver cv(h->mem, bytes);
+    double ones[FEM_AMG_MAX_LEVELS];  // initial damping (kept alive until the synchronisation below)
+    for (double& o : ones) o = 1.0;
     hipError_t e = hipSuccess;
     auto up = [&](void* dst, const void* src, size_t nbytes) {
         if (e == hipSuccess && nbytes) e = hipMemcpyAsync(dst, src, nbytes, hipMemcpyHostToDevice, s);
@@ -918,6 +1232,11 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
         }
     }
     if (dense) h->cinv = cv.take<double>((size_t)h->nd * h->nd);
+    h->om = cv.take<double>(FEM_AMG_MAX_LEVELS);
+    h->sc = cv.take<double>(2 * FEM_AMG_MAX_LEVELS);
+    h->npart = (int)blocks_for((int64_t)n0 * kLanes) + 1;
+    h->part = cv.take<double>(h->npart);
+    up(h->om, ones, sizeof ones);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors are freed on return
     if (e != hipSuccess || !cv.ok()) {
         (void)hipFree(h->mem);
@@ -942,7 +1261,8 @@ extern "C" int fem_amg_apply(fem_amg* amg, const double* r, double* z, void* str
     return FEM_OK;
 }
 
-extern "C" int fem_amg_info(const fem_amg* amg, int32_t* n_levels, int32_t* nodes, int64_t* blocks, int32_t* dense) {
+extern "C" int fem_amg_info(const fem_amg* amg, int32_t* n_levels, int32_t* nodes, int64_t* blocks, int32_t* dense,
+                            double* omega) {
     clear_error();
     if (!amg) return set_error(FEM_EINVAL, "fem_amg_info: handle must not be NULL");
     if (n_levels) *n_levels = amg->nl;
@@ -951,6 +1271,7 @@ extern "C" int fem_amg_info(const fem_amg* amg, int32_t* n_levels, int32_t* node
         if (nodes) nodes[l] = amg->L[l].n;
         if (blocks) blocks[l] = amg->L[l].nb;
     }
+    if (omega) FEM_HIP_CHECK(hipMemcpy(omega, amg->om, amg->nl * sizeof(double), hipMemcpyDeviceToHost));
     return FEM_OK;
 }
 

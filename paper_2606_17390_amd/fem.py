@@ -106,7 +106,7 @@ def lib():
     L.fem_amg_update.argtypes = [_c_p, _c_p, ctypes.c_int, _c_p]
     L.fem_amg_apply.argtypes = [_c_p, _c_p, _c_p, _c_p]
     L.fem_amg_info.argtypes = [_c_p, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_int64),
-                               ctypes.POINTER(_c_i32)]
+                               ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double)]
     L.fem_amg_aggregates.argtypes = [_c_p, _c_i32, _c_p]
     L.fem_amg_destroy.argtypes = [_c_p]
     L.fem_solve_amg.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, ctypes.c_int, _c_p, _c_p, _c_p,
@@ -599,13 +599,19 @@ class AMG:
         _check("fem_amg_apply", lib().fem_amg_apply(self.h, _ptr(r), _ptr(z), _stream(stream)))
         return z
 
-    def info(self):
-        """(levels as [(nodes, 3x3 blocks)], coarsest inverted exactly)"""
+    def info(self, omega=False):
+        """(levels as [(nodes, 3x3 blocks)], coarsest inverted exactly) and,
+        with omega, the smoother damping per level"""
         nl, dense = _c_i32(0), _c_i32(0)
         nodes = (_c_i32 * AMG_MAX_LEVELS)()
         blocks = (ctypes.c_int64 * AMG_MAX_LEVELS)()
-        _check("fem_amg_info", lib().fem_amg_info(self.h, ctypes.byref(nl), nodes, blocks, ctypes.byref(dense)))
-        return [(int(nodes[i]), int(blocks[i])) for i in range(nl.value)], bool(dense.value)
+        om = (ctypes.c_double * AMG_MAX_LEVELS)()
+        _check("fem_amg_info", lib().fem_amg_info(self.h, ctypes.byref(nl), nodes, blocks, ctypes.byref(dense),
+                                                  om if omega else None))
+        levels = [(int(nodes[i]), int(blocks[i])) for i in range(nl.value)]
+        if omega:
+            return levels, bool(dense.value), [float(om[i]) for i in range(nl.value)]
+        return levels, bool(dense.value)
 
     def aggregates(self, level):
         """numpy int32 [nodes of level - 1]: aggregate of each node of the level above"""

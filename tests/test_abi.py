@@ -142,7 +142,7 @@ def test_multigrid_arguments_are_rejected_on_the_host(lib):
     assert create(nnz=17) == fem.FEM_EINVAL and b"multiple of 9" in lib.fem_last_error()
     assert lib.fem_amg_update(None, fake, fem.FP64, None) == fem.FEM_EINVAL
     assert lib.fem_amg_apply(None, fake, fake, None) == fem.FEM_EINVAL
-    assert lib.fem_amg_info(None, None, None, None, None) == fem.FEM_EINVAL
+    assert lib.fem_amg_info(None, None, None, None, None, None) == fem.FEM_EINVAL
     assert lib.fem_amg_aggregates(None, 1, fake) == fem.FEM_EINVAL
     assert lib.fem_amg_destroy(None) == fem.FEM_OK
     c = fem.FemCsr(6, 18, fake, fake, None, None, None)

@@ -3,8 +3,10 @@
   - the aggregates partition each level into connected groups of at most
     eight nodes, and the level sizes agree with them;
   - one V-cycle equals a numpy V-cycle built from the documented definitions
-    (masked piecewise-constant prolongation, FP32 Galerkin operators, l1
-    block-Jacobi sweeps, dense coarsest inverse) on the same aggregates;
+    (masked piecewise-constant prolongation, FP32 Galerkin operators, damped
+    block-Jacobi sweeps, dense coarsest inverse) on the same aggregates and
+    damping factors, and the damping times the exact spectral radius of
+    D^-1 A lies in [1.2, 1.6] (4/3 for an exact estimate);
   - the preconditioned CG (plain tangent) and BiCGSTAB (F-bar tangent) solves
     match a dense solve, and repeat bitwise;
   - fewer iterations than node-block Jacobi on a 16^3 plastic state, and a
@@ -63,25 +65,25 @@ def host_csr(csr, K):
                          shape=(n, n))
 
 
-def ref_vcycle(A0, free0, aggs, r, fine_is_float):
+def bj_blocks(A, omega=1.0):
+    """omega times the inverses of the 3x3 diagonal blocks of A (scipy)"""
+    import scipy.sparse as sp
+    n = A.shape[0] // 3
+    coo = A.tocoo()
+    inb = (coo.row // 3) == (coo.col // 3)
+    D = np.zeros((n, 3, 3))
+    np.add.at(D, (coo.row[inb] // 3, coo.row[inb] % 3, coo.col[inb] % 3), coo.data[inb])
+    Minv = omega * np.linalg.inv(D)
+    rows = np.repeat(np.arange(3 * n), 3)
+    cols = (3 * (np.arange(3 * n) // 3))[:, None] + np.arange(3)[None, :]
+    return sp.csr_matrix((Minv.reshape(-1), (rows, cols.reshape(-1))), shape=A.shape)
+
+
+def ref_vcycle(A0, free0, aggs, omegas, r):
     """V(1,1)-cycle from the definitions (host, FP64 vectors): A0 the finest
     operator (scipy CSR), free0 its free-dof mask, aggs the aggregate map of
-    each level transition."""
+    each level transition, omegas the smoother damping per level."""
     import scipy.sparse as sp
-
-    def l1_blocks(A):
-        n = A.shape[0] // 3
-        coo = A.tocoo()
-        inb = (coo.row // 3) == (coo.col // 3)
-        D = np.zeros((n, 3, 3))
-        np.add.at(D, (coo.row[inb] // 3, coo.row[inb] % 3, coo.col[inb] % 3), coo.data[inb])
-        l1 = np.zeros(A.shape[0])
-        np.add.at(l1, coo.row[~inb], np.abs(coo.data[~inb]))
-        D[:, [0, 1, 2], [0, 1, 2]] += l1.reshape(n, 3)
-        Minv = np.linalg.inv(D)
-        rows = np.repeat(np.arange(3 * n), 3)
-        cols = (3 * (np.arange(3 * n) // 3))[:, None] + np.arange(3)[None, :]
-        return sp.csr_matrix((Minv.reshape(-1), (rows, cols.reshape(-1))), shape=A.shape)
 
     As, Ms, Ps, masks = [A0], [], [], [free0]
     for agg in aggs:
@@ -97,8 +99,8 @@ def ref_vcycle(A0, free0, aggs, r, fine_is_float):
         Ps.append(P)
         As.append(Ac.tocsr())
         masks.append(mc)
-    for A in As:
-        Ms.append(l1_blocks(A))
+    for A, om in zip(As, omegas):
+        Ms.append(bj_blocks(A, om))
     Cinv = np.linalg.inv(As[-1].toarray())
 
     def cycle(l, b):
@@ -155,10 +157,10 @@ def test_hierarchy_and_vcycle_match_the_definitions(fem, prec_name):
     csr, K, bc = tangent(fem, p, getattr(fem, prec_name))
     amg = fem.AMG(csr, K, bc)
     amg.update(K)
-    levels, dense = amg.info()
-    say(f"hierarchy {prec_name}: {levels} dense {dense}")
+    levels, dense, omegas = amg.info(omega=True)
+    say(f"hierarchy {prec_name}: {levels} dense {dense} omega {omegas}")
     assert len(levels) >= 3 and dense and levels[0] == (p.n_nodes, csr.nnz // 9)
-    assert levels[-1][0] <= 32
+    assert levels[-1][0] <= 32 and omegas[-1] == 1.0
     A0 = host_csr(csr, K)
     free0 = p.bc_mask == 0
     coo = A0.tocoo()
@@ -173,12 +175,17 @@ def test_hierarchy_and_vcycle_match_the_definitions(fem, prec_name):
         G = (Pn.T @ G @ Pn).tocsr()
         assert G.nnz == levels[l][1]
         aggs.append(agg)
+    # the damping against the spectral radius of D^-1 A on the free dofs
+    Dinv = bj_blocks(A0).toarray()
+    rho = np.abs(np.linalg.eigvals((Dinv @ A0.toarray())[np.ix_(free0, free0)])).max()
+    say(f"  level 0: omega {omegas[0]:.4f}, rho {rho:.4f}, omega rho {omegas[0] * rho:.3f}")
+    assert 1.2 <= omegas[0] * rho <= 1.6
     rng = np.random.default_rng(11)
     for trial in range(2):
         r = rng.standard_normal(csr.n_rows) * free0
         z = amg.apply(torch.as_tensor(r).cuda())
         torch.cuda.synchronize()
-        ref = ref_vcycle(A0, free0, aggs, r, prec_name != "FP64")
+        ref = ref_vcycle(A0, free0, aggs, omegas, r)
         err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
         say(f"  V-cycle {trial}: rel err {err:.2e}")
         assert err <= 2e-6
