@@ -293,43 +293,45 @@ __global__ __launch_bounds__(256) void smooth0_kernel(int32_t n, const double* _
     for (int a = 0; a < 3; ++a) x[3 * I + a] = m[3 * a] * b0 + m[3 * a + 1] * b1 + m[3 * a + 2] * b2;
 }
 
-// POST = 0: out = b - A x;  POST = 1: out = x + M (b - A x)
-// (32 lanes per node, butterfly over the lanes in a fixed order)
-template <typename RV, int POST>
-__global__ __launch_bounds__(256) void residual_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
-                                                       const int32_t* __restrict__ ncol, const RV* __restrict__ val,
-                                                       const double* __restrict__ x, const double* __restrict__ b,
-                                                       const double* __restrict__ minv, double* __restrict__ out,
-                                                       const int32_t* __restrict__ fl) {
+// Second sweep: out = x + M (b - A x); 32 lanes per node over a fixed grid
+// of at most kPostGrid workgroups (8 nodes per workgroup and round),
+// butterfly over the lanes in a fixed order
+constexpr int kPostGrid = 2048;
+
+template <typename RV>
+__global__ __launch_bounds__(256) void post_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ ncol, const RV* __restrict__ val,
+                                                   const double* __restrict__ x, const double* __restrict__ b,
+                                                   const double* __restrict__ minv, double* __restrict__ out,
+                                                   const int32_t* __restrict__ fl) {
     if (stopped(fl)) return;
-    const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
     const int l = (int)(threadIdx.x & (kLanes - 1));
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (I < n) {
-        const int32_t bs = row_ptr[3 * I], len = row_ptr[3 * I + 1] - bs, deg = len / 3;
-        const int32_t* __restrict__ nc = ncol + bs / 9;
-        for (int32_t k = l; k < deg; k += kLanes) {
-            const int64_t J = nc[k];
-            const double x0 = x[3 * J], x1 = x[3 * J + 1], x2 = x[3 * J + 2];
-            const RV* __restrict__ v = val + bs + 3 * k;
-            s0 += (double)v[0] * x0 + (double)v[1] * x1 + (double)v[2] * x2;
-            s1 += (double)v[len] * x0 + (double)v[len + 1] * x1 + (double)v[len + 2] * x2;
-            s2 += (double)v[2 * len] * x0 + (double)v[2 * len + 1] * x1 + (double)v[2 * len + 2] * x2;
+    for (int64_t base = (int64_t)blockIdx.x * 8; base < n; base += (int64_t)gridDim.x * 8) {
+        const int64_t I = base + (threadIdx.x >> 5);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        if (I < n) {
+            const int32_t bs = row_ptr[3 * I], len = row_ptr[3 * I + 1] - bs, deg = len / 3;
+            const int32_t* __restrict__ nc = ncol + bs / 9;
+            for (int32_t k = l; k < deg; k += kLanes) {
+                const int64_t J = nc[k];
+                const double x0 = x[3 * J], x1 = x[3 * J + 1], x2 = x[3 * J + 2];
+                const RV* __restrict__ v = val + bs + 3 * k;
+                s0 += (double)v[0] * x0 + (double)v[1] * x1 + (double)v[2] * x2;
+                s1 += (double)v[len] * x0 + (double)v[len + 1] * x1 + (double)v[len + 2] * x2;
+                s2 += (double)v[2 * len] * x0 + (double)v[2 * len + 1] * x1 + (double)v[2 * len + 2] * x2;
+            }
         }
-    }
 #pragma unroll
-    for (int m = 1; m < kLanes; m <<= 1) {
-        s0 += __shfl_xor(s0, m, kLanes);
-        s1 += __shfl_xor(s1, m, kLanes);
-        s2 += __shfl_xor(s2, m, kLanes);
-    }
-    if (I >= n || l >= 3) return;
-    const double r0 = b[3 * I] - s0, r1 = b[3 * I + 1] - s1, r2 = b[3 * I + 2] - s2;
-    if (POST) {
-        const double* m = minv + 9 * I;
-        out[3 * I + l] = x[3 * I + l] + m[3 * l] * r0 + m[3 * l + 1] * r1 + m[3 * l + 2] * r2;
-    } else {
-        out[3 * I + l] = l == 0 ? r0 : (l == 1 ? r1 : r2);
+        for (int m = 1; m < kLanes; m <<= 1) {
+            s0 += __shfl_xor(s0, m, kLanes);
+            s1 += __shfl_xor(s1, m, kLanes);
+            s2 += __shfl_xor(s2, m, kLanes);
+        }
+        if (I < n && l < 3) {
+            const double r0 = b[3 * I] - s0, r1 = b[3 * I + 1] - s1, r2 = b[3 * I + 2] - s2;
+            const double* m = minv + 9 * I;
+            out[3 * I + l] = x[3 * I + l] + m[3 * l] * r0 + m[3 * l + 1] * r1 + m[3 * l + 2] * r2;
+        }
     }
 }
 
@@ -597,41 +599,47 @@ __global__ __launch_bounds__(256) void power_init(int64_t n3, const uint8_t* __r
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// w = D^-1 A (sc[1] v) (32 lanes per node); part = block sums of w.w
+// w = D^-1 A (sc[1] v), 32 lanes per node over a fixed grid of
+// kPowerGrid workgroups (8 nodes per workgroup and round); part = one sum
+// of w.w per workgroup
+constexpr int kPowerGrid = 2048;
+
 template <typename RV>
 __global__ __launch_bounds__(256) void power_apply(int32_t n, const int32_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ ncol, const RV* __restrict__ val,
                                                    const double* __restrict__ minv, const double* __restrict__ v,
                                                    const double* __restrict__ sc, double* __restrict__ w,
                                                    double* __restrict__ part) {
-    const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
     const int l = (int)(threadIdx.x & (kLanes - 1));
     const double scale = sc[1];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (I < n) {
-        const int32_t bs = row_ptr[3 * I], len = row_ptr[3 * I + 1] - bs, deg = len / 3;
-        const int32_t* __restrict__ nc = ncol + bs / 9;
-        for (int32_t k = l; k < deg; k += kLanes) {
-            const int64_t J = nc[k];
-            const double x0 = v[3 * J], x1 = v[3 * J + 1], x2 = v[3 * J + 2];
-            const RV* __restrict__ q = val + bs + 3 * k;
-            s0 += (double)q[0] * x0 + (double)q[1] * x1 + (double)q[2] * x2;
-            s1 += (double)q[len] * x0 + (double)q[len + 1] * x1 + (double)q[len + 2] * x2;
-            s2 += (double)q[2 * len] * x0 + (double)q[2 * len + 1] * x1 + (double)q[2 * len + 2] * x2;
-        }
-    }
-#pragma unroll
-    for (int m = 1; m < kLanes; m <<= 1) {
-        s0 += __shfl_xor(s0, m, kLanes);
-        s1 += __shfl_xor(s1, m, kLanes);
-        s2 += __shfl_xor(s2, m, kLanes);
-    }
     double ww = 0.0;
-    if (I < n && l < 3) {
-        const double* m = minv + 9 * I;
-        const double wl = scale * (m[3 * l] * s0 + m[3 * l + 1] * s1 + m[3 * l + 2] * s2);
-        w[3 * I + l] = wl;
-        ww = wl * wl;
+    for (int64_t base = (int64_t)blockIdx.x * 8; base < n; base += (int64_t)gridDim.x * 8) {
+        const int64_t I = base + (threadIdx.x >> 5);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        if (I < n) {
+            const int32_t bs = row_ptr[3 * I], len = row_ptr[3 * I + 1] - bs, deg = len / 3;
+            const int32_t* __restrict__ nc = ncol + bs / 9;
+            for (int32_t k = l; k < deg; k += kLanes) {
+                const int64_t J = nc[k];
+                const double x0 = v[3 * J], x1 = v[3 * J + 1], x2 = v[3 * J + 2];
+                const RV* __restrict__ q = val + bs + 3 * k;
+                s0 += (double)q[0] * x0 + (double)q[1] * x1 + (double)q[2] * x2;
+                s1 += (double)q[len] * x0 + (double)q[len + 1] * x1 + (double)q[len + 2] * x2;
+                s2 += (double)q[2 * len] * x0 + (double)q[2 * len + 1] * x1 + (double)q[2 * len + 2] * x2;
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < kLanes; m <<= 1) {
+            s0 += __shfl_xor(s0, m, kLanes);
+            s1 += __shfl_xor(s1, m, kLanes);
+            s2 += __shfl_xor(s2, m, kLanes);
+        }
+        if (I < n && l < 3) {
+            const double* m = minv + 9 * I;
+            const double wl = scale * (m[3 * l] * s0 + m[3 * l + 1] * s1 + m[3 * l + 2] * s2);
+            w[3 * I + l] = wl;
+            ww += wl * wl;
+        }
     }
     const double t = block_sum256(ww);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -888,12 +896,13 @@ void smoother_setup(fem_amg* h, int l, const V* vals, hipStream_t s) {
     const unsigned nbi = blocks_for(3 * (int64_t)L.n);
     hipLaunchKernelGGL(power_init, dim3(nbi), dim3(256), 0, s, 3 * (int64_t)L.n, L.mask, L.r, h->part);
     hipLaunchKernelGGL(power_norm, dim3(1), dim3(256), 0, s, h->part, (int)nbi, sc);
+    const unsigned npg = std::min<unsigned>(kPowerGrid, blocks_for((int64_t)L.n * kLanes));
     for (int k = 0; k < kPowerSteps; ++k) {
         const double* v = (k & 1) ? L.y : L.r;
         double* w = (k & 1) ? L.r : L.y;
-        hipLaunchKernelGGL(power_apply<V>, dim3(nbl), dim3(256), 0, s, L.n, L.row_ptr, L.ncol, vals, L.minv, v, sc, w,
+        hipLaunchKernelGGL(power_apply<V>, dim3(npg), dim3(256), 0, s, L.n, L.row_ptr, L.ncol, vals, L.minv, v, sc, w,
                            h->part);
-        hipLaunchKernelGGL(power_norm, dim3(1), dim3(256), 0, s, h->part, (int)nbl, sc);
+        hipLaunchKernelGGL(power_norm, dim3(1), dim3(256), 0, s, h->part, (int)npg, sc);
     }
     hipLaunchKernelGGL(power_finish, dim3(blocks_for(9 * (int64_t)L.n)), dim3(256), 0, s, L.n, sc, L.minv, h->om + l);
 }
@@ -923,23 +932,23 @@ hipError_t update_typed(fem_amg* h, const RV* K, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename RV, int POST>
-void launch_residual(const Level& L, const RV* vals, const double* x, const double* b, double* out,
-                     const int32_t* fl, hipStream_t s) {
-    hipLaunchKernelGGL((residual_kernel<RV, POST>), dim3(blocks_for((int64_t)L.n * kLanes)), dim3(256), 0, s, L.n,
-                       L.row_ptr, L.ncol, vals, x, b, L.minv, out, fl);
+template <typename RV>
+void launch_post(const Level& L, const RV* vals, const double* x, const double* b, double* out, const int32_t* fl,
+                 hipStream_t s) {
+    const unsigned nb = std::min<unsigned>(kPostGrid, blocks_for((int64_t)L.n * kLanes));
+    hipLaunchKernelGGL(post_kernel<RV>, dim3(nb), dim3(256), 0, s, L.n, L.row_ptr, L.ncol, vals, x, b, L.minv, out, fl);
 }
 
-template <int POST>
-void level_residual(const fem_amg* h, int l, const double* x, const double* b, double* out, const int32_t* fl,
-                    hipStream_t s) {
+// out = x + M_l (b - A_l x) on level l (the finest level reads K)
+void level_post(const fem_amg* h, int l, const double* x, const double* b, double* out, const int32_t* fl,
+                hipStream_t s) {
     const Level& L = h->L[l];
     if (l > 0)
-        launch_residual<float, POST>(L, L.vals, x, b, out, fl, s);
+        launch_post<float>(L, L.vals, x, b, out, fl, s);
     else if (h->prec == FEM_FP64)
-        launch_residual<double, POST>(L, static_cast<const double*>(h->K), x, b, out, fl, s);
+        launch_post<double>(L, static_cast<const double*>(h->K), x, b, out, fl, s);
     else
-        launch_residual<float, POST>(L, static_cast<const float*>(h->K), x, b, out, fl, s);
+        launch_post<float>(L, static_cast<const float*>(h->K), x, b, out, fl, s);
 }
 
 }  // namespace
@@ -976,7 +985,7 @@ hipError_t amg_vcycle(fem_amg* h, const double* b, double* z, bool presmoothed, 
         hipLaunchKernelGGL(smooth0_kernel, dim3(blocks_for(L[0].n)), dim3(256), 0, s, L[0].n, L[0].minv, b, L[0].x,
                            fl);
     if (nl == 1) {  // one level, not inverted: the two sweeps
-        level_residual<1>(h, 0, L[0].x, b, z, fl, s);
+        level_post(h, 0, L[0].x, b, z, fl, s);
         return hipGetLastError();
     }
     // levels [t, nl) run in the tail kernel; t = nl if no level is small enough
@@ -1030,14 +1039,14 @@ hipError_t amg_vcycle(fem_amg* h, const double* b, double* z, bool presmoothed, 
         hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, A, fl);
         yc = (t == nl - 1 && h->dense) ? L[t].x : L[t].y;
     } else {  // coarsest level not inverted and too large for the tail: the second sweep
-        level_residual<1>(h, nl - 1, L[nl - 1].x, L[nl - 1].b, L[nl - 1].y, fl, s);
+        level_post(h, nl - 1, L[nl - 1].x, L[nl - 1].b, L[nl - 1].y, fl, s);
         yc = L[nl - 1].y;
     }
     for (int l = down - 1; l >= 0; --l) {
         hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(L[l].n)), dim3(256), 0, s, L[l].n, L[l + 1].agg, L[l].mask,
                            yc, L[l].x, fl);
         double* out = l == 0 ? z : L[l].y;
-        level_residual<1>(h, l, L[l].x, l == 0 ? b : L[l].b, out, fl, s);
+        level_post(h, l, L[l].x, l == 0 ? b : L[l].b, out, fl, s);
         yc = out;
     }
     return hipGetLastError();
@@ -1150,7 +1159,7 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
         if (dense) c.take<double>((size_t)9 * H.back().n * H.back().n);
         c.take<double>(FEM_AMG_MAX_LEVELS);
         c.take<double>(2 * FEM_AMG_MAX_LEVELS);
-        c.take<double>(blocks_for((int64_t)H[0].n * kLanes) + 1);
+        c.take<double>(std::max<int64_t>(blocks_for(3 * (int64_t)H[0].n), kPowerGrid) + 1);
     };
     WsCounter cnt;
     sizes(cnt);
@@ -1234,7 +1243,7 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
     if (dense) h->cinv = cv.take<double>((size_t)h->nd * h->nd);
     h->om = cv.take<double>(FEM_AMG_MAX_LEVELS);
     h->sc = cv.take<double>(2 * FEM_AMG_MAX_LEVELS);
-    h->npart = (int)blocks_for((int64_t)n0 * kLanes) + 1;
+    h->npart = (int)std::max<int64_t>(blocks_for(3 * (int64_t)n0), kPowerGrid) + 1;
     h->part = cv.take<double>(h->npart);
     up(h->om, ones, sizeof ones);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors are freed on return

@@ -22,7 +22,9 @@ with the automatic stepping of Sec. 2.2.5:
   lin_rtol) unless forcing is None (then lin_rtol throughout); the linear
   step of the tangent start, or without it the first solve of an increment
   with no extrapolated start, goes to first_eta, since that direction
-  carries the whole boundary increment.
+  carries the whole boundary increment; preconditioner: the aggregation
+  multigrid (precond=fem.PC_AMG: hierarchy built at the first solve,
+  numeric set-up for every tangent) or fem.PC_BLOCK_JACOBI.
 
 The performance study of Sec. 3.1.3 uses dt0 1e-3, dt_min 1e-5, dt_max 5e-2.
 
@@ -67,7 +69,7 @@ def linearised_start(mesh, csr, params, d, h, trial, bc_mask, prec, out, solver,
 
 def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt_min=1e-5, dt_max=5e-2, grow=2.0,
           grow_after=1, cutback=0.5, ftol=1e-6, max_it=30, stall_window=5, stall_ratio=0.5, lin_rtol=1e-6,
-          lin_max_iter=20000, t_end=1.0, max_steps=10000, log=None, precond=fem.PC_BLOCK_JACOBI, forcing="ew",
+          lin_max_iter=20000, t_end=1.0, max_steps=10000, log=None, precond=fem.PC_AMG, forcing="ew",
           first_eta=1e-4, eta_max=0.1, krylov="auto", line_search=True, tangent_start=True):
     """Returns a dict with the final displacement and history, the accepted
     increments [(t, dt, Newton iterations, linear iterations)], the failed

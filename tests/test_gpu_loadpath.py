@@ -32,8 +32,9 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("variant,t_end", [("plain", 1.0), ("fbar", 0.3)])
-def test_load_path_matches_oracle_newton(fem, variant, t_end):
+@pytest.mark.parametrize("variant,t_end,pc", [("plain", 1.0, "PC_AMG"), ("fbar", 0.3, "PC_AMG"),
+                                              ("plain", 1.0, "PC_BLOCK_JACOBI")])
+def test_load_path_matches_oracle_newton(fem, variant, t_end, pc):
     from paper_2606_17390_amd import loadpath
     p = synth.unit_cube_forward(3)
     fbar = variant == "fbar"
@@ -45,7 +46,7 @@ def test_load_path_matches_oracle_newton(fem, variant, t_end):
     h0 = torch.zeros((7, 8 * p.n_elems), dtype=torch.float64, device="cuda")
     say(f"load path {variant}: {3 * p.n_nodes} dofs to t = {t_end}")
     res = loadpath.solve(mesh, csr, params, bc, torch.as_tensor(u1).cuda(), h0, dt0=0.02, dt_max=0.1, ftol=1e-11,
-                         t_end=t_end, log=say)
+                         t_end=t_end, log=say, precond=getattr(fem, pc))
     ts = [s[0] for s in res["steps"]]
     assert abs(ts[-1] - t_end) <= 1e-12 and all(s[2] >= 1 for s in res["steps"])
     assert res["newton_iterations"] == sum(s[2] for s in res["steps"])
