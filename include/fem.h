@@ -402,6 +402,15 @@ int fem_csr_transpose(const fem_csr *csr, const void *K_vals, fem_precision prec
  * fem_amg_aggregates -- agg (host [nodes of level - 1]) = the aggregate, a
  *   node of `level` (1 <= level < n_levels), of each node of the level above.
  *   Synchronous.
+ * fem_amg_plan_host -- the aggregation of fem_amg_create on host arrays
+ *   only (no device work): node-block pattern bptr (host [n_nodes + 1],
+ *   int64, first block of each node), ncol (host [bptr[n_nodes]], node column
+ *   of each block), strength (host, the block norms), bc_mask (host [3
+ *   n_nodes] or NULL).  Outputs: n_levels; nodes and blocks per level (host
+ *   [FEM_AMG_MAX_LEVELS] each, may be NULL); agg (host, at least 7 n_nodes
+ *   entries, or NULL) = the aggregate maps of levels 1, ..., n_levels - 1
+ *   one after the other.  fem_amg_create with the same strengths builds the
+ *   same hierarchy.
  * fem_solve_amg -- fem_solve (same arguments, workspace and stop rules)
  *   with M = one V-cycle of amg, after fem_amg_update(amg, K_vals, prec).
  *   csr must be the pattern amg was created on.
@@ -416,6 +425,8 @@ int fem_amg_apply(fem_amg *amg, const double *r, double *z, void *stream);
 int fem_amg_info(const fem_amg *amg, int32_t *n_levels, int32_t *nodes, int64_t *blocks, int32_t *dense,
                  double *omega);
 int fem_amg_aggregates(const fem_amg *amg, int32_t level, int32_t *agg);
+int fem_amg_plan_host(int32_t n_nodes, const int64_t *bptr, const int32_t *ncol, const float *strength,
+                      const uint8_t *bc_mask, int32_t *n_levels, int32_t *nodes, int64_t *blocks, int32_t *agg);
 int fem_amg_destroy(fem_amg *amg);
 int fem_solve_amg(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_krylov method, fem_amg *amg,
                   const double *b, double *x, int32_t max_iter, double rtol, int32_t *iters, double *rel_res,

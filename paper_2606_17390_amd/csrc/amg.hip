@@ -1256,6 +1256,46 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
     return FEM_OK;
 }
 
+extern "C" int fem_amg_plan_host(int32_t n_nodes, const int64_t* bptr, const int32_t* ncol, const float* strength,
+                                 const uint8_t* bc_mask, int32_t* n_levels, int32_t* nodes, int64_t* blocks,
+                                 int32_t* agg) {
+    clear_error();
+    if (n_nodes <= 0 || !bptr || !ncol || !strength || !n_levels)
+        return set_error(FEM_EINVAL, "fem_amg_plan_host: n_nodes > 0, bptr, ncol, strength and n_levels required");
+    const int64_t nb = bptr[n_nodes];
+    if (bptr[0] != 0 || nb <= 0 || 9 * nb > (int64_t)INT32_MAX)
+        return set_error(FEM_EINVAL, "fem_amg_plan_host: bptr must start at 0 and end below 2^31 / 9");
+    for (int32_t I = 0; I < n_nodes; ++I) {
+        if (bptr[I + 1] < bptr[I]) return set_error(FEM_EINVAL, "fem_amg_plan_host: bptr not ascending");
+        if (3 * (bptr[I + 1] - bptr[I]) > 65535)
+            return set_error(FEM_EINVAL, "fem_amg_plan_host: node %d has more than 21845 neighbours", I);
+    }
+    for (int64_t q = 0; q < nb; ++q)
+        if (ncol[q] < 0 || ncol[q] >= n_nodes) return set_error(FEM_EINVAL, "fem_amg_plan_host: ncol out of range");
+    std::vector<HostLevel> H(1);
+    HostLevel& h0 = H[0];
+    h0.n = n_nodes;
+    h0.bptr.assign(bptr, bptr + n_nodes + 1);
+    h0.ncol.assign(ncol, ncol + nb);
+    h0.s.assign(strength, strength + nb);
+    h0.mask.assign(3 * (size_t)n_nodes, 1);
+    if (bc_mask)
+        for (size_t i = 0; i < h0.mask.size(); ++i) h0.mask[i] = bc_mask[i] ? 0 : 1;
+    if (!build_hierarchy(H))
+        return set_error(FEM_EINVAL, "fem_amg_plan_host: a coarse node has more than 21845 neighbours");
+    *n_levels = (int32_t)H.size();
+    size_t off = 0;
+    for (size_t l = 0; l < H.size(); ++l) {
+        if (nodes) nodes[l] = H[l].n;
+        if (blocks) blocks[l] = H[l].bptr[H[l].n];
+        if (agg && l > 0) {
+            std::copy(H[l].agg.begin(), H[l].agg.end(), agg + off);
+            off += H[l].agg.size();
+        }
+    }
+    return FEM_OK;
+}
+
 extern "C" int fem_amg_update(fem_amg* amg, const void* K_vals, fem_precision prec, void* stream) {
     clear_error();
     return amg_update(amg, K_vals, prec, (hipStream_t)stream);

@@ -59,7 +59,7 @@ EXPORTS = ("fem_version", "fem_last_error", "fem_set_launch", "fem_get_launch", 
            "fem_graph_begin", "fem_graph_end", "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes", "fem_csr_spmv", "fem_solve",
            "fem_csr_transpose", "fem_history_adjoint_workspace_bytes", "fem_history_adjoint", "fem_amg_create",
            "fem_amg_update", "fem_amg_apply", "fem_amg_info", "fem_amg_aggregates", "fem_amg_destroy",
-           "fem_solve_amg")
+           "fem_solve_amg", "fem_amg_plan_host")
 
 
 def lib():
@@ -108,6 +108,7 @@ def lib():
     L.fem_amg_info.argtypes = [_c_p, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double)]
     L.fem_amg_aggregates.argtypes = [_c_p, _c_i32, _c_p]
+    L.fem_amg_plan_host.argtypes = [_c_i32, _c_p, _c_p, _c_p, _c_p, ctypes.POINTER(_c_i32), _c_p, _c_p, _c_p]
     L.fem_amg_destroy.argtypes = [_c_p]
     L.fem_solve_amg.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, ctypes.c_int, _c_p, _c_p, _c_p,
                                 _c_i32, ctypes.c_double,
@@ -631,6 +632,31 @@ class AMG:
             self.close()
         except Exception:
             pass
+
+
+def amg_plan_host(bptr, ncol, strength, bc_mask=None):
+    """fem_amg_plan_host on numpy arrays: returns ([(nodes, blocks)] per
+    level, [aggregate map of level l for l = 1 .. levels - 1])."""
+    bptr = np.ascontiguousarray(bptr, dtype=np.int64)
+    ncol = np.ascontiguousarray(ncol, dtype=np.int32)
+    strength = np.ascontiguousarray(strength, dtype=np.float32)
+    n = bptr.size - 1
+    bc = None if bc_mask is None else np.ascontiguousarray(bc_mask, dtype=np.uint8)
+    nl = _c_i32(0)
+    nodes = np.zeros(AMG_MAX_LEVELS, dtype=np.int32)
+    blocks = np.zeros(AMG_MAX_LEVELS, dtype=np.int64)
+    agg = np.zeros(7 * n, dtype=np.int32)  # every level keeps at most 85 % of the one above
+
+    def p(a):
+        return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    _check("fem_amg_plan_host", lib().fem_amg_plan_host(n, p(bptr), p(ncol), p(strength), p(bc), ctypes.byref(nl),
+                                                        p(nodes), p(blocks), p(agg)))
+    levels = [(int(nodes[i]), int(blocks[i])) for i in range(nl.value)]
+    maps, off = [], 0
+    for l in range(1, nl.value):
+        maps.append(agg[off:off + levels[l - 1][0]].copy())
+        off += levels[l - 1][0]
+    return levels, maps
 
 
 class Solver:

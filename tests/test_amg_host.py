@@ -1,0 +1,108 @@
+"""Aggregation of the multigrid preconditioner on the host (fem_amg_plan_host,
+no device work): on node-block patterns of hex meshes (unit cubes, a long
+bar, two disconnected blocks, constrained faces) every level's aggregates
+partition its nodes into connected groups of at most eight nodes, the
+coarse block counts are the numbers of aggregate pairs joined by a block,
+levels shrink to at most 32 nodes, and the plan is deterministic."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_17390_amd import synth
+
+
+@pytest.fixture(scope="module")
+def fem():
+    from paper_2606_17390_amd import fem as F
+    F.lib()
+    return F
+
+
+def node_pattern(conn, n_nodes):
+    """bptr, ncol of the node-block pattern (the oracle's CSR of the mesh)"""
+    rp, ci, _ = oracle.csr_pattern(conn, n_nodes)
+    rp = np.asarray(rp, dtype=np.int64)
+    ci = np.asarray(ci, dtype=np.int64)
+    bptr = rp[0::3] // 9
+    ncol = np.empty(bptr[-1], dtype=np.int32)
+    for i in range(n_nodes):
+        deg = bptr[i + 1] - bptr[i]
+        ncol[bptr[i]:bptr[i + 1]] = ci[rp[3 * i] + 3 * np.arange(deg)] // 3
+    return bptr, ncol
+
+
+def strengths(X, bptr, ncol):
+    """a strength per block that decays with the distance of the two nodes
+    (diagonal blocks strongest), like the block norms of an elastic tangent"""
+    rows = np.repeat(np.arange(bptr.size - 1), np.diff(bptr))
+    dist = np.linalg.norm(X[rows] - X[ncol], axis=1)
+    return (1.0 / (1.0 + 4.0 * dist / dist[dist > 0].min())).astype(np.float32)
+
+
+def check_plan(levels, maps, bptr, ncol):
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as cg
+    n = bptr.size - 1
+    rows = np.repeat(np.arange(n), np.diff(bptr))
+    G = sp.csr_matrix((np.ones(rows.size), (rows, ncol)), shape=(n, n))
+    assert levels[0] == (n, int(bptr[-1]))
+    assert len(maps) == len(levels) - 1
+    for l, agg in enumerate(maps, start=1):
+        nf, nc = levels[l - 1][0], levels[l][0]
+        assert agg.shape == (nf,) and agg.min() == 0 and agg.max() == nc - 1
+        sizes = np.bincount(agg, minlength=nc)
+        assert sizes.min() >= 1 and sizes.max() <= 8
+        assert nc <= 0.85 * nf
+        coo = G.tocoo()
+        same = agg[coo.row] == agg[coo.col]
+        Gin = sp.csr_matrix((np.ones(same.sum()), (coo.row[same], coo.col[same])), shape=(nf, nf))
+        assert cg.connected_components(Gin, directed=False)[0] == nc
+        Pn = sp.csr_matrix((np.ones(nf), (np.arange(nf), agg)), shape=(nf, nc))
+        G = (Pn.T @ G @ Pn).tocsr()
+        assert G.nnz == levels[l][1]
+    return G
+
+
+@pytest.mark.parametrize("dims", [(10, 9, 7), (20, 20, 20), (33, 5, 2), (3, 2, 1)])
+def test_plan_partitions_levels_into_connected_aggregates(fem, dims):
+    X, conn = synth.hex_grid(*dims)
+    bptr, ncol = node_pattern(conn, X.shape[0])
+    s = strengths(X, bptr, ncol)
+    levels, maps = fem.amg_plan_host(bptr, ncol, s)
+    check_plan(levels, maps, bptr, ncol)
+    if X.shape[0] > 32:
+        assert levels[-1][0] <= 32
+        # about eight nodes per aggregate on a structured hex mesh
+        assert levels[1][0] <= X.shape[0] / 5
+    else:
+        assert len(levels) == 1
+    again = fem.amg_plan_host(bptr, ncol, s)
+    assert again[0] == levels and all(np.array_equal(a, b) for a, b in zip(again[1], maps))
+
+
+def test_plan_keeps_disconnected_blocks_apart(fem):
+    X1, c1 = synth.hex_grid(6, 5, 4)
+    X2, c2 = synth.hex_grid(4, 4, 4)
+    X = np.concatenate([X1, X2 + 100.0])
+    conn = np.concatenate([c1, c2 + X1.shape[0]]).astype(np.int32)
+    bptr, ncol = node_pattern(conn, X.shape[0])
+    levels, maps = fem.amg_plan_host(bptr, ncol, strengths(X, bptr, ncol))
+    check_plan(levels, maps, bptr, ncol)
+    agg = maps[0]
+    assert not set(agg[:X1.shape[0]]) & set(agg[X1.shape[0]:])
+
+
+def test_plan_with_constrained_dofs_and_rejections(fem):
+    p = synth.unit_cube_forward(8)
+    bptr, ncol = node_pattern(p.conn, p.n_nodes)
+    s = strengths(p.X, bptr, ncol)
+    levels, maps = fem.amg_plan_host(bptr, ncol, s, p.bc_mask)
+    check_plan(levels, maps, bptr, ncol)
+    # the mask changes the prolongation, not the aggregation
+    assert fem.amg_plan_host(bptr, ncol, s)[0] == levels
+    bad = ncol.copy()
+    bad[5] = p.n_nodes
+    with pytest.raises(fem.FemError):
+        fem.amg_plan_host(bptr, bad, s)
+    with pytest.raises(fem.FemError):
+        fem.amg_plan_host(bptr[::-1].copy(), ncol, s)
