@@ -347,7 +347,7 @@ def gradient_benchmark(torch, fem, synth):
     }
 
 
-def forward_benchmark(spec, torch, fem, synth, fbar=True, precond="amg"):
+def forward_benchmark(spec, torch, fem, synth, fbar=True, precond="amg", krylov="auto"):
     """The unit-cube forward simulation of the performance study, Sec. 3.1.3 (Hill-48
     from the r-values, Voce, x = 0 clamped, x = 1 moved by t (0.2, 0.1) mm)
     through the adaptive load path: FP64 residual and history, float tangent
@@ -373,7 +373,9 @@ def forward_benchmark(spec, torch, fem, synth, fbar=True, precond="amg"):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     pc = fem.PC_AMG if precond == "amg" else fem.PC_BLOCK_JACOBI
-    res = loadpath.solve(mesh, csr, params, bc, u1, h0, log=lambda m: log(m), precond=pc)
+    res = loadpath.solve(mesh, csr, params, bc, u1, h0, log=lambda m: log(m), precond=pc, krylov=krylov)
+    if krylov == "auto":
+        krylov = "bicgstab" if fbar else "cg"
     n_it = max(res["newton_iterations"], 1)
     alpha = res["hist"][6]
     paper = PAPER_FORWARD_S.get(dims)
@@ -395,7 +397,7 @@ def forward_benchmark(spec, torch, fem, synth, fbar=True, precond="amg"):
                                "r = (1.5449, 1.0666, 1, 1.0307, 1, 1), Voce sigma0 138 Q 410 b 3.8, E 219 GPa, "
                                "nu 0.3; dt0 1e-3, dt_min 1e-5, dt_max 5e-2",
                    "nnz": csr.nnz, "element": "fbar" if fbar else "plain",
-                   "krylov": "bicgstab" if fbar else "cg",
+                   "krylov": krylov,
                    "preconditioner": "aggregation multigrid V(1,1)" if precond == "amg" else "3x3 node-block Jacobi"},
         "increments": len(res["steps"]),
         "failed_increments": len(res["failed"]),
@@ -438,6 +440,8 @@ def main():
                          "adjoint) on the tensile-specimen stand-in, one JSON line with its wall time")
     ap.add_argument("--element", choices=("fbar", "plain"), default="fbar",
                     help="element of --forward-benchmark: the paper's F-bar hex8 (BiCGSTAB) or the plain hex8 (CG)")
+    ap.add_argument("--krylov", choices=("auto", "gmres", "bicgstab", "cg"), default="auto",
+                    help="Krylov method of --forward-benchmark (auto: BiCGSTAB for F-bar, CG for the plain element)")
     ap.add_argument("--precond", choices=("amg", "bj"), default="amg",
                     help="preconditioner of --forward-benchmark: aggregation multigrid or 3x3 node-block Jacobi")
     ap.add_argument("--copy-probe", action="store_true",
@@ -467,7 +471,7 @@ def main():
         return
     if args.forward_benchmark:
         print(json.dumps(forward_benchmark(args.forward_benchmark, torch, fem, synth, args.element == "fbar",
-                                           args.precond)), flush=True)
+                                           args.precond, args.krylov)), flush=True)
         return
     log("generating the 100^3 cube")
     p = synth.large_cube()

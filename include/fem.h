@@ -298,6 +298,16 @@ int fem_residual_vjp_noalloc(const fem_mesh *mesh, const fem_batch *batch, const
  * fem_solve -- K x = b (the linear solve of the global Newton iteration,
  * Sec. 2.2.4 / Eq. (Stiffness_mat); Sec. 2.2.5 lists CG and BiCGSTAB) by
  *   FEM_KRYLOV_BICGSTAB  BiCGSTAB, right-preconditioned by M (any K)
+ *   FEM_KRYLOV_GMRES     restarted GMRES(FEM_GMRES_RESTART), right-
+ *                        preconditioned (any K): classical Gram-Schmidt with
+ *                        fused dot products, Givens rotations on the device,
+ *                        the solution formed at the end of each cycle and
+ *                        the true residual recomputed for the next; the
+ *                        reported residual is the cycle's least-squares
+ *                        residual |g_{j+1}| / ||b||; workspace of
+ *                        fem_solver_workspace_bytes_method (about
+ *                        FEM_GMRES_RESTART + 1 more vectors); the host reads
+ *                        the stop flag once per cycle
  *   FEM_KRYLOV_CG        preconditioned conjugate gradients, for a K that is
  *                        symmetric positive definite on the free dofs (the
  *                        tangent without F-bar) with identity rows on the
@@ -318,6 +328,7 @@ int fem_residual_vjp_noalloc(const fem_mesh *mesh, const fem_batch *batch, const
  *   iters, rel_res  host outputs (iterations done, final relative residual),
  *            or NULL
  *   ws       device workspace of fem_solver_workspace_bytes(n_rows, nnz) bytes
+ *            (GMRES: fem_solver_workspace_bytes_method(n_rows, nnz, method))
  * The reductions are fixed-order (bitwise reproducible).  The iteration state
  * stays on the device; the host reads the stop flag once per 32 iterations
  * (one stream synchronisation each).  A breakdown (a zero inner product) or
@@ -327,8 +338,10 @@ int fem_residual_vjp_noalloc(const fem_mesh *mesh, const fem_batch *batch, const
  * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOCONV.
  */
 typedef enum { FEM_PC_JACOBI = 0, FEM_PC_BLOCK_JACOBI = 1, FEM_PC_AMG = 2 /* fem_solve_amg only */ } fem_precond;
-typedef enum { FEM_KRYLOV_BICGSTAB = 0, FEM_KRYLOV_CG = 1 } fem_krylov;
-size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz);
+typedef enum { FEM_KRYLOV_BICGSTAB = 0, FEM_KRYLOV_CG = 1, FEM_KRYLOV_GMRES = 2 } fem_krylov;
+#define FEM_GMRES_RESTART 30
+size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz);        /* CG, BiCGSTAB */
+size_t fem_solver_workspace_bytes_method(int32_t n_rows, int64_t nnz, fem_krylov method);
 int fem_csr_spmv(const fem_csr *csr, const void *K_vals, fem_precision prec, const double *x, double *y,
                  void *stream);
 int fem_solve(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_krylov method, fem_precond pc,

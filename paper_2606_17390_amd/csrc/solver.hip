@@ -101,7 +101,7 @@ constexpr int kChunk = 32;       // iterations enqueued between two reads of the
 
 // Scalars of the iteration (device memory) and integer flags.
 enum { S_RHO, S_RHO_NEW, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_RES, S_COUNT };
-enum { F_STOP, F_ITER, F_COUNT };
+enum { F_STOP, F_ITER, F_CYC, F_J, F_COUNT };  // F_CYC: the GMRES cycle has ended; F_J: its length
 
 // ncol[row_ptr[3I]/9 + k] = J, the node of the k-th 3x3 block of node I's rows
 // (each row of node I has 3 deg(I) entries, so row_ptr[3I] is a multiple of 9).
@@ -247,8 +247,7 @@ __device__ inline void apply_minv(const double* __restrict__ minv, int64_t I, co
 }
 
 __global__ void reset_flags(int32_t* __restrict__ fl) {
-    fl[F_STOP] = 0;
-    fl[F_ITER] = 0;
+    for (int k = 0; k < F_COUNT; ++k) fl[k] = 0;
 }
 
 // r = b - y, rh = r, p = v = 0; part0 = partials of r . r, part1 = of b . b
@@ -565,6 +564,217 @@ __global__ __launch_bounds__(256) void dot_kernel(int64_t n, const double* __res
     if (threadIdx.x == 0) part0[blockIdx.x] = t0;
 }
 
+// ---- restarted GMRES(kGmresM), right-preconditioned (K M y = b, x = M y):
+// Arnoldi by classical Gram-Schmidt with fused dot products (fixed-order
+// two-stage sums), Givens rotations of the Hessenberg column on the device,
+// the solution formed at the end of each cycle and the true residual
+// recomputed for the restart.  Inner kernels return at once when the cycle
+// has ended (F_CYC, passed as the flag pointer), end-of-cycle kernels when
+// it had no step (F_J = 0).
+constexpr int kGmresM = FEM_GMRES_RESTART;
+
+// v = scale v (scale = sc[S_BETA]); mx = M0 v (node blocks)
+__global__ __launch_bounds__(256) void gm_normalize(int32_t n_nodes, double* __restrict__ v,
+                                                    const double* __restrict__ minv, double* __restrict__ mx,
+                                                    const double* __restrict__ sc, const int32_t* __restrict__ fl) {
+    if (fl[0]) return;
+    const double scale = sc[S_BETA];
+    for (int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x; I < n_nodes; I += (int64_t)kGrid * 256) {
+        double q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q[a] = scale * v[3 * I + a];
+            v[3 * I + a] = q[a];
+        }
+        apply_minv(minv, I, q, mx);
+    }
+}
+
+// hpart[i][block] = partial of (w, v_i), i = 0..j
+__global__ __launch_bounds__(256) void gm_dots(int64_t n, int j, const double* __restrict__ V, int64_t ldv,
+                                               const double* __restrict__ w, double* __restrict__ hpart,
+                                               const int32_t* __restrict__ fl) {
+    if (fl[0]) return;
+    for (int i = 0; i <= j; ++i) {
+        const double* __restrict__ vi = V + (int64_t)i * ldv;
+        double d = 0.0;
+        for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)kGrid * 256) d += w[k] * vi[k];
+        const double t = block_sum(d);
+        if (threadIdx.x == 0) hpart[(int64_t)i * kGrid + blockIdx.x] = t;
+    }
+}
+
+// H(i, j) = sum of hpart[i][*], one block per i
+__global__ __launch_bounds__(256) void gm_hreduce(const double* __restrict__ hpart, int j, double* __restrict__ H,
+                                                  const int32_t* __restrict__ fl) {
+    if (fl[0]) return;
+    const int i = blockIdx.x;
+    const double t = sum_parts(hpart + (int64_t)i * kGrid, kGrid);
+    if (threadIdx.x == 0) H[(int64_t)j * (kGmresM + 1) + i] = t;
+}
+
+// w -= sum_i H(i, j) v_i; part0 = partials of (w, w)
+__global__ __launch_bounds__(256) void gm_update(int64_t n, int j, const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ H, double* __restrict__ w,
+                                                 double* __restrict__ part0, const int32_t* __restrict__ fl) {
+    if (fl[0]) return;
+    const double* __restrict__ h = H + (int64_t)j * (kGmresM + 1);
+    double d = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)kGrid * 256) {
+        double wk = w[k];
+        for (int i = 0; i <= j; ++i) wk -= h[i] * V[(int64_t)i * ldv + k];
+        w[k] = wk;
+        d += wk * wk;
+    }
+    const double t = block_sum(d);
+    if (threadIdx.x == 0) part0[blockIdx.x] = t;
+}
+
+// End of step j: H(j+1, j) = ||w||, the earlier rotations applied to column
+// j, a new rotation zeroing H(j+1, j), g rotated; |g(j+1)| / ||b|| is the
+// residual of the cycle's least-squares solution.  The cycle ends on
+// convergence, a breakdown (H(j+1, j) = 0: the solution is in the space),
+// a non-finite value, the iteration limit or after kGmresM steps.
+__global__ __launch_bounds__(256) void gm_finish(const double* __restrict__ part0, int j, double* __restrict__ H,
+                                                 double* __restrict__ cs, double* __restrict__ sn,
+                                                 double* __restrict__ g, double* __restrict__ sc,
+                                                 int32_t* __restrict__ fl, double rtol, int32_t max_iter) {
+    if (fl[F_CYC]) return;
+    const double ww = sum_parts(part0, kGrid);
+    if (threadIdx.x != 0) return;
+    double* h = H + (int64_t)j * (kGmresM + 1);
+    const double hn = sqrt(ww);
+    h[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = h[i], b = h[i + 1];
+        h[i] = cs[i] * a + sn[i] * b;
+        h[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = h[j], b = h[j + 1];
+    const double r = hypot(a, b);
+    const double c = r > 0.0 ? a / r : 1.0, sgn = r > 0.0 ? b / r : 0.0;
+    cs[j] = c;
+    sn[j] = sgn;
+    h[j] = r;
+    h[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j] = c * gj;
+    g[j + 1] = -sgn * gj;
+    const double bn = sqrt(sc[S_BB]);
+    const double res = bn > 0.0 ? fabs(g[j + 1]) / bn : fabs(g[j + 1]);
+    const int32_t it = fl[F_ITER] + 1;
+    fl[F_ITER] = it;
+    fl[F_J] = j + 1;
+    sc[S_RES] = res;
+    sc[S_BETA] = hn > 0.0 ? 1.0 / hn : 0.0;
+    const bool stop = res <= rtol || !isfinite(res) || hn == 0.0 || !(r > 0.0) || it >= max_iter;
+    if (stop) fl[F_STOP] = 1;
+    if (stop || j + 1 == kGmresM) fl[F_CYC] = 1;
+}
+
+// y = R^-1 g over the cycle's F_J steps (upper triangular H), one thread
+__global__ void gm_solve_y(const double* __restrict__ H, const double* __restrict__ g, double* __restrict__ y,
+                           const int32_t* __restrict__ fl) {
+    const int m = fl[F_J];
+    for (int i = m - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < m; ++k) t -= H[(int64_t)k * (kGmresM + 1) + i] * y[k];
+        const double d = H[(int64_t)i * (kGmresM + 1) + i];
+        y[i] = d != 0.0 ? t / d : 0.0;
+    }
+}
+
+// u = sum_{i < F_J} y_i v_i (zero if the cycle had no step)
+__global__ __launch_bounds__(256) void gm_combine(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                  const double* __restrict__ y, double* __restrict__ u,
+                                                  const int32_t* __restrict__ fl) {
+    const int m = fl[F_J];
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)kGrid * 256) {
+        double t = 0.0;
+        for (int i = 0; i < m; ++i) t += y[i] * V[(int64_t)i * ldv + k];
+        u[k] = t;
+    }
+}
+
+// z = M0 u (node blocks: the block-Jacobi preconditioner)
+__global__ __launch_bounds__(256) void gm_apply_minv(int32_t n_nodes, const double* __restrict__ minv,
+                                                     const double* __restrict__ u, double* __restrict__ z) {
+    for (int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x; I < n_nodes; I += (int64_t)kGrid * 256) {
+        const double q[3] = {u[3 * I], u[3 * I + 1], u[3 * I + 2]};
+        apply_minv(minv, I, q, z);
+    }
+}
+
+// x += z
+__global__ __launch_bounds__(256) void gm_addx(int64_t n, const double* __restrict__ z, double* __restrict__ x) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)kGrid * 256) x[k] += z[k];
+}
+
+// v0 = b - y (y = K x); part0 = partials of (v0, v0), part1 = of (b, b)
+__global__ __launch_bounds__(256) void gm_residual(int64_t n, const double* __restrict__ b,
+                                                   const double* __restrict__ y, double* __restrict__ v0,
+                                                   double* __restrict__ part0, double* __restrict__ part1,
+                                                   const int32_t* __restrict__ fl) {
+    if (fl[F_STOP]) return;
+    double rr = 0.0, bb = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)kGrid * 256) {
+        const double bk = b[k], rk = bk - y[k];
+        v0[k] = rk;
+        rr += rk * rk;
+        bb += bk * bk;
+    }
+    const double t0 = block_sum(rr), t1 = block_sum(bb);
+    if (threadIdx.x == 0) {
+        part0[blockIdx.x] = t0;
+        part1[blockIdx.x] = t1;
+    }
+}
+
+// start of a cycle: beta = ||v0||, g = beta e1, S_BETA = 1/beta (||b||
+// taken on the first start only); stops on a converged or non-finite
+// residual or max_iter <= 0
+__global__ __launch_bounds__(256) void gm_start(const double* __restrict__ part0, const double* __restrict__ part1,
+                                                double* __restrict__ g, double* __restrict__ sc,
+                                                int32_t* __restrict__ fl, double rtol, int32_t max_iter,
+                                                int first) {
+    if (fl[F_STOP]) return;
+    const double rr = sum_parts(part0, kGrid);
+    const double bb = first ? sum_parts(part1, kGrid) : 0.0;
+    if (threadIdx.x != 0) return;
+    if (first) sc[S_BB] = bb;
+    const double beta = sqrt(rr);
+    const double res = rel_of(rr, sc[S_BB]);
+    for (int i = 0; i <= kGmresM; ++i) g[i] = 0.0;
+    g[0] = beta;
+    sc[S_RES] = res;
+    sc[S_BETA] = beta > 0.0 ? 1.0 / beta : 0.0;
+    fl[F_J] = 0;
+    fl[F_CYC] = 0;
+    if (res <= rtol || !isfinite(res) || beta == 0.0 || max_iter <= 0 || fl[F_ITER] >= max_iter) {
+        fl[F_STOP] = 1;
+        fl[F_CYC] = 1;
+    }
+}
+
+struct GmresWs {
+    double *V, *H, *cs, *sn, *g, *y, *hpart;
+    int64_t ldv;
+};
+
+template <typename C>
+void carve_gmres(C& c, int32_t n, GmresWs* w) {
+    GmresWs o;
+    o.ldv = ((int64_t)n + 31) / 32 * 32;
+    o.V = c.template take<double>((size_t)o.ldv * (kGmresM + 1));
+    o.H = c.template take<double>((size_t)(kGmresM + 1) * kGmresM);
+    o.cs = c.template take<double>(kGmresM + 1);
+    o.sn = c.template take<double>(kGmresM + 1);
+    o.g = c.template take<double>(kGmresM + 1);
+    o.y = c.template take<double>(kGmresM + 1);
+    o.hpart = c.template take<double>((size_t)(kGmresM + 1) * kGrid);
+    if (w) *w = o;
+}
+
 struct SolverWs {
     double *r, *rh, *p, *ph, *v, *s, *sh, *t, *minv, *part0, *part1, *part2, *sc;
     int32_t *ncol, *fl;
@@ -639,11 +849,16 @@ int check_csr(const fem_csr* csr, const void* vals, const char* who) {
 
 using namespace fem;
 
-extern "C" size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz) {
+extern "C" size_t fem_solver_workspace_bytes_method(int32_t n_rows, int64_t nnz, fem_krylov method) {
     if (n_rows < 0 || nnz < 0) return 0;
     CountAdapterS c;
     carve_solver(c, n_rows, nnz, (SolverWs*)nullptr);
+    if (method == FEM_KRYLOV_GMRES) carve_gmres(c, n_rows, (GmresWs*)nullptr);
     return c.cnt.used + 256;
+}
+
+extern "C" size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz) {
+    return fem_solver_workspace_bytes_method(n_rows, nnz, FEM_KRYLOV_BICGSTAB);
 }
 
 extern "C" int fem_csr_spmv(const fem_csr* csr, const void* K_vals, fem_precision prec, const double* x, double* y,
@@ -689,7 +904,7 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
     if (prec != FEM_FP64 && prec != FEM_FP32_MIXED) return set_error(FEM_EINVAL, "%s: bad precision", who);
     if (!amg && pc != FEM_PC_JACOBI && pc != FEM_PC_BLOCK_JACOBI)
         return set_error(FEM_EINVAL, "%s: bad preconditioner", who);
-    if (method != FEM_KRYLOV_BICGSTAB && method != FEM_KRYLOV_CG)
+    if (method != FEM_KRYLOV_BICGSTAB && method != FEM_KRYLOV_CG && method != FEM_KRYLOV_GMRES)
         return set_error(FEM_EINVAL, "%s: bad Krylov method", who);
     if (max_iter < 0 || !(rtol >= 0.0)) return set_error(FEM_EINVAL, "%s: max_iter >= 0 and rtol >= 0", who);
     const int32_t n = csr->n_rows, nn = n / 3;
@@ -700,7 +915,7 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
     if (csr->nnz < 0 || csr->nnz % 9) return set_error(FEM_EINVAL, "%s: nnz must be a multiple of 9", who);
     if (amg && !amg_matches(amg, csr))
         return set_error(FEM_EINVAL, "%s: the multigrid handle was built on another pattern", who);
-    const size_t need = fem_solver_workspace_bytes(n, csr->nnz);
+    const size_t need = fem_solver_workspace_bytes_method(n, csr->nnz, method);
     if (!ws || ws_bytes < need)
         return set_error(FEM_ENOMEM, "%s: workspace of %zu bytes required, %zu given", who, need, ws_bytes);
     hipStream_t s = (hipStream_t)stream;
@@ -728,6 +943,65 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
     }
     hipLaunchKernelGGL(reset_flags, dim3(1), dim3(1), 0, s, w.fl);
     spmv_dot<0>(csr, w.ncol, K_vals, prec, x, w.t, nullptr, nullptr, nullptr, nullptr, s);
+    if (method == FEM_KRYLOV_GMRES) {
+        GmresWs g;
+        carve_gmres(c, n, &g);
+        // M v: with multigrid the normalisation writes the first sweep M_0 v
+        // into the cycle's finest iterate and the cycle writes M v to ph;
+        // with block Jacobi the normalisation writes M v to ph itself
+        double* m0 = amg ? mx : w.ph;
+        const int32_t* cyc = w.fl + F_CYC;
+        const int32_t* stp = w.fl + F_STOP;
+        hipLaunchKernelGGL(gm_residual, dim3(kGrid), dim3(256), 0, s, (int64_t)n, b, w.t, g.V, w.part0, w.part1,
+                           w.fl);
+        hipLaunchKernelGGL(gm_start, dim3(1), dim3(256), 0, s, w.part0, w.part1, g.g, w.sc, w.fl, rtol, max_iter, 1);
+        FEM_HIP_CHECK(hipGetLastError());
+        int32_t flh[F_COUNT];
+        double res = 0.0;
+        auto read_back = [&]() -> hipError_t {
+            hipError_t e = hipMemcpyAsync(flh, w.fl, sizeof(flh), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(&res, w.sc + S_RES, sizeof(double), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            return e;
+        };
+        FEM_HIP_CHECK(read_back());
+        while (!flh[F_STOP]) {
+            for (int j = 0; j < kGmresM; ++j) {
+                double* vj = g.V + (int64_t)j * g.ldv;
+                double* vn = g.V + (int64_t)(j + 1) * g.ldv;
+                hipLaunchKernelGGL(gm_normalize, dim3(kGrid), dim3(256), 0, s, nn, vj, minv, m0, w.sc, cyc);
+                if (amg) FEM_HIP_CHECK(amg_vcycle(amg, vj, w.ph, true, cyc, s));
+                spmv_dot<0>(csr, w.ncol, K_vals, prec, w.ph, vn, nullptr, nullptr, nullptr, cyc, s);
+                hipLaunchKernelGGL(gm_dots, dim3(kGrid), dim3(256), 0, s, (int64_t)n, j, g.V, g.ldv, vn, g.hpart, cyc);
+                hipLaunchKernelGGL(gm_hreduce, dim3(j + 1), dim3(256), 0, s, g.hpart, j, g.H, cyc);
+                hipLaunchKernelGGL(gm_update, dim3(kGrid), dim3(256), 0, s, (int64_t)n, j, g.V, g.ldv, g.H, vn,
+                                   w.part0, cyc);
+                hipLaunchKernelGGL(gm_finish, dim3(1), dim3(256), 0, s, w.part0, j, g.H, g.cs, g.sn, g.g, w.sc, w.fl,
+                                   rtol, max_iter);
+            }
+            // x += M (V y); then the true residual of the restart
+            hipLaunchKernelGGL(gm_solve_y, dim3(1), dim3(1), 0, s, g.H, g.g, g.y, w.fl);
+            hipLaunchKernelGGL(gm_combine, dim3(kGrid), dim3(256), 0, s, (int64_t)n, g.V, g.ldv, g.y, w.p, w.fl);
+            if (amg)
+                FEM_HIP_CHECK(amg_vcycle(amg, w.p, w.sh, false, nullptr, s));
+            else
+                hipLaunchKernelGGL(gm_apply_minv, dim3(kGrid), dim3(256), 0, s, nn, minv, w.p, w.sh);
+            hipLaunchKernelGGL(gm_addx, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.sh, x);
+            spmv_dot<0>(csr, w.ncol, K_vals, prec, x, w.t, nullptr, nullptr, nullptr, stp, s);
+            hipLaunchKernelGGL(gm_residual, dim3(kGrid), dim3(256), 0, s, (int64_t)n, b, w.t, g.V, w.part0, w.part1,
+                               w.fl);
+            hipLaunchKernelGGL(gm_start, dim3(1), dim3(256), 0, s, w.part0, w.part1, g.g, w.sc, w.fl, rtol, max_iter,
+                               0);
+            FEM_HIP_CHECK(hipGetLastError());
+            FEM_HIP_CHECK(read_back());
+        }
+        if (iters) *iters = flh[F_ITER];
+        if (rel_res) *rel_res = res;
+        if (!(res <= rtol))
+            return set_error(FEM_ENOCONV, "%s: relative residual %.3e after %d iterations (rtol %.3e)", who, res,
+                             flh[F_ITER], rtol);
+        return FEM_OK;
+    }
     const bool cg = method == FEM_KRYLOV_CG;
     if (cg && amg) {
         // r = b - K x, mx = M_0 r; z (in s) = M r; p = z; (r, z)

@@ -56,7 +56,8 @@ _lib = None
 EXPORTS = ("fem_version", "fem_last_error", "fem_set_launch", "fem_get_launch", "fem_csr_workspace_bytes",
            "fem_forward_workspace_bytes", "fem_vjp_workspace_bytes", "fem_csr_pattern", "fem_residual_tangent",
            "fem_residual_vjp", "fem_residual_vjp_noalloc", "fem_timing_enable", "fem_timing_read",
-           "fem_graph_begin", "fem_graph_end", "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes", "fem_csr_spmv", "fem_solve",
+           "fem_graph_begin", "fem_graph_end", "fem_graph_launch", "fem_graph_destroy", "fem_solver_workspace_bytes",
+           "fem_solver_workspace_bytes_method", "fem_csr_spmv", "fem_solve",
            "fem_csr_transpose", "fem_history_adjoint_workspace_bytes", "fem_history_adjoint", "fem_amg_create",
            "fem_amg_update", "fem_amg_apply", "fem_amg_info", "fem_amg_aggregates", "fem_amg_destroy",
            "fem_solve_amg", "fem_amg_plan_host")
@@ -97,6 +98,8 @@ def lib():
     L.fem_graph_destroy.argtypes = [_c_p]
     L.fem_solver_workspace_bytes.argtypes = [_c_i32, ctypes.c_int64]
     L.fem_solver_workspace_bytes.restype = _c_sz
+    L.fem_solver_workspace_bytes_method.argtypes = [_c_i32, ctypes.c_int64, ctypes.c_int]
+    L.fem_solver_workspace_bytes_method.restype = _c_sz
     L.fem_csr_spmv.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, _c_p, _c_p, _c_p]
     L.fem_solve.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_p, _c_p,
                             _c_i32, ctypes.c_double,
@@ -573,7 +576,7 @@ def csr_spmv(csr, K, x, y=None, stream=None):
 
 
 PC_JACOBI, PC_BLOCK_JACOBI, PC_AMG = 0, 1, 2
-KRYLOV = {"bicgstab": 0, "cg": 1}
+KRYLOV = {"bicgstab": 0, "cg": 1, "gmres": 2}
 AMG_MAX_LEVELS = 12
 
 
@@ -669,7 +672,8 @@ class Solver:
         self.csr = csr
         self.precond = int(precond)
         self.method = KRYLOV[method]
-        self.ws_bytes = lib().fem_solver_workspace_bytes(csr.n_rows, csr.nnz)
+        self.device = device
+        self.ws_bytes = lib().fem_solver_workspace_bytes_method(csr.n_rows, csr.nnz, self.method)
         self.ws = _ws(self.ws_bytes, device)
         self.bc_mask = bc_mask
         self.amg = None
@@ -684,6 +688,10 @@ class Solver:
         res = ctypes.c_double(0.0)
         pc = self.precond if precond is None else int(precond)
         mt = self.method if method is None else KRYLOV[method]
+        need = lib().fem_solver_workspace_bytes_method(self.csr.n_rows, self.csr.nnz, mt)
+        if need > self.ws_bytes:  # GMRES asked of a solver made for another method
+            self.ws_bytes = need
+            self.ws = _ws(need, b.device)
         if pc == PC_AMG:
             if self.amg is None:
                 self.amg = AMG(self.csr, K, self.bc_mask, stream)

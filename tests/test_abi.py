@@ -106,7 +106,13 @@ def test_solver_arguments_are_rejected_on_the_host(lib):
                            ctypes.byref(res), fake, ws_bytes, None)
         return rc, it.value, res.value
 
-    assert solve(method=2)[0] == fem.FEM_EINVAL and b"Krylov" in lib.fem_last_error()
+    assert solve(method=3)[0] == fem.FEM_EINVAL and b"Krylov" in lib.fem_last_error()
+    # GMRES needs its basis: FEM_GMRES_RESTART + 1 more vectors
+    assert solve(method=2, ws_bytes=lib.fem_solver_workspace_bytes(6, 18))[0] == fem.FEM_ENOMEM
+    gm = lib.fem_solver_workspace_bytes_method(3000, 9 * 27 * 1000, 2)
+    assert gm >= lib.fem_solver_workspace_bytes(3000, 9 * 27 * 1000) + 31 * 3000 * 8
+    assert lib.fem_solver_workspace_bytes_method(3000, 9 * 27 * 1000, 0) == lib.fem_solver_workspace_bytes(
+        3000, 9 * 27 * 1000)
     assert solve(pc=5)[0] == fem.FEM_EINVAL and b"preconditioner" in lib.fem_last_error()
     assert solve(prec=7)[0] == fem.FEM_EINVAL
     assert solve(n_rows=5)[0] == fem.FEM_EINVAL  # not 3 n_nodes
