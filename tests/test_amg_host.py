@@ -106,3 +106,26 @@ def test_plan_with_constrained_dofs_and_rejections(fem):
         fem.amg_plan_host(bptr, bad, s)
     with pytest.raises(fem.FemError):
         fem.amg_plan_host(bptr[::-1].copy(), ncol, s)
+
+
+def test_plan_stops_when_the_coarsening_stalls(fem):
+    """Nodes whose coupling strengths are all zero find no partner: with all
+    of them the plan is one level; with half of them (the first half in
+    index order) one coarsening still halves the other half's count, and the
+    next keeps more than 85 % of the nodes, so the hierarchy stops there."""
+    p = synth.unit_cube_forward(14, 12, 10)
+    bptr, ncol = node_pattern(p.conn, p.n_nodes)
+    s = strengths(p.X, bptr, ncol)
+    rows = np.repeat(np.arange(p.n_nodes), np.diff(bptr))
+    for frac, n_levels in ((1.0, 1), (0.5, 2)):
+        dec = np.arange(p.n_nodes) < int(frac * p.n_nodes)
+        s2 = np.where((rows == ncol) | ~(dec[rows] | dec[ncol]), s, 0.0).astype(np.float32)
+        levels, maps = fem.amg_plan_host(bptr, ncol, s2)
+        assert len(levels) == n_levels
+        if n_levels == 2:
+            agg = maps[0]
+            # the decoupled nodes stay alone; the coupled ones are paired
+            sizes = np.bincount(agg)
+            assert np.all(sizes[agg[dec]] == 1)
+            assert levels[1][0] < 0.85 * p.n_nodes and levels[1][0] > 512
+            check_plan(levels, maps, bptr, ncol)

@@ -79,10 +79,11 @@ def bj_blocks(A, omega=1.0):
     return sp.csr_matrix((Minv.reshape(-1), (rows, cols.reshape(-1))), shape=A.shape)
 
 
-def ref_vcycle(A0, free0, aggs, omegas, r):
+def ref_vcycle(A0, free0, aggs, omegas, r, dense=True):
     """V(1,1)-cycle from the definitions (host, FP64 vectors): A0 the finest
     operator (scipy CSR), free0 its free-dof mask, aggs the aggregate map of
-    each level transition, omegas the smoother damping per level."""
+    each level transition, omegas the smoother damping per level; the
+    coarsest level inverted exactly (dense) or smoothed twice."""
     import scipy.sparse as sp
 
     As, Ms, Ps, masks = [A0], [], [], [free0]
@@ -101,11 +102,14 @@ def ref_vcycle(A0, free0, aggs, omegas, r):
         masks.append(mc)
     for A, om in zip(As, omegas):
         Ms.append(bj_blocks(A, om))
-    Cinv = np.linalg.inv(As[-1].toarray())
+    Cinv = np.linalg.inv(As[-1].toarray()) if dense else None
 
     def cycle(l, b):
         if l == len(As) - 1:
-            return Cinv @ b
+            if dense:
+                return Cinv @ b
+            x = Ms[l] @ b
+            return x + Ms[l] @ (b - As[l] @ x)
         x = Ms[l] @ b
         rc = Ps[l].T @ (b - As[l] @ x)
         x = x + Ps[l] @ cycle(l + 1, rc)
@@ -238,3 +242,43 @@ def test_fewer_iterations_than_block_jacobi_and_symmetric(fem):
     say(f"  v.Mu {a:.12e} u.Mv {c:.12e}")
     assert abs(a - c) <= 1e-6 * max(abs(a), abs(c))
     assert float(torch.dot(u, Mu)) > 0.0
+
+
+@pytest.mark.parametrize("case", ["all_decoupled", "half_decoupled"])
+def test_stalled_coarsening_paths(fem, case):
+    """Coupling blocks of some nodes zeroed (rows and columns, the pattern
+    kept), so the matching finds no partner for them and the coarsening
+    stalls: with every node decoupled the hierarchy is one level that is not
+    inverted exactly (two damped block-Jacobi sweeps); with half of them the
+    coarsest level keeps more than 512 nodes (no single-workgroup tail, no
+    dense inverse).  The cycle equals the numpy cycle on the same
+    aggregates and damping."""
+    import scipy.sparse as sp
+    p = cube_state(14, ny=12, nz=10)
+    csr, K, bc = tangent(fem, p, fem.FP64)
+    A = host_csr(csr, K).tocoo()
+    n = p.n_nodes
+    dec = np.ones(n, bool) if case == "all_decoupled" else (np.arange(n) < n // 2)
+    bi, bj = A.row // 3, A.col // 3
+    keep = (bi == bj) | ~(dec[bi] | dec[bj])
+    vals = np.where(keep, A.data, 0.0)
+    # back into the CSR order of csr (coo of a csr keeps the order)
+    K2 = torch.as_tensor(vals).cuda()
+    amg = fem.AMG(csr, K2, bc)
+    amg.update(K2)
+    levels, dense, omegas = amg.info(omega=True)
+    say(f"{case}: levels {levels} dense {dense} omega {omegas}")
+    if case == "all_decoupled":
+        assert len(levels) == 1 and not dense
+    else:
+        assert not dense and levels[-1][0] > 512
+    A0 = sp.csr_matrix((vals, (A.row, A.col)), shape=A.shape)
+    free0 = p.bc_mask == 0
+    aggs = [amg.aggregates(l) for l in range(1, len(levels))]
+    r = np.random.default_rng(12).standard_normal(csr.n_rows) * free0
+    z = amg.apply(torch.as_tensor(r).cuda())
+    torch.cuda.synchronize()
+    ref = ref_vcycle(A0, free0, aggs, omegas, r, dense=False)
+    err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say(f"  rel err {err:.2e}")
+    assert err <= 2e-6
