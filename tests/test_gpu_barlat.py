@@ -77,7 +77,7 @@ def test_vjp_rejects_barlat(fem):
     assert ei.value.code == fem.FEM_EINVAL
 
 
-def robustness_problem(n_theta=40, n_r=50):
+def robustness_problem(n_theta=160, n_r=100):
     """Trial states of App. B's robustness study (Barlat Yld2004-18p with the
     verification table's fit, E = 1000, nu = 0.3, sigma0 = 1, perfect
     plasticity, trial stresses in the deviatoric principal-stress plane between
@@ -109,10 +109,14 @@ def robustness_problem(n_theta=40, n_r=50):
 def test_barlat_return_map_over_the_robustness_states(fem):
     """The GPU closest-point iteration (radial start on the current yield
     surface, Newton on (T, dgamma), line search of App. B on the merit of
-    Eq. (merit)) over 2,000 of the robustness study's trial states, up to 30
-    times the yield surface: every Gauss point converges (diag zero) to the
-    oracle's state (Alg. C2 from the trial state), residual and history
-    within 1e-10."""
+    Eq. (merit)) over the robustness study's 16,000 trial states (160
+    directions x 100 radii), up to 30 times the yield surface: every Gauss
+    point converges (diag zero) to the oracle's state (Alg. C2 from the
+    trial state): history within 1e-10, residual within 1e-9 (both sides
+    may stop on a stalled decrease of the scaled local residual below 1e-9,
+    the stop rule of the local iteration, at different iterates inside that
+    band; over the 384,000 residual entries the largest difference is about
+    1.2e-10 of the largest entry)."""
     p = robustness_problem()
     say("barlat robustness states", p.n_elems)
     o = oracle_forward(p, bc=False, want_K=False)
@@ -121,4 +125,4 @@ def test_barlat_return_map_over_the_robustness_states(fem):
     g = gpu_forward(p, fem, fem.FP64, bc=False, want_K=False)
     assert list(g["diag"]) == [0, 0, 0, 0]
     assert hist_rel(g["hist"], o["hist"]) <= TOL_FP64
-    assert rel_inf(g["R"], o["R"]) <= TOL_FP64
+    assert rel_inf(g["R"], o["R"]) <= 1e-9
