@@ -448,8 +448,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the path is a design "
-              "note (z-slab row ownership, one-plane halo), not an implementation", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; sharding the path over GPUs (z-slab row ownership, "
+              "one-plane halo) is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
