@@ -42,14 +42,16 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
     once ||R|| has not fallen by the factor stall_ratio over that many
     iterations.  Returns (hist_np1, iterations, list of
     ||R||).  Raises RuntimeError if the tolerance is not reached in max_it
-    iterations, a linear solve fails or ||R|| is not finite.  A list passed
+    iterations, a linear solve fails or ||R|| is not finite.  solver: a
+    fem.Solver of the pattern (default BiCGSTAB preconditioned by the
+    aggregation multigrid built for bc_mask).  A list passed
     as trace receives one (linear iterations, linear relative residual, step
     length, seconds in the linear solve, linear tolerance) tuple per Newton
     iteration."""
     if out is None:
         out = fem.Forward(mesh, csr, prec)
     if solver is None:
-        solver = fem.Solver(csr, d.device)
+        solver = fem.Solver(csr, d.device, precond=fem.PC_AMG, bc_mask=bc_mask)
     flat = d.view(-1)
 
     def evaluate():
