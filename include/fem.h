@@ -366,9 +366,10 @@ int fem_csr_transpose(const fem_csr *csr, const void *K_vals, fem_precision prec
  * App. F solve the linear systems with an algebraic-multigrid-preconditioned
  * Krylov method).  The hierarchy works on 3x3 node blocks:
  *   - aggregation: each level pairs nodes three times by greedy matching
- *     along the strongest connection (Frobenius norm of the block of K over
- *     the geometric mean of the two diagonal-block norms; nodes visited in
- *     index order), so an aggregate holds up to eight nodes; levels are added
+ *     along the strongest connection (Frobenius norm of the block of K,
+ *     the larger of the blocks (I, J) and (J, I), over the geometric mean of
+ *     the two diagonal-block norms; nodes visited in index order), so an
+ *     aggregate holds up to eight nodes; levels are added
  *     until at most FEM_AMG_DENSE_NODES nodes remain or a level keeps more
  *     than 85 % of the nodes of the one above (or FEM_AMG_MAX_LEVELS);
  *   - prolongation P: piecewise-constant per displacement component (the

@@ -870,9 +870,30 @@ bool build_coarse(const HostLevel& f, std::vector<int32_t>&& agg, int32_t nc, Ho
     return 9 * c.bptr[nc] < (int64_t)INT32_MAX;
 }
 
+// s(I, J) = s(J, I) = the larger of the two (row elimination of constrained
+// dofs zeroes their rows, not their columns: a clamped node still couples
+// to its neighbours through the columns and must be able to join an
+// aggregate; the pattern is structurally symmetric, columns ascending).
+void symmetrize_strength(HostLevel& f) {
+    for (int32_t I = 0; I < f.n; ++I)
+        for (int64_t q = f.bptr[I]; q < f.bptr[I + 1]; ++q) {
+            const int32_t J = f.ncol[q];
+            if (J <= I) continue;
+            const int32_t* b0 = f.ncol.data() + f.bptr[J];
+            const int32_t* b1 = f.ncol.data() + f.bptr[J + 1];
+            const int32_t* it = std::lower_bound(b0, b1, I);
+            if (it == b1 || *it != I) continue;
+            const int64_t qt = f.bptr[J] + (it - b0);
+            const double m = std::max(f.s[q], f.s[qt]);
+            f.s[q] = m;
+            f.s[qt] = m;
+        }
+}
+
 // Levels below H[0] (host): aggregate until at most FEM_AMG_DENSE_NODES
 // nodes remain, the coarsening stalls or FEM_AMG_MAX_LEVELS is reached.
 bool build_hierarchy(std::vector<HostLevel>& H) {
+    symmetrize_strength(H[0]);
     while ((int)H.size() < FEM_AMG_MAX_LEVELS && H.back().n > FEM_AMG_DENSE_NODES) {
         int32_t nc = 0;
         std::vector<int32_t> agg = aggregate(H.back(), nc);

@@ -129,3 +129,25 @@ def test_plan_stops_when_the_coarsening_stalls(fem):
             assert np.all(sizes[agg[dec]] == 1)
             assert levels[1][0] < 0.85 * p.n_nodes and levels[1][0] > 512
             check_plan(levels, maps, bptr, ncol)
+
+
+def test_clamped_nodes_join_aggregates(fem):
+    """Row elimination zeroes the rows of constrained dofs but not their
+    columns: on a thin sheet whose bottom third of nodes is clamped (block
+    rows zero except the diagonal), the clamped nodes still join aggregates
+    through the column blocks, so the hierarchy coarsens by about eight per
+    level down to at most 32 nodes."""
+    X, conn = synth.hex_grid(24, 24, 2)
+    bptr, ncol = node_pattern(conn, X.shape[0])
+    s = strengths(X, bptr, ncol)
+    rows = np.repeat(np.arange(X.shape[0]), np.diff(bptr))
+    clamped = np.isclose(X[:, 2], 0.0)
+    s_rows = np.where(clamped[rows] & (rows != ncol), 0.0, s).astype(np.float32)
+    levels, maps = fem.amg_plan_host(bptr, ncol, s_rows)
+    check_plan(levels, maps, bptr, ncol)
+    assert levels[-1][0] <= 32
+    assert levels[1][0] <= X.shape[0] / 5
+    # every clamped node shares its aggregate with at least one free node
+    agg = maps[0]
+    free_aggs = set(agg[~clamped])
+    assert all(a in free_aggs for a in agg[clamped])
