@@ -173,3 +173,24 @@ def test_noalloc_vjp_rejects_meshes_beyond_its_scratch(lib):
     assert b"maximum" in lib.fem_last_error()
     assert lib.fem_residual_vjp_noalloc(None, None, None, None, None, None, 0, None, None, None, None) == \
         fem.FEM_EINVAL
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/fem.h is a C header: it compiles as C99 with -pedantic, every
+    declared entry point taken by address (so a C caller can link them)."""
+    import re
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    hdr = open(os.path.join(root, "include", "fem.h")).read()
+    names = sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s+(fem_\w+)\(", hdr, re.M)))
+    assert "fem_solve_amg" in names and "fem_residual_tangent" in names
+    src = tmp_path / "use.c"
+    src.write_text('#include "fem.h"\ntypedef void (*fn)(void);\nfn table[] = {' + ", ".join(f"(fn){n}" for n in names)
+                   + "};\n")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(root, "include"), "-c", str(src), "-o", str(tmp_path / "use.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
