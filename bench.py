@@ -250,7 +250,7 @@ def elastic_solve(csr, torch, fem, synth):
     res = {"dofs": 3 * p.n_nodes, "context": "paper App. F, same mesh, linear elastic, one H100: AMGX BiCGSTAB "
                                              "1.96 s, JAX BiCGSTAB 11.21 s (tolerance not stated)"}
     for pc, tag in ((fem.PC_BLOCK_JACOBI, ""), (fem.PC_AMG, "_amg")):
-        for method in ("cg", "bicgstab"):
+        for method in ("cg", "bicgstab") + (("fgmres",) if pc == fem.PC_AMG else ()):
             solver = fem.Solver(csr, method=method, precond=pc, bc_mask=bc)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -375,7 +375,7 @@ def forward_benchmark(spec, torch, fem, synth, fbar=True, precond="amg", krylov=
     pc = fem.PC_AMG if precond == "amg" else fem.PC_BLOCK_JACOBI
     res = loadpath.solve(mesh, csr, params, bc, u1, h0, log=lambda m: log(m), precond=pc, krylov=krylov)
     if krylov == "auto":
-        krylov = "bicgstab" if fbar else "cg"
+        krylov = fem.default_krylov(pc, fbar)
     n_it = max(res["newton_iterations"], 1)
     alpha = res["hist"][6]
     paper = PAPER_FORWARD_S.get(dims)
@@ -398,7 +398,9 @@ def forward_benchmark(spec, torch, fem, synth, fbar=True, precond="amg", krylov=
                                "nu 0.3; dt0 1e-3, dt_min 1e-5, dt_max 5e-2",
                    "nnz": csr.nnz, "element": "fbar" if fbar else "plain",
                    "krylov": krylov,
-                   "preconditioner": "aggregation multigrid V(1,1)" if precond == "amg" else "3x3 node-block Jacobi"},
+                   "preconditioner": ("3x3 node-block Jacobi" if precond != "amg" else
+                                      "aggregation multigrid K-cycle" if krylov == "fgmres" else
+                                      "aggregation multigrid V(1,1)")},
         "increments": len(res["steps"]),
         "failed_increments": len(res["failed"]),
         "newton_iterations": res["newton_iterations"],
@@ -440,8 +442,9 @@ def main():
                          "adjoint) on the tensile-specimen stand-in, one JSON line with its wall time")
     ap.add_argument("--element", choices=("fbar", "plain"), default="fbar",
                     help="element of --forward-benchmark: the paper's F-bar hex8 (BiCGSTAB) or the plain hex8 (CG)")
-    ap.add_argument("--krylov", choices=("auto", "gmres", "bicgstab", "cg"), default="auto",
-                    help="Krylov method of --forward-benchmark (auto: BiCGSTAB for F-bar, CG for the plain element)")
+    ap.add_argument("--krylov", choices=("auto", "fgmres", "gmres", "bicgstab", "cg"), default="auto",
+                    help="Krylov method of --forward-benchmark (auto: FGMRES with the multigrid K-cycle; with "
+                         "block Jacobi BiCGSTAB for F-bar, CG for the plain element)")
     ap.add_argument("--precond", choices=("amg", "bj"), default="amg",
                     help="preconditioner of --forward-benchmark: aggregation multigrid or 3x3 node-block Jacobi")
     ap.add_argument("--copy-probe", action="store_true",

@@ -306,8 +306,12 @@ int fem_residual_vjp_noalloc(const fem_mesh *mesh, const fem_batch *batch, const
  *                        reported residual is the cycle's least-squares
  *                        residual |g_{j+1}| / ||b||; workspace of
  *                        fem_solver_workspace_bytes_method (about
- *                        FEM_GMRES_RESTART + 1 more vectors); the host reads
- *                        the stop flag once per cycle
+ *                        FEM_GMRES_RESTART + 1 more vectors)
+ *   FEM_KRYLOV_FGMRES    flexible GMRES(FEM_GMRES_RESTART) (Saad's FGMRES):
+ *                        as FEM_KRYLOV_GMRES but keeps z_j = M v_j of every
+ *                        step and forms x += Z y, so M may change between
+ *                        steps (required by a K-cycle multigrid); the
+ *                        workspace holds FEM_GMRES_RESTART more vectors
  *   FEM_KRYLOV_CG        preconditioned conjugate gradients, for a K that is
  *                        symmetric positive definite on the free dofs (the
  *                        tangent without F-bar) with identity rows on the
@@ -328,17 +332,24 @@ int fem_residual_vjp_noalloc(const fem_mesh *mesh, const fem_batch *batch, const
  *   iters, rel_res  host outputs (iterations done, final relative residual),
  *            or NULL
  *   ws       device workspace of fem_solver_workspace_bytes(n_rows, nnz) bytes
- *            (GMRES: fem_solver_workspace_bytes_method(n_rows, nnz, method))
+ *            (GMRES, FGMRES: fem_solver_workspace_bytes_method(n_rows, nnz,
+ *            method))
  * The reductions are fixed-order (bitwise reproducible).  The iteration state
  * stays on the device; the host reads the stop flag once per 32 iterations
- * (one stream synchronisation each).  A breakdown (a zero inner product) or
+ * (4 with fem_solve_amg; GMRES: once per restart cycle, after every step
+ * with fem_solve_amg), one stream synchronisation each.  A breakdown (a zero inner product) or
  * a non-finite residual ends the iteration.  ||b - K x|| is the recursive
  * residual of the method.
  * Returns FEM_ENOCONV if rtol is not reached (x holds the last iterate).
  * Errors: FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOCONV.
  */
 typedef enum { FEM_PC_JACOBI = 0, FEM_PC_BLOCK_JACOBI = 1, FEM_PC_AMG = 2 /* fem_solve_amg only */ } fem_precond;
-typedef enum { FEM_KRYLOV_BICGSTAB = 0, FEM_KRYLOV_CG = 1, FEM_KRYLOV_GMRES = 2 } fem_krylov;
+typedef enum {
+    FEM_KRYLOV_BICGSTAB = 0,
+    FEM_KRYLOV_CG = 1,
+    FEM_KRYLOV_GMRES = 2,
+    FEM_KRYLOV_FGMRES = 3
+} fem_krylov;
 #define FEM_GMRES_RESTART 30
 size_t fem_solver_workspace_bytes(int32_t n_rows, int64_t nnz);        /* CG, BiCGSTAB */
 size_t fem_solver_workspace_bytes_method(int32_t n_rows, int64_t nnz, fem_krylov method);
@@ -388,8 +399,18 @@ int fem_csr_transpose(const fem_csr *csr, const void *K_vals, fem_precision prec
  *     pivoting in FP64; a pivot below 1e-13 of the largest diagonal entry
  *     drops that dof) when it has at most FEM_AMG_DENSE_NODES nodes, else
  *     one smoothing sweep pair.
- * One application z = M r is one V(1,1)-cycle; for a symmetric K it is a
- * symmetric operator (usable with CG).
+ * One application z = M r is one V(1,1)-cycle (the default); for a
+ * symmetric K it is a symmetric operator (usable with CG).  In a K-cycle
+ * (Notay and Vassilevski's recursive Krylov-based cycle) every level c that
+ * has at least k_min_nodes nodes, lies above the levels of at most 512 nodes
+ * and is not the coarsest replaces its coarse correction by two
+ * minimal-residual steps with the cycle below as preconditioner:
+ * c1 = B_c rc, v1 = A_c c1, a1 = (v1, rc) / (v1, v1), r2 = rc - a1 v1,
+ * c2 = B_c r2, v2 = A_c c2, g = (v2, v1) / (v1, v1),
+ * a2 = (v2, r2) / ((v2, v2) - g (v2, v1)), correction (a1 - a2 g) c1 + a2 c2
+ * (zero coefficients where a denominator is not positive).  A K-cycle is
+ * not a fixed linear operator: fem_solve_amg accepts it with
+ * FEM_KRYLOV_FGMRES only.
  *
  * fem_amg_create -- aggregation and coarse patterns, built on the host from
  *   the pattern of csr (fem_csr_pattern) and the block norms of K_vals
@@ -425,13 +446,18 @@ int fem_csr_transpose(const fem_csr *csr, const void *K_vals, fem_precision prec
  *   entries, or NULL) = the aggregate maps of levels 1, ..., n_levels - 1
  *   one after the other.  fem_amg_create with the same strengths builds the
  *   same hierarchy.
+ * fem_amg_set_cycle -- the cycle of later applications: FEM_AMG_CYCLE_V, or
+ *   FEM_AMG_CYCLE_K with the two Krylov steps on levels of at least
+ *   k_min_nodes (>= 0) nodes.  Host only.  Errors: FEM_EINVAL.
  * fem_solve_amg -- fem_solve (same arguments, workspace and stop rules)
- *   with M = one V-cycle of amg, after fem_amg_update(amg, K_vals, prec).
- *   csr must be the pattern amg was created on.
+ *   with M = one cycle of amg, after fem_amg_update(amg, K_vals, prec).
+ *   csr must be the pattern amg was created on; a K-cycle needs method
+ *   FEM_KRYLOV_FGMRES (else FEM_EINVAL).
  */
 #define FEM_AMG_MAX_LEVELS 12
 #define FEM_AMG_DENSE_NODES 32
 typedef struct fem_amg fem_amg;
+typedef enum { FEM_AMG_CYCLE_V = 0, FEM_AMG_CYCLE_K = 1 } fem_amg_cycle;
 int fem_amg_create(const fem_csr *csr, const void *K_vals, fem_precision prec, const uint8_t *bc_mask,
                    fem_amg **out, void *stream);
 int fem_amg_update(fem_amg *amg, const void *K_vals, fem_precision prec, void *stream);
@@ -441,6 +467,7 @@ int fem_amg_info(const fem_amg *amg, int32_t *n_levels, int32_t *nodes, int64_t 
 int fem_amg_aggregates(const fem_amg *amg, int32_t level, int32_t *agg);
 int fem_amg_plan_host(int32_t n_nodes, const int64_t *bptr, const int32_t *ncol, const float *strength,
                       const uint8_t *bc_mask, int32_t *n_levels, int32_t *nodes, int64_t *blocks, int32_t *agg);
+int fem_amg_set_cycle(fem_amg *amg, fem_amg_cycle cycle, int32_t k_min_nodes);
 int fem_amg_destroy(fem_amg *amg);
 int fem_solve_amg(const fem_csr *csr, const void *K_vals, fem_precision prec, fem_krylov method, fem_amg *amg,
                   const double *b, double *x, int32_t max_iter, double rtol, int32_t *iters, double *rel_res,

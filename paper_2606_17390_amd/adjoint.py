@@ -41,11 +41,11 @@ def forward(mesh, csr, params, bc_mask, bc_steps, hist0, prec=fem.FP64, tol=1e-1
     linear tolerances (floor lin_rtol); tangent_start: each step starts from
     the problem linearised about the previous converged state
     (loadpath.linearised_start, solved to 1e-4) instead of the previous
-    solution with the new boundary values.  The default solver is BiCGSTAB
-    with the aggregation multigrid (also for gradient)."""
+    solution with the new boundary values.  The default solver is flexible
+    GMRES with the aggregation multigrid's K-cycle (also for gradient)."""
     ck = Checkpoints(hist0)
     out = fem.Forward(mesh, csr, prec)
-    solver = solver or fem.Solver(csr, hist0.device, precond=fem.PC_AMG, bc_mask=bc_mask)
+    solver = solver or fem.Solver(csr, hist0.device, precond=fem.PC_AMG, method="fgmres", bc_mask=bc_mask)
     d = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=hist0.device)
     bc = bc_mask.bool().view(-1)
     for ub in bc_steps:
@@ -75,7 +75,7 @@ def gradient(mesh, csr, params, bc_mask, ck, u_gt, w, lin_rtol=1e-12, lin_max_it
     """dJ/dtheta [7] (sum over elements; per-element parameters: the element
     gradients are summed per step into g_elem_total) and the multipliers lambda^n."""
     dev = ck.h[0].device
-    solver = solver or fem.Solver(csr, dev, precond=fem.PC_AMG, bc_mask=bc_mask)
+    solver = solver or fem.Solver(csr, dev, precond=fem.PC_AMG, method="fgmres", bc_mask=bc_mask)
     fwd = fem.Forward(mesh, csr, fem.FP64)
     adj = fem.HistoryAdjoint(mesh)
     bc = bc_mask.bool().view(-1)

@@ -32,6 +32,7 @@ namespace {
 constexpr int kLanes = 32;                       // lanes per node of the block products
 constexpr int kDenseMax = 3 * FEM_AMG_DENSE_NODES;  // dofs of a dense coarsest level
 constexpr double kStall = 0.85;                  // stop when a level keeps more nodes than this
+constexpr int kPostGrid = 2048;                  // workgroup cap of the persistent level products
 
 struct Level {
     int32_t n = 0;           // nodes
@@ -53,6 +54,12 @@ struct Level {
     int32_t* gdst = nullptr;   // [nb] entry offset of the coarse block's (0,0) entry
     uint16_t* gdlen = nullptr; // [nb] row length of the coarse block's rows
     uint8_t* gfix = nullptr;   // [nb] bit a: identity on row a (diagonal block, no free fine dof)
+    // K-cycle steps on this level (levels >= 1)
+    double* kc1 = nullptr;     // [3 n] first cycle result c1
+    double* kv1 = nullptr;     // [3 n] A c1
+    double* kpart = nullptr;   // [3 kPostGrid] workgroup partial sums
+    double* ksc = nullptr;     // [4] (v1, v1), a1, then the coefficients e1, e2 of c1 and c2
+    uint32_t* ktick = nullptr; // [1] finished workgroups of the product (0 between launches)
 };
 
 }  // namespace
@@ -74,6 +81,8 @@ struct fem_amg {
     const void* K = nullptr;   // values of the last fem_amg_update
     fem_precision prec = FEM_FP64;
     bool updated = false;
+    fem_amg_cycle cycle = FEM_AMG_CYCLE_V;
+    int32_t kmin = 0;          // K-cycle steps on levels of at least this many nodes
 };
 
 namespace fem {
@@ -296,7 +305,6 @@ __global__ __launch_bounds__(256) void smooth0_kernel(int32_t n, const double* _
 // Second sweep: out = x + M (b - A x); 32 lanes per node over a fixed grid
 // of at most kPostGrid workgroups (8 nodes per workgroup and round),
 // butterfly over the lanes in a fixed order
-constexpr int kPostGrid = 2048;
 
 template <typename RV>
 __global__ __launch_bounds__(256) void post_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
@@ -400,8 +408,7 @@ __global__ __launch_bounds__(256) void resid_restrict_kernel(const int32_t* __re
 // latency, not by work): on entry level t holds its right-hand side b and
 // first sweep x = M b; on exit its post-smoothed iterate y (or, when level t
 // is the dense coarsest level, x = Cinv b).  Phases are separated by
-// workgroup barriers; the products take 32 lanes per node as on the large
-// levels.
+// workgroup barriers.
 constexpr int kTailNodes = 512;
 
 struct TailLevel {
@@ -423,16 +430,20 @@ struct TailArgs {
     TailLevel L[FEM_AMG_MAX_LEVELS];
 };
 
-// POST = 0: r = b - A x;  POST = 1: y = x + M (b - A x); 32 lanes per node.
+// POST = 0: r = b - A x;  POST = 1: y = x + M (b - A x); kTailLanes lanes
+// per node (coarse rows hold some 15 to 25 blocks: 128 nodes per round
+// keeps the dependent-load rounds few)
+constexpr int kTailLanes = 8;
+
 template <int POST>
 __device__ inline void tail_sweep(const TailLevel& F, int tid) {
-    const int g = tid >> 5, l = tid & (kLanes - 1);
-    for (int64_t base = 0; base < F.n; base += 1024 / kLanes) {
+    const int g = tid / kTailLanes, l = tid & (kTailLanes - 1);
+    for (int64_t base = 0; base < F.n; base += 1024 / kTailLanes) {
         const int64_t I = base + g;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         if (I < F.n) {
             const int32_t bs = F.row_ptr[3 * I], len = F.row_ptr[3 * I + 1] - bs, deg = len / 3;
-            for (int32_t k = l; k < deg; k += kLanes) {
+            for (int32_t k = l; k < deg; k += kTailLanes) {
                 const int64_t J = F.ncol[bs / 9 + k];
                 const double x0 = F.x[3 * J], x1 = F.x[3 * J + 1], x2 = F.x[3 * J + 2];
                 const float* v = F.vals + bs + 3 * k;
@@ -442,10 +453,10 @@ __device__ inline void tail_sweep(const TailLevel& F, int tid) {
             }
         }
 #pragma unroll
-        for (int m = 1; m < kLanes; m <<= 1) {
-            s0 += __shfl_xor(s0, m, kLanes);
-            s1 += __shfl_xor(s1, m, kLanes);
-            s2 += __shfl_xor(s2, m, kLanes);
+        for (int m = 1; m < kTailLanes; m <<= 1) {
+            s0 += __shfl_xor(s0, m, kTailLanes);
+            s1 += __shfl_xor(s1, m, kTailLanes);
+            s2 += __shfl_xor(s2, m, kTailLanes);
         }
         if (I < F.n && l < 3) {
             const double r0 = F.b[3 * I] - s0, r1 = F.b[3 * I + 1] - s1, r2 = F.b[3 * I + 2] - s2;
@@ -666,6 +677,136 @@ __global__ __launch_bounds__(256) void power_finish(int32_t n, const double* __r
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < 9 * (int64_t)n) minv[i] *= omega;
     if (i == 0) om[0] = omega;
+}
+
+// ---- K-cycle (recursive Krylov-accelerated cycle): on a coarse level c the
+// coarse-grid correction is not one cycle B_c rc but the minimal-residual
+// combination of two: c1 = B_c rc, v1 = A_c c1, a1 = (v1, rc) / (v1, v1),
+// r2 = rc - a1 v1, c2 = B_c r2, v2 = A_c c2, g = (v2, v1) / (v1, v1) and
+// a2 = (v2, r2) / ((v2, v2) - g (v2, v1)); the correction
+// (a1 - a2 g) c1 + a2 c2 minimises |rc - A_c e| over e in span{c1, c2}
+// (two steps of GCR; (v1, r2) = 0 gives the short forms).  The cycle then
+// varies from one application to the next, so the outer Krylov method must
+// be a flexible one.
+
+// STEP 1: v1 = A c (stored), sums (v1, b) and (v1, v1) -> ksc[0] = (v1, v1),
+// ksc[1] = a1.  STEP 2: v2 = A c (not stored), sums (v2, v1), (v2, v2),
+// (v2, b) -> ksc[2] = a1 - a2 g, ksc[3] = a2.  Rows by 32 lanes as in
+// post_kernel; workgroup sums to part, and the last workgroup to finish
+// (ticket) adds them in workgroup order and resets the ticket.
+template <int STEP>
+__global__ __launch_bounds__(256) void kstep_product(int32_t n, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ ncol, const float* __restrict__ val,
+                                                     const double* __restrict__ c, const double* __restrict__ b,
+                                                     double* __restrict__ v1, double* __restrict__ part,
+                                                     uint32_t* __restrict__ ticket, double* __restrict__ ksc,
+                                                     const int32_t* __restrict__ fl) {
+    if (stopped(fl)) return;
+    __shared__ int last;
+    const int l = (int)(threadIdx.x & (kLanes - 1));
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 8; base < n; base += (int64_t)gridDim.x * 8) {
+        const int64_t I = base + (threadIdx.x >> 5);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        if (I < n) {
+            const int32_t bs = row_ptr[3 * I], len = row_ptr[3 * I + 1] - bs, deg = len / 3;
+            const int32_t* __restrict__ nc = ncol + bs / 9;
+            for (int32_t k = l; k < deg; k += kLanes) {
+                const int64_t J = nc[k];
+                const double x0 = c[3 * J], x1 = c[3 * J + 1], x2 = c[3 * J + 2];
+                const float* __restrict__ v = val + bs + 3 * k;
+                s0 += (double)v[0] * x0 + (double)v[1] * x1 + (double)v[2] * x2;
+                s1 += (double)v[len] * x0 + (double)v[len + 1] * x1 + (double)v[len + 2] * x2;
+                s2 += (double)v[2 * len] * x0 + (double)v[2 * len + 1] * x1 + (double)v[2 * len + 2] * x2;
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < kLanes; m <<= 1) {
+            s0 += __shfl_xor(s0, m, kLanes);
+            s1 += __shfl_xor(s1, m, kLanes);
+            s2 += __shfl_xor(s2, m, kLanes);
+        }
+        if (I < n && l < 3) {
+            const int64_t k = 3 * I + l;
+            const double va = l == 0 ? s0 : (l == 1 ? s1 : s2);
+            if (STEP == 1) {
+                v1[k] = va;
+                d0 += va * b[k];
+                d1 += va * va;
+            } else {
+                d0 += va * v1[k];
+                d1 += va * va;
+                d2 += va * b[k];
+            }
+        }
+    }
+    const double t0 = block_sum256(d0), t1 = block_sum256(d1), t2 = STEP == 2 ? block_sum256(d2) : 0.0;
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = t0;
+        part[3 * blockIdx.x + 1] = t1;
+        part[3 * blockIdx.x + 2] = t2;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    for (int k = (int)threadIdx.x; k < (int)gridDim.x; k += 256) {
+        q0 += part[3 * k];
+        q1 += part[3 * k + 1];
+        q2 += part[3 * k + 2];
+    }
+    const double u0 = block_sum256(q0), u1 = block_sum256(q1), u2 = block_sum256(q2);
+    if (threadIdx.x == 0) {
+        *ticket = 0u;
+        if (STEP == 1) {
+            ksc[0] = u1;
+            ksc[1] = u1 > 0.0 ? u0 / u1 : 0.0;
+        } else {
+            const double vv1 = ksc[0], a1 = ksc[1];
+            const double g = vv1 > 0.0 ? u0 / vv1 : 0.0;
+            const double den = u1 - g * u0;
+            const double a2 = den > 0.0 ? u2 / den : 0.0;
+            ksc[2] = a1 - a2 * g;
+            ksc[3] = a2;
+        }
+    }
+}
+
+// b -= a1 v1 (b becomes r2) and the first sweep x = M b, one thread per node
+__global__ __launch_bounds__(256) void kstep_update(int32_t n, const double* __restrict__ v1,
+                                                    const double* __restrict__ ksc, const double* __restrict__ minv,
+                                                    double* __restrict__ b, double* __restrict__ x,
+                                                    const int32_t* __restrict__ fl) {
+    if (stopped(fl)) return;
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= n) return;
+    const double a1 = ksc[1];
+    double r[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r[a] = b[3 * I + a] - a1 * v1[3 * I + a];
+        b[3 * I + a] = r[a];
+    }
+    const double* m = minv + 9 * I;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[3 * I + a] = m[3 * a] * r[0] + m[3 * a + 1] * r[1] + m[3 * a + 2] * r[2];
+}
+
+// x_fine += P (e1 c1 + e2 c2) (masked), e1, e2 = ksc[2], ksc[3] of the coarse level
+__global__ __launch_bounds__(256) void kprolong_kernel(int32_t n, const int32_t* __restrict__ agg,
+                                                       const uint8_t* __restrict__ fmask, const double* __restrict__ c1,
+                                                       const double* __restrict__ c2, const double* __restrict__ ksc,
+                                                       double* __restrict__ x, const int32_t* __restrict__ fl) {
+    if (stopped(fl)) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double e1 = ksc[2], e2 = ksc[3];
+    const int64_t C = agg[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (fmask[3 * i + a]) x[3 * i + a] += e1 * c1[3 * C + a] + e2 * c2[3 * C + a];
 }
 
 inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + 255) / 256); }
@@ -990,59 +1131,42 @@ int amg_update(fem_amg* h, const void* K, fem_precision prec, hipStream_t s) {
 
 const double* amg_smoother0(const fem_amg* h) { return h->L[0].minv; }
 double* amg_level0_x(fem_amg* h) { return h->L[0].x; }
+fem_amg_cycle amg_cycle_type(const fem_amg* h) { return h->cycle; }
 bool amg_matches(const fem_amg* h, const fem_csr* csr) {
     return h && csr && h->n_rows == csr->n_rows && h->nnz == csr->nnz && h->L[0].row_ptr == csr->row_ptr;
 }
 
-hipError_t amg_vcycle(fem_amg* h, const double* b, double* z, bool presmoothed, const int32_t* fl, hipStream_t s) {
+namespace {
+
+// first level of the single-workgroup tail (nl if no level is small enough)
+int tail_start(const fem_amg* h) {
+    for (int l = 1; l < h->nl; ++l)
+        if (h->L[l].n <= kTailNodes) return l;
+    return h->nl;
+}
+
+// level c takes the two K-cycle steps: a level above the tail, not the
+// coarsest, with at least kmin nodes, in a K-cycle hierarchy
+bool krylov_level(const fem_amg* h, int c, int t) {
+    return h->cycle == FEM_AMG_CYCLE_K && c >= 1 && c < t && c < h->nl - 1 && h->L[c].n >= h->kmin;
+}
+
+// The cycle from level l down: on entry bl is level l's right-hand side and
+// L[l].x its first sweep M_l bl; the result is written to out (levels above
+// the tail; at the tail start and below, the tail's own buffers) and
+// returned.
+const double* cycle_from(fem_amg* h, int l, const double* bl, double* out, int t, const int32_t* fl, hipStream_t s) {
     Level* L = h->L;
     const int nl = h->nl;
-    if (nl == 1 && h->dense) {
-        hipLaunchKernelGGL(dense_apply_kernel, dim3(1), dim3(256), 0, s, L[0].n, nullptr, nullptr, nullptr, b,
-                           h->cinv, z, fl);
-        return hipGetLastError();
-    }
-    if (!presmoothed)
-        hipLaunchKernelGGL(smooth0_kernel, dim3(blocks_for(L[0].n)), dim3(256), 0, s, L[0].n, L[0].minv, b, L[0].x,
-                           fl);
-    if (nl == 1) {  // one level, not inverted: the two sweeps
-        level_post(h, 0, L[0].x, b, z, fl, s);
-        return hipGetLastError();
-    }
-    // levels [t, nl) run in the tail kernel; t = nl if no level is small enough
-    int t = nl;
-    for (int l = 1; l < nl; ++l)
-        if (L[l].n <= kTailNodes) {
-            t = l;
-            break;
-        }
-    const int down = std::min(t, nl - 1);  // fused residual-restriction steps 0 -> 1, ..., down - 1 -> down
-    const double* bl = b;
-    for (int l = 0; l < down; ++l) {
-        Level& c = L[l + 1];
-        if (l > 0)
-            hipLaunchKernelGGL(resid_restrict_kernel<float>, dim3(c.n), dim3(256), 0, s, c.mptr, c.mem, L[l].mask,
-                               L[l].row_ptr, L[l].ncol, (const float*)L[l].vals, L[l].x, bl, c.minv, c.b, c.x, fl);
-        else if (h->prec == FEM_FP64)
-            hipLaunchKernelGGL(resid_restrict_kernel<double>, dim3(c.n), dim3(256), 0, s, c.mptr, c.mem, L[0].mask,
-                               L[0].row_ptr, L[0].ncol, static_cast<const double*>(h->K), L[0].x, bl, c.minv, c.b,
-                               c.x, fl);
-        else
-            hipLaunchKernelGGL(resid_restrict_kernel<float>, dim3(c.n), dim3(256), 0, s, c.mptr, c.mem, L[0].mask,
-                               L[0].row_ptr, L[0].ncol, static_cast<const float*>(h->K), L[0].x, bl, c.minv, c.b,
-                               c.x, fl);
-        bl = c.b;
-    }
-    const double* yc;
-    if (t < nl) {
+    if (l >= t) {  // levels t, ..., nl - 1 in one workgroup
         TailArgs A;
         A.nlv = nl - t;
         A.dense = h->dense ? 1 : 0;
         A.nd = h->nd;
         A.cinv = h->cinv;
-        for (int l = t; l < nl; ++l) {
-            const Level& S = L[l];
-            TailLevel& T = A.L[l - t];
+        for (int k = t; k < nl; ++k) {
+            const Level& S = L[k];
+            TailLevel& T = A.L[k - t];
             T.n = S.n;
             T.row_ptr = S.row_ptr;
             T.ncol = S.ncol;
@@ -1058,18 +1182,67 @@ hipError_t amg_vcycle(fem_amg* h, const double* b, double* z, bool presmoothed, 
             T.mem = S.mem;
         }
         hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, A, fl);
-        yc = (t == nl - 1 && h->dense) ? L[t].x : L[t].y;
-    } else {  // coarsest level not inverted and too large for the tail: the second sweep
-        level_post(h, nl - 1, L[nl - 1].x, L[nl - 1].b, L[nl - 1].y, fl, s);
-        yc = L[nl - 1].y;
+        return (t == nl - 1 && h->dense) ? L[t].x : L[t].y;
     }
-    for (int l = down - 1; l >= 0; --l) {
-        hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(L[l].n)), dim3(256), 0, s, L[l].n, L[l + 1].agg, L[l].mask,
-                           yc, L[l].x, fl);
-        double* out = l == 0 ? z : L[l].y;
-        level_post(h, l, L[l].x, l == 0 ? b : L[l].b, out, fl, s);
-        yc = out;
+    if (l == nl - 1) {  // coarsest level, not inverted and too large for the tail: the second sweep
+        level_post(h, l, L[l].x, bl, out, fl, s);
+        return out;
     }
+    // residual, restriction and the first sweep of level c
+    const int c = l + 1;
+    Level& C = L[c];
+    if (l > 0)
+        hipLaunchKernelGGL(resid_restrict_kernel<float>, dim3(C.n), dim3(256), 0, s, C.mptr, C.mem, L[l].mask,
+                           L[l].row_ptr, L[l].ncol, (const float*)L[l].vals, L[l].x, bl, C.minv, C.b, C.x, fl);
+    else if (h->prec == FEM_FP64)
+        hipLaunchKernelGGL(resid_restrict_kernel<double>, dim3(C.n), dim3(256), 0, s, C.mptr, C.mem, L[0].mask,
+                           L[0].row_ptr, L[0].ncol, static_cast<const double*>(h->K), L[0].x, bl, C.minv, C.b, C.x,
+                           fl);
+    else
+        hipLaunchKernelGGL(resid_restrict_kernel<float>, dim3(C.n), dim3(256), 0, s, C.mptr, C.mem, L[0].mask,
+                           L[0].row_ptr, L[0].ncol, static_cast<const float*>(h->K), L[0].x, bl, C.minv, C.b, C.x,
+                           fl);
+    if (krylov_level(h, c, t)) {
+        const unsigned ng = std::min<unsigned>(kPostGrid, blocks_for((int64_t)C.n * kLanes));
+        cycle_from(h, c, C.b, C.kc1, t, fl, s);
+        hipLaunchKernelGGL(kstep_product<1>, dim3(ng), dim3(256), 0, s, C.n, C.row_ptr, C.ncol,
+                           (const float*)C.vals, (const double*)C.kc1, (const double*)C.b, C.kv1, C.kpart, C.ktick,
+                           C.ksc, fl);
+        hipLaunchKernelGGL(kstep_update, dim3(blocks_for(C.n)), dim3(256), 0, s, C.n, (const double*)C.kv1,
+                           (const double*)C.ksc, (const double*)C.minv, C.b, C.x, fl);
+        cycle_from(h, c, C.b, C.y, t, fl, s);
+        hipLaunchKernelGGL(kstep_product<2>, dim3(ng), dim3(256), 0, s, C.n, C.row_ptr, C.ncol,
+                           (const float*)C.vals, (const double*)C.y, (const double*)C.b, C.kv1, C.kpart, C.ktick,
+                           C.ksc, fl);
+        hipLaunchKernelGGL(kprolong_kernel, dim3(blocks_for(L[l].n)), dim3(256), 0, s, L[l].n, C.agg, L[l].mask,
+                           (const double*)C.kc1, (const double*)C.y, (const double*)C.ksc, L[l].x, fl);
+    } else {
+        const double* yc = cycle_from(h, c, C.b, C.y, t, fl, s);
+        hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(L[l].n)), dim3(256), 0, s, L[l].n, C.agg, L[l].mask, yc,
+                           L[l].x, fl);
+    }
+    level_post(h, l, L[l].x, bl, out, fl, s);
+    return out;
+}
+
+}  // namespace
+
+hipError_t amg_apply_cycle(fem_amg* h, const double* b, double* z, bool presmoothed, const int32_t* fl, hipStream_t s) {
+    Level* L = h->L;
+    const int nl = h->nl;
+    if (nl == 1 && h->dense) {
+        hipLaunchKernelGGL(dense_apply_kernel, dim3(1), dim3(256), 0, s, L[0].n, nullptr, nullptr, nullptr, b,
+                           h->cinv, z, fl);
+        return hipGetLastError();
+    }
+    if (!presmoothed)
+        hipLaunchKernelGGL(smooth0_kernel, dim3(blocks_for(L[0].n)), dim3(256), 0, s, L[0].n, L[0].minv, b, L[0].x,
+                           fl);
+    if (nl == 1) {  // one level, not inverted: the two sweeps
+        level_post(h, 0, L[0].x, b, z, fl, s);
+        return hipGetLastError();
+    }
+    cycle_from(h, 0, b, z, tail_start(h), fl, s);
     return hipGetLastError();
 }
 
@@ -1175,6 +1348,11 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
                 c.take<int32_t>(nb);
                 c.take<uint16_t>(nb);
                 c.take<uint8_t>(nb);
+                c.take<double>(3 * n);
+                c.take<double>(3 * n);
+                c.take<double>(3 * kPostGrid);
+                c.take<double>(4);
+                c.take<uint32_t>(1);
             }
         }
         if (dense) c.take<double>((size_t)9 * H.back().n * H.back().n);
@@ -1249,6 +1427,12 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
             L.gdst = cv.take<int32_t>(nb);
             L.gdlen = cv.take<uint16_t>(nb);
             L.gfix = cv.take<uint8_t>(nb);
+            L.kc1 = cv.take<double>(3 * n);
+            L.kv1 = cv.take<double>(3 * n);
+            L.kpart = cv.take<double>(3 * kPostGrid);
+            L.ksc = cv.take<double>(4);
+            L.ktick = cv.take<uint32_t>(1);
+            if (e == hipSuccess) e = hipMemsetAsync(L.ktick, 0, sizeof(uint32_t), s);
             up(L.agg, hl.agg.data(), nf * 4);
             up(L.mptr, hl.mptr.data(), (n + 1) * 4);
             up(L.mem, hl.mem.data(), nf * 4);
@@ -1322,12 +1506,23 @@ extern "C" int fem_amg_update(fem_amg* amg, const void* K_vals, fem_precision pr
     return amg_update(amg, K_vals, prec, (hipStream_t)stream);
 }
 
+extern "C" int fem_amg_set_cycle(fem_amg* amg, fem_amg_cycle cycle, int32_t k_min_nodes) {
+    clear_error();
+    if (!amg) return set_error(FEM_EINVAL, "fem_amg_set_cycle: handle must not be NULL");
+    if (cycle != FEM_AMG_CYCLE_V && cycle != FEM_AMG_CYCLE_K)
+        return set_error(FEM_EINVAL, "fem_amg_set_cycle: bad cycle type");
+    if (k_min_nodes < 0) return set_error(FEM_EINVAL, "fem_amg_set_cycle: k_min_nodes must be >= 0");
+    amg->cycle = cycle;
+    amg->kmin = k_min_nodes;
+    return FEM_OK;
+}
+
 extern "C" int fem_amg_apply(fem_amg* amg, const double* r, double* z, void* stream) {
     clear_error();
     if (!amg || !r || !z) return set_error(FEM_EINVAL, "fem_amg_apply: handle, r and z must not be NULL");
     if (r == z) return set_error(FEM_EINVAL, "fem_amg_apply: r and z must not alias");
     if (!amg->updated) return set_error(FEM_EINVAL, "fem_amg_apply: fem_amg_update has not been called");
-    FEM_HIP_CHECK(amg_vcycle(amg, r, z, false, nullptr, (hipStream_t)stream));
+    FEM_HIP_CHECK(amg_apply_cycle(amg, r, z, false, nullptr, (hipStream_t)stream));
     return FEM_OK;
 }
 

@@ -81,15 +81,17 @@ hipError_t reduce_g_uniform(const double* g_elem, int64_t n_elems, const int64_t
                             double* g_uniform, hipStream_t s);
 
 // Aggregation multigrid (amg.hip) as fem_solve_amg drives it: numeric
-// set-up for K, then one V-cycle z = M b per call on stream s.  With
+// set-up for K, then one cycle z = M b per call on stream s (a V-cycle, or
+// a K-cycle, which varies between calls: amg_cycle_type).  With
 // presmoothed, amg_level0_x already holds M_0 b (M_0 = amg_smoother0, the
 // finest level's 3x3 smoother blocks), as the solver's fused update kernels
 // write it.  Every cycle kernel returns at once when *stop is nonzero (stop
 // may be NULL).
 int amg_update(fem_amg* h, const void* K, fem_precision prec, hipStream_t s);
-hipError_t amg_vcycle(fem_amg* h, const double* b, double* z, bool presmoothed, const int32_t* stop, hipStream_t s);
+hipError_t amg_apply_cycle(fem_amg* h, const double* b, double* z, bool presmoothed, const int32_t* stop, hipStream_t s);
 const double* amg_smoother0(const fem_amg* h);
 double* amg_level0_x(fem_amg* h);
 bool amg_matches(const fem_amg* h, const fem_csr* csr);
+fem_amg_cycle amg_cycle_type(const fem_amg* h);
 
 }  // namespace fem

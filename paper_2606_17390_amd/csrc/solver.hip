@@ -98,6 +98,7 @@ constexpr int kGrid = 1024;      // blocks of the fused vector kernels (fixed: r
 constexpr int kSpmvGrid = 2048;  // blocks of the fused matrix-vector products
 constexpr int kParts = kSpmvGrid > kGrid ? kSpmvGrid : kGrid;
 constexpr int kChunk = 32;       // iterations enqueued between two reads of the stop flag
+constexpr int kChunkAmg = 4;     // the same with a multigrid cycle per iteration
 
 // Scalars of the iteration (device memory) and integer flags.
 enum { S_RHO, S_RHO_NEW, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_RES, S_COUNT };
@@ -568,7 +569,9 @@ __global__ __launch_bounds__(256) void dot_kernel(int64_t n, const double* __res
 // Arnoldi by classical Gram-Schmidt with fused dot products (fixed-order
 // two-stage sums), Givens rotations of the Hessenberg column on the device,
 // the solution formed at the end of each cycle and the true residual
-// recomputed for the restart.  Inner kernels return at once when the cycle
+// recomputed for the restart.  The flexible variant (FGMRES, Saad 1993)
+// keeps z_j = M v_j of every step and forms x += Z y, so M may change from
+// step to step (a K-cycle).  Inner kernels return at once when the cycle
 // has ended (F_CYC, passed as the flag pointer), end-of-cycle kernels when
 // it had no step (F_J = 0).
 constexpr int kGmresM = FEM_GMRES_RESTART;
@@ -757,15 +760,17 @@ __global__ __launch_bounds__(256) void gm_start(const double* __restrict__ part0
 }
 
 struct GmresWs {
-    double *V, *H, *cs, *sn, *g, *y, *hpart;
+    double *V, *Z, *H, *cs, *sn, *g, *y, *hpart;
     int64_t ldv;
 };
 
+// flexible: also the preconditioned vectors z_j = M_j v_j (FGMRES)
 template <typename C>
-void carve_gmres(C& c, int32_t n, GmresWs* w) {
+void carve_gmres(C& c, int32_t n, bool flexible, GmresWs* w) {
     GmresWs o;
     o.ldv = ((int64_t)n + 31) / 32 * 32;
     o.V = c.template take<double>((size_t)o.ldv * (kGmresM + 1));
+    o.Z = flexible ? c.template take<double>((size_t)o.ldv * kGmresM) : nullptr;
     o.H = c.template take<double>((size_t)(kGmresM + 1) * kGmresM);
     o.cs = c.template take<double>(kGmresM + 1);
     o.sn = c.template take<double>(kGmresM + 1);
@@ -853,7 +858,8 @@ extern "C" size_t fem_solver_workspace_bytes_method(int32_t n_rows, int64_t nnz,
     if (n_rows < 0 || nnz < 0) return 0;
     CountAdapterS c;
     carve_solver(c, n_rows, nnz, (SolverWs*)nullptr);
-    if (method == FEM_KRYLOV_GMRES) carve_gmres(c, n_rows, (GmresWs*)nullptr);
+    if (method == FEM_KRYLOV_GMRES || method == FEM_KRYLOV_FGMRES)
+        carve_gmres(c, n_rows, method == FEM_KRYLOV_FGMRES, (GmresWs*)nullptr);
     return c.cnt.used + 256;
 }
 
@@ -904,8 +910,12 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
     if (prec != FEM_FP64 && prec != FEM_FP32_MIXED) return set_error(FEM_EINVAL, "%s: bad precision", who);
     if (!amg && pc != FEM_PC_JACOBI && pc != FEM_PC_BLOCK_JACOBI)
         return set_error(FEM_EINVAL, "%s: bad preconditioner", who);
-    if (method != FEM_KRYLOV_BICGSTAB && method != FEM_KRYLOV_CG && method != FEM_KRYLOV_GMRES)
+    if (method != FEM_KRYLOV_BICGSTAB && method != FEM_KRYLOV_CG && method != FEM_KRYLOV_GMRES &&
+        method != FEM_KRYLOV_FGMRES)
         return set_error(FEM_EINVAL, "%s: bad Krylov method", who);
+    if (amg && amg_cycle_type(amg) == FEM_AMG_CYCLE_K && method != FEM_KRYLOV_FGMRES)
+        return set_error(FEM_EINVAL, "%s: a K-cycle preconditioner varies between applications and needs the "
+                                     "flexible method FEM_KRYLOV_FGMRES", who);
     if (max_iter < 0 || !(rtol >= 0.0)) return set_error(FEM_EINVAL, "%s: max_iter >= 0 and rtol >= 0", who);
     const int32_t n = csr->n_rows, nn = n / 3;
     if (iters) *iters = 0;
@@ -943,13 +953,14 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
     }
     hipLaunchKernelGGL(reset_flags, dim3(1), dim3(1), 0, s, w.fl);
     spmv_dot<0>(csr, w.ncol, K_vals, prec, x, w.t, nullptr, nullptr, nullptr, nullptr, s);
-    if (method == FEM_KRYLOV_GMRES) {
+    if (method == FEM_KRYLOV_GMRES || method == FEM_KRYLOV_FGMRES) {
+        const bool flex = method == FEM_KRYLOV_FGMRES;
         GmresWs g;
-        carve_gmres(c, n, &g);
+        carve_gmres(c, n, flex, &g);
         // M v: with multigrid the normalisation writes the first sweep M_0 v
-        // into the cycle's finest iterate and the cycle writes M v to ph;
-        // with block Jacobi the normalisation writes M v to ph itself
-        double* m0 = amg ? mx : w.ph;
+        // into the cycle's finest iterate and the cycle writes M v to ph (to
+        // z_j when flexible); with block Jacobi the normalisation writes M v
+        // there itself
         const int32_t* cyc = w.fl + F_CYC;
         const int32_t* stp = w.fl + F_STOP;
         hipLaunchKernelGGL(gm_residual, dim3(kGrid), dim3(256), 0, s, (int64_t)n, b, w.t, g.V, w.part0, w.part1,
@@ -969,23 +980,38 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
             for (int j = 0; j < kGmresM; ++j) {
                 double* vj = g.V + (int64_t)j * g.ldv;
                 double* vn = g.V + (int64_t)(j + 1) * g.ldv;
-                hipLaunchKernelGGL(gm_normalize, dim3(kGrid), dim3(256), 0, s, nn, vj, minv, m0, w.sc, cyc);
-                if (amg) FEM_HIP_CHECK(amg_vcycle(amg, vj, w.ph, true, cyc, s));
-                spmv_dot<0>(csr, w.ncol, K_vals, prec, w.ph, vn, nullptr, nullptr, nullptr, cyc, s);
+                double* zj = flex ? g.Z + (int64_t)j * g.ldv : w.ph;
+                hipLaunchKernelGGL(gm_normalize, dim3(kGrid), dim3(256), 0, s, nn, vj, minv, amg ? mx : zj, w.sc,
+                                   cyc);
+                if (amg) FEM_HIP_CHECK(amg_apply_cycle(amg, vj, zj, true, cyc, s));
+                spmv_dot<0>(csr, w.ncol, K_vals, prec, zj, vn, nullptr, nullptr, nullptr, cyc, s);
                 hipLaunchKernelGGL(gm_dots, dim3(kGrid), dim3(256), 0, s, (int64_t)n, j, g.V, g.ldv, vn, g.hpart, cyc);
                 hipLaunchKernelGGL(gm_hreduce, dim3(j + 1), dim3(256), 0, s, g.hpart, j, g.H, cyc);
                 hipLaunchKernelGGL(gm_update, dim3(kGrid), dim3(256), 0, s, (int64_t)n, j, g.V, g.ldv, g.H, vn,
                                    w.part0, cyc);
                 hipLaunchKernelGGL(gm_finish, dim3(1), dim3(256), 0, s, w.part0, j, g.H, g.cs, g.sn, g.g, w.sc, w.fl,
                                    rtol, max_iter);
+                // a multigrid step costs far more than a stream synchronisation:
+                // stop launching once the cycle has ended
+                if (amg) {
+                    FEM_HIP_CHECK(hipGetLastError());
+                    FEM_HIP_CHECK(read_back());
+                    if (flh[F_CYC]) break;
+                }
             }
-            // x += M (V y); then the true residual of the restart
+            // x += M (V y) (flexible: x += Z y); then the true residual of the restart
             hipLaunchKernelGGL(gm_solve_y, dim3(1), dim3(1), 0, s, g.H, g.g, g.y, w.fl);
-            hipLaunchKernelGGL(gm_combine, dim3(kGrid), dim3(256), 0, s, (int64_t)n, g.V, g.ldv, g.y, w.p, w.fl);
-            if (amg)
-                FEM_HIP_CHECK(amg_vcycle(amg, w.p, w.sh, false, nullptr, s));
-            else
-                hipLaunchKernelGGL(gm_apply_minv, dim3(kGrid), dim3(256), 0, s, nn, minv, w.p, w.sh);
+            if (flex) {
+                hipLaunchKernelGGL(gm_combine, dim3(kGrid), dim3(256), 0, s, (int64_t)n, g.Z, g.ldv, g.y, w.sh,
+                                   w.fl);
+            } else {
+                hipLaunchKernelGGL(gm_combine, dim3(kGrid), dim3(256), 0, s, (int64_t)n, g.V, g.ldv, g.y, w.p,
+                                   w.fl);
+                if (amg)
+                    FEM_HIP_CHECK(amg_apply_cycle(amg, w.p, w.sh, false, nullptr, s));
+                else
+                    hipLaunchKernelGGL(gm_apply_minv, dim3(kGrid), dim3(256), 0, s, nn, minv, w.p, w.sh);
+            }
             hipLaunchKernelGGL(gm_addx, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.sh, x);
             spmv_dot<0>(csr, w.ncol, K_vals, prec, x, w.t, nullptr, nullptr, nullptr, stp, s);
             hipLaunchKernelGGL(gm_residual, dim3(kGrid), dim3(256), 0, s, (int64_t)n, b, w.t, g.V, w.part0, w.part1,
@@ -1007,7 +1033,7 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
         // r = b - K x, mx = M_0 r; z (in s) = M r; p = z; (r, z)
         hipLaunchKernelGGL(cg_init, dim3(kGrid), dim3(256), 0, s, nn, b, w.t, minv, w.r, mx, w.p, w.part0, w.part1,
                            w.part2);
-        FEM_HIP_CHECK(amg_vcycle(amg, w.r, w.s, true, w.fl, s));
+        FEM_HIP_CHECK(amg_apply_cycle(amg, w.r, w.s, true, w.fl, s));
         hipLaunchKernelGGL(cg_amg_start, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.s, w.r, w.p, w.part0, w.fl);
         hipLaunchKernelGGL(cg_fin_init, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.part2, w.sc, w.fl, rtol,
                            max_iter);
@@ -1032,14 +1058,14 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
     };
     FEM_HIP_CHECK(read_back());
     while (!fl[F_STOP] && fl[F_ITER] < max_iter) {
-        const int32_t chunk = std::min<int32_t>(kChunk, max_iter - fl[F_ITER]);
+        const int32_t chunk = std::min<int32_t>(amg ? kChunkAmg : kChunk, max_iter - fl[F_ITER]);
         for (int32_t k = 0; cg && k < chunk; ++k) {
             spmv_dot<1>(csr, w.ncol, K_vals, prec, w.p, w.v, w.p, w.part0, nullptr, w.fl, s);
             hipLaunchKernelGGL(cg_fin_alpha, dim3(1), dim3(256), 0, s, w.part0, w.sc, w.fl);
             hipLaunchKernelGGL(cg_update, dim3(kGrid), dim3(256), 0, s, nn, w.p, w.v, minv, x, w.r, amg ? mx : w.s,
                                w.part0, w.part1, w.sc, w.fl);
             if (amg) {
-                FEM_HIP_CHECK(amg_vcycle(amg, w.r, w.s, true, w.fl, s));
+                FEM_HIP_CHECK(amg_apply_cycle(amg, w.r, w.s, true, w.fl, s));
                 hipLaunchKernelGGL(dot_kernel, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.r, w.s, w.part0, w.fl);
             }
             hipLaunchKernelGGL(cg_fin_beta, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl, rtol, max_iter);
@@ -1048,12 +1074,12 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
         for (int32_t k = 0; !cg && k < chunk; ++k) {
             hipLaunchKernelGGL(update_p, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, minv, w.p, amg ? mx : w.ph, w.sc,
                                w.fl);
-            if (amg) FEM_HIP_CHECK(amg_vcycle(amg, w.p, w.ph, true, w.fl, s));
+            if (amg) FEM_HIP_CHECK(amg_apply_cycle(amg, w.p, w.ph, true, w.fl, s));
             spmv_dot<1>(csr, w.ncol, K_vals, prec, w.ph, w.v, w.rh, w.part0, nullptr, w.fl, s);
             hipLaunchKernelGGL(fin_alpha, dim3(1), dim3(256), 0, s, w.part0, w.sc, w.fl);
             hipLaunchKernelGGL(update_s, dim3(kGrid), dim3(256), 0, s, nn, w.r, w.v, minv, w.s, amg ? mx : w.sh, w.sc,
                                w.fl);
-            if (amg) FEM_HIP_CHECK(amg_vcycle(amg, w.s, w.sh, true, w.fl, s));
+            if (amg) FEM_HIP_CHECK(amg_apply_cycle(amg, w.s, w.sh, true, w.fl, s));
             spmv_dot<2>(csr, w.ncol, K_vals, prec, w.sh, w.t, w.s, w.part0, w.part1, w.fl, s);
             hipLaunchKernelGGL(fin_omega, dim3(1), dim3(256), 0, s, w.part0, w.part1, w.sc, w.fl);
             hipLaunchKernelGGL(update_x, dim3(kGrid), dim3(256), 0, s, (int64_t)n, w.ph, w.sh, w.s, w.t, w.rh, x, w.r,

@@ -60,7 +60,7 @@ EXPORTS = ("fem_version", "fem_last_error", "fem_set_launch", "fem_get_launch", 
            "fem_solver_workspace_bytes_method", "fem_csr_spmv", "fem_solve",
            "fem_csr_transpose", "fem_history_adjoint_workspace_bytes", "fem_history_adjoint", "fem_amg_create",
            "fem_amg_update", "fem_amg_apply", "fem_amg_info", "fem_amg_aggregates", "fem_amg_destroy",
-           "fem_solve_amg", "fem_amg_plan_host")
+           "fem_solve_amg", "fem_amg_plan_host", "fem_amg_set_cycle")
 
 
 def lib():
@@ -113,6 +113,7 @@ def lib():
     L.fem_amg_aggregates.argtypes = [_c_p, _c_i32, _c_p]
     L.fem_amg_plan_host.argtypes = [_c_i32, _c_p, _c_p, _c_p, _c_p, ctypes.POINTER(_c_i32), _c_p, _c_p, _c_p]
     L.fem_amg_destroy.argtypes = [_c_p]
+    L.fem_amg_set_cycle.argtypes = [_c_p, ctypes.c_int, _c_i32]
     L.fem_solve_amg.argtypes = [ctypes.POINTER(FemCsr), _c_p, ctypes.c_int, ctypes.c_int, _c_p, _c_p, _c_p,
                                 _c_i32, ctypes.c_double,
                                 ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double), _c_p, _c_sz, _c_p]
@@ -576,7 +577,19 @@ def csr_spmv(csr, K, x, y=None, stream=None):
 
 
 PC_JACOBI, PC_BLOCK_JACOBI, PC_AMG = 0, 1, 2
-KRYLOV = {"bicgstab": 0, "cg": 1, "gmres": 2}
+KRYLOV = {"bicgstab": 0, "cg": 1, "gmres": 2, "fgmres": 3}
+AMG_CYCLE = {"v": 0, "k": 1}
+
+
+def default_krylov(precond, fbar):
+    """The drivers' Krylov method: FGMRES (with the multigrid K-cycle) under
+    the multigrid, else BiCGSTAB for the F-bar tangent and CG for the
+    plain one (symmetric on the free dofs)."""
+    if int(precond) == PC_AMG:
+        return "fgmres"
+    return "bicgstab" if fbar else "cg"
+# levels of at least this many nodes take the K-cycle's two Krylov steps
+AMG_K_MIN_NODES = 0
 AMG_MAX_LEVELS = 12
 
 
@@ -584,7 +597,7 @@ class AMG:
     """Aggregation multigrid hierarchy of fem_amg_create for pattern csr,
     aggregated from the block norms of K; bc_mask (device [n_rows] uint8 or
     bool, nonzero on constrained dofs) or None.  update(K) sets the numeric
-    operators, apply(r) is one V-cycle."""
+    operators, apply(r) is one cycle (a V-cycle unless set_cycle("k"))."""
 
     def __init__(self, csr, K, bc_mask=None, stream=None):
         self.csr = csr
@@ -596,6 +609,12 @@ class AMG:
     def update(self, K, stream=None):
         self.K = K
         _check("fem_amg_update", lib().fem_amg_update(self.h, _ptr(K), _kprec(K), _stream(stream)))
+
+    def set_cycle(self, cycle="v", k_min_nodes=None):
+        """"v" or "k" (the K-cycle on levels of at least k_min_nodes nodes)"""
+        kmin = AMG_K_MIN_NODES if k_min_nodes is None else int(k_min_nodes)
+        _check("fem_amg_set_cycle", lib().fem_amg_set_cycle(self.h, AMG_CYCLE[cycle], kmin))
+        self.cycle = cycle
 
     def apply(self, r, z=None, stream=None):
         if z is None:
@@ -668,10 +687,14 @@ class Solver:
     that K (bc_mask: the constrained dofs, as for fem_residual_tangent) and
     its numeric operators are rebuilt for each K."""
 
-    def __init__(self, csr, device="cuda", precond=PC_BLOCK_JACOBI, method="bicgstab", bc_mask=None):
+    def __init__(self, csr, device="cuda", precond=PC_BLOCK_JACOBI, method="bicgstab", bc_mask=None, cycle=None,
+                 k_min_nodes=None):
         self.csr = csr
         self.precond = int(precond)
         self.method = KRYLOV[method]
+        # multigrid cycle: the K-cycle with the flexible method, else the V-cycle
+        self.cycle = cycle if cycle is not None else ("k" if method == "fgmres" else "v")
+        self.k_min_nodes = k_min_nodes
         self.device = device
         self.ws_bytes = lib().fem_solver_workspace_bytes_method(csr.n_rows, csr.nnz, self.method)
         self.ws = _ws(self.ws_bytes, device)
@@ -679,9 +702,11 @@ class Solver:
         self.amg = None
 
     def solve(self, K, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True, precond=None, method=None):
-        """Solve K x = b (method "bicgstab", or "cg" for a tangent symmetric
-        on the free dofs; preconditioner PC_BLOCK_JACOBI, the 3x3 node blocks,
-        unless given); returns (x, iterations, relative residual)."""
+        """Solve K x = b (method "bicgstab", "gmres", "fgmres", or "cg" for
+        a tangent symmetric on the free dofs; preconditioner PC_BLOCK_JACOBI,
+        the 3x3 node blocks, unless given; with PC_AMG the K-cycle under
+        "fgmres" unless the solver was made with cycle="v", else the
+        V-cycle); returns (x, iterations, relative residual)."""
         if x is None:
             x = torch.zeros(self.csr.n_rows, dtype=torch.float64, device=b.device)
         it = _c_i32(0)
@@ -695,6 +720,9 @@ class Solver:
         if pc == PC_AMG:
             if self.amg is None:
                 self.amg = AMG(self.csr, K, self.bc_mask, stream)
+            cyc = self.cycle if mt == KRYLOV["fgmres"] else "v"
+            if getattr(self.amg, "cycle", "v") != cyc or cyc == "k":
+                self.amg.set_cycle(cyc, self.k_min_nodes)
             fn = "fem_solve_amg"
             rc = lib().fem_solve_amg(ctypes.byref(self.csr.c()), _ptr(K), _kprec(K), mt, self.amg.h, _ptr(b), _ptr(x),
                                      int(max_iter), float(rtol), ctypes.byref(it), ctypes.byref(res), _ptr(self.ws),

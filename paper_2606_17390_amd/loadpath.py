@@ -16,10 +16,12 @@ with the automatic stepping of Sec. 2.2.5:
 * convergence: ||R|| <= ftol f_ref, f_ref the largest norm of the reactions
   (the unconstrained residual on the constrained dofs) met so far, or of the
   first increment's starting residual before any reaction exists;
-* linear solves by conjugate gradients where the tangent is symmetric (every
-  model but F-bar; BiCGSTAB for F-bar, and where CG meets a direction of
-  non-positive curvature), to the Eisenstat-Walker tolerance of newton.py (floor
-  lin_rtol) unless forcing is None (then lin_rtol throughout); the linear
+* linear solves (krylov="auto") by flexible GMRES with the multigrid
+  K-cycle, or with block Jacobi by conjugate gradients where the tangent is
+  symmetric (every model but F-bar; BiCGSTAB for F-bar, and where CG meets a
+  direction of non-positive curvature), to the Eisenstat-Walker tolerance of
+  newton.py (floor lin_rtol) unless forcing is None (then lin_rtol
+  throughout); the linear
   step of the tangent start, or without it the first solve of an increment
   with no extrapolated start, goes to first_eta, since that direction
   carries the whole boundary increment; preconditioner: the aggregation
@@ -79,7 +81,7 @@ def solve(mesh, csr, params, bc_mask, u1, hist0, prec=fem.FP64_K32, dt0=1e-3, dt
     bc = bc_mask.bool().view(-1)
     out = fem.Forward(mesh, csr, prec)
     if krylov == "auto":
-        krylov = "bicgstab" if params.model & fem.MODEL_FBAR else "cg"
+        krylov = fem.default_krylov(precond, params.model & fem.MODEL_FBAR)
     solver = fem.Solver(csr, dev, precond=precond, method=krylov, bc_mask=bc_mask)
     d = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
     d_prev, dt_prev = None, None

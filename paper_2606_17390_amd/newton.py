@@ -43,15 +43,15 @@ def solve_step(mesh, csr, params, d, hist_n, bc_mask, prec=fem.FP64, tol=1e-10, 
     iterations.  Returns (hist_np1, iterations, list of
     ||R||).  Raises RuntimeError if the tolerance is not reached in max_it
     iterations, a linear solve fails or ||R|| is not finite.  solver: a
-    fem.Solver of the pattern (default BiCGSTAB preconditioned by the
-    aggregation multigrid built for bc_mask).  A list passed
+    fem.Solver of the pattern (default flexible GMRES preconditioned by the
+    aggregation multigrid's K-cycle, built for bc_mask).  A list passed
     as trace receives one (linear iterations, linear relative residual, step
     length, seconds in the linear solve, linear tolerance) tuple per Newton
     iteration."""
     if out is None:
         out = fem.Forward(mesh, csr, prec)
     if solver is None:
-        solver = fem.Solver(csr, d.device, precond=fem.PC_AMG, bc_mask=bc_mask)
+        solver = fem.Solver(csr, d.device, precond=fem.PC_AMG, method="fgmres", bc_mask=bc_mask)
     flat = d.view(-1)
 
     def evaluate():

@@ -106,11 +106,15 @@ def test_solver_arguments_are_rejected_on_the_host(lib):
                            ctypes.byref(res), fake, ws_bytes, None)
         return rc, it.value, res.value
 
-    assert solve(method=3)[0] == fem.FEM_EINVAL and b"Krylov" in lib.fem_last_error()
-    # GMRES needs its basis: FEM_GMRES_RESTART + 1 more vectors
+    assert solve(method=4)[0] == fem.FEM_EINVAL and b"Krylov" in lib.fem_last_error()
+    # GMRES needs its basis: FEM_GMRES_RESTART + 1 more vectors; FGMRES also
+    # the FEM_GMRES_RESTART preconditioned ones
     assert solve(method=2, ws_bytes=lib.fem_solver_workspace_bytes(6, 18))[0] == fem.FEM_ENOMEM
     gm = lib.fem_solver_workspace_bytes_method(3000, 9 * 27 * 1000, 2)
     assert gm >= lib.fem_solver_workspace_bytes(3000, 9 * 27 * 1000) + 31 * 3000 * 8
+    fgm = lib.fem_solver_workspace_bytes_method(3000, 9 * 27 * 1000, 3)
+    assert fgm >= gm + 30 * 3000 * 8
+    assert solve(method=3, ws_bytes=lib.fem_solver_workspace_bytes_method(6, 18, 2))[0] == fem.FEM_ENOMEM
     assert lib.fem_solver_workspace_bytes_method(3000, 9 * 27 * 1000, 0) == lib.fem_solver_workspace_bytes(
         3000, 9 * 27 * 1000)
     assert solve(pc=5)[0] == fem.FEM_EINVAL and b"preconditioner" in lib.fem_last_error()
@@ -151,6 +155,7 @@ def test_multigrid_arguments_are_rejected_on_the_host(lib):
     assert lib.fem_amg_info(None, None, None, None, None, None) == fem.FEM_EINVAL
     assert lib.fem_amg_aggregates(None, 1, fake) == fem.FEM_EINVAL
     assert lib.fem_amg_destroy(None) == fem.FEM_OK
+    assert lib.fem_amg_set_cycle(None, 1, 0) == fem.FEM_EINVAL
     c = fem.FemCsr(6, 18, fake, fake, None, None, None)
     it, res = ctypes.c_int32(-1), ctypes.c_double(-1.0)
     assert lib.fem_solve_amg(ctypes.byref(c), fake, fem.FP64, 1, None, fake, fake, 10, 1e-8, ctypes.byref(it),

@@ -79,11 +79,14 @@ def bj_blocks(A, omega=1.0):
     return sp.csr_matrix((Minv.reshape(-1), (rows, cols.reshape(-1))), shape=A.shape)
 
 
-def ref_vcycle(A0, free0, aggs, omegas, r, dense=True):
+def ref_vcycle(A0, free0, aggs, omegas, r, dense=True, klevels=()):
     """V(1,1)-cycle from the definitions (host, FP64 vectors): A0 the finest
     operator (scipy CSR), free0 its free-dof mask, aggs the aggregate map of
     each level transition, omegas the smoother damping per level; the
-    coarsest level inverted exactly (dense) or smoothed twice."""
+    coarsest level inverted exactly (dense) or smoothed twice.  On the
+    levels in klevels the coarse correction is the K-cycle's: two GCR steps
+    with the cycle below as preconditioner (the minimal-residual combination
+    of c1 = B rc and c2 = B r2)."""
     import scipy.sparse as sp
 
     As, Ms, Ps, masks = [A0], [], [], [free0]
@@ -112,7 +115,23 @@ def ref_vcycle(A0, free0, aggs, omegas, r, dense=True):
             return x + Ms[l] @ (b - As[l] @ x)
         x = Ms[l] @ b
         rc = Ps[l].T @ (b - As[l] @ x)
-        x = x + Ps[l] @ cycle(l + 1, rc)
+        c = l + 1
+        if c in klevels:
+            Ac = As[c]
+            c1 = cycle(c, rc)
+            v1 = Ac @ c1
+            vv = v1 @ v1
+            a1 = (v1 @ rc) / vv if vv > 0 else 0.0
+            r2 = rc - a1 * v1
+            c2 = cycle(c, r2)
+            v2 = Ac @ c2
+            g = (v2 @ v1) / vv if vv > 0 else 0.0
+            den = v2 @ v2 - g * (v2 @ v1)  # |v2 - g v1|^2
+            a2 = (v2 @ r2) / den if den > 0 else 0.0
+            e = (a1 - a2 * g) * c1 + a2 * c2
+        else:
+            e = cycle(c, rc)
+        x = x + Ps[l] @ e
         return x + Ms[l] @ (b - As[l] @ x)
 
     return cycle(0, r)
@@ -309,3 +328,93 @@ def test_voided_sheet_solve_matches_dense_solve(fem, method):
     G = sp.csr_matrix((np.ones(coo.nnz), (coo.row // 3, coo.col // 3)), shape=(p.n_nodes, p.n_nodes))
     agg = s.amg.aggregates(1)
     check_aggregates(G, agg)
+
+
+def k_levels(levels, k_min_nodes):
+    """Levels that take the K-cycle's two Krylov steps: above the first
+    level of at most 512 nodes, not the coarsest, at least k_min_nodes nodes."""
+    nl = len(levels)
+    t = next((l for l in range(1, nl) if levels[l][0] <= 512), nl)
+    return {c for c in range(1, nl) if c < t and c < nl - 1 and levels[c][0] >= k_min_nodes}
+
+
+@pytest.mark.parametrize("n,fbar,k_min", [(24, False, 0), (32, True, 0), (24, False, 10 ** 9)])
+def test_kcycle_matches_the_definition(fem, n, fbar, k_min):
+    """The K-cycle against the numpy cycle on the same aggregates and damping
+    (the plain tangent and the nonsymmetric F-bar one; with k_min above every
+    level it is the V-cycle), and two applications agree bitwise (the
+    device-side sums restart cleanly)."""
+    p = cube_state(n, fbar=fbar)
+    csr, K, bc = tangent(fem, p, fem.FP64)
+    amg = fem.AMG(csr, K, bc)
+    amg.update(K)
+    amg.set_cycle("k", k_min)
+    levels, dense, omegas = amg.info(omega=True)
+    kl = k_levels(levels, k_min)
+    say(f"K-cycle {n}^3 fbar={fbar} k_min={k_min}: levels {levels}, Krylov levels {sorted(kl)}")
+    assert dense and (len(kl) >= (2 if n == 32 else 1) or k_min > 0)
+    A0 = host_csr(csr, K)
+    free0 = p.bc_mask == 0
+    aggs = [amg.aggregates(l) for l in range(1, len(levels))]
+    r = np.random.default_rng(13).standard_normal(csr.n_rows) * free0
+    rt = torch.as_tensor(r).cuda()
+    z = amg.apply(rt)
+    z2 = amg.apply(rt)
+    torch.cuda.synchronize()
+    ref = ref_vcycle(A0, free0, aggs, omegas, r, klevels=kl)
+    err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say(f"  rel err {err:.2e}")
+    assert err <= 2e-6
+    assert torch.equal(z, z2)
+    assert np.all(z.cpu().numpy()[~free0] == 0.0)
+    if k_min > 0:
+        amg.set_cycle("v")
+        assert torch.equal(amg.apply(rt), z)
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "FP32_MIXED"])
+@pytest.mark.parametrize("fbar", [False, True])
+def test_flexible_gmres_with_kcycle_matches_sparse_solve(fem, prec_name, fbar):
+    """FGMRES preconditioned by the K-cycle solves the 24^3 tangent (plain and
+    F-bar) to the sparse direct solution, in fewer iterations than FGMRES
+    with the V-cycle; FGMRES with block Jacobi (a fixed preconditioner)
+    forms the GMRES iterate; a K-cycle with a method that is not
+    flexible is rejected."""
+    import ctypes
+    import scipy.sparse.linalg as spla
+    p = cube_state(24, fbar=fbar)
+    csr, K, bc = tangent(fem, p, getattr(fem, prec_name))
+    A = host_csr(csr, K).tocsc()
+    b = np.random.default_rng(6).standard_normal(csr.n_rows)
+    b[p.bc_mask.astype(bool)] = 0.0
+    bt = torch.as_tensor(b).cuda()
+    ref = spla.spsolve(A, b)
+    s = fem.Solver(csr, precond=fem.PC_AMG, method="fgmres", bc_mask=bc)
+    x, its_k, res = s.solve(K, bt, rtol=1e-10, max_iter=2000)
+    x2, its_k2, _ = s.solve(K, bt, rtol=1e-10, max_iter=2000)
+    sv = fem.Solver(csr, precond=fem.PC_AMG, method="fgmres", bc_mask=bc, cycle="v")
+    xv, its_v, res_v = sv.solve(K, bt, rtol=1e-10, max_iter=2000)
+    torch.cuda.synchronize()
+    say(f"24^3 fbar={fbar} {prec_name}: FGMRES K-cycle {its_k} ({res:.1e}), V-cycle {its_v} ({res_v:.1e}), "
+        f"levels {s.amg.info()}")
+    assert res <= 1e-10 and res_v <= 1e-10
+    for xs in (x, xv):
+        assert np.abs(xs.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+    assert its_k < its_v
+    assert its_k2 == its_k and torch.equal(x, x2)
+    # within one restart cycle FGMRES with a fixed preconditioner forms the
+    # GMRES iterate (x0 + Z y = x0 + M V y)
+    sb = fem.Solver(csr, precond=fem.PC_BLOCK_JACOBI, method="fgmres")
+    xb, its_b, res_b = sb.solve(K, bt, rtol=1e-14, max_iter=25, check=False)
+    xg, its_g, res_g = sb.solve(K, bt, rtol=1e-14, max_iter=25, method="gmres", check=False)
+    torch.cuda.synchronize()
+    dx = float((xb - xg).abs().max() / xg.abs().max())
+    say(f"  block Jacobi, 25 steps: FGMRES res {res_b:.3e}, GMRES res {res_g:.3e}, rel diff {dx:.1e}")
+    assert its_b == its_g == 25 and dx <= 1e-9 and abs(res_b - res_g) <= 1e-9 * res_g
+    # the K-cycle with CG is refused (the cycle is not a fixed linear operator)
+    s.amg.set_cycle("k")
+    it, rr = ctypes.c_int32(0), ctypes.c_double(0.0)
+    rc = fem.lib().fem_solve_amg(ctypes.byref(csr.c()), fem._ptr(K), fem._kprec(K), fem.KRYLOV["cg"], s.amg.h,
+                                 fem._ptr(bt), fem._ptr(torch.zeros_like(bt)), 10, 1e-8, ctypes.byref(it),
+                                 ctypes.byref(rr), fem._ptr(s.ws), s.ws_bytes, None)
+    assert rc == fem.FEM_EINVAL and b"flexible" in fem.lib().fem_last_error()
