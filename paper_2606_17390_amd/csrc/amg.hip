@@ -59,7 +59,6 @@ struct Level {
     double* kv1 = nullptr;     // [3 n] A c1
     double* kpart = nullptr;   // [3 kPostGrid] workgroup partial sums
     double* ksc = nullptr;     // [4] (v1, v1), a1, then the coefficients e1, e2 of c1 and c2
-    uint32_t* ktick = nullptr; // [1] finished workgroups of the product (0 between launches)
 };
 
 }  // namespace
@@ -689,20 +688,16 @@ __global__ __launch_bounds__(256) void power_finish(int32_t n, const double* __r
 // varies from one application to the next, so the outer Krylov method must
 // be a flexible one.
 
-// STEP 1: v1 = A c (stored), sums (v1, b) and (v1, v1) -> ksc[0] = (v1, v1),
-// ksc[1] = a1.  STEP 2: v2 = A c (not stored), sums (v2, v1), (v2, v2),
-// (v2, b) -> ksc[2] = a1 - a2 g, ksc[3] = a2.  Rows by 32 lanes as in
-// post_kernel; workgroup sums to part, and the last workgroup to finish
-// (ticket) adds them in workgroup order and resets the ticket.
+// STEP 1: v1 = A c (stored), part = workgroup sums of (v1, b), (v1, v1).
+// STEP 2: v2 = A c (not stored), part = workgroup sums of (v2, v1),
+// (v2, v2), (v2, b).  Rows by 32 lanes as in post_kernel.
 template <int STEP>
 __global__ __launch_bounds__(256) void kstep_product(int32_t n, const int32_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ ncol, const float* __restrict__ val,
                                                      const double* __restrict__ c, const double* __restrict__ b,
                                                      double* __restrict__ v1, double* __restrict__ part,
-                                                     uint32_t* __restrict__ ticket, double* __restrict__ ksc,
                                                      const int32_t* __restrict__ fl) {
     if (stopped(fl)) return;
-    __shared__ int last;
     const int l = (int)(threadIdx.x & (kLanes - 1));
     double d0 = 0.0, d1 = 0.0, d2 = 0.0;
     for (int64_t base = (int64_t)blockIdx.x * 8; base < n; base += (int64_t)gridDim.x * 8) {
@@ -745,32 +740,34 @@ __global__ __launch_bounds__(256) void kstep_product(int32_t n, const int32_t* _
         part[3 * blockIdx.x] = t0;
         part[3 * blockIdx.x + 1] = t1;
         part[3 * blockIdx.x + 2] = t2;
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1 ? 1 : 0;
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// One workgroup: the sums of the np workgroup partials (fixed order), then
+// STEP 1: ksc[0] = (v1, v1), ksc[1] = a1;  STEP 2: ksc[2] = a1 - a2 g,
+// ksc[3] = a2 (zero where a denominator is not positive)
+template <int STEP>
+__global__ __launch_bounds__(256) void kstep_scalars(int np, const double* __restrict__ part, double* __restrict__ ksc,
+                                                     const int32_t* __restrict__ fl) {
+    if (stopped(fl)) return;
     double q0 = 0.0, q1 = 0.0, q2 = 0.0;
-    for (int k = (int)threadIdx.x; k < (int)gridDim.x; k += 256) {
+    for (int k = (int)threadIdx.x; k < np; k += 256) {
         q0 += part[3 * k];
         q1 += part[3 * k + 1];
         q2 += part[3 * k + 2];
     }
     const double u0 = block_sum256(q0), u1 = block_sum256(q1), u2 = block_sum256(q2);
-    if (threadIdx.x == 0) {
-        *ticket = 0u;
-        if (STEP == 1) {
-            ksc[0] = u1;
-            ksc[1] = u1 > 0.0 ? u0 / u1 : 0.0;
-        } else {
-            const double vv1 = ksc[0], a1 = ksc[1];
-            const double g = vv1 > 0.0 ? u0 / vv1 : 0.0;
-            const double den = u1 - g * u0;
-            const double a2 = den > 0.0 ? u2 / den : 0.0;
-            ksc[2] = a1 - a2 * g;
-            ksc[3] = a2;
-        }
+    if (threadIdx.x != 0) return;
+    if (STEP == 1) {
+        ksc[0] = u1;
+        ksc[1] = u1 > 0.0 ? u0 / u1 : 0.0;
+    } else {
+        const double vv1 = ksc[0], a1 = ksc[1];
+        const double g = vv1 > 0.0 ? u0 / vv1 : 0.0;
+        const double den = u1 - g * u0;
+        const double a2 = den > 0.0 ? u2 / den : 0.0;
+        ksc[2] = a1 - a2 * g;
+        ksc[3] = a2;
     }
 }
 
@@ -1206,14 +1203,14 @@ const double* cycle_from(fem_amg* h, int l, const double* bl, double* out, int t
         const unsigned ng = std::min<unsigned>(kPostGrid, blocks_for((int64_t)C.n * kLanes));
         cycle_from(h, c, C.b, C.kc1, t, fl, s);
         hipLaunchKernelGGL(kstep_product<1>, dim3(ng), dim3(256), 0, s, C.n, C.row_ptr, C.ncol,
-                           (const float*)C.vals, (const double*)C.kc1, (const double*)C.b, C.kv1, C.kpart, C.ktick,
-                           C.ksc, fl);
+                           (const float*)C.vals, (const double*)C.kc1, (const double*)C.b, C.kv1, C.kpart, fl);
+        hipLaunchKernelGGL(kstep_scalars<1>, dim3(1), dim3(256), 0, s, (int)ng, (const double*)C.kpart, C.ksc, fl);
         hipLaunchKernelGGL(kstep_update, dim3(blocks_for(C.n)), dim3(256), 0, s, C.n, (const double*)C.kv1,
                            (const double*)C.ksc, (const double*)C.minv, C.b, C.x, fl);
         cycle_from(h, c, C.b, C.y, t, fl, s);
         hipLaunchKernelGGL(kstep_product<2>, dim3(ng), dim3(256), 0, s, C.n, C.row_ptr, C.ncol,
-                           (const float*)C.vals, (const double*)C.y, (const double*)C.b, C.kv1, C.kpart, C.ktick,
-                           C.ksc, fl);
+                           (const float*)C.vals, (const double*)C.y, (const double*)C.b, C.kv1, C.kpart, fl);
+        hipLaunchKernelGGL(kstep_scalars<2>, dim3(1), dim3(256), 0, s, (int)ng, (const double*)C.kpart, C.ksc, fl);
         hipLaunchKernelGGL(kprolong_kernel, dim3(blocks_for(L[l].n)), dim3(256), 0, s, L[l].n, C.agg, L[l].mask,
                            (const double*)C.kc1, (const double*)C.y, (const double*)C.ksc, L[l].x, fl);
     } else {
@@ -1352,7 +1349,6 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
                 c.take<double>(3 * n);
                 c.take<double>(3 * kPostGrid);
                 c.take<double>(4);
-                c.take<uint32_t>(1);
             }
         }
         if (dense) c.take<double>((size_t)9 * H.back().n * H.back().n);
@@ -1431,8 +1427,6 @@ extern "C" int fem_amg_create(const fem_csr* csr, const void* K_vals, fem_precis
             L.kv1 = cv.take<double>(3 * n);
             L.kpart = cv.take<double>(3 * kPostGrid);
             L.ksc = cv.take<double>(4);
-            L.ktick = cv.take<uint32_t>(1);
-            if (e == hipSuccess) e = hipMemsetAsync(L.ktick, 0, sizeof(uint32_t), s);
             up(L.agg, hl.agg.data(), nf * 4);
             up(L.mptr, hl.mptr.data(), (n + 1) * 4);
             up(L.mem, hl.mem.data(), nf * 4);
