@@ -478,19 +478,31 @@ __global__ __launch_bounds__(1024) void tail_kernel(TailArgs A, const int32_t* f
         const TailLevel& C = A.L[l + 1];
         tail_sweep<0>(F, tid);
         __syncthreads();
-        for (int64_t c = tid; c < C.n; c += 1024) {
-            double s[3] = {0.0, 0.0, 0.0};
-            for (int32_t k = C.mptr[c]; k < C.mptr[c + 1]; ++k) {
-                const int64_t i = C.mem[k];
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    if (F.mask[3 * i + a]) s[a] += F.r[3 * i + a];
+        // restriction: 8 lanes per coarse node, lane j its member j (an
+        // aggregate holds at most 8 nodes), butterfly sums in a fixed order
+        for (int64_t base = 0; base < C.n; base += 1024 / 8) {
+            const int64_t c = base + (tid >> 3);
+            const int j = tid & 7;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            if (c < C.n) {
+                const int32_t k0 = C.mptr[c];
+                if (j < C.mptr[c + 1] - k0) {
+                    const int64_t i = C.mem[k0 + j];
+                    if (F.mask[3 * i]) s0 = F.r[3 * i];
+                    if (F.mask[3 * i + 1]) s1 = F.r[3 * i + 1];
+                    if (F.mask[3 * i + 2]) s2 = F.r[3 * i + 2];
+                }
             }
-            const double* m = C.minv + 9 * c;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                C.b[3 * c + a] = s[a];
-                C.x[3 * c + a] = m[3 * a] * s[0] + m[3 * a + 1] * s[1] + m[3 * a + 2] * s[2];
+            for (int m = 1; m < 8; m <<= 1) {
+                s0 += __shfl_xor(s0, m, 8);
+                s1 += __shfl_xor(s1, m, 8);
+                s2 += __shfl_xor(s2, m, 8);
+            }
+            if (c < C.n && j < 3) {
+                const double* m = C.minv + 9 * c;
+                C.b[3 * c + j] = j == 0 ? s0 : (j == 1 ? s1 : s2);
+                C.x[3 * c + j] = m[3 * j] * s0 + m[3 * j + 1] * s1 + m[3 * j + 2] * s2;
             }
         }
         __syncthreads();
