@@ -591,6 +591,7 @@ def default_krylov(precond, fbar):
 # levels of at least this many nodes take the K-cycle's two Krylov steps
 AMG_K_MIN_NODES = 0
 AMG_MAX_LEVELS = 12
+AMG_DENSE_NODES = 32  # coarsest level inverted exactly at or below this many nodes
 
 
 class AMG:

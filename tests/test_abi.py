@@ -199,3 +199,24 @@ def test_header_is_plain_c(tmp_path):
                         os.path.join(root, "include"), "-c", str(src), "-o", str(tmp_path / "use.o")],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_binding_constants_match_the_header():
+    """The Python binding's copies of the header's constants and enum values
+    (levels, dense threshold, Krylov methods, cycle types)."""
+    from paper_2606_17390_amd import fem
+    h = open(os.path.join(ROOT, "include", "fem.h")).read()
+
+    def define(name):
+        return int(re.search(r"#define %s (\d+)" % name, h).group(1))
+
+    def enum(name):
+        return int(re.search(r"\b%s = (\d+)" % name, h).group(1))
+
+    assert define("FEM_AMG_MAX_LEVELS") == fem.AMG_MAX_LEVELS
+    assert define("FEM_AMG_DENSE_NODES") == fem.AMG_DENSE_NODES
+    for k, v in fem.KRYLOV.items():
+        assert enum("FEM_KRYLOV_" + k.upper()) == v
+    for k, v in fem.AMG_CYCLE.items():
+        assert enum("FEM_AMG_CYCLE_" + k.upper()) == v
+    assert enum("FEM_PC_AMG") == fem.PC_AMG

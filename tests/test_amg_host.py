@@ -71,7 +71,7 @@ def test_plan_partitions_levels_into_connected_aggregates(fem, dims):
     levels, maps = fem.amg_plan_host(bptr, ncol, s)
     check_plan(levels, maps, bptr, ncol)
     if X.shape[0] > 32:
-        assert levels[-1][0] <= 32
+        assert levels[-1][0] <= fem.AMG_DENSE_NODES
         # about eight nodes per aggregate on a structured hex mesh
         assert levels[1][0] <= X.shape[0] / 5
     else:
@@ -145,7 +145,7 @@ def test_clamped_nodes_join_aggregates(fem):
     s_rows = np.where(clamped[rows] & (rows != ncol), 0.0, s).astype(np.float32)
     levels, maps = fem.amg_plan_host(bptr, ncol, s_rows)
     check_plan(levels, maps, bptr, ncol)
-    assert levels[-1][0] <= 32
+    assert levels[-1][0] <= fem.AMG_DENSE_NODES
     assert levels[1][0] <= X.shape[0] / 5
     # every clamped node shares its aggregate with at least one free node
     agg = maps[0]

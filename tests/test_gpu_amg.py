@@ -183,7 +183,7 @@ def test_hierarchy_and_vcycle_match_the_definitions(fem, prec_name):
     levels, dense, omegas = amg.info(omega=True)
     say(f"hierarchy {prec_name}: {levels} dense {dense} omega {omegas}")
     assert len(levels) >= 3 and dense and levels[0] == (p.n_nodes, csr.nnz // 9)
-    assert levels[-1][0] <= 32 and omegas[-1] == 1.0
+    assert levels[-1][0] <= fem.AMG_DENSE_NODES and omegas[-1] == 1.0
     A0 = host_csr(csr, K)
     free0 = p.bc_mask == 0
     coo = A0.tocoo()
