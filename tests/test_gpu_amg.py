@@ -418,3 +418,6 @@ def test_flexible_gmres_with_kcycle_matches_sparse_solve(fem, prec_name, fbar):
                                  fem._ptr(bt), fem._ptr(torch.zeros_like(bt)), 10, 1e-8, ctypes.byref(it),
                                  ctypes.byref(rr), fem._ptr(s.ws), s.ws_bytes, None)
     assert rc == fem.FEM_EINVAL and b"flexible" in fem.lib().fem_last_error()
+    # the cycle setter checks its arguments on a live handle
+    assert fem.lib().fem_amg_set_cycle(s.amg.h, 7, 0) == fem.FEM_EINVAL
+    assert fem.lib().fem_amg_set_cycle(s.amg.h, fem.AMG_CYCLE["k"], -1) == fem.FEM_EINVAL
