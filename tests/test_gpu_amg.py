@@ -421,3 +421,32 @@ def test_flexible_gmres_with_kcycle_matches_sparse_solve(fem, prec_name, fbar):
     # the cycle setter checks its arguments on a live handle
     assert fem.lib().fem_amg_set_cycle(s.amg.h, 7, 0) == fem.FEM_EINVAL
     assert fem.lib().fem_amg_set_cycle(s.amg.h, fem.AMG_CYCLE["k"], -1) == fem.FEM_EINVAL
+
+
+def test_fgmres_kcycle_full_size_true_residual(fem):
+    """The 100^3 unit cube (3,090,903 dofs): FGMRES with the K-cycle on the
+    elastic tangent of the undeformed cube with the first load increment's
+    right-hand side reaches rtol 1e-8 by the true residual b - K x (the CSR
+    product, itself checked against scipy), with the hierarchy's Krylov
+    levels in use, and repeats bitwise."""
+    p = synth.unit_cube_forward(100)
+    mesh, params, d, h, bc, _ = gpu_problem(p, fem)
+    csr = fem.csr_pattern(mesh)
+    params = fem.Params(p.prm, p.n_elems, hardening="voce")
+    h0 = torch.zeros((7, 8 * p.n_elems), dtype=torch.float64, device="cuda")
+    u = torch.as_tensor(p.meta["bc_at"](1e-3)).cuda()
+    K = fem.residual_tangent(mesh, csr, params, torch.zeros_like(u), h0, bc_mask=bc, prec=fem.FP64_K32).K
+    b = -fem.residual_tangent(mesh, csr, params, u, h0, bc_mask=bc, prec=fem.FP64, want_K=False).R
+    s = fem.Solver(csr, precond=fem.PC_AMG, method="fgmres", bc_mask=bc)
+    x, its, res = s.solve(K, b, rtol=1e-8, max_iter=500)
+    x2, its2, _ = s.solve(K, b, rtol=1e-8, max_iter=500)
+    r = b - fem.csr_spmv(csr, K, x)
+    true = float(r.norm() / b.norm())
+    levels, _ = s.amg.info()
+    kl = k_levels(levels, 0)
+    torch.cuda.synchronize()
+    say(f"100^3 FGMRES K-cycle: {its} iterations, recursive {res:.2e}, true {true:.2e}, levels {levels}, "
+        f"Krylov levels {sorted(kl)}")
+    assert len(kl) >= 2 and its <= 60
+    assert res <= 1e-8 and true <= 1.5e-8
+    assert its2 == its and torch.equal(x, x2)
