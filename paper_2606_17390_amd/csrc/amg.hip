@@ -10,13 +10,17 @@
 //     norms, the coarse patterns, and for every coarse block the list of fine
 //     blocks that sum into it (with the 9-bit mask of free row/column dofs);
 //   - a numeric part on the device, once per matrix: Galerkin block sums
-//     (one thread per coarse block, fixed order), l1 block-Jacobi inverses
-//     (32 lanes per node) and the dense inverse of the coarsest operator (one
-//     workgroup, Gauss-Jordan in LDS).
+//     (one thread per coarse block, fixed order), 3x3 block-Jacobi inverses
+//     (32 lanes per node) damped by (4/3) / rho from a power iteration, and
+//     the dense inverse of the coarsest operator (one workgroup, Gauss-Jordan
+//     in LDS).
 // One application is a V(1,1)-cycle: per level a residual product, a
 // restriction fused with the next level's first smoothing sweep, and on the
-// way up a prolongation and a post-smoothing product.  Vectors are FP64; the
-// finest operator is K as given (FP64 or FP32), the coarse ones FP32.
+// way up a prolongation and a post-smoothing product; or a K-cycle, whose
+// coarse levels above the single-workgroup tail replace the coarse
+// correction by two minimal-residual steps (for a flexible outer method).
+// Vectors are FP64; the finest operator is K as given (FP64 or FP32), the
+// coarse ones FP32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
