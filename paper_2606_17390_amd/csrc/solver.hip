@@ -593,27 +593,18 @@ __global__ __launch_bounds__(256) void gm_normalize(int32_t n_nodes, double* __r
     }
 }
 
-// hpart[i][block] = partial of (w, v_i), i = 0..j: one pass over w with
-// the j + 1 sums in registers (each in the same order as a pass per v_i)
+// hpart[i][block] = partial of (w, v_i), i = 0..j
 __global__ __launch_bounds__(256) void gm_dots(int64_t n, int j, const double* __restrict__ V, int64_t ldv,
                                                const double* __restrict__ w, double* __restrict__ hpart,
                                                const int32_t* __restrict__ fl) {
     if (fl[0]) return;
-    double d[kGmresM + 1];
-#pragma unroll
-    for (int i = 0; i <= kGmresM; ++i) d[i] = 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)kGrid * 256) {
-        const double wk = w[k];
-#pragma unroll
-        for (int i = 0; i <= kGmresM; ++i)
-            if (i <= j) d[i] += wk * V[(int64_t)i * ldv + k];
+    for (int i = 0; i <= j; ++i) {
+        const double* __restrict__ vi = V + (int64_t)i * ldv;
+        double d = 0.0;
+        for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)kGrid * 256) d += w[k] * vi[k];
+        const double t = block_sum(d);
+        if (threadIdx.x == 0) hpart[(int64_t)i * kGrid + blockIdx.x] = t;
     }
-#pragma unroll
-    for (int i = 0; i <= kGmresM; ++i)
-        if (i <= j) {
-            const double t = block_sum(d[i]);
-            if (threadIdx.x == 0) hpart[(int64_t)i * kGrid + blockIdx.x] = t;
-        }
 }
 
 // H(i, j) = sum of hpart[i][*], one block per i
