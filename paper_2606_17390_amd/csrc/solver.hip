@@ -975,6 +975,11 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             return e;
         };
+        auto read_flags = [&]() -> hipError_t {  // within a cycle: the flags only
+            hipError_t e = hipMemcpyAsync(flh, w.fl, sizeof(flh), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            return e;
+        };
         FEM_HIP_CHECK(read_back());
         while (!flh[F_STOP]) {
             for (int j = 0; j < kGmresM; ++j) {
@@ -995,7 +1000,7 @@ int krylov_solve(const char* who, const fem_csr* csr, const void* K_vals, fem_pr
                 // stop launching once the cycle has ended
                 if (amg) {
                     FEM_HIP_CHECK(hipGetLastError());
-                    FEM_HIP_CHECK(read_back());
+                    FEM_HIP_CHECK(read_flags());
                     if (flh[F_CYC]) break;
                 }
             }
